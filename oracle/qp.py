@@ -1,0 +1,252 @@
+"""Oracle: the least-change bounded problem of Sec. 3.2 (eq. opti_masscons).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Statement.  One unknown x_k per stored entry a_k of A^(N) (the paper
+writes x as indexed by cells, which cannot be meant: A_hat has n_z
+columns, so x has n_z entries, one per nonzero).  Minimise x^T x subject to
+
+    sum_{k in row i} a_k (1 + x_k) = b_row[i]      (local, eq. localmassconsMat)
+    sum_{k in col j} a_k (1 + x_k) = b_col[j]      (global, eq. globalmassconsMat)
+    lo <= x_k <= hi.
+
+The paper asks for 1 + x positive and at most 2.  Read as the closed box
+-1 <= x <= 1 (a strictly convex objective over a closed convex set has a
+unique minimiser; an open bound would have none when it is active).  The
+box can be infeasible (a tracked cell that must take more than twice what
+it overlaps); ``box_policy="paper_then_relax"`` then drops the upper cap
+(level 1: x >= -1, volumes stay non-negative) and, if that is still
+infeasible, keeps the equalities alone (level 2).  ``"strict"`` raises
+``QPInfeasible`` instead.
+
+Method.  The minimiser is unique, so any exact method yields it.  This one
+works on the dual: with multipliers mu (rows) and nu (columns), the
+stationarity condition gives x_k = clip(a_k (mu_i + nu_j), lo, hi); the
+dual function theta(mu, nu) = sum_k psi(a_k (mu_i + nu_j)) - mu.r - nu.s
+(psi' = clip) is convex and C^1, its gradient is the constraint residual,
+and it is minimised by a damped semismooth Newton method whose linear
+systems are solved directly (SuperLU), with an Armijo backtracking line
+search.  The returned x is *defined* as clip(A_hat^T lambda), so it
+satisfies stationarity and the bounds exactly; ``verify_kkt`` then checks
+primal feasibility, which together certify optimality.  Feasibility of a
+box level, when Newton does not converge, is decided by a linear program
+(HiGHS).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from scipy.optimize import linprog
+
+BOX_LEVELS = {0: (-1.0, 1.0), 1: (-1.0, np.inf), 2: (-np.inf, np.inf)}
+
+
+class QPInfeasible(RuntimeError):
+    pass
+
+
+class QPNotConverged(RuntimeError):
+    pass
+
+
+def constraint_matrix(row_ptr, col, val, n_cols):
+    """A_hat (2 n_c x n_z) of Sec. 3.2, built as the paper describes it.
+
+    The nonzeros of each row of A^(N) are laid side by side (row i's
+    entries occupy the unknown slots row_ptr[i] .. row_ptr[i+1]-1, in
+    ascending column order): the first n_c rows of A_hat carry row i's
+    entries on its slots; row n_c + j carries, on the slot of every entry
+    a_{i,j} of column j, that same value.  Returned dense (small cases)."""
+    nr = len(row_ptr) - 1
+    nz = len(val)
+    Ah = np.zeros((nr + n_cols, nz))
+    for i in range(nr):
+        for k in range(row_ptr[i], row_ptr[i + 1]):
+            Ah[i, k] = val[k]
+            Ah[nr + col[k], k] = val[k]
+    return Ah
+
+
+def constraint_rhs(rows, cols, a, b_row, b_col):
+    """r, s: what sum a_k x_k must equal on each row / column."""
+    nr, nc = len(b_row), len(b_col)
+    r = np.asarray(b_row, dtype=np.float64) - np.bincount(rows, weights=a, minlength=nr)
+    s = np.asarray(b_col, dtype=np.float64) - np.bincount(cols, weights=a, minlength=nc)
+    return r, s
+
+
+def residual(rows, cols, a, x, r, s):
+    nr, nc = r.size, s.size
+    ax = a * x
+    return np.concatenate([np.bincount(rows, weights=ax, minlength=nr) - r,
+                           np.bincount(cols, weights=ax, minlength=nc) - s])
+
+
+def _dpsi(t, d, lo, hi):
+    """psi(t + d) - psi(t), where psi is the primitive of clip(., lo, hi)
+    vanishing at 0, evaluated without cancelling large terms: psi(u) =
+    c^2/2 + c (u - c) with c = clip(u)."""
+    u = t + d
+    c1 = np.clip(t, lo, hi)
+    c2 = np.clip(u, lo, hi)
+    free1 = c1 == t
+    free2 = c2 == u
+    out = 0.5 * (c2 * c2 - c1 * c1) + c2 * np.where(free2, 0.0, u - c2) \
+        - c1 * np.where(free1, 0.0, t - c1)
+    both = free1 & free2
+    out[both] = d[both] * (t[both] + 0.5 * d[both])
+    same = (~free1) & (~free2) & (c1 == c2)
+    out[same] = c1[same] * d[same]
+    return out
+
+
+def feasible_lp(rows, cols, a, b_row, b_col, lo, hi):
+    """Is {lo <= x <= hi, row/col sums of a(1+x) = b} non-empty?  Decided
+    with an LP on y = a(1+x) >= 0 plus slacks: minimise the total slack."""
+    nz = a.size
+    nr, nc = len(b_row), len(b_col)
+    ylo = a * (1.0 + lo) if np.isfinite(lo) else np.full(nz, -np.inf)
+    yhi = a * (1.0 + hi) if np.isfinite(hi) else np.full(nz, np.inf)
+    # A_eq [y; sp; sm] = b with sp, sm >= 0
+    E = sp.vstack([
+        sp.csr_matrix((np.ones(nz), (rows, np.arange(nz))), shape=(nr, nz)),
+        sp.csr_matrix((np.ones(nz), (cols, np.arange(nz))), shape=(nc, nz)),
+    ])
+    m = nr + nc
+    I = sp.identity(m, format="csr")
+    Aeq = sp.hstack([E, I, -I]).tocsr()
+    beq = np.concatenate([b_row, b_col])
+    cvec = np.concatenate([np.zeros(nz), np.ones(2 * m)])
+    bounds = [(ylo[k] if np.isfinite(ylo[k]) else None,
+               yhi[k] if np.isfinite(yhi[k]) else None) for k in range(nz)]
+    bounds += [(0, None)] * (2 * m)
+    res = linprog(cvec, A_eq=Aeq, b_eq=beq, bounds=bounds, method="highs")
+    if res.status != 0:
+        raise RuntimeError("feasibility LP failed: " + res.message)
+    scale = max(float(np.max(np.abs(beq))), 1e-300)
+    return res.fun <= 1e-9 * scale, res.fun
+
+
+def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
+    """Damped semismooth Newton on the dual; inputs already scaled so that
+    max |b| = 1.  Returns (x, t, mu, nu, residual_inf, iterations, ok).
+
+    t_k = a_k (mu_i + nu_j) is carried entry by entry and updated by the
+    increments a_k (dmu_i + dnu_j): weakly coupled cells give multipliers
+    of very different sizes, and recomputing t from them would cancel
+    digits.  Newton systems J d = -F, J = A_hat diag(free) A_hat^T (plus a
+    relative 1e-13 diagonal shift for the singular directions), are solved
+    by sparse LU with two steps of iterative refinement.  The component of
+    d along the null vector (1_rows, -1_cols), which moves no t_k, is
+    removed.  The step length is chosen by Armijo backtracking on theta,
+    whose change is summed entry by entry (psi differences) rather than as
+    a difference of two large totals.
+    """
+    nr, nc = r.size, s.size
+    mu = np.zeros(nr)
+    nu = np.zeros(nc)
+    t = np.zeros(a.size)
+    rs = np.concatenate([r, s])
+    v0 = np.concatenate([np.ones(nr), -np.ones(nc)])
+    a2 = a * a
+    x = np.clip(t, lo, hi)
+    F = residual(rows, cols, a, x, r, s)
+    for it in range(1, max_iter + 1):
+        fn = float(np.max(np.abs(F)))
+        if fn <= tol:
+            return x, t, mu, nu, fn, it - 1, True
+        free = (t > lo) & (t < hi)
+        w = a2 * free
+        dr = np.bincount(rows, weights=w, minlength=nr)
+        dc = np.bincount(cols, weights=w, minlength=nc)
+        W = sp.csr_matrix((w, (rows, cols)), shape=(nr, nc))
+        tau = 1e-13 * max(float(np.max(dr, initial=0.0)), float(np.max(dc, initial=0.0)), 1e-300)
+        J = sp.bmat([[sp.diags(dr + tau), W], [W.T, sp.diags(dc + tau)]], format="csc")
+        lu = spla.splu(J)
+        d = lu.solve(-F)
+        for _ in range(2):
+            d = d + lu.solve(-F - J @ d)
+        d = d - (d @ v0) / (nr + nc) * v0
+        dmu, dnu = d[:nr], d[nr:]
+        dt = a * (dmu[rows] + dnu[cols])
+        slope = float(F @ d)
+        if not slope < 0.0:
+            return x, t, mu, nu, fn, it, False
+        step = 1.0
+        while True:
+            dtheta = float(np.sum(_dpsi(t, step * dt, lo, hi))) - step * float(d @ rs)
+            if dtheta <= 1e-4 * step * slope:
+                break
+            # near the solution theta changes by less than its rounding;
+            # accept a full step that shrinks the residual
+            if step == 1.0:
+                xt = np.clip(t + dt, lo, hi)
+                Ft = residual(rows, cols, a, xt, r, s)
+                if float(np.max(np.abs(Ft))) < 0.5 * fn:
+                    break
+            step *= 0.5
+            if step < 1e-12:
+                return x, t, mu, nu, fn, it, False
+        t = t + step * dt
+        mu, nu = mu + step * dmu, nu + step * dnu
+        x = np.clip(t, lo, hi)
+        F = residual(rows, cols, a, x, r, s)
+        if not np.all(np.isfinite(F)) or float(np.max(np.abs(t))) > 1e12:
+            return x, t, mu, nu, float(np.max(np.abs(F))), it, False
+    fn = float(np.max(np.abs(F)))
+    return x, t, mu, nu, fn, max_iter, fn <= tol
+
+
+def solve_mass_qp(rows, cols, a, b_row, b_col, box_policy="paper_then_relax",
+                  tol=1e-14, max_iter=200, levels=None):
+    """Unique minimiser of eq. opti_masscons; see the module docstring.
+
+    ``tol`` bounds max |A_hat(1+x) - b| relative to max |b|.
+    Returns a dict: ``x`` (n_z), ``mu``, ``nu`` (dual, in the units of the
+    scaled problem a / max|b|), ``level``, ``residual`` (relative),
+    ``iterations``, ``lo``, ``hi``.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    a = np.asarray(a, dtype=np.float64)
+    b_row = np.asarray(b_row, dtype=np.float64)
+    b_col = np.asarray(b_col, dtype=np.float64)
+    scale = float(max(np.max(np.abs(b_row)), np.max(np.abs(b_col))))
+    As, bR, bC = a / scale, b_row / scale, b_col / scale
+    r, s = constraint_rhs(rows, cols, As, bR, bC)
+    if levels is None:
+        levels = (0,) if box_policy == "strict" else (0, 1, 2)
+    for level in levels:
+        lo, hi = BOX_LEVELS[level]
+        x, t, mu, nu, res, it, ok = _newton(rows, cols, As, r, s, lo, hi, tol, max_iter)
+        if ok:
+            return {"x": x, "t": t, "mu": mu, "nu": nu, "level": level, "residual": res,
+                    "iterations": it, "lo": lo, "hi": hi, "scale": scale}
+        if level < 2:
+            feas, _ = feasible_lp(rows, cols, As, bR, bC, lo, hi)
+            if feas:
+                raise QPNotConverged(f"Newton stalled at level {level} (residual {res:.3e})"
+                                     " although the LP finds the box feasible")
+        elif not ok:
+            raise QPNotConverged(f"equality-only level did not converge ({res:.3e})")
+    raise QPInfeasible("box infeasible at every allowed level")
+
+
+def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol):
+    """Certificate of optimality for a returned (x, lambda): x lies in the
+    box, meets every constraint to ``tol`` (relative to ``scale``), and
+    equals clip(a (mu_i + nu_j)) entrywise up to the rounding of the sum
+    mu_i + nu_j (the multipliers of weakly coupled cells can be large, so
+    the check allows 1e-12 of |a| (|mu_i| + |nu_j|)).  Returns the worst
+    violation of each condition and ``ok``."""
+    As = np.asarray(a) / scale
+    t = As * (mu[rows] + nu[cols])
+    mag = np.abs(As) * (np.abs(mu[rows]) + np.abs(nu[cols]))
+    stat = float(np.max((np.abs(np.clip(t, lo, hi) - x)) / (1.0 + mag), initial=0.0))
+    box = float(max(np.max(lo - x, initial=-np.inf), np.max(x - hi, initial=-np.inf), 0.0))
+    r, s = constraint_rhs(rows, cols, As, np.asarray(b_row) / scale, np.asarray(b_col) / scale)
+    prim = float(np.max(np.abs(residual(rows, cols, As, x, r, s)), initial=0.0))
+    return {"stationarity": stat, "box": box, "primal": prim,
+            "ok": stat <= 1e-12 and box == 0.0 and prim <= tol}

@@ -1,0 +1,219 @@
+"""Oracle, algebraic part: V, the scaling sweeps, apply, mass, one full step.
+
+Test infrastructure only (see ``oracle/__init__.py``).  Plain NumPy/SciPy,
+binary64.
+
+A sparse matrix is kept as CSR arrays ``(row_ptr, col, val)`` with the
+columns of each row strictly ascending; row i is the tracked cell K_i and
+column j the residing cell M_j (Sec. 3.2).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import geometry as geo
+from .qp import solve_mass_qp
+
+
+class VoidRowError(RuntimeError):
+    """A tracked ball overlaps no residing ball: the denominator of
+    eq. fracMaterial is zero and its mass cannot be placed."""
+
+    def __init__(self, ball, cell):
+        super().__init__(f"tracked ball {ball} of cell {cell} meets no residing ball")
+        self.ball, self.cell = ball, cell
+
+
+class VoidColumnError(RuntimeError):
+    """Column j of A^(0) sums to zero (Sec. 3.2: no tracked ball reaches a
+    ball of M_j), so the column scaling of eq. volAdj is undefined."""
+
+    def __init__(self, col):
+        super().__init__(f"residing cell {col} receives no tracked ball")
+        self.col = col
+
+
+def csr_from_coo(nrows, rows, cols, vals):
+    """Sum duplicate (row, col) entries; columns ascending within rows."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    ncols = int(cols.max()) + 1 if cols.size else 1
+    key = rows * ncols + cols
+    uniq, inv = np.unique(key, return_inverse=True)
+    v = np.zeros(uniq.size, dtype=np.float64)
+    np.add.at(v, inv, vals)
+    r = uniq // ncols
+    c = uniq % ncols
+    row_ptr = np.zeros(nrows + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return row_ptr, c.astype(np.int64), v
+
+
+def csr_rows(row_ptr):
+    """Row index of every stored entry."""
+    return np.repeat(np.arange(row_ptr.size - 1, dtype=np.int64), np.diff(row_ptr))
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.1: initial approximation V
+# --------------------------------------------------------------------------
+
+def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
+                    traced, r_hat, ia, ib, precision="fp64"):
+    """V_{K_hat, M} of eq. ball_int, as CSR.
+
+    For a candidate pair (tracked ball a of cell K, residing ball b of cell
+    M) the weight is omega = rho_M phi_M |B_hat_a cap B_b| (Remark
+    porousBallInt).  S_a = sum of omega over the pairs of a is the
+    denominator of eq. fracMaterial.  The tracked ball carries the porous
+    mass rho_K phi_hat |B_hat| = rho_K phi_K |B_a| (eq. expPhiB), and that
+    mass is split over the residing balls in the ratios omega / S_a;
+    V_{K,M} sums those shares over the balls of K and of M.
+
+    ``precision="fp32"`` (FP32-volume mode) rounds centres and radii to
+    binary32 before the distance and the lens, which are then evaluated in
+    binary64 on those rounded inputs.
+    """
+    ball_cell = np.asarray(ball_cell, dtype=np.int64)
+    phi = np.asarray(phi, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    if precision == "fp32":
+        def rd(x):
+            return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    else:
+        def rd(x):
+            return np.asarray(x, dtype=np.float64)
+    tc, rc = rd(traced), rd(centres)
+    r1, r2 = rd(r_hat)[ia], rd(radii)[ib]
+    d = np.sqrt(np.sum((tc[ia] - rc[ib]) ** 2, axis=1))
+    lens = geo.lens_measure(r1, r2, d, dim)
+    cb = ball_cell[ib]
+    ca = ball_cell[ia]
+    omega = rho[cb] * phi[cb] * lens
+    nballs = ball_cell.size
+    S = np.bincount(ia, weights=omega, minlength=nballs)
+    void = np.nonzero(S <= 0.0)[0]
+    if void.size:
+        raise VoidRowError(int(void[0]), int(ball_cell[void[0]]))
+    mass = rho[ball_cell] * phi[ball_cell] * geo.ball_measure(radii, dim)
+    share = mass[ia] * omega / S[ia]
+    return csr_from_coo(nc, ca, cb, share)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.2: mass adjustment sweeps, eq. volAdj
+# --------------------------------------------------------------------------
+
+def scaling_sweeps(row_ptr, col, val, b_loc, b_glob, n_sweeps):
+    """A^(N) from A^(0) = V by N sweeps of eq. volAdj.
+
+    Each sweep first scales every column j to sum |M_j|_phi, then every row
+    i to sum |F_{-dt}(K_i)|_phi (= |K_i|_phi for solenoidal u, eq.
+    exactVol_traceback).  Rows therefore hold exactly after every sweep.
+    """
+    a = np.array(val, dtype=np.float64, copy=True)
+    rows = csr_rows(row_ptr)
+    nc = row_ptr.size - 1
+    for _ in range(int(n_sweeps)):
+        cs = np.bincount(col, weights=a, minlength=nc)
+        if np.any(cs <= 0.0):
+            raise VoidColumnError(int(np.nonzero(cs <= 0.0)[0][0]))
+        a = a * (np.asarray(b_glob)[col] / cs[col])
+        rs = np.bincount(rows, weights=a, minlength=nc)
+        a = a * (np.asarray(b_loc)[rows] / rs[rows])
+    return a
+
+
+def check_columns(col, val, nc):
+    cs = np.bincount(col, weights=val, minlength=nc)
+    if np.any(cs <= 0.0):
+        raise VoidColumnError(int(np.nonzero(cs <= 0.0)[0][0]))
+
+
+# --------------------------------------------------------------------------
+# Sec. 2: the update and the mass
+# --------------------------------------------------------------------------
+
+def apply(row_ptr, col, val, b_loc, c):
+    """c^{n+1}_K = (1/|K|_phi) sum_M |M cap F_{-dt}(K)|_phi c^n_M
+    (eq. phys-inter-ELLAM) with the final volumes as the matrix."""
+    rows = csr_rows(row_ptr)
+    c = np.asarray(c, dtype=np.float64)
+    num = np.bincount(rows, weights=np.asarray(val) * c[col], minlength=row_ptr.size - 1)
+    return num / np.asarray(b_loc, dtype=np.float64)
+
+
+def mass(phi, cell_vol, c):
+    """sum_K phi_K |K| c_K (Sec. 2.1), correctly rounded (math.fsum)."""
+    terms = np.asarray(phi, dtype=np.float64) * np.asarray(cell_vol, dtype=np.float64) \
+        * np.asarray(c, dtype=np.float64)
+    return math.fsum(terms.tolist())
+
+
+# --------------------------------------------------------------------------
+# One time step of Algorithm 1 plus the update
+# --------------------------------------------------------------------------
+
+def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
+                   precision="fp64", box_policy="paper_then_relax", stop_after="all",
+                   traced_override=None, qp_tol=1e-14):
+    """Transfer matrix of one time step: Algorithm 1 of Sec. 3.3.
+
+    ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) and ``phi``
+    (per cell).  ``vel``: velocity lattice dict (``m``, ``origin``,
+    ``spacing``, ``u``).  Returns a dict holding every intermediate stage.
+    ``traced_override`` replaces the tracked centres (to compare the
+    later stages on identical geometry).
+    """
+    n = tuple(int(v) for v in mesh["n"])
+    dim = len(n)
+    nc = int(np.prod(n))
+    h = tuple(float(v) for v in mesh["h"])
+    phi = np.asarray(mesh["phi"], dtype=np.float64)
+    if phi.shape != (nc,) or not np.all(np.isfinite(phi)) or np.any(phi <= 0):
+        raise ValueError("phi must be finite and > 0 on every cell (Sec. 1.2)")
+    kvol = geo.cell_volume(h)
+    centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
+    rho = geo.porous_density(nc, np.full(nc, kvol), radii, bcell, dim)
+    b = phi * kvol                      # |K|_phi = b_loc = b_glob (eq. exactVol_traceback)
+    out = {"centres": centres, "radii": radii, "ball_cell": bcell, "rho": rho, "b": b,
+           "cell_vol": kvol}
+    if traced_override is None:
+        traced = geo.trace_points(centres, mesh, vel, dt, substeps)
+    else:
+        traced = np.asarray(traced_override, dtype=np.float64)
+    r_hat = geo.tracked_radius(centres, radii, traced, mesh, vel, dt, substeps)
+    out["traced"], out["r_hat"] = traced, r_hat
+    ia, ib = geo.candidate_pairs(traced, r_hat, centres, radii, precision=precision)
+    out["pairs"] = (ia, ib)
+    if stop_after == "pairs":
+        return out
+    rp, cl, V = initial_volumes(nc, dim, bcell, centres, radii, rho, phi, traced, r_hat,
+                                ia, ib, precision=precision)
+    out["row_ptr"], out["col"], out["V"] = rp, cl, V
+    check_columns(cl, V, nc)
+    if stop_after == "v":
+        return out
+    AN = scaling_sweeps(rp, cl, V, b, b, n_sweeps)
+    out["AN"] = AN
+    if stop_after == "sinkhorn":
+        return out
+    res = solve_mass_qp(csr_rows(rp), cl, AN, b, b, box_policy=box_policy, tol=qp_tol)
+    out["qp"] = res
+    out["A"] = AN * (1.0 + res["x"])
+    return out
+
+
+def run(mesh, vel_fn, c0, dt, steps, **kw):
+    """``steps`` time steps; ``vel_fn(step)`` returns the velocity lattice
+    of the interval (t^n, t^{n+1}).  Returns the list of concentrations."""
+    cs = [np.asarray(c0, dtype=np.float64)]
+    for s in range(steps):
+        T = build_transfer(mesh, vel_fn(s), dt, **kw)
+        cs.append(apply(T["row_ptr"], T["col"], T["A"], T["b"], cs[-1]))
+    return cs

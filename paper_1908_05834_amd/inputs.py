@@ -1,0 +1,225 @@
+"""Seeded synthetic inputs: meshes, porosity, velocity lattices, c^0.
+
+This module only *describes problems*; it holds none of the B-char
+arithmetic (no balls, no tracking, no intersections, no adjustment).  Both
+the HIP path and the CPU oracle receive what it produces.
+
+* A Cartesian mesh is a dict ``{"n", "origin", "h", "phi"}``: cells per
+  axis (x first), the domain corner, the cell size per axis and the
+  porosity per cell (cell ids x-fastest).
+* A velocity lattice is a dict ``{"m", "origin", "spacing", "u"}``: nodes
+  per axis, the first node, the node spacing and ``u`` of shape
+  ``(dim, prod(m))`` stored x-fastest.  For a Cartesian mesh the lattice
+  nodes are the mesh vertices, so the Q1 interpolant of the nodal values is
+  a piecewise polynomial on the mesh as the scheme assumes.
+* A time-dependent field is sampled at the middle of each time interval.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# meshes and lattices
+# --------------------------------------------------------------------------
+
+def cartesian_mesh(n, length=1.0, origin=None, phi=None):
+    n = tuple(int(v) for v in n)
+    dim = len(n)
+    if origin is None:
+        origin = (0.0,) * dim
+    L = (float(length),) * dim if np.isscalar(length) else tuple(float(v) for v in length)
+    h = tuple(L[a] / n[a] for a in range(dim))
+    nc = int(np.prod(n))
+    if phi is None:
+        phi = np.ones(nc)
+    return {"n": n, "origin": tuple(float(v) for v in origin), "h": h,
+            "phi": np.ascontiguousarray(phi, dtype=np.float64)}
+
+
+def cell_centroids(mesh):
+    n, o, h = mesh["n"], mesh["origin"], mesh["h"]
+    dim = len(n)
+    ids = np.arange(int(np.prod(n)))
+    out = np.empty((ids.size, dim))
+    rem = ids.copy()
+    for a in range(dim):
+        out[:, a] = o[a] + ((rem % n[a]) + 0.5) * h[a]
+        rem //= n[a]
+    return out
+
+
+def lattice_nodes(m, origin, spacing):
+    dim = len(m)
+    ids = np.arange(int(np.prod(m)))
+    out = np.empty((ids.size, dim))
+    rem = ids.copy()
+    for a in range(dim):
+        out[:, a] = origin[a] + (rem % m[a]) * spacing[a]
+        rem //= m[a]
+    return out
+
+
+def sample_velocity(mesh, field, t=0.0):
+    """Nodal lattice on the mesh vertices of ``field(points, t)``."""
+    m = tuple(v + 1 for v in mesh["n"])
+    pts = lattice_nodes(m, mesh["origin"], mesh["h"])
+    u = np.ascontiguousarray(np.asarray(field(pts, t), dtype=np.float64).T)
+    return {"m": m, "origin": mesh["origin"], "spacing": mesh["h"], "u": u}
+
+
+# --------------------------------------------------------------------------
+# velocity fields
+# --------------------------------------------------------------------------
+
+def solid_body_2d(p, t=0.0):
+    """u = 2 pi (-(y - 1/2), x - 1/2): one turn per unit time."""
+    x, y = p[:, 0], p[:, 1]
+    return np.stack([-2.0 * math.pi * (y - 0.5), 2.0 * math.pi * (x - 0.5)], axis=1)
+
+
+def rotation_stretch_2d(p, t=0.0):
+    """u = ((1-2y)(x-x^2), -(1-2x)(y-y^2)): divergence free, tangential on
+    the unit square (the rotation-with-stretching field of the 2D tests)."""
+    x, y = p[:, 0], p[:, 1]
+    return np.stack([(1 - 2 * y) * (x - x * x), -(1 - 2 * x) * (y - y * y)], axis=1)
+
+
+def swirl_3d(p, t=0.0, period=1.0, amplitude=1.0):
+    """Divergence-free 3D swirl, reversing at t = period/2:
+    u = (2 sin^2(pi x) sin(2 pi y) sin(2 pi z),
+         -sin(2 pi x) sin^2(pi y) sin(2 pi z),
+         -sin(2 pi x) sin(2 pi y) sin^2(pi z)) cos(pi t / period)."""
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    s = amplitude * math.cos(math.pi * t / period)
+    sx, sy, sz = np.sin(math.pi * x), np.sin(math.pi * y), np.sin(math.pi * z)
+    s2x, s2y, s2z = np.sin(2 * math.pi * x), np.sin(2 * math.pi * y), np.sin(2 * math.pi * z)
+    return s * np.stack([2 * sx * sx * s2y * s2z, -s2x * sy * sy * s2z, -s2x * s2y * sz * sz],
+                        axis=1)
+
+
+def deformation_2d(p, t=0.0, period=1.0, amplitude=1.0):
+    """2D analogue: u = (sin^2(pi x) sin(2 pi y), -sin^2(pi y) sin(2 pi x)) cos(pi t/T)."""
+    x, y = p[:, 0], p[:, 1]
+    s = amplitude * math.cos(math.pi * t / period)
+    return s * np.stack([np.sin(math.pi * x) ** 2 * np.sin(2 * math.pi * y),
+                         -np.sin(math.pi * y) ** 2 * np.sin(2 * math.pi * x)], axis=1)
+
+
+def constant_field(vec):
+    vec = np.asarray(vec, dtype=np.float64)
+
+    def f(p, t=0.0):
+        return np.broadcast_to(vec, p.shape).copy()
+    return f
+
+
+def fourier_modes_field(dim, seed, n_modes=4):
+    """Sum of ``n_modes`` divergence-free modes a_m curl(psi_m e_alpha) with
+    psi_m = prod_axes sin(k_axis pi x_axis), k in {1,2,3}, a_m ~ N(0,1);
+    tangential on the unit box boundary."""
+    rng = np.random.default_rng(seed)
+    modes = []
+    for _ in range(n_modes):
+        k = rng.integers(1, 4, size=dim)
+        amp = rng.standard_normal()
+        alpha = 2 if dim == 2 else int(rng.integers(0, 3))
+        modes.append((k, amp, alpha))
+
+    def f(p, t=0.0):
+        out = np.zeros_like(p)
+        for k, amp, alpha in modes:
+            s = [np.sin(k[a] * math.pi * p[:, a]) for a in range(dim)]
+            c = [k[a] * math.pi * np.cos(k[a] * math.pi * p[:, a]) for a in range(dim)]
+            if dim == 2:
+                # curl(psi e_z) = (d psi/dy, -d psi/dx)
+                out[:, 0] += amp * s[0] * c[1]
+                out[:, 1] += -amp * c[0] * s[1]
+            else:
+                psi_d = []
+                for a in range(3):
+                    term = c[a].copy()
+                    for b in range(3):
+                        if b != a:
+                            term = term * s[b]
+                    psi_d.append(term)
+                # curl(psi e_alpha): e_alpha x ... written component-wise
+                if alpha == 0:
+                    out[:, 1] += amp * psi_d[2]
+                    out[:, 2] += -amp * psi_d[1]
+                elif alpha == 1:
+                    out[:, 0] += -amp * psi_d[2]
+                    out[:, 2] += amp * psi_d[0]
+                else:
+                    out[:, 0] += amp * psi_d[1]
+                    out[:, 1] += -amp * psi_d[0]
+        return out
+    return f
+
+
+# --------------------------------------------------------------------------
+# initial concentrations and porosity
+# --------------------------------------------------------------------------
+
+def disk_indicator(mesh, centre, radius):
+    """c^0 = 1 on cells whose centroid is within ``radius`` of ``centre``."""
+    x = cell_centroids(mesh)
+    d2 = np.sum((x - np.asarray(centre)) ** 2, axis=1)
+    return (d2 < radius * radius).astype(np.float64)
+
+
+def uniform_c(mesh, seed):
+    return np.random.default_rng(seed).uniform(0.0, 1.0, int(np.prod(mesh["n"])))
+
+
+def lognormal_phi(n_cells, seed, sigma=0.5, lo=0.05, hi=1.0):
+    z = np.random.default_rng(seed).standard_normal(n_cells)
+    return np.clip(np.exp(sigma * z), lo, hi)
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+def solid_body_32():
+    """2D solid-body rotation: unit square, 32 x 32 cells, phi = 1,
+    u = 2 pi (-(y-1/2), x-1/2), c^0 = indicator of the disk of radius 0.15
+    at (0.5, 0.75), dt = 0.01, 10 steps (velocity time independent)."""
+    mesh = cartesian_mesh((32, 32))
+    vel = sample_velocity(mesh, solid_body_2d)
+    c0 = disk_indicator(mesh, (0.5, 0.75), 0.15)
+    return {"name": "solid_body_2d_32x32", "mesh": mesh, "vel_fn": lambda step: vel,
+            "c0": c0, "dt": 0.01, "steps": 10, "time_dependent": False}
+
+
+def swirl_hex(n=64, steps=None):
+    """3D swirl on the unit cube, n^3 hexahedra, phi = 1, dt = 1/128, the
+    field sampled at t^{n+1/2} each step, c^0 = indicator of the ball of
+    radius 0.15 at (0.35, 0.35, 0.35); 128 steps reach t = 1 where the
+    flow has returned."""
+    mesh = cartesian_mesh((n, n, n))
+    dt = 1.0 / 128.0
+
+    def vel_fn(step):
+        return sample_velocity(mesh, lambda p, t: swirl_3d(p, t), (step + 0.5) * dt)
+    c0 = disk_indicator(mesh, (0.35, 0.35, 0.35), 0.15)
+    return {"name": f"swirl_hex_{n}^3", "mesh": mesh, "vel_fn": vel_fn, "c0": c0, "dt": dt,
+            "steps": 128 if steps is None else steps, "time_dependent": True}
+
+
+def porous_swirl_hex(n=32, seed=5834, steps=20):
+    """3D swirl with a lognormal porosity phi = clip(exp(0.5 Z), 0.05, 1)
+    per cell, c^0 ~ U[0,1]; exercises the tracked-radius rule for
+    non-constant phi."""
+    nc = n ** 3
+    mesh = cartesian_mesh((n, n, n), phi=lognormal_phi(nc, seed))
+    dt = 1.0 / 128.0
+
+    def vel_fn(step):
+        return sample_velocity(mesh, lambda p, t: swirl_3d(p, t), (step + 0.5) * dt)
+    c0 = uniform_c(mesh, 33)
+    return {"name": f"porous_swirl_hex_{n}^3", "mesh": mesh, "vel_fn": vel_fn, "c0": c0,
+            "dt": dt, "steps": steps, "time_dependent": True}
