@@ -1,0 +1,241 @@
+/*
+ * bchar.h -- C ABI of the B-char transfer build and apply on AMD MI355X.
+ *
+ * Method: Cheng & Droniou, "An efficient implementation of mass conserving
+ * characteristic-based schemes in 2D and 3D" (arXiv:1908.05834).  The
+ * problem is the pure advection equation phi dc/dt + div(u c) = 0 on a
+ * box with u.n = 0 on its boundary (Sec. 1.1, eq. advection); cells carry a
+ * piecewise-constant porosity phi > 0 and one concentration value each
+ * (Sec. 1.2).  One time step computes the transfer matrix A whose entry
+ * (K, M) approximates |M cap F_{-dt}(K)|_phi, and applies it:
+ *     |K|_phi c_K^{n+1} = sum_M A_{K,M} c_M^n        (Sec. 2, eq. phys-inter-ELLAM)
+ * A is built by Algorithm 1 (Sec. 3.3): balls per cell (Sec. 3), backward
+ * tracking of their centres (eq. charac), ball-ball intersection volumes
+ * combined into V (Sec. 3.1, eq. ball_int), N alternating column/row
+ * scalings (Sec. 3.2, eq. volAdj) and the least-change bounded problem
+ * (Sec. 3.2, eq. opti_masscons), so that every row sums to |K|_phi and
+ * every column to |M|_phi (local and global mass conservation).
+ *
+ * Conventions
+ *  - Every pointer argument documented "device" is a HIP device address on
+ *    the current device; "host" is ordinary host memory.  The library
+ *    never frees caller memory.
+ *  - Handles own all device memory they allocate; *_destroy frees it.
+ *    Destroying NULL is a no-op; destroying twice is a caller error.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device
+ *    work is ordered on it.  Calls that return host values or statistics
+ *    synchronise that stream before returning.
+ *  - Errors are returned as bchar_status and never abort; no C++
+ *    exception crosses this interface.  bchar_last_error() returns a
+ *    thread-local message describing the most recent failure.  On error,
+ *    output handles are set to NULL.
+ *  - Handles are not safe for concurrent use from several threads.
+ *  - Cells are numbered x-fastest: id = i + n0*(j + n1*k).  Nodal velocity
+ *    lattices are stored the same way.  Sparse matrices are CSR with
+ *    strictly ascending columns in each row.
+ */
+#ifndef BCHAR_H
+#define BCHAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BCHAR_OK = 0,
+  BCHAR_E_INVALID_ARG = 1,      /* a size, pointer or value is out of range     */
+  BCHAR_E_OUT_OF_MEMORY = 2,    /* device allocation failed                     */
+  BCHAR_E_DEVICE = 3,           /* a HIP runtime call failed                    */
+  BCHAR_E_VOID_ROW = 4,         /* a tracked ball overlaps no residing ball:
+                                   the denominator of eq. fracMaterial is 0    */
+  BCHAR_E_VOID_COLUMN = 5,      /* a column of V sums to 0 (Sec. 3.2): no
+                                   tracked ball reaches that residing cell     */
+  BCHAR_E_QP_INFEASIBLE = 6,    /* eq. opti_masscons has no solution in the box
+                                   allowed by the box policy                   */
+  BCHAR_E_QP_NOT_CONVERGED = 7, /* the solver of eq. opti_masscons stopped
+                                   before reaching the tolerance               */
+  BCHAR_E_UNSUPPORTED = 8       /* a configuration outside what is built       */
+} bchar_status;
+
+/* Ball layouts: which balls B_{K,s} represent a cell (Sec. 3 leaves the
+ * choice open; Sec. 4 uses 4 balls per square and 8 per cube).
+ *   SUBCELL       2^d balls at the centres of the 2^d half-size sub-cells,
+ *                 radius min(h)/4 (disjoint, one quarter of the smallest face)
+ *   INSCRIBED     one ball at the centroid, radius min(h)/2
+ *   EQUAL_MEASURE one ball at the centroid with |B| = |K| (overlaps its
+ *                 neighbours)                                              */
+enum { BCHAR_LAYOUT_SUBCELL = 0, BCHAR_LAYOUT_INSCRIBED = 1, BCHAR_LAYOUT_EQUAL_MEASURE = 2 };
+
+/* Precision of the geometric part.  FP64: everything in binary64.
+ * FP32_VOLUME: tracking, the overlap predicate and the lens volumes in
+ * binary32; the weights, V, the scalings, the QP, the update and the mass
+ * stay in binary64 (compensated sums where they accumulate).           */
+enum { BCHAR_FP64 = 0, BCHAR_FP32_VOLUME = 1 };
+
+/* What to do when the box of eq. opti_masscons (0 <= 1 + x <= 2) admits no
+ * solution.  PAPER_THEN_RELAX: drop the upper cap (level 1, volumes stay
+ * non-negative), then keep the equalities alone (level 2).  STRICT: return
+ * BCHAR_E_QP_INFEASIBLE.                                                 */
+enum { BCHAR_BOX_PAPER_THEN_RELAX = 0, BCHAR_BOX_STRICT = 1 };
+
+/* Last stage of Algorithm 1 to run (for inspection).  PAIRS: candidate
+ * pairs only; V: A^(0) = V; SCALING: A^(N); ALL: the final matrix.        */
+enum { BCHAR_STAGE_PAIRS = 1, BCHAR_STAGE_V = 2, BCHAR_STAGE_SCALING = 3, BCHAR_STAGE_ALL = 4 };
+
+enum { BCHAR_MEM_HOST = 0, BCHAR_MEM_DEVICE = 1 };
+
+typedef struct bchar_mesh_s* bchar_mesh;
+typedef struct bchar_transfer_s* bchar_transfer;
+
+/* Cartesian mesh of the box [origin, origin + n*h] (Sec. 1.2).          */
+typedef struct {
+  int dim;               /* 2 or 3                                        */
+  int64_t n[3];          /* cells per axis (n[2] ignored in 2D), each >= 1 */
+  double origin[3];      /* lower corner                                  */
+  double h[3];           /* cell size per axis, > 0                       */
+  const double* phi;     /* porosity per cell, n0*n1*n2 values, each finite
+                            and > 0 (Sec. 1.2); copied at creation        */
+  int phi_mem;           /* BCHAR_MEM_HOST or BCHAR_MEM_DEVICE            */
+  int layout;            /* BCHAR_LAYOUT_*                                */
+} bchar_mesh_desc;
+
+/* Velocity u^{(n+1)} frozen over the time step (Sec. 1.2, eq. hyp:un) as
+ * a nodal lattice with multilinear (Q1) interpolation; queries outside the
+ * lattice box are clamped onto it.  For a Cartesian mesh the natural
+ * lattice is its vertices (m = n + 1, spacing = h).                     */
+typedef struct {
+  int64_t m[3];          /* nodes per axis, each >= 2                     */
+  double origin[3];      /* first node                                    */
+  double spacing[3];     /* node spacing, > 0                             */
+  const double* u[3];    /* device, one component each, m0*m1*m2 values,
+                            x-fastest; u[2] unused in 2D                  */
+} bchar_velocity;
+
+typedef struct {
+  int precision;         /* BCHAR_FP64 (default) or BCHAR_FP32_VOLUME      */
+  int n_sweeps;          /* N scaling sweeps of eq. volAdj, default 10 (Sec. 4) */
+  int rk_substeps;       /* RK4 sub-steps per time step, default 1         */
+  int box_policy;        /* BCHAR_BOX_*, default PAPER_THEN_RELAX          */
+  int stop_after;        /* BCHAR_STAGE_*, default ALL                     */
+  double qp_tol;         /* bound on max |A_hat(1+x) - b| / max |K|_phi,
+                            default 1e-13                                 */
+  int qp_max_newton;     /* Newton iterations per box level, default 500   */
+  int qp_max_cg;         /* CG iterations per Newton step, default 400     */
+  int keep_pairs;        /* non-zero: keep the candidate pairs for export  */
+} bchar_opts;
+
+typedef struct {
+  int64_t n_balls;             /* tracked balls                           */
+  int64_t n_pairs;             /* overlapping (tracked, residing) pairs   */
+  int64_t nnz;                 /* entries of the transfer matrix          */
+  int64_t first_void;          /* ball (void row) or cell (void column)
+                                  that failed, else -1                    */
+  double scaling_max_col_err;  /* max_j |sum_i a_ij^(N) / |M_j|_phi - 1|  */
+  double qp_residual;          /* max |A_hat(1+x) - b| / max |K|_phi      */
+  int qp_level;                /* box level used: 0 paper, 1 no cap, 2 none */
+  int qp_newton;               /* Newton iterations (all levels)          */
+  int qp_cg;                   /* CG iterations (all levels)              */
+  int64_t n_at_lower;          /* entries with 1 + x = 0                  */
+  int64_t n_at_upper;          /* entries with 1 + x = 2                  */
+} bchar_stats;
+
+/* Fill *opts with the defaults listed above.                            */
+void bchar_opts_default(bchar_opts* opts);
+
+/* Create the mesh-static data: the balls of every cell and their porous
+ * density rho_K with rho_K sum_s |B_{K,s}|_phi = |K|_phi (Sec. 3, eq.
+ * def:porous.density), the porous volumes |K|_phi, and a uniform-grid
+ * spatial hash of the balls.  Errors: INVALID_ARG (bad dims, sizes, phi
+ * not finite or <= 0), OUT_OF_MEMORY, DEVICE.                           */
+bchar_status bchar_mesh_create(const bchar_mesh_desc* desc, void* stream, bchar_mesh* out);
+bchar_status bchar_mesh_destroy(bchar_mesh mesh);
+
+/* Number of cells and balls of a mesh (host outputs, may be NULL).       */
+bchar_status bchar_mesh_info(bchar_mesh mesh, int64_t* n_cells, int64_t* n_balls,
+                             int* balls_per_cell);
+
+/* Build the transfer of one time step dt > 0 with velocity u (Algorithm 1,
+ * Sec. 3.3).  Allocates *out.  If `stats` is non-NULL it is filled.  The
+ * call synchronises `stream` (the scaling and the QP iterate under host
+ * control).  Errors: INVALID_ARG, VOID_ROW, VOID_COLUMN, QP_INFEASIBLE
+ * (STRICT policy, or no level feasible), QP_NOT_CONVERGED, OUT_OF_MEMORY,
+ * DEVICE.  On a VOID_* error stats->first_void names the culprit.       */
+bchar_status bchar_build_transfer(bchar_mesh mesh, const bchar_velocity* u, double dt,
+                                  const bchar_opts* opts, void* stream, bchar_transfer* out,
+                                  bchar_stats* stats);
+
+/* As bchar_build_transfer, but rebuild into an existing transfer of the
+ * same mesh, reusing its device memory where it is large enough.        */
+bchar_status bchar_rebuild_transfer(bchar_transfer t, const bchar_velocity* u, double dt,
+                                    const bchar_opts* opts, void* stream, bchar_stats* stats);
+
+/* As bchar_build_transfer, with the tracked centres and radii given
+ * instead of computed (for callers that track the balls themselves).
+ * `tracked` is device memory holding dim arrays of n_balls binary64
+ * values (x coordinates, then y, then z), balls in mesh order; `r_hat` is
+ * device memory with n_balls radii.  dt is not used.                    */
+bchar_status bchar_build_transfer_tracked(bchar_mesh mesh, const double* tracked,
+                                          const double* r_hat, const bchar_opts* opts,
+                                          void* stream, bchar_transfer* out,
+                                          bchar_stats* stats);
+
+bchar_status bchar_transfer_destroy(bchar_transfer t);
+
+/* One update (Sec. 2, eq. phys-inter-ELLAM): c_out = diag(|K|_phi)^-1 A c_in.
+ * c_in, c_out: device, n_cells binary64 each, must not overlap.  Needs a
+ * transfer built to BCHAR_STAGE_ALL.  Asynchronous on `stream`.         */
+bchar_status bchar_step(bchar_transfer t, const double* c_in, double* c_out, void* stream);
+
+/* Porous mass sum_K phi_K |K| c_K (Sec. 2.1) of a device vector c of
+ * n_cells values, summed in binary64 with compensation in a fixed order;
+ * the result is written to *host_out after synchronising `stream`.      */
+bchar_status bchar_mass(bchar_mesh mesh, const double* c, void* stream, double* host_out);
+
+const char* bchar_status_string(bchar_status s);
+const char* bchar_last_error(void);
+
+/* ---- inspection: copies to caller host buffers; synchronises -------- */
+
+/* Sizes of a built transfer.                                           */
+bchar_status bchar_transfer_info(bchar_transfer t, int64_t* n_rows, int64_t* nnz,
+                                 int64_t* n_pairs, int* stage);
+
+/* CSR of a stage (BCHAR_STAGE_V, _SCALING or _ALL; the pattern is shared):
+ * row_ptr n_rows+1, col nnz, val nnz.  Any pointer may be NULL.          */
+bchar_status bchar_transfer_export_csr(bchar_transfer t, int stage, int64_t* row_ptr,
+                                       int32_t* col, double* val);
+
+/* Candidate pairs (needs opts.keep_pairs): tracked ball ids and residing
+ * ball ids, n_pairs each, sorted by (tracked, residing).                */
+bchar_status bchar_transfer_export_pairs(bchar_transfer t, int32_t* tracked, int32_t* residing);
+
+/* Tracked centres (dim arrays of n_balls, x then y then z) and radii.   */
+bchar_status bchar_transfer_export_tracked(bchar_transfer t, double* tracked, double* r_hat);
+
+/* Solution of eq. opti_masscons: x (nnz) and the multipliers of the row
+ * and column constraints (n_rows each, in units of 1 / max |K|_phi).    */
+bchar_status bchar_transfer_export_qp(bchar_transfer t, double* x, double* mu, double* nu);
+
+/* ---- kernel timing (instrumentation) ------------------------------- */
+
+/* Time every later launch of the kernel called `name` (NULL or "" turns
+ * timing off): each launch is bracketed by two HIP events recorded on the
+ * stream it is launched on.  Resets the accumulated figures.  Meant for
+ * benchmarks; a kernel that is not being timed pays nothing.            */
+bchar_status bchar_profile_kernel(const char* name);
+
+/* Launches timed since bchar_profile_kernel and their summed duration in
+ * milliseconds (waits for the recorded events).                         */
+bchar_status bchar_profile_read(int64_t* launches, double* total_ms);
+
+/* Balls of the mesh: centres (dim arrays of n_balls), radii, cell ids.  */
+bchar_status bchar_mesh_export_balls(bchar_mesh mesh, double* centres, double* radii,
+                                     int32_t* cell);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCHAR_H */

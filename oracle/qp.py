@@ -129,6 +129,37 @@ def feasible_lp(rows, cols, a, b_row, b_col, lo, hi):
     return res.fun <= 1e-9 * scale, res.fun
 
 
+def _cell_coordinates_matrix(rows, cols, w, nr):
+    """Newton matrix in per-cell coordinates.
+
+    In the multipliers y = (mu, -nu) the Newton matrix is the graph
+    Laplacian of the bipartite graph rows-columns with weights w.  Cells
+    that barely move couple their row and column by a weight near 1 and to
+    everything else by slivers; their "gauge" (mu_K up, nu_K down) is then a
+    near-null mode whose eigenvalue is lost to rounding when the Laplacian
+    diagonal is formed as a sum including the large weight.  The change of
+    variables s_K = (y_rK + y_cK)/2, g_K = y_rK - y_cK (rows and columns are
+    both indexed by cells) keeps that mode: an entry (K, M) contributes
+    w v v^T with v = e_sK - e_sM + (e_gK + e_gM)/2 for K != M and v = e_gK
+    for K = M, so the s block is assembled from the off-diagonal weights
+    alone.  Unknowns: s_0..s_{n-1}, g_0..g_{n-1}."""
+    off = rows != cols
+    di = ~off
+    ro, co, wo = rows[off], cols[off], w[off]
+    parts = [(ro, 1.0), (co, -1.0), (nr + ro, 0.5), (nr + co, 0.5)]
+    I, J, V = [], [], []
+    for pi, ci in parts:
+        for pj, cj in parts:
+            I.append(pi)
+            J.append(pj)
+            V.append(wo * (ci * cj))
+    I.append(nr + rows[di])
+    J.append(nr + rows[di])
+    V.append(w[di])
+    return sp.csr_matrix((np.concatenate(V), (np.concatenate(I), np.concatenate(J))),
+                         shape=(2 * nr, 2 * nr))
+
+
 def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
     """Damped semismooth Newton on the dual; inputs already scaled so that
     max |b| = 1.  Returns (x, t, mu, nu, residual_inf, iterations, ok).
@@ -136,20 +167,23 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
     t_k = a_k (mu_i + nu_j) is carried entry by entry and updated by the
     increments a_k (dmu_i + dnu_j): weakly coupled cells give multipliers
     of very different sizes, and recomputing t from them would cancel
-    digits.  Newton systems J d = -F, J = A_hat diag(free) A_hat^T (plus a
-    relative 1e-13 diagonal shift for the singular directions), are solved
-    by sparse LU with two steps of iterative refinement.  The component of
-    d along the null vector (1_rows, -1_cols), which moves no t_k, is
-    removed.  The step length is chosen by Armijo backtracking on theta,
-    whose change is summed entry by entry (psi differences) rather than as
-    a difference of two large totals.
+    digits.  Each Newton system J d = -F (J = A_hat diag(free) A_hat^T) is
+    solved in the per-cell coordinates of ``_cell_coordinates_matrix``
+    (symmetrically scaled to unit diagonal, a relative 1e-14 diagonal shift
+    for the exactly singular directions, sparse LU, two refinement steps).
+    The increments of t are formed from (s, g) directly: a_k g_K for the
+    diagonal entry of cell K, a_k ((s_K - s_M) + (g_K + g_M)/2) otherwise.
+    The step length is chosen by Armijo backtracking on theta, whose change
+    is summed entry by entry (psi differences) rather than as a difference
+    of two large totals.
     """
     nr, nc = r.size, s.size
+    assert nr == nc, "rows and columns are both indexed by cells"
     mu = np.zeros(nr)
     nu = np.zeros(nc)
     t = np.zeros(a.size)
     rs = np.concatenate([r, s])
-    v0 = np.concatenate([np.ones(nr), -np.ones(nc)])
+    off = rows != cols
     a2 = a * a
     x = np.clip(t, lo, hi)
     F = residual(rows, cols, a, x, r, s)
@@ -158,19 +192,23 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
         if fn <= tol:
             return x, t, mu, nu, fn, it - 1, True
         free = (t > lo) & (t < hi)
-        w = a2 * free
-        dr = np.bincount(rows, weights=w, minlength=nr)
-        dc = np.bincount(cols, weights=w, minlength=nc)
-        W = sp.csr_matrix((w, (rows, cols)), shape=(nr, nc))
-        tau = 1e-13 * max(float(np.max(dr, initial=0.0)), float(np.max(dc, initial=0.0)), 1e-300)
-        J = sp.bmat([[sp.diags(dr + tau), W], [W.T, sp.diags(dc + tau)]], format="csc")
-        lu = spla.splu(J)
-        d = lu.solve(-F)
+        Jz = _cell_coordinates_matrix(rows, cols, a2 * free, nr)
+        dg = Jz.diagonal()
+        dg = np.where(dg > 0, dg, max(float(dg.max(initial=0.0)), 1e-300))
+        Jz = Jz + sp.diags(1e-14 * dg)
+        # right-hand side: y-space (-F_row, F_col) mapped to (s, g)
+        fr, fc = -F[:nr], F[nr:]
+        bz = np.concatenate([fr + fc, 0.5 * (fr - fc)])
+        Dh = 1.0 / np.sqrt(Jz.diagonal())
+        lu = spla.splu((sp.diags(Dh) @ Jz @ sp.diags(Dh)).tocsc())
+        z = Dh * lu.solve(Dh * bz)
         for _ in range(2):
-            d = d + lu.solve(-F - J @ d)
-        d = d - (d @ v0) / (nr + nc) * v0
-        dmu, dnu = d[:nr], d[nr:]
-        dt = a * (dmu[rows] + dnu[cols])
+            z = z + Dh * lu.solve(Dh * (bz - Jz @ z))
+        zs, zg = z[:nr], z[nr:]
+        dt = a * np.where(off, (zs[rows] - zs[cols]) + 0.5 * (zg[rows] + zg[cols]), zg[rows])
+        dmu = zs + 0.5 * zg
+        dnu = -(zs - 0.5 * zg)
+        d = np.concatenate([dmu, dnu])
         slope = float(F @ d)
         if not slope < 0.0:
             return x, t, mu, nu, fn, it, False

@@ -1,0 +1,321 @@
+"""Thin ctypes binding of libbchar (include/bchar.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module only turns
+Python/PyTorch objects into the C structs and pointers the ABI takes, and
+raises ``BcharError`` on a non-zero status.  The library must have been
+built (``python -m paper_1908_05834_amd.build_lib``); importing this module
+without it raises immediately -- there is no fallback path.
+
+PyTorch provides device memory and streams: pass CUDA (HIP) tensors and the
+library runs on ``torch.cuda.current_stream()`` unless a stream is given.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbchar.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_1908_05834_amd.build_lib`")
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants (bchar.h)
+OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_VOID_ROW, E_VOID_COLUMN, \
+    E_QP_INFEASIBLE, E_QP_NOT_CONVERGED, E_UNSUPPORTED = range(9)
+LAYOUT_SUBCELL, LAYOUT_INSCRIBED, LAYOUT_EQUAL_MEASURE = 0, 1, 2
+FP64, FP32_VOLUME = 0, 1
+BOX_PAPER_THEN_RELAX, BOX_STRICT = 0, 1
+STAGE_PAIRS, STAGE_V, STAGE_SCALING, STAGE_ALL = 1, 2, 3, 4
+MEM_HOST, MEM_DEVICE = 0, 1
+
+LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
+           "equal_measure": LAYOUT_EQUAL_MEASURE}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("origin", C.c_double * 3),
+                ("h", C.c_double * 3), ("phi", C.c_void_p), ("phi_mem", C.c_int),
+                ("layout", C.c_int)]
+
+
+class Velocity(C.Structure):
+    _fields_ = [("m", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("u", C.c_void_p * 3)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("n_sweeps", C.c_int), ("rk_substeps", C.c_int),
+                ("box_policy", C.c_int), ("stop_after", C.c_int), ("qp_tol", C.c_double),
+                ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_balls", C.c_int64), ("n_pairs", C.c_int64), ("nnz", C.c_int64),
+                ("first_void", C.c_int64), ("scaling_max_col_err", C.c_double),
+                ("qp_residual", C.c_double), ("qp_level", C.c_int), ("qp_newton", C.c_int),
+                ("qp_cg", C.c_int), ("n_at_lower", C.c_int64), ("n_at_upper", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_i64p = C.POINTER(C.c_int64)
+_ip = C.POINTER(C.c_int)
+
+
+def _sig(name, args, res=C.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_opts_default = _sig("bchar_opts_default", [C.POINTER(Opts)], None)
+_mesh_create = _sig("bchar_mesh_create", [C.POINTER(MeshDesc), _P, C.POINTER(_P)])
+_mesh_destroy = _sig("bchar_mesh_destroy", [_P])
+_mesh_info = _sig("bchar_mesh_info", [_P, _i64p, _i64p, _ip])
+_build = _sig("bchar_build_transfer", [_P, C.POINTER(Velocity), C.c_double, C.POINTER(Opts), _P,
+                                       C.POINTER(_P), C.POINTER(Stats)])
+_rebuild = _sig("bchar_rebuild_transfer", [_P, C.POINTER(Velocity), C.c_double,
+                                           C.POINTER(Opts), _P, C.POINTER(Stats)])
+_build_tracked = _sig("bchar_build_transfer_tracked", [_P, _P, _P, C.POINTER(Opts), _P,
+                                                       C.POINTER(_P), C.POINTER(Stats)])
+_transfer_destroy = _sig("bchar_transfer_destroy", [_P])
+_step = _sig("bchar_step", [_P, _P, _P, _P])
+_mass = _sig("bchar_mass", [_P, _P, _P, C.POINTER(C.c_double)])
+_status_string = _sig("bchar_status_string", [C.c_int], C.c_char_p)
+_last_error = _sig("bchar_last_error", [], C.c_char_p)
+_transfer_info = _sig("bchar_transfer_info", [_P, _i64p, _i64p, _i64p, _ip])
+_export_csr = _sig("bchar_transfer_export_csr", [_P, C.c_int, _P, _P, _P])
+_export_pairs = _sig("bchar_transfer_export_pairs", [_P, _P, _P])
+_export_tracked = _sig("bchar_transfer_export_tracked", [_P, _P, _P])
+_export_qp = _sig("bchar_transfer_export_qp", [_P, _P, _P, _P])
+_export_balls = _sig("bchar_mesh_export_balls", [_P, _P, _P, _P])
+_profile_kernel = _sig("bchar_profile_kernel", [C.c_char_p])
+_profile_read = _sig("bchar_profile_read", [_i64p, C.POINTER(C.c_double)])
+
+EXPORTED = [
+    "bchar_opts_default", "bchar_mesh_create", "bchar_mesh_destroy", "bchar_mesh_info",
+    "bchar_build_transfer", "bchar_rebuild_transfer", "bchar_build_transfer_tracked",
+    "bchar_transfer_destroy", "bchar_step", "bchar_mass", "bchar_status_string",
+    "bchar_last_error", "bchar_transfer_info", "bchar_transfer_export_csr",
+    "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
+    "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
+]
+
+
+class BcharError(RuntimeError):
+    def __init__(self, status, msg, stats=None):
+        super().__init__(f"{_status_string(status).decode()}: {msg}")
+        self.status = status
+        self.stats = stats
+
+
+def _check(rc, stats=None):
+    if rc != OK:
+        raise BcharError(rc, (_last_error() or b"").decode(), stats)
+
+
+def status_string(s):
+    return _status_string(s).decode()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def profile_kernel(name):
+    """Time every later launch of kernel ``name`` with HIP events (None: off)."""
+    _check(_profile_kernel(name.encode() if name else None))
+
+
+def profile_read():
+    """(launches, total milliseconds) timed since ``profile_kernel``."""
+    n, ms = C.c_int64(), C.c_double()
+    _check(_profile_read(C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def opts_default(**kw):
+    o = Opts()
+    _opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+# ---------------------------------------------------------------- handles
+
+class Mesh:
+    """bchar_mesh_create on a Cartesian mesh dict (``inputs.cartesian_mesh``)."""
+
+    def __init__(self, mesh, layout="subcell", stream=None):
+        n = tuple(int(v) for v in mesh["n"])
+        self.dim = len(n)
+        d = MeshDesc()
+        d.dim = self.dim
+        for a in range(3):
+            d.n[a] = n[a] if a < self.dim else 1
+            d.origin[a] = mesh["origin"][a] if a < self.dim else 0.0
+            d.h[a] = mesh["h"][a] if a < self.dim else 1.0
+        phi = np.ascontiguousarray(mesh["phi"], dtype=np.float64)
+        self._phi_host = phi
+        d.phi = phi.ctypes.data_as(C.c_void_p)
+        d.phi_mem = MEM_HOST
+        d.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        h = C.c_void_p()
+        _check(_mesh_create(C.byref(d), _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+        nc, nb, bpc = C.c_int64(), C.c_int64(), C.c_int()
+        _check(_mesh_info(h, C.byref(nc), C.byref(nb), C.byref(bpc)))
+        self.n_cells, self.n_balls, self.balls_per_cell = nc.value, nb.value, bpc.value
+
+    def close(self):
+        if self.handle:
+            _mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mass(self, c, stream=None):
+        out = C.c_double()
+        _check(_mass(self.handle, _dptr(c), _stream_ptr(stream), C.byref(out)))
+        return out.value
+
+    def export_balls(self):
+        cen = np.empty(self.dim * self.n_balls)
+        rad = np.empty(self.n_balls)
+        cell = np.empty(self.n_balls, dtype=np.int32)
+        _check(_export_balls(self.handle, cen.ctypes.data_as(_P), rad.ctypes.data_as(_P),
+                             cell.ctypes.data_as(_P)))
+        return cen.reshape(self.dim, self.n_balls).T.copy(), rad, cell
+
+
+class VelocityLattice:
+    """Device copy of a velocity lattice dict (``inputs.sample_velocity``)."""
+
+    def __init__(self, vel, device="cuda"):
+        import torch
+        self.dim = len(vel["m"])
+        self.comps = [torch.as_tensor(np.ascontiguousarray(vel["u"][a]), dtype=torch.float64,
+                                      device=device) for a in range(self.dim)]
+        v = Velocity()
+        for a in range(3):
+            v.m[a] = vel["m"][a] if a < self.dim else 1
+            v.origin[a] = vel["origin"][a] if a < self.dim else 0.0
+            v.spacing[a] = vel["spacing"][a] if a < self.dim else 1.0
+            v.u[a] = self.comps[a].data_ptr() if a < self.dim else None
+        self.struct = v
+
+
+class Transfer:
+    """A built transfer (bchar_build_transfer / _tracked / rebuild)."""
+
+    def __init__(self, handle, mesh, stats):
+        self.handle = handle
+        self.mesh = mesh
+        self.stats = stats
+
+    @classmethod
+    def build(cls, mesh, velocity, dt, opts=None, stream=None):
+        o = opts if opts is not None else opts_default()
+        st = Stats()
+        h = C.c_void_p()
+        rc = _build(mesh.handle, C.byref(velocity.struct), float(dt), C.byref(o),
+                    _stream_ptr(stream), C.byref(h), C.byref(st))
+        _check(rc, st.as_dict())
+        return cls(h, mesh, st.as_dict())
+
+    @classmethod
+    def build_tracked(cls, mesh, tracked, r_hat, opts=None, stream=None):
+        """``tracked``: device tensor (dim, n_balls); ``r_hat``: (n_balls,)."""
+        o = opts if opts is not None else opts_default()
+        st = Stats()
+        h = C.c_void_p()
+        rc = _build_tracked(mesh.handle, _dptr(tracked), _dptr(r_hat), C.byref(o),
+                            _stream_ptr(stream), C.byref(h), C.byref(st))
+        _check(rc, st.as_dict())
+        return cls(h, mesh, st.as_dict())
+
+    def rebuild(self, velocity, dt, opts=None, stream=None):
+        o = opts if opts is not None else opts_default()
+        st = Stats()
+        rc = _rebuild(self.handle, C.byref(velocity.struct), float(dt), C.byref(o),
+                      _stream_ptr(stream), C.byref(st))
+        self.stats = st.as_dict()
+        _check(rc, self.stats)
+        return self.stats
+
+    def step(self, c_in, c_out, stream=None):
+        _check(_step(self.handle, _dptr(c_in), _dptr(c_out), _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle:
+            _transfer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        nr, nnz, npairs, stage = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int()
+        _check(_transfer_info(self.handle, C.byref(nr), C.byref(nnz), C.byref(npairs),
+                              C.byref(stage)))
+        return nr.value, nnz.value, npairs.value, stage.value
+
+    def export_csr(self, stage=STAGE_ALL):
+        nr, nnz, _, _ = self.info()
+        rp = np.empty(nr + 1, dtype=np.int64)
+        col = np.empty(nnz, dtype=np.int32)
+        val = np.empty(nnz)
+        _check(_export_csr(self.handle, stage, rp.ctypes.data_as(_P), col.ctypes.data_as(_P),
+                           val.ctypes.data_as(_P)))
+        return rp, col.astype(np.int64), val
+
+    def export_pairs(self):
+        _, _, npairs, _ = self.info()
+        a = np.empty(npairs, dtype=np.int32)
+        b = np.empty(npairs, dtype=np.int32)
+        _check(_export_pairs(self.handle, a.ctypes.data_as(_P), b.ctypes.data_as(_P)))
+        return a.astype(np.int64), b.astype(np.int64)
+
+    def export_tracked(self):
+        dim, nb = self.mesh.dim, self.mesh.n_balls
+        t = np.empty(dim * nb)
+        r = np.empty(nb)
+        _check(_export_tracked(self.handle, t.ctypes.data_as(_P), r.ctypes.data_as(_P)))
+        return t.reshape(dim, nb).T.copy(), r
+
+    def export_qp(self):
+        nr, nnz, _, _ = self.info()
+        x = np.empty(nnz)
+        mu = np.empty(nr)
+        nu = np.empty(nr)
+        _check(_export_qp(self.handle, x.ctypes.data_as(_P), mu.ctypes.data_as(_P),
+                          nu.ctypes.data_as(_P)))
+        return x, mu, nu

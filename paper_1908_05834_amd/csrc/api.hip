@@ -1,0 +1,574 @@
+// The extern "C" entry points declared in include/bchar.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bchar {
+const char* last_error_cstr();
+}
+
+using bchar::Error;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <class F>
+bchar_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    bchar::set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    bchar::set_error("host allocation failed");
+    return BCHAR_E_OUT_OF_MEMORY;
+  } catch (...) {
+    bchar::set_error("unexpected exception");
+    return BCHAR_E_DEVICE;
+  }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void opts_or_default(const bchar_opts* in, bchar_opts& o) {
+  if (in)
+    o = *in;
+  else
+    bchar_opts_default(&o);
+}
+
+void validate_opts(const bchar_opts& o) {
+  BCHAR_REQUIRE(o.precision == BCHAR_FP64 || o.precision == BCHAR_FP32_VOLUME,
+                BCHAR_E_INVALID_ARG, "opts.precision");
+  BCHAR_REQUIRE(o.n_sweeps >= 0 && o.n_sweeps <= 100000, BCHAR_E_INVALID_ARG, "opts.n_sweeps");
+  BCHAR_REQUIRE(o.rk_substeps >= 1 && o.rk_substeps <= 4096, BCHAR_E_INVALID_ARG,
+                "opts.rk_substeps");
+  BCHAR_REQUIRE(o.box_policy == BCHAR_BOX_PAPER_THEN_RELAX || o.box_policy == BCHAR_BOX_STRICT,
+                BCHAR_E_INVALID_ARG, "opts.box_policy");
+  BCHAR_REQUIRE(o.stop_after >= BCHAR_STAGE_PAIRS && o.stop_after <= BCHAR_STAGE_ALL,
+                BCHAR_E_INVALID_ARG, "opts.stop_after");
+  BCHAR_REQUIRE(o.qp_tol > 0 && std::isfinite(o.qp_tol), BCHAR_E_INVALID_ARG, "opts.qp_tol");
+  BCHAR_REQUIRE(o.qp_max_newton >= 1 && o.qp_max_cg >= 1, BCHAR_E_INVALID_ARG,
+                "opts.qp_max_newton / qp_max_cg");
+}
+
+void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
+  BCHAR_REQUIRE(u != nullptr, BCHAR_E_INVALID_ARG, "velocity is NULL");
+  for (int a = 0; a < m->dim; ++a) {
+    BCHAR_REQUIRE(u->m[a] >= 2, BCHAR_E_INVALID_ARG, "velocity lattice needs >= 2 nodes per axis");
+    BCHAR_REQUIRE(u->spacing[a] > 0 && std::isfinite(u->spacing[a]) &&
+                      std::isfinite(u->origin[a]),
+                  BCHAR_E_INVALID_ARG, "velocity lattice spacing/origin");
+    BCHAR_REQUIRE(u->u[a] != nullptr, BCHAR_E_INVALID_ARG, "velocity component is NULL");
+  }
+  int64_t nn = 1;
+  for (int a = 0; a < m->dim; ++a) nn *= u->m[a];
+  BCHAR_REQUIRE(nn < ((int64_t)1 << 31), BCHAR_E_UNSUPPORTED, "velocity lattice too large");
+}
+
+// Everything after the tracked centres are known.
+bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_opts& o,
+                                hipStream_t s, bchar_stats* stats) {
+  using namespace bchar;
+  Arena& ws = m->ws;
+  const bool tr = trace_enabled();
+  double t0 = 0;
+  if (tr) {
+    BCHAR_HIP(hipStreamSynchronize(s));
+    t0 = wall_seconds();
+  }
+  bchar_stats st{};
+  st.n_balls = m->n_balls;
+  st.first_void = -1;
+  t->stage = 0;
+  int64_t first_void = -1;
+  bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(), o.precision,
+                               o.keep_pairs != 0, t, &first_void, s);
+  st.nnz = t->nnz;
+  st.n_pairs = t->n_pairs;
+  if (rc != BCHAR_OK) {
+    st.first_void = first_void;
+    if (stats) *stats = st;
+    t->stats = st;
+    set_error("void row: tracked ball " + std::to_string(first_void) +
+              " overlaps no residing ball");
+    return rc;
+  }
+  t->stage = BCHAR_STAGE_V;
+  if (tr) {
+    BCHAR_HIP(hipStreamSynchronize(s));
+    fprintf(stderr, "[bchar] V: %.3f ms (nnz %lld, pairs %lld)\n", 1e3 * (wall_seconds() - t0),
+            (long long)t->nnz, (long long)t->n_pairs);
+    t0 = wall_seconds();
+  }
+  if (o.stop_after <= BCHAR_STAGE_V) {
+    BCHAR_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    t->stats = st;
+    return BCHAR_OK;
+  }
+  const int64_t n = m->n_cells, nnz = t->nnz;
+  Csc csc{};
+  build_csc(t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), n, nnz, csc, ws, s);
+  t->AN.reserve(sizeof(double) * (nnz + 1));
+  int64_t void_col = -1;
+  double col_err = 0;
+  rc = scaling_sweeps(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->V.as<double>(),
+                      nnz, o.n_sweeps, t->AN.as<double>(), &void_col, &col_err, ws, s);
+  st.scaling_max_col_err = col_err;
+  if (rc != BCHAR_OK) {
+    st.first_void = void_col;
+    if (stats) *stats = st;
+    t->stats = st;
+    set_error("void column: residing cell " + std::to_string(void_col) +
+              " receives no tracked ball");
+    return rc;
+  }
+  t->stage = BCHAR_STAGE_SCALING;
+  if (tr) {
+    fprintf(stderr, "[bchar] scaling: %.3f ms (max column error %.3e)\n",
+            1e3 * (wall_seconds() - t0), col_err);
+    t0 = wall_seconds();
+  }
+  if (o.stop_after <= BCHAR_STAGE_SCALING) {
+    if (stats) *stats = st;
+    t->stats = st;
+    return BCHAR_OK;
+  }
+  t->x.reserve(sizeof(double) * (nnz + 1));
+  t->A.reserve(sizeof(double) * (nnz + 1));
+  t->mu.reserve(sizeof(double) * n);
+  t->nu.reserve(sizeof(double) * n);
+  QpResult qr;
+  rc = solve_qp(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->AN.as<double>(), nnz,
+                o, t->x.as<double>(), t->mu.as<double>(), t->nu.as<double>(), t->A.as<double>(),
+                qr, ws, s);
+  if (tr)
+    fprintf(stderr, "[bchar] qp: %.3f ms (level %d, newton %d, cg %d, residual %.3e)\n",
+            1e3 * (wall_seconds() - t0), qr.level, qr.newton, qr.cg, qr.residual);
+  st.qp_level = qr.level;
+  st.qp_newton = qr.newton;
+  st.qp_cg = qr.cg;
+  st.qp_residual = qr.residual;
+  st.n_at_lower = qr.at_lower;
+  st.n_at_upper = qr.at_upper;
+  if (stats) *stats = st;
+  t->stats = st;
+  if (rc != BCHAR_OK) {
+    set_error(rc == BCHAR_E_QP_INFEASIBLE
+                  ? "the box of the least-change problem admits no solution"
+                  : "the least-change problem did not reach the tolerance (residual " +
+                        std::to_string(qr.residual) + ")");
+    return rc;
+  }
+  t->stage = BCHAR_STAGE_ALL;
+  return BCHAR_OK;
+}
+
+bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity* u, double dt,
+                      const bchar_opts& o, hipStream_t s, bchar_stats* stats) {
+  using namespace bchar;
+  validate_opts(o);
+  validate_velocity(m, u);
+  BCHAR_REQUIRE(dt > 0 && std::isfinite(dt), BCHAR_E_INVALID_ARG, "dt must be finite and > 0");
+  m->ws.reset();
+  t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
+  t->r_hat.reserve(sizeof(double) * m->n_balls);
+  const double t0 = trace_enabled() ? wall_seconds() : 0.0;
+  trace_balls(m, *u, dt, o.rk_substeps, o.precision, t->tracked.as<double>(),
+              t->r_hat.as<double>(), m->ws, s);
+  if (trace_enabled()) {
+    BCHAR_HIP(hipStreamSynchronize(s));
+    fprintf(stderr, "[bchar] trace: %.3f ms\n", 1e3 * (wall_seconds() - t0));
+  }
+  return build_from_tracked(m, t, o, s, stats);
+}
+
+}  // namespace
+
+extern "C" {
+
+void bchar_opts_default(bchar_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = BCHAR_FP64;
+  o->n_sweeps = 10;
+  o->rk_substeps = 1;
+  o->box_policy = BCHAR_BOX_PAPER_THEN_RELAX;
+  o->stop_after = BCHAR_STAGE_ALL;
+  o->qp_tol = 1e-13;
+  o->qp_max_newton = 500;
+  o->qp_max_cg = 400;
+  o->keep_pairs = 0;
+}
+
+const char* bchar_status_string(bchar_status s) {
+  switch (s) {
+    case BCHAR_OK: return "ok";
+    case BCHAR_E_INVALID_ARG: return "invalid argument";
+    case BCHAR_E_OUT_OF_MEMORY: return "out of memory";
+    case BCHAR_E_DEVICE: return "device error";
+    case BCHAR_E_VOID_ROW: return "void row";
+    case BCHAR_E_VOID_COLUMN: return "void column";
+    case BCHAR_E_QP_INFEASIBLE: return "least-change problem infeasible";
+    case BCHAR_E_QP_NOT_CONVERGED: return "least-change problem not converged";
+    case BCHAR_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* bchar_last_error(void) { return bchar::last_error_cstr(); }
+
+bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mesh* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(d != nullptr && out != nullptr, BCHAR_E_INVALID_ARG, "NULL argument");
+    BCHAR_REQUIRE(d->dim == 2 || d->dim == 3, BCHAR_E_INVALID_ARG, "dim must be 2 or 3");
+    BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_EQUAL_MEASURE,
+                  BCHAR_E_INVALID_ARG, "unknown layout");
+    BCHAR_REQUIRE(d->phi != nullptr, BCHAR_E_INVALID_ARG, "phi is NULL");
+    BCHAR_REQUIRE(d->phi_mem == BCHAR_MEM_HOST || d->phi_mem == BCHAR_MEM_DEVICE,
+                  BCHAR_E_INVALID_ARG, "phi_mem");
+    hipStream_t s = as_stream(stream);
+    auto* m = new bchar_mesh_s();
+    try {
+      m->dim = d->dim;
+      m->layout = d->layout;
+      int64_t nc = 1;
+      double hmin = 1e300;
+      m->cell_vol = 1.0;
+      for (int a = 0; a < 3; ++a) {
+        if (a < d->dim) {
+          BCHAR_REQUIRE(d->n[a] >= 1, BCHAR_E_INVALID_ARG, "n must be >= 1");
+          BCHAR_REQUIRE(d->h[a] > 0 && std::isfinite(d->h[a]) && std::isfinite(d->origin[a]),
+                        BCHAR_E_INVALID_ARG, "h must be finite and > 0");
+          m->n[a] = d->n[a];
+          m->h[a] = d->h[a];
+          m->origin[a] = d->origin[a];
+          nc *= d->n[a];
+          hmin = std::min(hmin, d->h[a]);
+          m->cell_vol *= d->h[a];
+        } else {
+          m->n[a] = 1;
+          m->h[a] = 1;
+          m->origin[a] = 0;
+        }
+      }
+      m->n_cells = nc;
+      if (d->layout == BCHAR_LAYOUT_SUBCELL) {
+        m->nbpc = 1 << d->dim;
+        m->r = hmin / 4.0;
+      } else if (d->layout == BCHAR_LAYOUT_INSCRIBED) {
+        m->nbpc = 1;
+        m->r = hmin / 2.0;
+      } else {
+        m->nbpc = 1;
+        m->r = d->dim == 2 ? std::sqrt(m->cell_vol / kPi)
+                           : std::cbrt(3.0 * m->cell_vol / (4.0 * kPi));
+      }
+      m->n_balls = nc * m->nbpc;
+      BCHAR_REQUIRE(m->n_balls < ((int64_t)1 << 31) - 1, BCHAR_E_UNSUPPORTED,
+                    "more than 2^31 balls");
+      m->ball_vol = d->dim == 2 ? kPi * m->r * m->r : 4.0 / 3.0 * kPi * m->r * m->r * m->r;
+      // rho_K sum_s |B_{K,s}|_phi = |K|_phi with |B|_phi = phi_K |B|
+      m->rho = m->cell_vol / (m->nbpc * m->ball_vol);
+      // phi: validate on the host
+      std::vector<double> hphi(nc);
+      if (d->phi_mem == BCHAR_MEM_HOST) {
+        std::memcpy(hphi.data(), d->phi, sizeof(double) * nc);
+      } else {
+        BCHAR_HIP(hipMemcpyAsync(hphi.data(), d->phi, sizeof(double) * nc,
+                                 hipMemcpyDeviceToHost, s));
+        BCHAR_HIP(hipStreamSynchronize(s));
+      }
+      double pmax = 0;
+      bool same = true;
+      for (int64_t i = 0; i < nc; ++i) {
+        BCHAR_REQUIRE(std::isfinite(hphi[i]) && hphi[i] > 0, BCHAR_E_INVALID_ARG,
+                      "phi must be finite and > 0 on every cell");
+        pmax = std::max(pmax, hphi[i]);
+        same = same && hphi[i] == hphi[0];
+      }
+      m->phi_const = same;
+      m->phi0 = hphi[0];
+      m->bmax = pmax * m->cell_vol;
+      m->phi.reserve(sizeof(double) * nc);
+      BCHAR_HIP(hipMemcpyAsync(m->phi.p, hphi.data(), sizeof(double) * nc,
+                               hipMemcpyHostToDevice, s));
+      bchar::mesh_build_device(m, s);
+    } catch (...) {
+      bchar_mesh_destroy(m);
+      throw;
+    }
+    *out = m;
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_mesh_destroy(bchar_mesh m) {
+  if (!m) return BCHAR_OK;
+  (void)hipDeviceSynchronize();
+  m->phi.release();
+  m->b.release();
+  m->cen.release();
+  m->cen32.release();
+  m->bucket_start.release();
+  m->bk_cen.release();
+  m->bk_cen32.release();
+  m->bk_ball.release();
+  m->ws.release();
+  m->scratch_small.release();
+  delete m;
+  return BCHAR_OK;
+}
+
+bchar_status bchar_mesh_info(bchar_mesh m, int64_t* n_cells, int64_t* n_balls,
+                             int* balls_per_cell) {
+  if (!m) {
+    bchar::set_error("mesh is NULL");
+    return BCHAR_E_INVALID_ARG;
+  }
+  if (n_cells) *n_cells = m->n_cells;
+  if (n_balls) *n_balls = m->n_balls;
+  if (balls_per_cell) *balls_per_cell = m->nbpc;
+  return BCHAR_OK;
+}
+
+static void transfer_free(bchar_transfer t) {
+  t->row_ptr.release();
+  t->col.release();
+  t->V.release();
+  t->AN.release();
+  t->A.release();
+  t->x.release();
+  t->mu.release();
+  t->nu.release();
+  t->tracked.release();
+  t->r_hat.release();
+  t->pair_a.release();
+  t->pair_b.release();
+}
+
+bchar_status bchar_build_transfer(bchar_mesh m, const bchar_velocity* u, double dt,
+                                  const bchar_opts* opts, void* stream, bchar_transfer* out,
+                                  bchar_stats* stats) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(m != nullptr && out != nullptr, BCHAR_E_INVALID_ARG, "NULL argument");
+    bchar_opts o;
+    opts_or_default(opts, o);
+    auto* t = new bchar_transfer_s();
+    t->mesh = m;
+    bchar_status rc;
+    try {
+      rc = do_build(m, t, u, dt, o, as_stream(stream), stats);
+    } catch (...) {
+      transfer_free(t);
+      delete t;
+      throw;
+    }
+    if (rc != BCHAR_OK) {
+      transfer_free(t);
+      delete t;
+      return rc;
+    }
+    *out = t;
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_rebuild_transfer(bchar_transfer t, const bchar_velocity* u, double dt,
+                                    const bchar_opts* opts, void* stream, bchar_stats* stats) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr, BCHAR_E_INVALID_ARG, "transfer is NULL");
+    bchar_opts o;
+    opts_or_default(opts, o);
+    return do_build(t->mesh, t, u, dt, o, as_stream(stream), stats);
+  });
+}
+
+bchar_status bchar_build_transfer_tracked(bchar_mesh m, const double* tracked,
+                                          const double* r_hat, const bchar_opts* opts,
+                                          void* stream, bchar_transfer* out,
+                                          bchar_stats* stats) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(m != nullptr && out != nullptr && tracked != nullptr && r_hat != nullptr,
+                  BCHAR_E_INVALID_ARG, "NULL argument");
+    bchar_opts o;
+    opts_or_default(opts, o);
+    validate_opts(o);
+    hipStream_t s = as_stream(stream);
+    auto* t = new bchar_transfer_s();
+    t->mesh = m;
+    bchar_status rc;
+    try {
+      m->ws.reset();
+      t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
+      t->r_hat.reserve(sizeof(double) * m->n_balls);
+      BCHAR_HIP(hipMemcpyAsync(t->tracked.p, tracked, sizeof(double) * m->dim * m->n_balls,
+                               hipMemcpyDeviceToDevice, s));
+      BCHAR_HIP(hipMemcpyAsync(t->r_hat.p, r_hat, sizeof(double) * m->n_balls,
+                               hipMemcpyDeviceToDevice, s));
+      rc = build_from_tracked(m, t, o, s, stats);
+    } catch (...) {
+      transfer_free(t);
+      delete t;
+      throw;
+    }
+    if (rc != BCHAR_OK) {
+      transfer_free(t);
+      delete t;
+      return rc;
+    }
+    *out = t;
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_destroy(bchar_transfer t) {
+  if (!t) return BCHAR_OK;
+  (void)hipDeviceSynchronize();
+  transfer_free(t);
+  delete t;
+  return BCHAR_OK;
+}
+
+bchar_status bchar_step(bchar_transfer t, const double* cin, double* cout, void* stream) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr && cin != nullptr && cout != nullptr, BCHAR_E_INVALID_ARG,
+                  "NULL argument");
+    BCHAR_REQUIRE(t->stage == BCHAR_STAGE_ALL, BCHAR_E_INVALID_ARG,
+                  "transfer was not built to the final stage");
+    const int64_t n = t->mesh->n_cells;
+    const double* ce = cin + n;
+    BCHAR_REQUIRE(cout + n <= cin || ce <= cout, BCHAR_E_INVALID_ARG,
+                  "c_in and c_out overlap");
+    bchar::apply_transfer(t, cin, cout, as_stream(stream));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_mass(bchar_mesh m, const double* c, void* stream, double* host_out) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(m != nullptr && c != nullptr && host_out != nullptr, BCHAR_E_INVALID_ARG,
+                  "NULL argument");
+    *host_out = bchar::porous_mass(m, c, m->ws, as_stream(stream));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_info(bchar_transfer t, int64_t* n_rows, int64_t* nnz,
+                                 int64_t* n_pairs, int* stage) {
+  if (!t) {
+    bchar::set_error("transfer is NULL");
+    return BCHAR_E_INVALID_ARG;
+  }
+  if (n_rows) *n_rows = t->mesh->n_cells;
+  if (nnz) *nnz = t->nnz;
+  if (n_pairs) *n_pairs = t->n_pairs;
+  if (stage) *stage = t->stage;
+  return BCHAR_OK;
+}
+
+bchar_status bchar_transfer_export_csr(bchar_transfer t, int stage, int64_t* row_ptr,
+                                       int32_t* col, double* val) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr, BCHAR_E_INVALID_ARG, "transfer is NULL");
+    BCHAR_REQUIRE(stage >= BCHAR_STAGE_V && stage <= BCHAR_STAGE_ALL && stage <= t->stage,
+                  BCHAR_E_INVALID_ARG, "stage not built");
+    const int64_t n = t->mesh->n_cells;
+    BCHAR_HIP(hipDeviceSynchronize());
+    if (row_ptr) {
+      std::vector<int32_t> rp(n + 1);
+      BCHAR_HIP(hipMemcpy(rp.data(), t->row_ptr.p, sizeof(int32_t) * (n + 1),
+                          hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i <= n; ++i) row_ptr[i] = rp[i];
+    }
+    if (col)
+      BCHAR_HIP(hipMemcpy(col, t->col.p, sizeof(int32_t) * t->nnz, hipMemcpyDeviceToHost));
+    if (val) {
+      const bchar::DBuf& src = stage == BCHAR_STAGE_V ? t->V
+                               : stage == BCHAR_STAGE_SCALING ? t->AN
+                                                               : t->A;
+      BCHAR_HIP(hipMemcpy(val, src.p, sizeof(double) * t->nnz, hipMemcpyDeviceToHost));
+    }
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_export_pairs(bchar_transfer t, int32_t* tracked, int32_t* residing) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr && tracked != nullptr && residing != nullptr,
+                  BCHAR_E_INVALID_ARG, "NULL argument");
+    BCHAR_REQUIRE(t->pair_a.p != nullptr && t->stage >= BCHAR_STAGE_V, BCHAR_E_INVALID_ARG,
+                  "pairs were not kept (opts.keep_pairs)");
+    const int64_t np = t->n_pairs;
+    BCHAR_HIP(hipDeviceSynchronize());
+    std::vector<int32_t> a(np), b(np);
+    BCHAR_HIP(hipMemcpy(a.data(), t->pair_a.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    BCHAR_HIP(hipMemcpy(b.data(), t->pair_b.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost));
+    std::vector<int64_t> idx(np);
+    for (int64_t i = 0; i < np; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+      return a[x] != a[y] ? a[x] < a[y] : b[x] < b[y];
+    });
+    for (int64_t i = 0; i < np; ++i) {
+      tracked[i] = a[idx[i]];
+      residing[i] = b[idx[i]];
+    }
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_export_tracked(bchar_transfer t, double* tracked, double* r_hat) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr, BCHAR_E_INVALID_ARG, "transfer is NULL");
+    const bchar_mesh_s* m = t->mesh;
+    BCHAR_HIP(hipDeviceSynchronize());
+    if (tracked)
+      BCHAR_HIP(hipMemcpy(tracked, t->tracked.p, sizeof(double) * m->dim * m->n_balls,
+                          hipMemcpyDeviceToHost));
+    if (r_hat)
+      BCHAR_HIP(hipMemcpy(r_hat, t->r_hat.p, sizeof(double) * m->n_balls,
+                          hipMemcpyDeviceToHost));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_export_qp(bchar_transfer t, double* x, double* mu, double* nu) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr && t->stage == BCHAR_STAGE_ALL, BCHAR_E_INVALID_ARG,
+                  "transfer not built to the final stage");
+    const int64_t n = t->mesh->n_cells;
+    BCHAR_HIP(hipDeviceSynchronize());
+    if (x) BCHAR_HIP(hipMemcpy(x, t->x.p, sizeof(double) * t->nnz, hipMemcpyDeviceToHost));
+    if (mu) BCHAR_HIP(hipMemcpy(mu, t->mu.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (nu) BCHAR_HIP(hipMemcpy(nu, t->nu.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_mesh_export_balls(bchar_mesh m, double* centres, double* radii,
+                                     int32_t* cell) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(m != nullptr, BCHAR_E_INVALID_ARG, "mesh is NULL");
+    BCHAR_HIP(hipDeviceSynchronize());
+    if (centres)
+      BCHAR_HIP(hipMemcpy(centres, m->cen.p, sizeof(double) * m->dim * m->n_balls,
+                          hipMemcpyDeviceToHost));
+    for (int64_t b = 0; b < m->n_balls; ++b) {
+      if (radii) radii[b] = m->r;
+      if (cell) cell[b] = (int32_t)(b / m->nbpc);
+    }
+    return BCHAR_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// The update (Sec. 2, eq. phys-inter-ELLAM) and the porous mass (Sec. 2.1).
+//
+// apply: c_out[K] = (sum_M A[K,M] c_in[M]) / |K|_phi.  Rows hold a few
+//        entries (4-5 on the 3D workloads), so a group of 4 lanes takes a
+//        row: the lanes stride the row's entries, combine with two xor
+//        shuffles in a fixed order, and lane 0 writes.  Loads of A and of
+//        the column indices are coalesced across the group; c_in is
+//        gathered.
+// mass:  sum_K phi_K |K| c_K with TwoSum-compensated per-thread sums,
+//        a fixed-order block combine and a fixed-order final combine.
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace bchar {
+
+constexpr int kRowLanes = 4;
+
+__global__ void __launch_bounds__(256) k_apply(const int32_t* __restrict__ rptr,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ cin, int64_t n,
+                                               double* __restrict__ cout) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = g / kRowLanes;
+  const int sub = (int)(g % kRowLanes);
+  double acc = 0.0;
+  if (i < n) {
+    const int32_t lo = rptr[i], hi = rptr[i + 1];
+    for (int32_t k = lo + sub; k < hi; k += kRowLanes) acc += a[k] * cin[col[k]];
+  }
+  acc += __shfl_xor(acc, 1, kWave);
+  acc += __shfl_xor(acc, 2, kWave);
+  if (i < n && sub == 0) cout[i] = acc / b[i];
+}
+
+void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s) {
+  const bchar_mesh_s* m = t->mesh;
+  const int64_t n = m->n_cells;
+  {
+    ::bchar::ProfScope ps_("k_apply", s);
+    k_apply<<<blocks_for(n * kRowLanes, 256), 256, 0, s>>>(
+        t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), t->A.as<double>(), m->b.as<double>(), cin,
+        n, cout);
+  }
+  BCHAR_HIP(hipGetLastError());
+}
+
+constexpr int kMassBlocks = 512;
+
+__global__ void __launch_bounds__(256) k_mass_part(const double* __restrict__ b,
+                                                   const double* __restrict__ c, int64_t n,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // phi_K |K| c_K as the product of two roundings; the sum is compensated
+    acc.add(b[i] * c[i]);
+  }
+  CSum tot = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = tot.hi;
+    part[2 * blockIdx.x + 1] = tot.lo;
+  }
+}
+
+__global__ void k_mass_final(const double* __restrict__ part, int nparts,
+                             double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  CSum acc;
+  for (int i = 0; i < nparts; ++i) {
+    CSum o;
+    o.hi = part[2 * i];
+    o.lo = part[2 * i + 1];
+    acc.add(o);
+  }
+  out[0] = acc.value();
+}
+
+double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_t s) {
+  Arena::Mark mk = ws.mark();
+  double* part = ws.get<double>(2 * kMassBlocks + 1);
+  {
+    ::bchar::ProfScope ps_("k_mass_part", s);
+    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->n_cells, part);
+  }
+  BCHAR_HIP(hipGetLastError());
+  {
+    ::bchar::ProfScope ps_("k_mass_final", s);
+    k_mass_final<<<1, 64, 0, s>>>(part, kMassBlocks, part + 2 * kMassBlocks);
+  }
+  BCHAR_HIP(hipGetLastError());
+  double out = 0;
+  BCHAR_HIP(hipMemcpyAsync(&out, part + 2 * kMassBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+  BCHAR_HIP(hipStreamSynchronize(s));
+  ws.rewind(mk);
+  return out;
+}
+
+}  // namespace bchar

@@ -1,0 +1,212 @@
+// Internal declarations shared by the translation units of libbchar.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bchar.h"
+
+namespace bchar {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+
+struct Error {
+  bchar_status status;
+  std::string msg;
+};
+
+#define BCHAR_HIP(call)                                                            \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::bchar::Error{BCHAR_E_DEVICE, std::string(#call) + ": " +             \
+                                               hipGetErrorString(e_)};             \
+  } while (0)
+
+#define BCHAR_REQUIRE(cond, status, msg)                                           \
+  do {                                                                             \
+    if (!(cond)) throw ::bchar::Error{status, msg};                                \
+  } while (0)
+
+// ---------------------------------------------------------------- memory
+
+// Grow-only device buffer.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t n);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Bump allocator over a list of device chunks, reset at the start of every
+// build and kept between builds, so that steady-state builds allocate
+// nothing.  Allocations are 256-byte aligned and stay valid until reset.
+// `mark()` / `rewind()` free everything allocated after a mark.
+struct Arena {
+  std::vector<DBuf> chunks;
+  size_t cur = 0;   // chunk in use
+  size_t off = 0;   // offset in that chunk
+  void reset() { cur = 0; off = 0; }
+  struct Mark { size_t cur, off; };
+  Mark mark() const { return {cur, off}; }
+  void rewind(Mark m) { cur = m.cur; off = m.off; }
+  template <class T> T* get(size_t n) { return static_cast<T*>(raw(n * sizeof(T))); }
+  void* raw(size_t bytes);
+  void release();
+};
+
+// ---------------------------------------------------------------- handles
+
+}  // namespace bchar
+
+struct bchar_mesh_s {
+  int dim = 0;
+  int64_t n[3] = {1, 1, 1};
+  double origin[3] = {0, 0, 0};
+  double h[3] = {1, 1, 1};
+  int layout = 0;
+  int64_t n_cells = 0, n_balls = 0;
+  int nbpc = 1;                // balls per cell
+  double cell_vol = 0;         // |K|
+  double r = 0;                // radius of every ball
+  double ball_vol = 0;         // |B|
+  double rho = 0;              // porous density (same on every cell)
+  bool phi_const = true;
+  double phi0 = 1;
+  double bmax = 0;             // max |K|_phi
+  // device arrays
+  bchar::DBuf phi;             // n_cells
+  bchar::DBuf b;               // n_cells, |K|_phi
+  bchar::DBuf cen;             // dim * n_balls, ball order, fp64
+  bchar::DBuf cen32;           // dim * n_balls, fp32
+  // spatial hash of the residing balls
+  double hs = 0;               // bucket side
+  int64_t nbk[3] = {1, 1, 1};
+  int64_t n_buckets = 0;
+  bchar::DBuf bucket_start;    // int32 [n_buckets + 1]
+  bchar::DBuf bk_cen;          // fp64 dim * n_balls, bucket order
+  bchar::DBuf bk_cen32;        // fp32 dim * n_balls, bucket order
+  bchar::DBuf bk_ball;         // int32 n_balls: ball id of each bucket slot
+  // scratch reused by builds
+  bchar::Arena ws;
+  bchar::DBuf scratch_small;   // small device scalars
+};
+
+struct bchar_transfer_s {
+  bchar_mesh_s* mesh = nullptr;
+  int stage = 0;
+  int64_t nnz = 0, n_pairs = 0;
+  bchar::DBuf row_ptr;   // int32 n_cells + 1
+  bchar::DBuf col;       // int32 nnz
+  bchar::DBuf V;         // fp64 nnz, A^(0)
+  bchar::DBuf AN;        // fp64 nnz, A^(N)
+  bchar::DBuf A;         // fp64 nnz, final
+  bchar::DBuf x;         // fp64 nnz
+  bchar::DBuf mu, nu;    // fp64 n_cells
+  bchar::DBuf tracked;   // fp64 dim * n_balls
+  bchar::DBuf r_hat;     // fp64 n_balls
+  bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs)
+  bchar_stats stats{};
+};
+
+namespace bchar {
+
+// ---------------------------------------------------------------- kernels (host launchers)
+
+// utilities (util.hip)
+int64_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Arena& ws,
+                           hipStream_t s);          // returns total (syncs)
+void exclusive_scan_i32_async(const int32_t* in, int32_t* out, int64_t n, Arena& ws,
+                              hipStream_t s);        // total at out[n]
+// Stable counting sort of item ids 0..n-1 by key[i] in [0, nkeys):
+// ptr[nkeys+1], perm[n] with items of each key in ascending id order.
+void bucket_sort(const int32_t* key, int64_t n, int64_t nkeys, int32_t* ptr, int32_t* perm,
+                 Arena& ws, hipStream_t s);
+double max_abs(const double* v, int64_t n, Arena& ws, hipStream_t s);   // syncs
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+// mesh (mesh.hip)
+void mesh_build_device(bchar_mesh_s* m, hipStream_t s);
+
+// tracking + V (build.hip)
+struct BuildOut {
+  int32_t* row_ptr;    // n_cells + 1 (device)
+  int32_t* col;
+  double* V;
+  int64_t nnz, n_pairs;
+  int32_t* pair_a;     // optional
+  int32_t* pair_b;
+};
+void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int substeps,
+                 int precision, double* tracked, double* r_hat, Arena& ws, hipStream_t s);
+// Returns BCHAR_OK or VOID_ROW (first_void set); allocates the CSR in t.
+bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
+                        int precision, bool keep_pairs, bchar_transfer_s* t,
+                        int64_t* first_void, hipStream_t s);
+
+// scaling (scaling.hip)
+struct Csc {
+  int32_t* ptr;    // n + 1
+  int32_t* row;    // nnz: row of each entry, column-major order
+  int32_t* pos;    // nnz: CSR position of each entry
+};
+void build_csc(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, Csc& c,
+               Arena& ws, hipStream_t s);
+bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
+                            const Csc& csc, const double* V, int64_t nnz, int n_sweeps,
+                            double* AN, int64_t* void_col, double* max_col_err, Arena& ws,
+                            hipStream_t s);
+
+// QP (qp.hip)
+struct QpResult {
+  int level = 0, newton = 0, cg = 0;
+  double residual = 0;
+  int64_t at_lower = 0, at_upper = 0;
+};
+bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
+                      const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
+                      double* x, double* mu, double* nu, double* A, QpResult& res, Arena& ws,
+                      hipStream_t s);
+
+// apply / mass (apply.hip)
+void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s);
+double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_t s);
+
+// ---------------------------------------------------------------- small helpers
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace bchar
+
+namespace bchar {
+
+// ---------------------------------------------------------------- kernel timing
+//
+// When enabled for a kernel name, every launch of that kernel is bracketed
+// by two HIP events recorded on its stream; bchar_profile_read sums the
+// elapsed times.  Off by default: a disabled scope costs one string compare.
+// Opt-in progress trace on stderr (environment variable BCHAR_TRACE=1):
+// stage wall times of every build and the solver's iteration counts.
+bool trace_enabled();
+double wall_seconds();
+
+struct ProfScope {
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  int slot;
+  hipStream_t s;
+};
+
+}  // namespace bchar

@@ -1,0 +1,1469 @@
+// The least-change bounded problem of Sec. 3.2 (eq. opti_masscons).
+//
+// Unknowns: one x_k per stored entry a_k of A^(N).  Minimise x^T x subject
+// to the row sums and column sums of a (1 + x) equal to |K|_phi and
+// |M|_phi, and lo <= x <= hi (the paper's box is 0 <= 1 + x <= 2, read as
+// -1 <= x <= 1; the relaxation levels drop the cap, then the box).
+//
+// Method: the minimiser is unique; it is reached through the dual.  With
+// multipliers mu (rows) and nu (columns), x_k = clip(a_k (mu_i + nu_j)).
+// The dual function is convex and C^1 with gradient F = constraint
+// residual; a damped semismooth Newton method minimises it.  Each Newton
+// step solves J d = -F with J = A_hat diag(free) A_hat^T, a weighted
+// bipartite graph Laplacian once the column multipliers change sign
+// (L (d_mu; -d_nu) = (-F_row; F_col)), by preconditioned conjugate
+// gradients.  t_k = a_k (mu_i + nu_j) is carried per entry and updated by
+// increments, since weakly coupled cells give multipliers of very
+// different sizes.  The step length comes from Armijo backtracking on the
+// change of the dual function, summed entry by entry.
+//
+// Preconditioner: one symmetric two-grid cycle on the bipartite graph
+// (weighted Jacobi smoothing; each row node joins the column node it is
+// most strongly coupled to, which turns the graph into a graph on cells),
+// then a V-cycle of aggregation multigrid on the cell graph: pairwise
+// matching along strong couplings (w_pq >= beta max(w_p., w_q.)), Galerkin
+// coarse operators, l1-Jacobi smoothing, a dense Cholesky solve on the
+// coarsest level.  The aggregation is fixed once per solve from the
+// all-free weights a_k^2; each Newton step refreshes the weights of every
+// level (entries on the box weigh 0).  Weights span many decades on these
+// matrices (cells that barely move couple to their neighbours by slivers),
+// which is why plain Jacobi-preconditioned CG does not converge here.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace bchar {
+
+constexpr int kT = 256;   // threads per block for vector kernels
+constexpr int kRedBlocks = 512;
+constexpr int kMaxCoarse = 256;    // dense coarsest solve
+constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
+
+// ====================================================================== reductions
+
+__global__ void k_reduce_final_sum(const double* __restrict__ part, int np,
+                                   double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  CSum acc;
+  for (int i = 0; i < np; ++i) {
+    CSum o;
+    o.hi = part[2 * i];
+    o.lo = part[2 * i + 1];
+    acc.add(o);
+  }
+  out[0] = acc.value();
+}
+
+__global__ void k_reduce_final_max(const double* __restrict__ part, int np,
+                                   double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double m = 0;
+  for (int i = 0; i < np; ++i) m = fmax(m, part[i]);
+  out[0] = m;
+}
+
+// dot(a, b) over n, compensated, deterministic (fixed grid)
+__global__ void __launch_bounds__(kT) k_dot_part(const double* __restrict__ a,
+                                                 const double* __restrict__ b, int64_t n,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    acc.add(a[i] * b[i]);
+  CSum t = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t.hi;
+    part[2 * blockIdx.x + 1] = t.lo;
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_sum_part(const double* __restrict__ a, int64_t n,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    acc.add(a[i]);
+  CSum t = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t.hi;
+    part[2 * blockIdx.x + 1] = t.lo;
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_maxabs_part(const double* __restrict__ a, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[16];
+  double m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    m = fmax(m, fabs(a[i]));
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+struct Reducer {
+  double* part;   // 2 * kRedBlocks
+  double* out;    // device scalars
+  hipStream_t s;
+  // device scalar out[slot] = dot(a, b)
+  void dot(const double* a, const double* b, int64_t n, int slot) {
+    {
+      ::bchar::ProfScope ps_("k_dot_part", s);
+      k_dot_part<<<kRedBlocks, kT, 0, s>>>(a, b, n, part);
+    }
+    {
+      ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+      k_reduce_final_sum<<<1, 64, 0, s>>>(part, kRedBlocks, out + slot);
+    }
+  }
+  void sum(const double* a, int64_t n, int slot) {
+    {
+      ::bchar::ProfScope ps_("k_sum_part", s);
+      k_sum_part<<<kRedBlocks, kT, 0, s>>>(a, n, part);
+    }
+    {
+      ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+      k_reduce_final_sum<<<1, 64, 0, s>>>(part, kRedBlocks, out + slot);
+    }
+  }
+  void maxabs(const double* a, int64_t n, int slot) {
+    {
+      ::bchar::ProfScope ps_("k_maxabs_part", s);
+      k_maxabs_part<<<kRedBlocks, kT, 0, s>>>(a, n, part);
+    }
+    {
+      ::bchar::ProfScope ps_("k_reduce_final_max", s);
+      k_reduce_final_max<<<1, 64, 0, s>>>(part, kRedBlocks, out + slot);
+    }
+  }
+  double fetch(int slot) {
+    double v = 0;
+    BCHAR_HIP(hipMemcpyAsync(&v, out + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    BCHAR_HIP(hipStreamSynchronize(s));
+    return v;
+  }
+};
+
+// ====================================================================== graph levels
+
+struct Level {
+  int64_t n = 0, ne = 0;      // nodes, off-diagonal entries
+  int32_t* ptr = nullptr;      // n + 1
+  int32_t* nbr = nullptr;      // ne
+  double* w = nullptr;         // ne, current weights (>= 0)
+  double* w0 = nullptr;        // ne, structural weights (all entries free)
+  double* diag = nullptr;      // n: sum w + tau
+  double* sdinv = nullptr;     // n: smoother step (omega / d)
+  double omega = 1.0;
+  bool l1 = true;              // smoother diagonal = diag + sum w (l1-Jacobi)
+  double tau = 0.0;
+  // aggregation towards the next level
+  int32_t* agg = nullptr;      // n
+  int32_t* mptr = nullptr;     // next.n + 1
+  int32_t* mem = nullptr;      // members, grouped by coarse node
+  int32_t* cptr = nullptr;     // next.ne + 1: contributions of each coarse entry
+  int32_t* cedge = nullptr;    // this level's edge ids
+  // vectors
+  double *b = nullptr, *x = nullptr, *x2 = nullptr, *r = nullptr;
+};
+
+// ---------------------------------------------------------------------- level kernels
+
+__global__ void k_level_diag(const int32_t* __restrict__ ptr, const double* __restrict__ w,
+                             int64_t n, double tau, double omega, int l1,
+                             double* __restrict__ diag, double* __restrict__ sdinv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double s = 0;
+  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s += w[e];
+  const double d = s + tau;
+  diag[p] = d;
+  const double sd = l1 ? d + s : d;
+  sdinv[p] = sd > 0 ? omega / sd : 0.0;
+}
+
+// y = L x  (L = diag - W)
+__global__ void __launch_bounds__(kT) k_lap(const int32_t* __restrict__ ptr,
+                                            const int32_t* __restrict__ nbr,
+                                            const double* __restrict__ w,
+                                            const double* __restrict__ diag,
+                                            const double* __restrict__ x, int64_t n,
+                                            double* __restrict__ y) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= n) return;
+  double s = diag[p] * x[p];
+  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
+  y[p] = s;
+}
+
+// x = sdinv * b
+__global__ void k_smooth_first(const double* __restrict__ sdinv, const double* __restrict__ b,
+                               int64_t n, double* __restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) x[p] = sdinv[p] * b[p];
+}
+
+// xo = xi + sdinv (b - L xi)
+__global__ void __launch_bounds__(kT) k_smooth(const int32_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ nbr,
+                                               const double* __restrict__ w,
+                                               const double* __restrict__ diag,
+                                               const double* __restrict__ sdinv,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ xi, int64_t n,
+                                               double* __restrict__ xo) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= n) return;
+  double s = diag[p] * xi[p];
+  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * xi[nbr[e]];
+  xo[p] = xi[p] + sdinv[p] * (b[p] - s);
+}
+
+// bc[C] = sum over members p of C of (b - L x)[p]
+__global__ void __launch_bounds__(kT) k_resid_restrict(
+    const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
+    const double* __restrict__ w, const double* __restrict__ diag,
+    const double* __restrict__ b, const double* __restrict__ x,
+    const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem, int64_t nc,
+    double* __restrict__ bc) {
+  const int64_t C = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (C >= nc) return;
+  double acc = 0;
+  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) {
+    const int32_t p = mem[m];
+    double s = diag[p] * x[p];
+    for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
+    acc += b[p] - s;
+  }
+  bc[C] = acc;
+}
+
+__global__ void k_prolong(const int32_t* __restrict__ agg, const double* __restrict__ xc,
+                          int64_t n, double* __restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) x[p] += xc[agg[p]];
+}
+
+// coarse weights: sum of the fine edge weights of each coarse entry
+__global__ void k_coarse_values(const int32_t* __restrict__ cptr,
+                                const int32_t* __restrict__ cedge,
+                                const double* __restrict__ wf, int64_t ne,
+                                double* __restrict__ wc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ne) return;
+  double s = 0;
+  for (int32_t c = cptr[r]; c < cptr[r + 1]; ++c) s += wf[cedge[c]];
+  wc[r] = s;
+}
+
+// ---------------------------------------------------------------------- setup kernels
+
+// Row node i of the bipartite graph joins the column (cell) it is most
+// strongly coupled to; column node n + j stays with cell j.
+__global__ void k_agg_rows(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ a, int64_t n, int32_t* __restrict__ agg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double best = -1.0;
+  int32_t bj = col[rptr[i]];
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    const double v = fabs(a[k]);
+    if (v > best) {
+      best = v;
+      bj = col[k];
+    }
+  }
+  agg[i] = bj;
+  agg[n + i] = (int32_t)i;
+}
+
+// One coarse node per wave: gather the edges of its members, map their
+// far ends to coarse ids, drop internal edges, merge equal coarse
+// neighbours.  Count pass: row length and candidate count.  Fill pass:
+// sorted neighbours, and the candidate (fine edge) ids grouped by coarse
+// entry in ascending order.
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_galerkin(
+    const int32_t* __restrict__ fptr, const int32_t* __restrict__ fnbr,
+    const int32_t* __restrict__ agg, const int32_t* __restrict__ mptr,
+    const int32_t* __restrict__ mem, int64_t nc, int32_t* __restrict__ row_cnt,
+    int32_t* __restrict__ cand_cnt, const int32_t* __restrict__ cptr_row,
+    const int32_t* __restrict__ cbase, int32_t* __restrict__ cnbr,
+    int32_t* __restrict__ eptr, int32_t* __restrict__ cedge, int32_t* __restrict__ overflow) {
+  __shared__ int32_t s_key[kAmgCap];
+  __shared__ int32_t s_edge[kAmgCap];
+  __shared__ int32_t s_first[kAmgCap];
+  const int64_t C = blockIdx.x;
+  const int lane = threadIdx.x;
+  // candidates of each member, in member order then edge order
+  int H = 0;
+  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) {
+    const int32_t p = mem[m];
+    const int32_t lo = fptr[p], hi = fptr[p + 1];
+    for (int32_t base = lo; base < hi; base += kWave) {
+      const int32_t e = base + lane;
+      int keep = 0;
+      int32_t Q = -1;
+      if (e < hi) {
+        Q = agg[fnbr[e]];
+        keep = Q != (int32_t)C;
+      }
+      const int incl = wave_incl_scan_i(keep);
+      const int tot = __shfl(incl, kWave - 1, kWave);
+      if (keep && H + incl - 1 < kAmgCap) {
+        s_key[H + incl - 1] = Q;
+        s_edge[H + incl - 1] = e;
+      }
+      H += tot;
+    }
+  }
+  if (H > kAmgCap) {
+    if (lane == 0) atomicMax(overflow, H);
+    return;
+  }
+  __syncthreads();
+  for (int e = lane; e < H; e += kWave) {
+    const int32_t k = s_key[e];
+    int first = 1;
+    for (int j = 0; j < e; ++j)
+      if (s_key[j] == k) {
+        first = 0;
+        break;
+      }
+    s_first[e] = first;
+  }
+  __syncthreads();
+  if (!FILL) {
+    int u = 0;
+    for (int e = lane; e < H; e += kWave) u += s_first[e];
+    u = wave_sum_i(u);
+    if (lane == 0) {
+      row_cnt[C] = u;
+      cand_cnt[C] = H;
+    }
+    return;
+  }
+  const int32_t rb = cptr_row[C];
+  const int32_t cb = cbase[C];
+  for (int e = lane; e < H; e += kWave) {
+    const int32_t k = s_key[e];
+    int less = 0, before = 0, rank = 0;
+    for (int j = 0; j < H; ++j) {
+      const int32_t kj = s_key[j];
+      less += kj < k;
+      before += (kj == k) && (j < e);
+      rank += s_first[j] && kj < k;
+    }
+    cedge[cb + less + before] = s_edge[e];
+    if (s_first[e]) {
+      cnbr[rb + rank] = k;
+      eptr[rb + rank] = cb + less;
+    }
+  }
+}
+
+__global__ void k_max_w(const int32_t* __restrict__ ptr, const double* __restrict__ w,
+                        int64_t n, double* __restrict__ mx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double m = 0;
+  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) m = fmax(m, w[e]);
+  mx[p] = m;
+}
+
+// matching round: unmatched p proposes to its strongest unmatched,
+// symmetrically strong neighbour (ties to the smaller id)
+__global__ void k_propose(const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
+                          const double* __restrict__ w, const double* __restrict__ mx,
+                          const int32_t* __restrict__ partner, double beta, int64_t n,
+                          int32_t* __restrict__ prop) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t best = -1;
+  double bw = 0;
+  if (partner[p] < 0) {
+    for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) {
+      const int32_t q = nbr[e];
+      if (q == p || partner[q] >= 0) continue;
+      const double v = w[e];
+      if (!(v > 0) || v < beta * mx[p] || v < beta * mx[q]) continue;
+      if (v > bw || (v == bw && q < best)) {
+        bw = v;
+        best = q;
+      }
+    }
+  }
+  prop[p] = best;
+}
+
+__global__ void k_accept(const int32_t* __restrict__ prop, int64_t n,
+                         int32_t* __restrict__ partner) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = prop[p];
+  if (q >= 0 && prop[q] == (int32_t)p) partner[p] = q;
+}
+
+__global__ void k_rep_flag(const int32_t* __restrict__ partner, int64_t n,
+                           int32_t* __restrict__ flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = partner[p];
+  flag[p] = (q < 0 || (int32_t)p < q) ? 1 : 0;
+}
+
+__global__ void k_pair_agg(const int32_t* __restrict__ partner, const int32_t* __restrict__ cid,
+                           int64_t n, int32_t* __restrict__ agg) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = partner[p];
+  const int32_t rep = (q < 0 || (int32_t)p < q) ? (int32_t)p : q;
+  agg[p] = cid[rep];
+}
+
+__global__ void k_member_count(const int32_t* __restrict__ partner,
+                               const int32_t* __restrict__ cid, int64_t n,
+                               int32_t* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = partner[p];
+  if (q < 0 || (int32_t)p < q) cnt[cid[p]] = q < 0 ? 1 : 2;
+}
+
+__global__ void k_member_fill(const int32_t* __restrict__ partner,
+                              const int32_t* __restrict__ cid, int64_t n,
+                              const int32_t* __restrict__ mptr, int32_t* __restrict__ mem) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = partner[p];
+  if (q < 0 || (int32_t)p < q) {
+    const int32_t C = cid[p];
+    mem[mptr[C]] = (int32_t)p;
+    if (q >= 0) mem[mptr[C] + 1] = q;
+  }
+}
+
+// ---------------------------------------------------------------------- coarsest
+
+// Dense matrix of the coarsest level plus a relative shift, factorised in
+// place by one workgroup (Cholesky, lower triangle, row-major).
+__global__ void __launch_bounds__(256) k_coarse_factor(const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const double* __restrict__ w,
+                                                       const double* __restrict__ diag, int n,
+                                                       double* __restrict__ G) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += blockDim.x) G[e] = 0.0;
+  __syncthreads();
+  __shared__ double s_dmax;
+  if (tid == 0) {
+    double m = 0;
+    for (int p = 0; p < n; ++p) m = fmax(m, diag[p]);
+    s_dmax = m > 0 ? m : 1.0;
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += blockDim.x) {
+    G[p * n + p] = diag[p] + 1e-12 * s_dmax;
+    for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) G[p * n + nbr[e]] -= w[e];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      double d = G[k * n + k];
+      G[k * n + k] = d > 0 ? sqrt(d) : 1e-300;
+    }
+    __syncthreads();
+    const double dk = G[k * n + k];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) G[i * n + k] /= dk;
+    __syncthreads();
+    for (int e = tid; e < (n - k - 1) * (n - k - 1); e += blockDim.x) {
+      const int i = k + 1 + e / (n - k - 1);
+      const int j = k + 1 + e % (n - k - 1);
+      if (j <= i) G[i * n + j] -= G[i * n + k] * G[j * n + k];
+    }
+    __syncthreads();
+  }
+}
+
+// x = (G G^T)^-1 b, then the mean is removed (the constant vector spans
+// the null space of a connected graph Laplacian).
+__global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__ G,
+                                                      const double* __restrict__ b, int n,
+                                                      double* __restrict__ x) {
+  __shared__ double y[kMaxCoarse];
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  double sb = 0;
+  for (int i = tid; i < n; i += blockDim.x) sb += b[i];
+  sb = block_sum(sb, red);
+  const double bmean = sb / n;
+  for (int i = tid; i < n; i += blockDim.x) y[i] = b[i] - bmean;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) y[k] /= G[k * n + k];
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) y[i] -= G[i * n + k] * y[k];
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    if (tid == 0) y[k] /= G[k * n + k];
+    __syncthreads();
+    for (int i = tid; i < k; i += blockDim.x) y[i] -= G[k * n + i] * y[k];
+    __syncthreads();
+  }
+  double s = 0;
+  for (int i = tid; i < n; i += blockDim.x) s += y[i];
+  s = block_sum(s, red);
+  const double mean = s / n;
+  for (int i = tid; i < n; i += blockDim.x) x[i] = y[i] - mean;
+}
+
+// ====================================================================== hierarchy
+
+struct Hierarchy {
+  std::vector<Level> lv;
+  double* G = nullptr;   // coarsest factor
+  int coarse_n = 0;
+  bool dense = false;
+  int fine_pre = 2, fine_post = 2, pre = 2, post = 2;
+  int coarse_sweeps = 40;
+};
+
+static void level_refresh_diag(Level& L, hipStream_t s) {
+  {
+    ::bchar::ProfScope ps_("k_level_diag", s);
+    k_level_diag<<<blocks_for(L.n, kT), kT, 0, s>>>(L.ptr, L.w, L.n, L.tau, L.omega, L.l1 ? 1 : 0,
+                                                    L.diag, L.sdinv);
+  }
+  BCHAR_HIP(hipGetLastError());
+}
+
+// Build the Galerkin pattern of the next level from `L` and its
+// aggregation (agg, mptr, mem); returns the coarse level (pattern only).
+static Level galerkin_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
+  Level Cl;
+  Cl.n = nc;
+  int32_t* row_cnt = ws.get<int32_t>(nc + 1);
+  int32_t* cand_cnt = ws.get<int32_t>(nc + 1);
+  int32_t* overflow = ws.get<int32_t>(1);
+  fill_i32(overflow, 0, 1, s);
+  {
+    ::bchar::ProfScope ps_("k_galerkin", s);
+    k_galerkin<false><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.agg, L.mptr, L.mem, nc,
+                                                  row_cnt, cand_cnt, nullptr, nullptr, nullptr,
+                                                  nullptr, nullptr, overflow);
+  }
+  BCHAR_HIP(hipGetLastError());
+  int32_t hov = 0;
+  BCHAR_HIP(hipMemcpyAsync(&hov, overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BCHAR_HIP(hipStreamSynchronize(s));
+  if (hov > 0)
+    throw Error{BCHAR_E_UNSUPPORTED,
+                "aggregation: a coarse node has " + std::to_string(hov) + " candidate entries"};
+  Cl.ptr = ws.get<int32_t>(nc + 1);
+  int32_t* cbase = ws.get<int32_t>(nc + 1);
+  Cl.ne = exclusive_scan_i32(row_cnt, Cl.ptr, nc, ws, s);
+  const int64_t ncand = exclusive_scan_i32(cand_cnt, cbase, nc, ws, s);
+  Cl.nbr = ws.get<int32_t>(Cl.ne + 1);
+  L.cptr = ws.get<int32_t>(Cl.ne + 1);
+  L.cedge = ws.get<int32_t>(ncand + 1);
+  {
+    ::bchar::ProfScope ps_("k_galerkin", s);
+    k_galerkin<true><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.agg, L.mptr, L.mem, nc, nullptr,
+                                                 nullptr, Cl.ptr, cbase, Cl.nbr, L.cptr, L.cedge,
+                                                 overflow);
+  }
+  BCHAR_HIP(hipGetLastError());
+  // closing entry of the contribution pointer
+  BCHAR_HIP(hipMemcpyAsync(L.cptr + Cl.ne, cbase + nc, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                           s));
+  Cl.w = ws.get<double>(Cl.ne + 1);
+  Cl.w0 = ws.get<double>(Cl.ne + 1);
+  {
+    ::bchar::ProfScope ps_("k_coarse_values", s);
+    k_coarse_values<<<blocks_for(Cl.ne, kT), kT, 0, s>>>(L.cptr, L.cedge, L.w0, Cl.ne, Cl.w0);
+  }
+  BCHAR_HIP(hipGetLastError());
+  return Cl;
+}
+
+static void alloc_level_vectors(Level& L, Arena& ws) {
+  L.diag = ws.get<double>(L.n + 1);
+  L.sdinv = ws.get<double>(L.n + 1);
+  L.b = ws.get<double>(L.n + 1);
+  L.x = ws.get<double>(L.n + 1);
+  L.x2 = ws.get<double>(L.n + 1);
+  L.r = ws.get<double>(L.n + 1);
+}
+
+// Fine level: bipartite graph on 2n nodes (rows, then columns).
+static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const int32_t* col,
+                            const double* a, int64_t n, Arena& ws, hipStream_t s) {
+  H.lv.clear();
+  fine.omega = 0.6;
+  fine.l1 = false;
+  alloc_level_vectors(fine, ws);
+  H.lv.push_back(fine);
+  {
+    Level& L = H.lv.back();
+    L.agg = ws.get<int32_t>(L.n + 1);
+    {
+      ::bchar::ProfScope ps_("k_agg_rows", s);
+      k_agg_rows<<<blocks_for(n, kT), kT, 0, s>>>(rptr, col, a, n, L.agg);
+    }
+    BCHAR_HIP(hipGetLastError());
+    L.mptr = ws.get<int32_t>(n + 1);
+    L.mem = ws.get<int32_t>(L.n + 1);
+    bucket_sort(L.agg, L.n, n, L.mptr, L.mem, ws, s);
+    Level C = galerkin_pattern(L, n, ws, s);
+    C.omega = 1.0;
+    C.l1 = true;
+    alloc_level_vectors(C, ws);
+    H.lv.push_back(C);
+  }
+  double beta = 0.25;
+  while (H.lv.back().n > 64) {
+    Level& L = H.lv.back();
+    const int64_t nl = L.n;
+    double* mx = ws.get<double>(nl + 1);
+    int32_t* partner = ws.get<int32_t>(nl + 1);
+    int32_t* prop = ws.get<int32_t>(nl + 1);
+    {
+      ::bchar::ProfScope ps_("k_max_w", s);
+      k_max_w<<<blocks_for(nl, kT), kT, 0, s>>>(L.ptr, L.w0, nl, mx);
+    }
+    fill_i32(partner, -1, nl, s);
+    for (int round = 0; round < 10; ++round) {
+      {
+        ::bchar::ProfScope ps_("k_propose", s);
+        k_propose<<<blocks_for(nl, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w0, mx, partner, beta, nl,
+                                                    prop);
+      }
+      {
+        ::bchar::ProfScope ps_("k_accept", s);
+        k_accept<<<blocks_for(nl, kT), kT, 0, s>>>(prop, nl, partner);
+      }
+    }
+    BCHAR_HIP(hipGetLastError());
+    int32_t* flag = ws.get<int32_t>(nl + 1);
+    int32_t* cid = ws.get<int32_t>(nl + 1);
+    {
+      ::bchar::ProfScope ps_("k_rep_flag", s);
+      k_rep_flag<<<blocks_for(nl, kT), kT, 0, s>>>(partner, nl, flag);
+    }
+    const int64_t nc = exclusive_scan_i32(flag, cid, nl, ws, s);
+    if ((double)nc > 0.95 * (double)nl) break;   // nothing left to pair
+    if ((double)nc > 0.8 * (double)nl) beta = 0.0;
+    L.agg = ws.get<int32_t>(nl + 1);
+    {
+      ::bchar::ProfScope ps_("k_pair_agg", s);
+      k_pair_agg<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, L.agg);
+    }
+    int32_t* mcnt = ws.get<int32_t>(nc + 1);
+    {
+      ::bchar::ProfScope ps_("k_member_count", s);
+      k_member_count<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, mcnt);
+    }
+    L.mptr = ws.get<int32_t>(nc + 1);
+    exclusive_scan_i32_async(mcnt, L.mptr, nc, ws, s);
+    L.mem = ws.get<int32_t>(nl + 1);
+    {
+      ::bchar::ProfScope ps_("k_member_fill", s);
+      k_member_fill<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, L.mptr, L.mem);
+    }
+    BCHAR_HIP(hipGetLastError());
+    Level C = galerkin_pattern(L, nc, ws, s);
+    C.omega = 1.0;
+    C.l1 = true;
+    alloc_level_vectors(C, ws);
+    H.lv.push_back(C);
+  }
+  Level& last = H.lv.back();
+  H.coarse_n = (int)last.n;
+  H.dense = last.n <= kMaxCoarse;
+  if (H.dense) H.G = ws.get<double>((size_t)last.n * last.n + 1);
+}
+
+// New weights on every level (fine weights already in lv[0].w).
+static void refresh_hierarchy(Hierarchy& H, hipStream_t s) {
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = H.lv[l];
+    if (l > 0) {
+      Level& F = H.lv[l - 1];
+      {
+        ::bchar::ProfScope ps_("k_coarse_values", s);
+        k_coarse_values<<<blocks_for(L.ne, kT), kT, 0, s>>>(F.cptr, F.cedge, F.w, L.ne, L.w);
+      }
+      BCHAR_HIP(hipGetLastError());
+    }
+    level_refresh_diag(L, s);
+  }
+  if (H.dense) {
+    Level& L = H.lv.back();
+    {
+      ::bchar::ProfScope ps_("k_coarse_factor", s);
+      k_coarse_factor<<<1, 256, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, (int)L.n, H.G);
+    }
+    BCHAR_HIP(hipGetLastError());
+  }
+}
+
+static void smooth_steps(Level& L, const double* b, double*& x, double*& x2, int steps,
+                         bool from_zero, hipStream_t s) {
+  int k = 0;
+  if (from_zero && steps > 0) {
+    {
+      ::bchar::ProfScope ps_("k_smooth_first", s);
+      k_smooth_first<<<blocks_for(L.n, kT), kT, 0, s>>>(L.sdinv, b, L.n, x);
+    }
+    k = 1;
+  }
+  for (; k < steps; ++k) {
+    {
+      ::bchar::ProfScope ps_("k_smooth", s);
+      k_smooth<<<blocks_for(L.n, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, b, x, L.n,
+                                                  x2);
+    }
+    std::swap(x, x2);
+  }
+}
+
+// x_l = cycle(b_l); on return H.lv[l].x holds the result.
+static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
+  Level& L = H.lv[l];
+  if (l + 1 == H.lv.size()) {
+    if (H.dense) {
+      {
+        ::bchar::ProfScope ps_("k_coarse_solve", s);
+        k_coarse_solve<<<1, 256, 0, s>>>(H.G, L.b, (int)L.n, L.x);
+      }
+    } else {
+      double* x = L.x;
+      double* x2 = L.x2;
+      smooth_steps(L, L.b, x, x2, H.coarse_sweeps, true, s);
+      if (x != L.x) std::swap(L.x, L.x2);
+    }
+    return;
+  }
+  Level& C = H.lv[l + 1];
+  const int pre = l == 0 ? H.fine_pre : H.pre;
+  const int post = l == 0 ? H.fine_post : H.post;
+  double* x = L.x;
+  double* x2 = L.x2;
+  smooth_steps(L, L.b, x, x2, pre, true, s);
+  {
+    ::bchar::ProfScope ps_("k_resid_restrict", s);
+    k_resid_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, x, L.mptr,
+                                                        L.mem, C.n, C.b);
+  }
+  vcycle(H, l + 1, s);
+  {
+    ::bchar::ProfScope ps_("k_prolong", s);
+    k_prolong<<<blocks_for(L.n, kT), kT, 0, s>>>(L.agg, C.x, L.n, x);
+  }
+  smooth_steps(L, L.b, x, x2, post, false, s);
+  if (x != L.x) {
+    // keep the result in L.x
+    std::swap(L.x, L.x2);
+  }
+  BCHAR_HIP(hipGetLastError());
+}
+
+// z = M r: one cycle from the fine level
+// ====================================================================== per-cell (s, g) space
+//
+// The Newton system in the multipliers y = (mu, -nu) is the Laplacian of
+// the bipartite graph rows-columns.  Rows and columns are both indexed by
+// cells; in the coordinates s_K = (y_rK + y_cK)/2, g_K = y_rK - y_cK an
+// entry (K, M) of weight w contributes w v v^T with
+//     v = e_sK - e_sM + (e_gK + e_gM)/2   (K != M),     v = e_gK   (K == M).
+// Cells that barely move carry a weight near 1 on (K, K) and slivers
+// elsewhere: in y coordinates their gauge mode (s_K) is lost to rounding;
+// here the s part only ever sees the off-diagonal weights.  Every product
+// with this matrix is formed entry by entry from (s, g).
+
+struct ZCells {
+  int64_t n;
+  const int32_t *rptr, *col, *cptr, *crow, *cpos;
+  const int32_t* dpos;   // position of (K, K) in row K, or -1
+  const int32_t* best;   // strongest column of row K (level-1 aggregate of the row)
+  const double* w;       // weights, CSR order (nnz)
+  const double* wc;      // weights, CSC order (nnz)
+  double* tau_s;         // relative shifts
+  double* tau_g;
+  double* bi;            // 3 per cell: inverse of the 2x2 cell block (ss, sg, gg)
+};
+
+__global__ void k_diag_pos(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                           int64_t n, int32_t* __restrict__ dpos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t d = -1;
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k)
+    if (col[k] == (int32_t)i) d = k;
+  dpos[i] = d;
+}
+
+// per-cell block [[A, B], [B, C]] of J_z (+ shifts) and its inverse
+__global__ void k_zcells(ZCells Z, double rel) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= Z.n) return;
+  double R = 0, Cs = 0;
+  for (int32_t k = Z.rptr[K]; k < Z.rptr[K + 1]; ++k)
+    if (Z.col[k] != (int32_t)K) R += Z.w[k];
+  for (int32_t e = Z.cptr[K]; e < Z.cptr[K + 1]; ++e)
+    if (Z.crow[e] != (int32_t)K) Cs += Z.wc[e];
+  const double wkk = Z.dpos[K] >= 0 ? Z.w[Z.dpos[K]] : 0.0;
+  const double A0 = R + Cs;
+  const double C0 = wkk + 0.25 * (R + Cs);
+  const double ts = rel * (A0 > 0 ? A0 : 1.0);
+  const double tg = rel * (C0 > 0 ? C0 : 1.0);
+  Z.tau_s[K] = ts;
+  Z.tau_g[K] = tg;
+  const double A = A0 + ts, C = C0 + tg, B = 0.5 * (R - Cs);
+  // A C - B^2 written as a sum of non-negative terms
+  const double det = (R + Cs) * wkk + R * Cs + ts * C0 + tg * A0 + ts * tg;
+  Z.bi[3 * K + 0] = C / det;
+  Z.bi[3 * K + 1] = -B / det;
+  Z.bi[3 * K + 2] = A / det;
+}
+
+// out = J_z z for cell K
+__device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __restrict__ zs,
+                                            const double* __restrict__ zg, int64_t K,
+                                            double& os, double& og) {
+  const double sK = zs[K], gK = zg[K];
+  double fr = 0, fc = 0, fd = 0;
+  for (int32_t k = Z.rptr[K]; k < Z.rptr[K + 1]; ++k) {
+    const int32_t M = Z.col[k];
+    if (M == (int32_t)K) {
+      fd = Z.w[k] * gK;
+    } else {
+      fr += Z.w[k] * ((sK - zs[M]) + 0.5 * (gK + zg[M]));
+    }
+  }
+  for (int32_t e = Z.cptr[K]; e < Z.cptr[K + 1]; ++e) {
+    const int32_t I = Z.crow[e];
+    if (I != (int32_t)K) fc += Z.wc[e] * ((zs[I] - sK) + 0.5 * (zg[I] + gK));
+  }
+  os = fr - fc + Z.tau_s[K] * sK;
+  og = 0.5 * (fr + fc) + fd + Z.tau_g[K] * gK;
+}
+
+__global__ void __launch_bounds__(kT) k_zop(ZCells Z, const double* __restrict__ z,
+                                            double* __restrict__ out) {
+  const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (K >= Z.n) return;
+  double os, og;
+  zapply_cell(Z, z, z + Z.n, K, os, og);
+  out[K] = os;
+  out[Z.n + K] = og;
+}
+
+// x = omega B^-1 b
+__global__ void k_zsmooth_first(ZCells Z, double omega, const double* __restrict__ b,
+                                double* __restrict__ x) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= Z.n) return;
+  const double bs = b[K], bg = b[Z.n + K];
+  x[K] = omega * (Z.bi[3 * K] * bs + Z.bi[3 * K + 1] * bg);
+  x[Z.n + K] = omega * (Z.bi[3 * K + 1] * bs + Z.bi[3 * K + 2] * bg);
+}
+
+// xo = xi + omega B^-1 (b - J_z xi)
+__global__ void __launch_bounds__(kT) k_zsmooth(ZCells Z, double omega,
+                                                const double* __restrict__ b,
+                                                const double* __restrict__ xi,
+                                                double* __restrict__ xo) {
+  const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (K >= Z.n) return;
+  double os, og;
+  zapply_cell(Z, xi, xi + Z.n, K, os, og);
+  const double rs = b[K] - os, rg = b[Z.n + K] - og;
+  xo[K] = xi[K] + omega * (Z.bi[3 * K] * rs + Z.bi[3 * K + 1] * rg);
+  xo[Z.n + K] = xi[Z.n + K] + omega * (Z.bi[3 * K + 1] * rs + Z.bi[3 * K + 2] * rg);
+}
+
+// r = b - J_z x
+__global__ void __launch_bounds__(kT) k_zresid(ZCells Z, const double* __restrict__ b,
+                                               const double* __restrict__ x,
+                                               double* __restrict__ r) {
+  const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (K >= Z.n) return;
+  double os, og;
+  zapply_cell(Z, x, x + Z.n, K, os, og);
+  r[K] = b[K] - os;
+  r[Z.n + K] = b[Z.n + K] - og;
+}
+
+// coarse (cell) residual: y-space residual of the rows attached to M and
+// of column M, with r_row = r_s / 2 + r_g and r_col = r_s / 2 - r_g
+__global__ void k_zrestrict(const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                            const double* __restrict__ r, int64_t n, double* __restrict__ bc) {
+  const int64_t M = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (M >= n) return;
+  double acc = 0;
+  for (int32_t q = mptr[M]; q < mptr[M + 1]; ++q) {
+    const int32_t p = mem[q];
+    if (p < (int32_t)n)
+      acc += 0.5 * r[p] + r[n + p];
+    else
+      acc += 0.5 * r[p - n] - r[p];   // r[n + (p - n)] is the g part of cell p - n
+  }
+  bc[M] = acc;
+}
+
+// x += P e: row K takes e[best K], column K takes e[K]
+__global__ void k_zprolong(const int32_t* __restrict__ best, const double* __restrict__ e,
+                           int64_t n, double* __restrict__ x) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= n) return;
+  const double er = e[best[K]], ec = e[K];
+  x[K] += 0.5 * (er + ec);
+  x[n + K] += er - ec;
+}
+
+struct ZPrecond {
+  ZCells Z;
+  Hierarchy* H;
+  double omega = 0.7;
+  int pre = 2, post = 2;
+  double *x, *x2, *res;   // 2n work vectors
+};
+
+// z = M r: block-Jacobi smoothing in (s, g), coarse correction through
+// the cell hierarchy, block-Jacobi smoothing (symmetric)
+static void zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s) {
+  const int64_t n = P.Z.n;
+  const unsigned gb = blocks_for(n, kT);
+  double* x = P.x;
+  double* x2 = P.x2;
+  {
+    ::bchar::ProfScope ps_("k_zsmooth_first", s);
+    k_zsmooth_first<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x);
+  }
+  for (int k = 1; k < P.pre; ++k) {
+    {
+      ::bchar::ProfScope ps_("k_zsmooth", s);
+      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, x2);
+    }
+    std::swap(x, x2);
+  }
+  {
+    ::bchar::ProfScope ps_("k_zresid", s);
+    k_zresid<<<gb, kT, 0, s>>>(P.Z, r, x, P.res);
+  }
+  Level& L0 = P.H->lv[0];
+  Level& L1 = P.H->lv[1];
+  {
+    ::bchar::ProfScope ps_("k_zrestrict", s);
+    k_zrestrict<<<blocks_for(n, kT), kT, 0, s>>>(L0.mptr, L0.mem, P.res, n, L1.b);
+  }
+  vcycle(*P.H, 1, s);
+  {
+    ::bchar::ProfScope ps_("k_zprolong", s);
+    k_zprolong<<<gb, kT, 0, s>>>(P.Z.best, L1.x, n, x);
+  }
+  for (int k = 0; k < P.post; ++k) {
+    double* out = (k + 1 == P.post) ? z : x2;
+    {
+      ::bchar::ProfScope ps_("k_zsmooth", s);
+      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, out);
+    }
+    if (out == x2) std::swap(x, x2);
+  }
+  if (P.post == 0)
+    BCHAR_HIP(hipMemcpyAsync(z, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s));
+  BCHAR_HIP(hipGetLastError());
+}
+
+// ====================================================================== Newton kernels
+
+struct QpArrays {
+  int64_t n, nnz;
+  const int32_t *rptr, *col;        // CSR
+  const int32_t *cptr, *crow, *cpos;  // CSC
+  double *a;      // scaled A^(N), CSR order
+  double *ac;     // CSC order
+  double *rr, *ss;  // targets of sum a x (rows, cols)
+  double *t, *dt;   // per entry
+  double *F;        // 2n residual
+};
+
+__global__ void k_gather_q(const double* __restrict__ src, const int32_t* __restrict__ idx,
+                           int64_t n, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[idx[e]];
+}
+
+__global__ void k_scale_a(const double* __restrict__ an, double inv, int64_t nnz,
+                          double* __restrict__ a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) a[k] = an[k] * inv;
+}
+
+// rr[i] = b_i/scale - sum_row a ; ss[j] = b_j/scale - sum_col a
+__global__ void k_targets(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
+                          const double* __restrict__ a, const double* __restrict__ ac,
+                          const double* __restrict__ b, double inv, int64_t n,
+                          double* __restrict__ rr, double* __restrict__ ss) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CSum r, c;
+  r.add(b[i] * inv);
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) r.add(-a[k]);
+  c.add(b[i] * inv);
+  for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) c.add(-ac[e]);
+  rr[i] = r.value();
+  ss[i] = c.value();
+}
+
+__device__ __forceinline__ double clipv(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// F = [sum_row a clip(t + step dt) - rr ; sum_col ... - ss]
+__global__ void k_residual(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
+                           const int32_t* __restrict__ cpos, const double* __restrict__ a,
+                           const double* __restrict__ ac, const double* __restrict__ t,
+                           const double* __restrict__ dt, double step, double lo, double hi,
+                           const double* __restrict__ rr, const double* __restrict__ ss,
+                           int64_t n, double* __restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CSum r, c;
+  r.add(-rr[i]);
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    const double tk = dt ? t[k] + step * dt[k] : t[k];
+    r.add(a[k] * clipv(tk, lo, hi));
+  }
+  c.add(-ss[i]);
+  for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
+    const int32_t k = cpos[e];
+    const double tk = dt ? t[k] + step * dt[k] : t[k];
+    c.add(ac[e] * clipv(tk, lo, hi));
+  }
+  F[i] = r.value();
+  F[n + i] = c.value();
+}
+
+// fine bipartite weights a_k^2 * free_k in graph order: row part is CSR
+// order, column part is CSC order
+__global__ void k_fine_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
+                               const double* __restrict__ t, double lo, double hi, int64_t nnz,
+                               double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double tk = t[k];
+  w[k] = (tk > lo && tk < hi) ? a[k] * a[k] : 0.0;
+  const int32_t kp = cpos[k];
+  const double tp = t[kp];
+  w[nnz + k] = (tp > lo && tp < hi) ? a[kp] * a[kp] : 0.0;
+}
+
+__global__ void k_fine_graph(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                             const int32_t* __restrict__ cptr, const int32_t* __restrict__ crow,
+                             int64_t n, int64_t nnz, int32_t* __restrict__ gptr,
+                             int32_t* __restrict__ gnbr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    gptr[i] = rptr[i];
+    gptr[n + i] = (int32_t)nnz + cptr[i];
+    for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) gnbr[k] = (int32_t)n + col[k];
+    for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) gnbr[nnz + e] = crow[e];
+  }
+  if (i == 0) gptr[2 * n] = (int32_t)(2 * nnz);
+}
+
+// (s, g) right-hand side from F: fr = -F_row, fc = F_col;
+// b_s = fr + fc, b_g = (fr - fc) / 2
+__global__ void k_zrhs(const double* __restrict__ F, int64_t n, double* __restrict__ bz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double fr = -F[i], fc = F[n + i];
+    bz[i] = fr + fc;
+    bz[n + i] = 0.5 * (fr - fc);
+  }
+}
+
+__global__ void k_sub_scalar(double* __restrict__ v, const double* __restrict__ sum,
+                             double inv_n, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] -= sum[0] * inv_n;
+}
+
+// CG vector updates with device scalars sc[0] = rz, sc[1] = pq
+__global__ void k_cg_update(const double* __restrict__ sc, int64_t n, double* __restrict__ x,
+                            double* __restrict__ r, const double* __restrict__ p,
+                            const double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = sc[1] != 0.0 ? sc[0] / sc[1] : 0.0;
+  x[i] += alpha * p[i];
+  r[i] -= alpha * q[i];
+}
+
+// p = z + (sc[2] / sc[0]) p
+__global__ void k_cg_dir(const double* __restrict__ sc, int64_t n, const double* __restrict__ z,
+                         double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
+  p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_copy_scalar(double* sc, int from, int to) {
+  if (threadIdx.x == 0) sc[to] = sc[from];
+}
+
+// dual direction from the (s, g) solution (mean of s removed) and the
+// per-entry increments of t
+__global__ void k_zdual_dir(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ a, const double* __restrict__ z,
+                            const double* __restrict__ ssum, double inv_n, int64_t n,
+                            double* __restrict__ dmu, double* __restrict__ dnu,
+                            double* __restrict__ dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double si = z[i] - ssum[0] * inv_n;
+  const double gi = z[n + i];
+  dmu[i] = si + 0.5 * gi;
+  dnu[i] = -(si - 0.5 * gi);
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    const int32_t j = col[k];
+    dt[k] = a[k] * (j == (int32_t)i ? gi : (z[i] - z[j]) + 0.5 * (gi + z[n + j]));
+  }
+}
+
+// psi(t + d) - psi(t), psi the primitive of clip(., lo, hi) vanishing at 0
+__device__ __forceinline__ double dpsi(double t, double d, double lo, double hi) {
+  const double u = t + d;
+  const double c1 = clipv(t, lo, hi);
+  const double c2 = clipv(u, lo, hi);
+  const bool f1 = c1 == t, f2 = c2 == u;
+  if (f1 && f2) return d * (t + 0.5 * d);
+  if (!f1 && !f2 && c1 == c2) return c1 * d;
+  return 0.5 * (c2 * c2 - c1 * c1) + (f2 ? 0.0 : c2 * (u - c2)) - (f1 ? 0.0 : c1 * (t - c1));
+}
+
+__global__ void __launch_bounds__(kT) k_dtheta_part(const double* __restrict__ t,
+                                                    const double* __restrict__ dt, double step,
+                                                    double lo, double hi, int64_t nnz,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kT)
+    acc.add(dpsi(t[k], step * dt[k], lo, hi));
+  CSum r = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r.hi;
+    part[2 * blockIdx.x + 1] = r.lo;
+  }
+}
+
+__global__ void k_axpy2(double* __restrict__ y, const double* __restrict__ x, double s,
+                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += s * x[i];
+}
+
+__global__ void k_final(const double* __restrict__ an, const double* __restrict__ t, double lo,
+                        double hi, int64_t nnz, double* __restrict__ x, double* __restrict__ A,
+                        int32_t* __restrict__ counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double xk = clipv(t[k], lo, hi);
+  x[k] = xk;
+  A[k] = an[k] * (1.0 + xk);
+  if (xk == lo) atomicAdd(&counts[0], 1);
+  if (xk == hi) atomicAdd(&counts[1], 1);
+}
+
+// ====================================================================== solver
+
+bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
+                      const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
+                      double* x_out, double* mu_out, double* nu_out, double* A_out,
+                      QpResult& res, Arena& ws, hipStream_t s) {
+  const int64_t n = m->n_cells;
+  const int64_t n2 = 2 * n;
+  const double scale = m->bmax;
+  const double inv = 1.0 / scale;
+  const unsigned gn = blocks_for(n, kT), gn2 = blocks_for(n2, kT), gz = blocks_for(nnz, kT);
+
+  Reducer red{ws.get<double>(2 * kRedBlocks + 2), ws.get<double>(16), s};
+
+  QpArrays Q{};
+  Q.n = n;
+  Q.nnz = nnz;
+  Q.rptr = row_ptr;
+  Q.col = col;
+  Q.cptr = csc.ptr;
+  Q.crow = csc.row;
+  Q.cpos = csc.pos;
+  Q.a = ws.get<double>(nnz + 1);
+  Q.ac = ws.get<double>(nnz + 1);
+  Q.rr = ws.get<double>(n);
+  Q.ss = ws.get<double>(n);
+  Q.t = ws.get<double>(nnz + 1);
+  Q.dt = ws.get<double>(nnz + 1);
+  Q.F = ws.get<double>(n2);
+  double* dmu = ws.get<double>(n);
+  double* dnu = ws.get<double>(n);
+  {
+    ::bchar::ProfScope ps_("k_scale_a", s);
+    k_scale_a<<<gz, kT, 0, s>>>(AN, inv, nnz, Q.a);
+  }
+  {
+    ::bchar::ProfScope ps_("k_gather_q", s);
+    k_gather_q<<<gz, kT, 0, s>>>(Q.a, csc.pos, nnz, Q.ac);
+  }
+  {
+    ::bchar::ProfScope ps_("k_targets", s);
+    k_targets<<<gn, kT, 0, s>>>(row_ptr, csc.ptr, Q.a, Q.ac, m->b.as<double>(), inv, n, Q.rr,
+                                Q.ss);
+  }
+  BCHAR_HIP(hipGetLastError());
+
+  // bipartite graph (y space) and the cell hierarchy, pattern from a^2
+  Level fine;
+  fine.n = n2;
+  fine.ne = 2 * nnz;
+  fine.ptr = ws.get<int32_t>(n2 + 1);
+  fine.nbr = ws.get<int32_t>(2 * nnz + 1);
+  fine.w = ws.get<double>(2 * nnz + 1);
+  fine.w0 = ws.get<double>(2 * nnz + 1);
+  {
+    ::bchar::ProfScope ps_("k_fine_graph", s);
+    k_fine_graph<<<gn, kT, 0, s>>>(row_ptr, col, csc.ptr, csc.row, n, nnz, fine.ptr, fine.nbr);
+  }
+  fill_f64(Q.t, 0.0, nnz, s);
+  {
+    ::bchar::ProfScope ps_("k_fine_weights", s);
+    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, nnz, fine.w0);
+  }
+  BCHAR_HIP(hipGetLastError());
+  Hierarchy H;
+  const double th0 = trace_enabled() ? wall_seconds() : 0.0;
+  build_hierarchy(H, fine, row_ptr, col, Q.a, n, ws, s);
+  if (trace_enabled()) {
+    BCHAR_HIP(hipStreamSynchronize(s));
+    fprintf(stderr, "[bchar] hierarchy: %zu levels in %.3f ms:", H.lv.size(),
+            1e3 * (wall_seconds() - th0));
+    for (auto& L : H.lv) fprintf(stderr, " %lld/%lld", (long long)L.n, (long long)L.ne);
+    fprintf(stderr, "\n");
+  }
+  for (size_t l = 1; l < H.lv.size(); ++l) H.lv[l].tau = 0.0;
+  Level& L0 = H.lv[0];
+
+  ZPrecond P;
+  P.H = &H;
+  P.Z.n = n;
+  P.Z.rptr = row_ptr;
+  P.Z.col = col;
+  P.Z.cptr = csc.ptr;
+  P.Z.crow = csc.row;
+  P.Z.cpos = csc.pos;
+  int32_t* dpos = ws.get<int32_t>(n);
+  {
+    ::bchar::ProfScope ps_("k_diag_pos", s);
+    k_diag_pos<<<gn, kT, 0, s>>>(row_ptr, col, n, dpos);
+  }
+  P.Z.dpos = dpos;
+  P.Z.best = L0.agg;   // rows 0..n-1 of the level-0 aggregation
+  P.Z.w = L0.w;
+  P.Z.wc = L0.w + nnz;
+  P.Z.tau_s = ws.get<double>(n);
+  P.Z.tau_g = ws.get<double>(n);
+  P.Z.bi = ws.get<double>(3 * n);
+  P.x = ws.get<double>(n2);
+  P.x2 = ws.get<double>(n2);
+  P.res = ws.get<double>(n2);
+
+  double *cx = ws.get<double>(n2), *cr = ws.get<double>(n2), *cz = ws.get<double>(n2),
+         *cp = ws.get<double>(n2), *cq = ws.get<double>(n2);
+
+  const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
+  const double hi_levels[3] = {1.0, HUGE_VAL, HUGE_VAL};
+  const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : 2;
+  const double tol = o.qp_tol;
+  res = QpResult{};
+  bool converged = false;
+  int level = 0;
+  double fn = 0;
+  for (level = 0; level <= max_level && !converged; ++level) {
+    const double lo = lo_levels[level], hi = hi_levels[level];
+    fill_f64(Q.t, 0.0, nnz, s);
+    fill_f64(mu_out, 0.0, n, s);
+    fill_f64(nu_out, 0.0, n, s);
+    for (int it = 0; it < o.qp_max_newton; ++it) {
+      {
+        ::bchar::ProfScope ps_("k_residual", s);
+        k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
+                                     Q.rr, Q.ss, n, Q.F);
+      }
+      red.maxabs(Q.F, n2, 0);
+      fn = red.fetch(0);
+      if (!(fn == fn)) break;
+      if (fn <= tol) {
+        converged = true;
+        break;
+      }
+      ++res.newton;
+      // Newton matrix weights, per-cell blocks and the hierarchy values
+      {
+        ::bchar::ProfScope ps_("k_fine_weights", s);
+        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, nnz, L0.w);
+      }
+      {
+        ::bchar::ProfScope ps_("k_zcells", s);
+        k_zcells<<<gn, kT, 0, s>>>(P.Z, 1e-14);
+      }
+      BCHAR_HIP(hipGetLastError());
+      refresh_hierarchy(H, s);
+      // right-hand side with the constant-s direction removed
+      {
+        ::bchar::ProfScope ps_("k_zrhs", s);
+        k_zrhs<<<gn, kT, 0, s>>>(Q.F, n, cr);
+      }
+      red.sum(cr, n, 12);
+      {
+        ::bchar::ProfScope ps_("k_sub_scalar", s);
+        k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, 1.0 / (double)n, n);
+      }
+      fill_f64(cx, 0.0, n2, s);
+      // inexact Newton: relative inner tolerance on the y-space residual
+      // (near-exact solves once Newton needs many steps, as on faces of the
+      // box where the multipliers of the pinned entries grow without bound)
+      const double eta = it < 30 ? std::min(0.1, std::sqrt(fn)) * 0.1 : 1e-6;
+      const double cg_tol = std::max(eta * fn, 0.1 * tol);
+      // scalars: out[8] = rz, out[9] = pq, out[10] = rz_new, out[11] = max |r|
+      zprecondition(P, cr, cz, s);
+      BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+      red.dot(cr, cz, n2, 8);
+      int k = 0;
+      for (k = 0; k < o.qp_max_cg; ++k) {
+        {
+          ::bchar::ProfScope ps_("k_zop", s);
+          k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq);
+        }
+        red.dot(cp, cq, n2, 9);
+        {
+          ::bchar::ProfScope ps_("k_cg_update", s);
+          k_cg_update<<<gn2, kT, 0, s>>>(red.out + 8, n2, cx, cr, cp, cq);
+        }
+        BCHAR_HIP(hipGetLastError());
+        if ((k % 4) == 3 || k + 1 == o.qp_max_cg) {
+          red.maxabs(cr, n2, 11);
+          if (red.fetch(11) <= cg_tol) {
+            ++k;
+            break;
+          }
+        }
+        zprecondition(P, cr, cz, s);
+        red.dot(cr, cz, n2, 10);
+        {
+          ::bchar::ProfScope ps_("k_cg_dir", s);
+          k_cg_dir<<<gn2, kT, 0, s>>>(red.out + 8, n2, cz, cp);
+        }
+        {
+          ::bchar::ProfScope ps_("k_copy_scalar", s);
+          k_copy_scalar<<<1, 64, 0, s>>>(red.out, 10, 8);
+        }
+        BCHAR_HIP(hipGetLastError());
+      }
+      res.cg += k;
+      if (trace_enabled())
+        fprintf(stderr, "[bchar]   level %d newton %d: |F| %.3e, cg %d, t %.3f s\n", level, it,
+                fn, k, wall_seconds());
+      // dual direction and entry increments
+      red.sum(cx, n, 13);
+      {
+        ::bchar::ProfScope ps_("k_zdual_dir", s);
+        k_zdual_dir<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, cx, red.out + 13, 1.0 / (double)n, n,
+                                      dmu, dnu, Q.dt);
+      }
+      BCHAR_HIP(hipGetLastError());
+      // slope = F . d  and  d . (rr; ss)
+      red.dot(Q.F, dmu, n, 0);
+      red.dot(Q.F + n, dnu, n, 1);
+      red.dot(Q.rr, dmu, n, 2);
+      red.dot(Q.ss, dnu, n, 3);
+      double hs[4];
+      BCHAR_HIP(hipMemcpyAsync(hs, red.out, sizeof(hs), hipMemcpyDeviceToHost, s));
+      BCHAR_HIP(hipStreamSynchronize(s));
+      const double slope = hs[0] + hs[1];
+      const double drs = hs[2] + hs[3];
+      if (!(slope < 0.0)) break;
+      double step = 1.0;
+      while (true) {
+        {
+          ::bchar::ProfScope ps_("k_dtheta_part", s);
+          k_dtheta_part<<<kRedBlocks, kT, 0, s>>>(Q.t, Q.dt, step, lo, hi, nnz, red.part);
+        }
+        {
+          ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+          k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 14);
+        }
+        const double dth = red.fetch(14) - step * drs;
+        if (dth <= 1e-4 * step * slope) break;
+        if (step == 1.0) {
+          // near the solution the dual function changes by less than its
+          // rounding; accept a full step that halves the residual
+          {
+            ::bchar::ProfScope ps_("k_residual", s);
+            k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, 1.0, lo, hi,
+                                         Q.rr, Q.ss, n, cq);
+          }
+          red.maxabs(cq, n2, 14);
+          if (red.fetch(14) < 0.5 * fn) break;
+        }
+        step *= 0.5;
+        if (step < 1e-12) break;
+      }
+      if (step < 1e-12) break;
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, step, nnz);
+      }
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gn, kT, 0, s>>>(mu_out, dmu, step, n);
+      }
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gn, kT, 0, s>>>(nu_out, dnu, step, n);
+      }
+      BCHAR_HIP(hipGetLastError());
+      red.maxabs(Q.t, nnz, 15);
+      if (!(red.fetch(15) <= 1e12)) break;
+    }
+    if (converged) break;
+  }
+  res.residual = fn;
+  if (!converged) {
+    res.level = level > max_level ? max_level : level;
+    return max_level == 0 ? BCHAR_E_QP_INFEASIBLE : BCHAR_E_QP_NOT_CONVERGED;
+  }
+  res.level = level;
+  const double lo = lo_levels[level], hi = hi_levels[level];
+  int32_t* counts = ws.get<int32_t>(2);
+  fill_i32(counts, 0, 2, s);
+  {
+    ::bchar::ProfScope ps_("k_final", s);
+    k_final<<<gz, kT, 0, s>>>(AN, Q.t, lo, hi, nnz, x_out, A_out, counts);
+  }
+  BCHAR_HIP(hipGetLastError());
+  int32_t hc[2];
+  BCHAR_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, s));
+  BCHAR_HIP(hipStreamSynchronize(s));
+  res.at_lower = hc[0];
+  res.at_upper = hc[1];
+  return BCHAR_OK;
+}
+
+}  // namespace bchar

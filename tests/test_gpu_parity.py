@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (BASELINE the benchmark spec): candidate pairs and the CSR pattern bit-exact
+on identical tracked centres; V within 1e-13 (relative to max |V|) in FP64;
+A^(N) within 1e-12; concentrations within 1e-10 relative (max norm) in
+FP64 and 1e-5 in the FP32-volume mode; mass conserved to 1e-12.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry as ogeo
+from oracle import qp as oqp
+from oracle import transfer as otr
+from paper_1908_05834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05834_amd import bchar
+    return torch, bchar
+
+
+def _case(name):
+    if name == "rot2d_subcell":
+        mesh = inputs.cartesian_mesh((16, 16))
+        return mesh, inputs.sample_velocity(mesh, inputs.rotation_stretch_2d), 0.8, "subcell"
+    if name == "solid_equal":
+        w = inputs.solid_body_32()
+        return w["mesh"], w["vel_fn"](0), w["dt"], "equal_measure"
+    if name == "solid_inscribed":
+        w = inputs.solid_body_32()
+        return w["mesh"], w["vel_fn"](0), w["dt"], "inscribed"
+    if name == "swirl3d_subcell_8":
+        w = inputs.swirl_hex(8)
+        return w["mesh"], w["vel_fn"](0), 0.05, "subcell"
+    if name == "swirl3d_subcell_16":
+        w = inputs.swirl_hex(16)
+        return w["mesh"], w["vel_fn"](3), 1.0 / 64.0, "subcell"
+    if name == "swirl3d_inscribed_12":
+        w = inputs.swirl_hex(12)
+        return w["mesh"], w["vel_fn"](0), 0.03, "inscribed"
+    if name == "porous2d_subcell":
+        mesh = inputs.cartesian_mesh((12, 12), phi=inputs.lognormal_phi(144, 5834))
+        return mesh, inputs.sample_velocity(mesh, inputs.rotation_stretch_2d), 0.6, "subcell"
+    if name == "porous3d_subcell":
+        w = inputs.porous_swirl_hex(8)
+        return w["mesh"], w["vel_fn"](0), 0.05, "subcell"
+    raise KeyError(name)
+
+
+GEOM_CASES = ["rot2d_subcell", "solid_equal", "solid_inscribed", "swirl3d_subcell_8",
+              "swirl3d_inscribed_12", "porous2d_subcell", "porous3d_subcell"]
+
+
+def _tracked_tensors(torch, T):
+    tr = np.ascontiguousarray(T["traced"].T)          # (dim, n_balls)
+    return (torch.as_tensor(tr, device="cuda"),
+            torch.as_tensor(np.ascontiguousarray(T["r_hat"]), device="cuda"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", GEOM_CASES)
+def test_pairs_pattern_and_v(env, name, precision):
+    torch, bchar = env
+    _say(f"[gpu] pairs/V {name} {precision}")
+    mesh, vel, dt, layout = _case(name)
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, precision=precision, stop_after="v")
+    M = bchar.Mesh(mesh, layout)
+    tr, rh = _tracked_tensors(torch, ref)
+    prec = bchar.FP64 if precision == "fp64" else bchar.FP32_VOLUME
+    T = bchar.Transfer.build_tracked(
+        M, tr, rh, bchar.opts_default(stop_after=bchar.STAGE_V, keep_pairs=1, precision=prec))
+    a, b = T.export_pairs()
+    ia, ib = ref["pairs"]
+    assert np.array_equal(a, ia) and np.array_equal(b, ib), "candidate pairs differ"
+    rp, col, V = T.export_csr(bchar.STAGE_V)
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(col, ref["col"])
+    err = np.max(np.abs(V - ref["V"])) / np.max(np.abs(ref["V"]))
+    _say(f"    V rel err {err:.3e}")
+    assert err <= (1e-13 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_16", "porous2d_subcell",
+                                  "porous3d_subcell"])
+def test_tracking(env, name):
+    torch, bchar = env
+    _say(f"[gpu] tracking {name}")
+    mesh, vel, dt, layout = _case(name)
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    C, r, _ = ogeo.ball_layout(mesh["n"], mesh["origin"], mesh["h"], layout)
+    want = ogeo.trace_points(C, mesh, vel, dt)
+    want_r = ogeo.tracked_radius(C, r, want, mesh, vel, dt)
+    porous = not np.all(mesh["phi"] == mesh["phi"][0])
+    # binary64 tracking repeats the oracle's operations one by one: equal
+    # bits.  Binary32 tracking is within its rounding, except on meshes
+    # with variable porosity, which the library tracks in binary64.
+    for prec, tol in ((bchar.FP64, 0.0), (bchar.FP32_VOLUME, 0.0 if porous else 2e-6)):
+        T = bchar.Transfer.build(M, U, dt, bchar.opts_default(stop_after=bchar.STAGE_V,
+                                                              precision=prec))
+        got, got_r = T.export_tracked()
+        e1, e2 = np.max(np.abs(got - want)), np.max(np.abs(got_r - want_r))
+        _say(f"    precision {prec}: centre err {e1:.3e}, radius err {e2:.3e}")
+        assert e1 <= tol and e2 <= tol
+
+
+@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_8", "solid_equal",
+                                  "porous3d_subcell"])
+def test_scaling(env, name):
+    torch, bchar = env
+    _say(f"[gpu] scaling {name}")
+    mesh, vel, dt, layout = _case(name)
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, stop_after="sinkhorn")
+    M = bchar.Mesh(mesh, layout)
+    tr, rh = _tracked_tensors(torch, ref)
+    T = bchar.Transfer.build_tracked(M, tr, rh, bchar.opts_default(stop_after=bchar.STAGE_SCALING))
+    _, _, AN = T.export_csr(bchar.STAGE_SCALING)
+    err = np.max(np.abs(AN - ref["AN"])) / np.max(np.abs(ref["AN"]))
+    _say(f"    A^(N) rel err {err:.3e}, col err {T.stats['scaling_max_col_err']:.3e}")
+    assert err <= 1e-12
+
+
+def _full(env, name, precision="fp64"):
+    torch, bchar = env
+    mesh, vel, dt, layout = _case(name)
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, precision=precision)
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    prec = bchar.FP64 if precision == "fp64" else bchar.FP32_VOLUME
+    T = bchar.Transfer.build(M, U, dt, bchar.opts_default(precision=prec))
+    return torch, bchar, mesh, ref, M, T
+
+
+@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_8", "swirl3d_subcell_16",
+                                  "solid_equal", "solid_inscribed", "porous2d_subcell",
+                                  "porous3d_subcell", "swirl3d_inscribed_12"])
+def test_full_step(env, name):
+    _say(f"[gpu] full step {name}")
+    torch, bchar, mesh, ref, M, T = _full(env, name)
+    st = T.stats
+    _say(f"    stats {st}; oracle level {ref['qp']['level']} it {ref['qp']['iterations']}")
+    assert st["qp_level"] == ref["qp"]["level"]
+    rp, col, A = T.export_csr(bchar.STAGE_ALL)
+    nc = rp.size - 1
+    c0 = inputs.uniform_c(mesh, 11)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], c0)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    # conservation and constants, on the GPU result alone
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    ones = torch.ones(nc, dtype=torch.float64, device="cuda")
+    T.step(ones, cout)
+    assert torch.max(torch.abs(cout - 1.0)).item() <= 1e-12
+    # KKT certificate of the GPU's QP solution
+    x, mu, nu = T.export_qp()
+    _, _, AN = T.export_csr(bchar.STAGE_SCALING)
+    rows = otr.csr_rows(rp)
+    lo, hi = oqp.BOX_LEVELS[st["qp_level"]]
+    chk = oqp.verify_kkt(rows, col, AN, ref["b"], ref["b"], x, mu, nu, lo, hi, ref["b"].max(),
+                         2e-13)
+    _say(f"    kkt {chk}")
+    assert chk["ok"]
+
+
+@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_16", "porous3d_subcell"])
+def test_full_step_fp32(env, name):
+    _say(f"[gpu] full step fp32 {name}")
+    torch, bchar, mesh, ref, M, T = _full(env, name, "fp32")
+    c0 = inputs.uniform_c(mesh, 12)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    # against the plain FP64 oracle (tracking in binary64)
+    ref64 = otr.build_transfer(mesh, *_case(name)[1:3], layout=_case(name)[3])
+    want = otr.apply(ref64["row_ptr"], ref64["col"], ref64["A"], ref64["b"], c0)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err vs fp64 oracle {err:.3e}")
+    assert err <= 1e-5
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+
+
+def test_solid_body_ten_steps(env):
+    """2D solid-body rotation, 32 x 32, equal-area disks, dt = 0.01, 10
+    steps with the transfer built once."""
+    torch, bchar = env
+    _say("[gpu] solid body 10 steps")
+    w = inputs.solid_body_32()
+    mesh, vel = w["mesh"], w["vel_fn"](0)
+    ref = otr.build_transfer(mesh, vel, w["dt"], layout="equal_measure")
+    M = bchar.Mesh(mesh, "equal_measure")
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), w["dt"])
+    c = torch.as_tensor(w["c0"], device="cuda")
+    nxt = torch.empty_like(c)
+    cref = w["c0"].copy()
+    m0 = M.mass(c)
+    for _ in range(w["steps"]):
+        T.step(c, nxt)
+        c, nxt = nxt, c
+        cref = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], cref)
+    err = np.max(np.abs(c.cpu().numpy() - cref)) / np.max(np.abs(cref))
+    _say(f"    c rel err after 10 steps {err:.3e}")
+    assert err <= 1e-10
+    assert abs(M.mass(c) - m0) <= 1e-12 * abs(m0)
