@@ -124,6 +124,11 @@ typedef struct {
   int qp_max_newton;     /* Newton iterations per box level, default 500   */
   int qp_max_cg;         /* CG iterations per Newton step, default 400     */
   int keep_pairs;        /* non-zero: keep the candidate pairs for export  */
+  int warm_start;        /* non-zero (default): a rebuild starts the least-
+                            change solve from the multipliers of the
+                            transfer's previous solve (same mesh); the
+                            solution is unique, only the iteration count
+                            changes; a failed warm start is retried cold */
 } bchar_opts;
 
 typedef struct {

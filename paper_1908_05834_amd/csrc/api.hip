@@ -145,10 +145,15 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   t->A.reserve(sizeof(double) * (nnz + 1));
   t->mu.reserve(sizeof(double) * n);
   t->nu.reserve(sizeof(double) * n);
+  if (t->zdual.bytes < sizeof(double) * 2 * n) {
+    t->zdual.reserve(sizeof(double) * 2 * n);
+    t->warm_level = -1;
+  }
   QpResult qr;
   rc = solve_qp(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->AN.as<double>(), nnz,
                 o, t->x.as<double>(), t->mu.as<double>(), t->nu.as<double>(), t->A.as<double>(),
-                qr, ws, s);
+                t->zdual.as<double>(), t->warm_level, qr, ws, s);
+  t->warm_level = rc == BCHAR_OK ? qr.level : -1;
   if (tr)
     fprintf(stderr, "[bchar] qp: %.3f ms (level %d, newton %d, cg %d, residual %.3e)\n",
             1e3 * (wall_seconds() - t0), qr.level, qr.newton, qr.cg, qr.residual);
@@ -206,6 +211,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->qp_max_newton = 500;
   o->qp_max_cg = 400;
   o->keep_pairs = 0;
+  o->warm_start = 1;
 }
 
 const char* bchar_status_string(bchar_status s) {
@@ -349,6 +355,7 @@ static void transfer_free(bchar_transfer t) {
   t->x.release();
   t->mu.release();
   t->nu.release();
+  t->zdual.release();
   t->tracked.release();
   t->r_hat.release();
   t->pair_a.release();

@@ -110,6 +110,8 @@ struct bchar_transfer_s {
   bchar::DBuf A;         // fp64 nnz, final
   bchar::DBuf x;         // fp64 nnz
   bchar::DBuf mu, nu;    // fp64 n_cells
+  bchar::DBuf zdual;     // fp64 2 n_cells: per-cell multipliers of the last solve
+  int warm_level = -1;   // box level of the last converged solve
   bchar::DBuf tracked;   // fp64 dim * n_balls
   bchar::DBuf r_hat;     // fp64 n_balls
   bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs)
@@ -171,10 +173,12 @@ struct QpResult {
   double residual = 0;
   int64_t at_lower = 0, at_upper = 0;
 };
+// zdual: per-cell multipliers (s, g), 2 n values kept by the transfer;
+// warm_level: box level of the previous converged solve, or -1.
 bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
                       const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
-                      double* x, double* mu, double* nu, double* A, QpResult& res, Arena& ws,
-                      hipStream_t s);
+                      double* x, double* mu, double* nu, double* A, double* zdual,
+                      int warm_level, QpResult& res, Arena& ws, hipStream_t s);
 
 // apply / mass (apply.hip)
 void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s);

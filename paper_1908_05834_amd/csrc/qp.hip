@@ -40,7 +40,7 @@ namespace bchar {
 
 constexpr int kT = 256;   // threads per block for vector kernels
 constexpr int kRedBlocks = 512;
-constexpr int kMaxCoarse = 256;    // dense coarsest solve
+constexpr int kMaxCoarse = 512;    // dense coarsest solve
 constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
 
 // ====================================================================== reductions
@@ -159,7 +159,7 @@ struct Level {
   double* sdinv = nullptr;     // n: smoother step (omega / d)
   double omega = 1.0;
   bool l1 = true;              // smoother diagonal = diag + sum w (l1-Jacobi)
-  double tau = 0.0;
+  int32_t* cnt = nullptr;      // fine nodes merged into each node (null on level 0)
   // aggregation towards the next level
   int32_t* agg = nullptr;      // n
   int32_t* mptr = nullptr;     // next.n + 1
@@ -170,19 +170,58 @@ struct Level {
   double *b = nullptr, *x = nullptr, *x2 = nullptr, *r = nullptr;
 };
 
+// Levels small enough for one workgroup run in a single launch
+// (k_fused_cycle): their descriptions live in device memory.
+constexpr int kFusedMaxNodes = 8192;
+constexpr int kFusedMaxLevels = 48;
+
+struct FusedLevels {
+  int count;                          // fused levels, the last is the coarsest
+  int dense;                          // coarsest solved with the inverse G
+  int pre, post, coarse_sweeps;
+  int n[kFusedMaxLevels];
+  const int32_t* ptr[kFusedMaxLevels];
+  const int32_t* nbr[kFusedMaxLevels];
+  const double* w[kFusedMaxLevels];
+  const double* diag[kFusedMaxLevels];
+  const double* sdinv[kFusedMaxLevels];
+  const int32_t* agg[kFusedMaxLevels];
+  const int32_t* mptr[kFusedMaxLevels];
+  const int32_t* mem[kFusedMaxLevels];
+  double* b[kFusedMaxLevels];
+  double* x[kFusedMaxLevels];
+  double* x2[kFusedMaxLevels];
+  const double* G;
+};
+
 // ---------------------------------------------------------------------- level kernels
 
+// diag = sum w + mu * cnt (cnt: fine nodes of the bipartite graph merged
+// into the node, so that a shift mu I of the finest operator is carried
+// to every level exactly); sdinv = omega / (smoother diagonal)
 __global__ void k_level_diag(const int32_t* __restrict__ ptr, const double* __restrict__ w,
-                             int64_t n, double tau, double omega, int l1,
-                             double* __restrict__ diag, double* __restrict__ sdinv) {
+                             const int32_t* __restrict__ cnt, int64_t n, double mu,
+                             double omega, int l1, double* __restrict__ diag,
+                             double* __restrict__ sdinv) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double s = 0;
   for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s += w[e];
-  const double d = s + tau;
+  const double d = s + (cnt ? mu * (double)cnt[p] : 0.0);
   diag[p] = d;
   const double sd = l1 ? d + s : d;
   sdinv[p] = sd > 0 ? omega / sd : 0.0;
+}
+
+// fine-node count of each coarse node
+__global__ void k_node_count(const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                             const int32_t* __restrict__ fcnt, int64_t nc,
+                             int32_t* __restrict__ cnt) {
+  const int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= nc) return;
+  int32_t c = 0;
+  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) c += fcnt ? fcnt[mem[m]] : 1;
+  cnt[C] = c;
 }
 
 // y = L x  (L = diag - W)
@@ -407,135 +446,240 @@ __global__ void k_accept(const int32_t* __restrict__ prop, int64_t n,
   if (q >= 0 && prop[q] == (int32_t)p) partner[p] = q;
 }
 
-__global__ void k_rep_flag(const int32_t* __restrict__ partner, int64_t n,
+// An unmatched node joins the aggregate of its strongest matched
+// neighbour when that coupling is strong for it (>= beta of its strongest).
+__global__ void k_join(const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
+                       const double* __restrict__ w, const double* __restrict__ mx,
+                       const int32_t* __restrict__ partner, double beta, int64_t n,
+                       int32_t* __restrict__ target) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t best = -1;
+  if (partner[p] < 0) {
+    double bw = 0;
+    for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) {
+      const int32_t q = nbr[e];
+      if (q == p || partner[q] < 0) continue;
+      const double v = w[e];
+      if (!(v > 0) || v < beta * mx[p]) continue;
+      if (v > bw || (v == bw && q < best)) {
+        bw = v;
+        best = q;
+      }
+    }
+  }
+  target[p] = best;
+}
+
+// representative of the aggregate of p: the smaller node of its pair, the
+// pair it joined, or itself
+__device__ __forceinline__ int32_t agg_rep(const int32_t* partner, const int32_t* target,
+                                           int32_t p) {
+  int32_t q = partner[p];
+  if (q >= 0) return p < q ? p : q;
+  const int32_t t = target[p];
+  if (t >= 0) {
+    q = partner[t];
+    return t < q ? t : q;
+  }
+  return p;
+}
+
+__global__ void k_rep_flag(const int32_t* __restrict__ partner,
+                           const int32_t* __restrict__ target, int64_t n,
                            int32_t* __restrict__ flag) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int32_t q = partner[p];
-  flag[p] = (q < 0 || (int32_t)p < q) ? 1 : 0;
+  flag[p] = agg_rep(partner, target, (int32_t)p) == (int32_t)p ? 1 : 0;
 }
 
-__global__ void k_pair_agg(const int32_t* __restrict__ partner, const int32_t* __restrict__ cid,
+__global__ void k_pair_agg(const int32_t* __restrict__ partner,
+                           const int32_t* __restrict__ target, const int32_t* __restrict__ cid,
                            int64_t n, int32_t* __restrict__ agg) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int32_t q = partner[p];
-  const int32_t rep = (q < 0 || (int32_t)p < q) ? (int32_t)p : q;
-  agg[p] = cid[rep];
-}
-
-__global__ void k_member_count(const int32_t* __restrict__ partner,
-                               const int32_t* __restrict__ cid, int64_t n,
-                               int32_t* __restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int32_t q = partner[p];
-  if (q < 0 || (int32_t)p < q) cnt[cid[p]] = q < 0 ? 1 : 2;
-}
-
-__global__ void k_member_fill(const int32_t* __restrict__ partner,
-                              const int32_t* __restrict__ cid, int64_t n,
-                              const int32_t* __restrict__ mptr, int32_t* __restrict__ mem) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int32_t q = partner[p];
-  if (q < 0 || (int32_t)p < q) {
-    const int32_t C = cid[p];
-    mem[mptr[C]] = (int32_t)p;
-    if (q >= 0) mem[mptr[C] + 1] = q;
-  }
+  agg[p] = cid[agg_rep(partner, target, (int32_t)p)];
 }
 
 // ---------------------------------------------------------------------- coarsest
 
-// Dense matrix of the coarsest level plus a relative shift, factorised in
-// place by one workgroup (Cholesky, lower triangle, row-major).
-__global__ void __launch_bounds__(256) k_coarse_factor(const int32_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ nbr,
-                                                       const double* __restrict__ w,
-                                                       const double* __restrict__ diag, int n,
-                                                       double* __restrict__ G) {
+// Inverse of the coarsest matrix plus a relative shift, by Gauss-Jordan
+// elimination in place (the matrix is symmetric positive definite, so no
+// pivoting), one workgroup.
+__global__ void __launch_bounds__(1024) k_coarse_inverse(const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ diag,
+                                                         int n, double* __restrict__ G) {
+  __shared__ double f[kMaxCoarse];
+  __shared__ double s_piv;
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += blockDim.x) G[e] = 0.0;
+  const int nt = blockDim.x;
+  for (int e = tid; e < n * n; e += nt) G[e] = 0.0;
   __syncthreads();
-  __shared__ double s_dmax;
   if (tid == 0) {
     double m = 0;
     for (int p = 0; p < n; ++p) m = fmax(m, diag[p]);
-    s_dmax = m > 0 ? m : 1.0;
+    s_piv = m > 0 ? m : 1.0;
   }
   __syncthreads();
-  for (int p = tid; p < n; p += blockDim.x) {
-    G[p * n + p] = diag[p] + 1e-12 * s_dmax;
+  const double shift = 1e-12 * s_piv;
+  for (int p = tid; p < n; p += nt) {
+    G[p * n + p] = diag[p] + shift;
     for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) G[p * n + nbr[e]] -= w[e];
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      double d = G[k * n + k];
-      G[k * n + k] = d > 0 ? sqrt(d) : 1e-300;
-    }
+    if (tid == 0) s_piv = G[k * n + k];
+    for (int i = tid; i < n; i += nt) f[i] = G[i * n + k];
     __syncthreads();
-    const double dk = G[k * n + k];
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) G[i * n + k] /= dk;
+    const double piv = s_piv;
+    for (int j = tid; j < n; j += nt) G[k * n + j] = (j == k ? 1.0 : G[k * n + j]) / piv;
     __syncthreads();
-    for (int e = tid; e < (n - k - 1) * (n - k - 1); e += blockDim.x) {
-      const int i = k + 1 + e / (n - k - 1);
-      const int j = k + 1 + e % (n - k - 1);
-      if (j <= i) G[i * n + j] -= G[i * n + k] * G[j * n + k];
+    for (int e = tid; e < n * n; e += nt) {
+      const int i = e / n, j = e % n;
+      if (i == k) continue;
+      G[e] = (j == k ? 0.0 : G[e]) - f[i] * G[k * n + j];
     }
     __syncthreads();
   }
 }
 
-// x = (G G^T)^-1 b, then the mean is removed (the constant vector spans
-// the null space of a connected graph Laplacian).
-__global__ void __launch_bounds__(256) k_coarse_solve(const double* __restrict__ G,
-                                                      const double* __restrict__ b, int n,
-                                                      double* __restrict__ x) {
-  __shared__ double y[kMaxCoarse];
+__device__ __forceinline__ double block_sum_1024(double v, double* red) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double r = 0;
+  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// (b - L x)[p] for one node
+__device__ __forceinline__ double lap_resid(const int32_t* ptr, const int32_t* nbr,
+                                            const double* w, const double* diag, const double* b,
+                                            const double* x, int p) {
+  double s = diag[p] * x[p];
+  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
+  return b[p] - s;
+}
+
+// The V-cycle below and including the first fused level, in one workgroup.
+// On entry F->b[0] holds that level's right-hand side; on exit F->x[0]
+// holds the cycle's result.  Every dependent phase is separated by a
+// workgroup barrier.
+__global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
   const int tid = threadIdx.x;
-  double sb = 0;
-  for (int i = tid; i < n; i += blockDim.x) sb += b[i];
-  sb = block_sum(sb, red);
-  const double bmean = sb / n;
-  for (int i = tid; i < n; i += blockDim.x) y[i] = b[i] - bmean;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) y[k] /= G[k * n + k];
+  const int nt = blockDim.x;
+  const int L = F->count;
+  double* cur[kFusedMaxLevels];
+  double* oth[kFusedMaxLevels];
+  for (int l = 0; l < L; ++l) {
+    cur[l] = F->x[l];
+    oth[l] = F->x2[l];
+  }
+  // downward: pre-smoothing and restriction of the residual
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = F->n[l];
+    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
+    const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
+    for (int p = tid; p < n; p += nt) cur[l][p] = sd[p] * b[p];
     __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) y[i] -= G[i * n + k] * y[k];
+    for (int k = 1; k < F->pre; ++k) {
+      for (int p = tid; p < n; p += nt)
+        oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
+      __syncthreads();
+      double* t = cur[l];
+      cur[l] = oth[l];
+      oth[l] = t;
+    }
+    const int nc = F->n[l + 1];
+    for (int C = tid; C < nc; C += nt) {
+      double acc = 0;
+      for (int32_t m = F->mptr[l][C]; m < F->mptr[l][C + 1]; ++m)
+        acc += lap_resid(ptr, nbr, w, dg, b, cur[l], F->mem[l][m]);
+      F->b[l + 1][C] = acc;
+    }
     __syncthreads();
   }
-  for (int k = n - 1; k >= 0; --k) {
-    if (tid == 0) y[k] /= G[k * n + k];
-    __syncthreads();
-    for (int i = tid; i < k; i += blockDim.x) y[i] -= G[k * n + i] * y[k];
-    __syncthreads();
+  // coarsest
+  {
+    const int l = L - 1;
+    const int n = F->n[l];
+    const double* b = F->b[l];
+    if (F->dense) {
+      double sb = 0;
+      for (int p = tid; p < n; p += nt) sb += b[p];
+      const double bmean = block_sum_1024(sb, red) / n;
+      double sx = 0;
+      for (int i = tid; i < n; i += nt) {
+        double acc = 0;
+        for (int j = 0; j < n; ++j) acc += F->G[i * n + j] * (b[j] - bmean);
+        cur[l][i] = acc;
+        sx += acc;
+      }
+      const double xmean = block_sum_1024(sx, red) / n;
+      for (int i = tid; i < n; i += nt) cur[l][i] -= xmean;
+      __syncthreads();
+    } else {
+      const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
+      const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l];
+      for (int p = tid; p < n; p += nt) cur[l][p] = sd[p] * b[p];
+      __syncthreads();
+      for (int k = 1; k < F->coarse_sweeps; ++k) {
+        for (int p = tid; p < n; p += nt)
+          oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
+        __syncthreads();
+        double* t = cur[l];
+        cur[l] = oth[l];
+        oth[l] = t;
+      }
+    }
   }
-  double s = 0;
-  for (int i = tid; i < n; i += blockDim.x) s += y[i];
-  s = block_sum(s, red);
-  const double mean = s / n;
-  for (int i = tid; i < n; i += blockDim.x) x[i] = y[i] - mean;
+  // upward: prolongation and post-smoothing
+  for (int l = L - 2; l >= 0; --l) {
+    const int n = F->n[l];
+    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l], *agg = F->agg[l];
+    const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
+    const double* e = cur[l + 1];
+    for (int p = tid; p < n; p += nt) cur[l][p] += e[agg[p]];
+    __syncthreads();
+    for (int k = 0; k < F->post; ++k) {
+      for (int p = tid; p < n; p += nt)
+        oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
+      __syncthreads();
+      double* t = cur[l];
+      cur[l] = oth[l];
+      oth[l] = t;
+    }
+  }
+  if (cur[0] != F->x[0]) {
+    for (int p = tid; p < F->n[0]; p += nt) F->x[0][p] = cur[0][p];
+  }
 }
 
 // ====================================================================== hierarchy
 
 struct Hierarchy {
   std::vector<Level> lv;
-  double* G = nullptr;   // coarsest factor
+  double mu = 0.0;       // shift mu I of the bipartite operator (all levels)
+  double* G = nullptr;   // inverse of the shifted coarsest matrix
   int coarse_n = 0;
   bool dense = false;
   int fine_pre = 2, fine_post = 2, pre = 2, post = 2;
   int coarse_sweeps = 40;
+  size_t fused_first = 0;          // first level handled by k_fused_cycle
+  FusedLevels* fused = nullptr;    // device copy
 };
 
-static void level_refresh_diag(Level& L, hipStream_t s) {
+static void level_refresh_diag(Level& L, double mu, hipStream_t s) {
   {
     ::bchar::ProfScope ps_("k_level_diag", s);
-    k_level_diag<<<blocks_for(L.n, kT), kT, 0, s>>>(L.ptr, L.w, L.n, L.tau, L.omega, L.l1 ? 1 : 0,
+    k_level_diag<<<blocks_for(L.n, kT), kT, 0, s>>>(L.ptr, L.w, L.cnt, L.n, mu, L.omega, L.l1 ? 1 : 0,
                                                     L.diag, L.sdinv);
   }
   BCHAR_HIP(hipGetLastError());
@@ -586,6 +730,11 @@ static Level galerkin_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
     ::bchar::ProfScope ps_("k_coarse_values", s);
     k_coarse_values<<<blocks_for(Cl.ne, kT), kT, 0, s>>>(L.cptr, L.cedge, L.w0, Cl.ne, Cl.w0);
   }
+  Cl.cnt = ws.get<int32_t>(nc + 1);
+  {
+    ::bchar::ProfScope ps_("k_node_count", s);
+    k_node_count<<<blocks_for(nc, kT), kT, 0, s>>>(L.mptr, L.mem, L.cnt, nc, Cl.cnt);
+  }
   BCHAR_HIP(hipGetLastError());
   return Cl;
 }
@@ -625,7 +774,7 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     H.lv.push_back(C);
   }
   double beta = 0.25;
-  while (H.lv.back().n > 64) {
+  while (H.lv.back().n > 128) {
     Level& L = H.lv.back();
     const int64_t nl = L.n;
     double* mx = ws.get<double>(nl + 1);
@@ -648,32 +797,28 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
       }
     }
     BCHAR_HIP(hipGetLastError());
+    int32_t* target = ws.get<int32_t>(nl + 1);
+    {
+      ::bchar::ProfScope ps_("k_join", s);
+      k_join<<<blocks_for(nl, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w0, mx, partner, beta, nl, target);
+    }
     int32_t* flag = ws.get<int32_t>(nl + 1);
     int32_t* cid = ws.get<int32_t>(nl + 1);
     {
       ::bchar::ProfScope ps_("k_rep_flag", s);
-      k_rep_flag<<<blocks_for(nl, kT), kT, 0, s>>>(partner, nl, flag);
+      k_rep_flag<<<blocks_for(nl, kT), kT, 0, s>>>(partner, target, nl, flag);
     }
     const int64_t nc = exclusive_scan_i32(flag, cid, nl, ws, s);
-    if ((double)nc > 0.95 * (double)nl) break;   // nothing left to pair
-    if ((double)nc > 0.8 * (double)nl) beta = 0.0;
+    if ((double)nc > 0.97 * (double)nl) break;   // nothing left to aggregate
+    if ((double)nc > 0.75 * (double)nl) beta = 0.0;
     L.agg = ws.get<int32_t>(nl + 1);
     {
       ::bchar::ProfScope ps_("k_pair_agg", s);
-      k_pair_agg<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, L.agg);
-    }
-    int32_t* mcnt = ws.get<int32_t>(nc + 1);
-    {
-      ::bchar::ProfScope ps_("k_member_count", s);
-      k_member_count<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, mcnt);
+      k_pair_agg<<<blocks_for(nl, kT), kT, 0, s>>>(partner, target, cid, nl, L.agg);
     }
     L.mptr = ws.get<int32_t>(nc + 1);
-    exclusive_scan_i32_async(mcnt, L.mptr, nc, ws, s);
     L.mem = ws.get<int32_t>(nl + 1);
-    {
-      ::bchar::ProfScope ps_("k_member_fill", s);
-      k_member_fill<<<blocks_for(nl, kT), kT, 0, s>>>(partner, cid, nl, L.mptr, L.mem);
-    }
+    bucket_sort(L.agg, nl, nc, L.mptr, L.mem, ws, s);
     BCHAR_HIP(hipGetLastError());
     Level C = galerkin_pattern(L, nc, ws, s);
     C.omega = 1.0;
@@ -685,6 +830,38 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   H.coarse_n = (int)last.n;
   H.dense = last.n <= kMaxCoarse;
   if (H.dense) H.G = ws.get<double>((size_t)last.n * last.n + 1);
+  // the cell levels from the first one with at most kFusedMaxNodes nodes
+  // down to the coarsest run in one workgroup
+  size_t first = H.lv.size() - 1;
+  while (first > 1 && H.lv[first - 1].n <= kFusedMaxNodes &&
+         H.lv.size() - (first - 1) <= (size_t)kFusedMaxLevels)
+    --first;
+  H.fused_first = first;
+  FusedLevels hf{};
+  hf.count = (int)(H.lv.size() - first);
+  hf.dense = H.dense ? 1 : 0;
+  hf.pre = H.pre;
+  hf.post = H.post;
+  hf.coarse_sweeps = H.coarse_sweeps;
+  hf.G = H.G;
+  for (int k = 0; k < hf.count; ++k) {
+    Level& Lk = H.lv[first + k];
+    hf.n[k] = (int)Lk.n;
+    hf.ptr[k] = Lk.ptr;
+    hf.nbr[k] = Lk.nbr;
+    hf.w[k] = Lk.w;
+    hf.diag[k] = Lk.diag;
+    hf.sdinv[k] = Lk.sdinv;
+    hf.agg[k] = Lk.agg;
+    hf.mptr[k] = Lk.mptr;
+    hf.mem[k] = Lk.mem;
+    hf.b[k] = Lk.b;
+    hf.x[k] = Lk.x;
+    hf.x2[k] = Lk.x2;
+  }
+  H.fused = ws.get<FusedLevels>(1);
+  BCHAR_HIP(hipMemcpyAsync(H.fused, &hf, sizeof(hf), hipMemcpyHostToDevice, s));
+  BCHAR_HIP(hipStreamSynchronize(s));
 }
 
 // New weights on every level (fine weights already in lv[0].w).
@@ -699,13 +876,13 @@ static void refresh_hierarchy(Hierarchy& H, hipStream_t s) {
       }
       BCHAR_HIP(hipGetLastError());
     }
-    level_refresh_diag(L, s);
+    level_refresh_diag(L, H.mu, s);
   }
   if (H.dense) {
     Level& L = H.lv.back();
     {
-      ::bchar::ProfScope ps_("k_coarse_factor", s);
-      k_coarse_factor<<<1, 256, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, (int)L.n, H.G);
+      ::bchar::ProfScope ps_("k_coarse_inverse", s);
+      k_coarse_inverse<<<1, 1024, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, (int)L.n, H.G);
     }
     BCHAR_HIP(hipGetLastError());
   }
@@ -734,18 +911,13 @@ static void smooth_steps(Level& L, const double* b, double*& x, double*& x2, int
 // x_l = cycle(b_l); on return H.lv[l].x holds the result.
 static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   Level& L = H.lv[l];
-  if (l + 1 == H.lv.size()) {
-    if (H.dense) {
-      {
-        ::bchar::ProfScope ps_("k_coarse_solve", s);
-        k_coarse_solve<<<1, 256, 0, s>>>(H.G, L.b, (int)L.n, L.x);
-      }
-    } else {
-      double* x = L.x;
-      double* x2 = L.x2;
-      smooth_steps(L, L.b, x, x2, H.coarse_sweeps, true, s);
-      if (x != L.x) std::swap(L.x, L.x2);
+  if (l >= H.fused_first) {
+    // this level and all coarser ones: one workgroup, one launch
+    {
+      ::bchar::ProfScope ps_("k_fused_cycle", s);
+      k_fused_cycle<<<1, 1024, 0, s>>>(H.fused);
     }
+    BCHAR_HIP(hipGetLastError());
     return;
   }
   Level& C = H.lv[l + 1];
@@ -808,7 +980,7 @@ __global__ void k_diag_pos(const int32_t* __restrict__ rptr, const int32_t* __re
 }
 
 // per-cell block [[A, B], [B, C]] of J_z (+ shifts) and its inverse
-__global__ void k_zcells(ZCells Z, double rel) {
+__global__ void k_zcells(ZCells Z, double rel, double mu) {
   const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= Z.n) return;
   double R = 0, Cs = 0;
@@ -819,8 +991,10 @@ __global__ void k_zcells(ZCells Z, double rel) {
   const double wkk = Z.dpos[K] >= 0 ? Z.w[Z.dpos[K]] : 0.0;
   const double A0 = R + Cs;
   const double C0 = wkk + 0.25 * (R + Cs);
-  const double ts = rel * (A0 > 0 ? A0 : 1.0);
-  const double tg = rel * (C0 > 0 ? C0 : 1.0);
+  // a relative shift for the exactly singular directions, plus mu I of
+  // the (mu, -nu) operator, which reads 2 mu on s and mu / 2 on g
+  const double ts = rel * (A0 > 0 ? A0 : 1.0) + 2.0 * mu;
+  const double tg = rel * (C0 > 0 ? C0 : 1.0) + 0.5 * mu;
   Z.tau_s[K] = ts;
   Z.tau_g[K] = tg;
   const double A = A0 + ts, C = C0 + tg, B = 0.5 * (R - Cs);
@@ -1025,43 +1199,79 @@ __device__ __forceinline__ double clipv(double v, double lo, double hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// F = [sum_row a clip(t + step dt) - rr ; sum_col ... - ss]
+// Smoothed clip.  max(0, u) is replaced by the Chen-Harker-Kanzow-Smale
+// function p(u) = (u + sqrt(u^2 + 4 eps^2)) / 2, so that
+//   clip_eps(t) = lo + p(t - lo) - p(t - hi) = hi - p(hi - t) + p(lo - t),
+// strictly increasing for eps > 0 and equal to clip for eps = 0.  p and p'
+// are evaluated without cancellation (for u < 0, p = 2 eps^2 / (s - u) and
+// p' = 2 eps^2 / (s (s - u))), and the form used on each half of the box
+// keeps the far bound's term tiny, so that an entry far outside the box
+// gets its bound to the last bit.
+__device__ __forceinline__ double smax0(double u, double eps) {
+  const double e2 = 2.0 * eps * eps;
+  const double s = sqrt(u * u + 2.0 * e2);
+  return u >= 0.0 ? 0.5 * (u + s) : e2 / (s - u);
+}
+__device__ __forceinline__ double dsmax0(double u, double eps) {
+  const double e2 = 2.0 * eps * eps;
+  const double s = sqrt(u * u + 2.0 * e2);
+  return u >= 0.0 ? 0.5 * (1.0 + u / s) : e2 / (s * (s - u));
+}
+__device__ __forceinline__ double clip_s(double t, double lo, double hi, double eps) {
+  if (eps == 0.0) return clipv(t, lo, hi);
+  const bool bl = !isinf(lo), bh = !isinf(hi);
+  if (!bl && !bh) return t;
+  if (!bh) return lo + smax0(t - lo, eps);
+  if (!bl) return hi - smax0(hi - t, eps);
+  return t <= 0.5 * (lo + hi) ? lo + smax0(t - lo, eps) - smax0(t - hi, eps)
+                              : hi - smax0(hi - t, eps) + smax0(lo - t, eps);
+}
+// derivative of clip_s in t (for eps = 0: 1 strictly inside the box, else 0)
+__device__ __forceinline__ double dclip_s(double t, double lo, double hi, double eps) {
+  if (eps == 0.0) return (t > lo && t < hi) ? 1.0 : 0.0;
+  const bool bl = !isinf(lo), bh = !isinf(hi);
+  if (!bl && !bh) return 1.0;
+  if (!bh) return dsmax0(t - lo, eps);
+  if (!bl) return dsmax0(hi - t, eps);
+  return t <= 0.5 * (lo + hi) ? dsmax0(t - lo, eps) - dsmax0(t - hi, eps)
+                              : dsmax0(hi - t, eps) - dsmax0(lo - t, eps);
+}
+
+// F = [sum_row a clip_eps(t + step dt) - rr ; sum_col ... - ss]
 __global__ void k_residual(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
                            const int32_t* __restrict__ cpos, const double* __restrict__ a,
                            const double* __restrict__ ac, const double* __restrict__ t,
                            const double* __restrict__ dt, double step, double lo, double hi,
-                           const double* __restrict__ rr, const double* __restrict__ ss,
-                           int64_t n, double* __restrict__ F) {
+                           double eps, const double* __restrict__ rr,
+                           const double* __restrict__ ss, int64_t n, double* __restrict__ F) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   CSum r, c;
   r.add(-rr[i]);
   for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
     const double tk = dt ? t[k] + step * dt[k] : t[k];
-    r.add(a[k] * clipv(tk, lo, hi));
+    r.add(a[k] * clip_s(tk, lo, hi, eps));
   }
   c.add(-ss[i]);
   for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
     const int32_t k = cpos[e];
     const double tk = dt ? t[k] + step * dt[k] : t[k];
-    c.add(ac[e] * clipv(tk, lo, hi));
+    c.add(ac[e] * clip_s(tk, lo, hi, eps));
   }
   F[i] = r.value();
   F[n + i] = c.value();
 }
 
-// fine bipartite weights a_k^2 * free_k in graph order: row part is CSR
-// order, column part is CSC order
+// fine bipartite weights a_k^2 clip_eps'(t_k) in graph order: row part is
+// CSR order, column part is CSC order
 __global__ void k_fine_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
-                               const double* __restrict__ t, double lo, double hi, int64_t nnz,
-                               double* __restrict__ w) {
+                               const double* __restrict__ t, double lo, double hi, double eps,
+                               int64_t nnz, double* __restrict__ w) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  const double tk = t[k];
-  w[k] = (tk > lo && tk < hi) ? a[k] * a[k] : 0.0;
+  w[k] = (a[k] * a[k]) * dclip_s(t[k], lo, hi, eps);
   const int32_t kp = cpos[k];
-  const double tp = t[kp];
-  w[nnz + k] = (tp > lo && tp < hi) ? a[kp] * a[kp] : 0.0;
+  w[nnz + k] = (a[kp] * a[kp]) * dclip_s(t[kp], lo, hi, eps);
 }
 
 __global__ void k_fine_graph(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
@@ -1138,31 +1348,71 @@ __global__ void k_zdual_dir(const int32_t* __restrict__ rptr, const int32_t* __r
   }
 }
 
-// psi(t + d) - psi(t), psi the primitive of clip(., lo, hi) vanishing at 0
-__device__ __forceinline__ double dpsi(double t, double d, double lo, double hi) {
-  const double u = t + d;
-  const double c1 = clipv(t, lo, hi);
-  const double c2 = clipv(u, lo, hi);
-  const bool f1 = c1 == t, f2 = c2 == u;
-  if (f1 && f2) return d * (t + 0.5 * d);
-  if (!f1 && !f2 && c1 == c2) return c1 * d;
-  return 0.5 * (c2 * c2 - c1 * c1) + (f2 ? 0.0 : c2 * (u - c2)) - (f1 ? 0.0 : c1 * (t - c1));
-}
-
-__global__ void __launch_bounds__(kT) k_dtheta_part(const double* __restrict__ t,
-                                                    const double* __restrict__ dt, double step,
-                                                    double lo, double hi, int64_t nnz,
-                                                    double* __restrict__ part) {
+// derivative of the dual function along the direction, at y + step d:
+// sum over cells of dmu_i F_i + dnu_i G_i with the row and column residuals
+// F_i, G_i of t + step dt formed cell by cell (each is small near the
+// solution, so the sum does not cancel the large terms of sum_k x_k dt_k
+// against d . (r; s))
+__global__ void __launch_bounds__(kT) k_dphi_part(
+    const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
+    const int32_t* __restrict__ cpos, const double* __restrict__ a,
+    const double* __restrict__ ac, const double* __restrict__ t, const double* __restrict__ dt,
+    double step, double lo, double hi, double eps, const double* __restrict__ rr,
+    const double* __restrict__ ss, const double* __restrict__ dmu,
+    const double* __restrict__ dnu, int64_t n, double* __restrict__ part) {
   __shared__ double sh[32];
   CSum acc;
-  for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < nnz;
-       k += (int64_t)gridDim.x * kT)
-    acc.add(dpsi(t[k], step * dt[k], lo, hi));
-  CSum r = block_csum(acc, sh);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = r.hi;
-    part[2 * blockIdx.x + 1] = r.lo;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kT) {
+    CSum r, c;
+    r.add(-rr[i]);
+    for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k)
+      r.add(a[k] * clip_s(t[k] + step * dt[k], lo, hi, eps));
+    c.add(-ss[i]);
+    for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
+      const int32_t k = cpos[e];
+      c.add(ac[e] * clip_s(t[k] + step * dt[k], lo, hi, eps));
+    }
+    acc.add(dmu[i] * r.value());
+    acc.add(dnu[i] * c.value());
   }
+  CSum tot = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = tot.hi;
+    part[2 * blockIdx.x + 1] = tot.lo;
+  }
+}
+
+// t_k from per-cell multipliers z = (s, g): a_k g_K on the diagonal entry
+// of cell K, a_k ((s_K - s_M) + (g_K + g_M) / 2) elsewhere
+__global__ void k_t_from_z(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ a, const double* __restrict__ z, int64_t n,
+                           double* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double si = z[i], gi = z[n + i];
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    const int32_t j = col[k];
+    t[k] = a[k] * (j == (int32_t)i ? gi : (si - z[j]) + 0.5 * (gi + z[n + j]));
+  }
+}
+
+// z += step * (solution with the mean of its s part removed)
+__global__ void k_zdual_acc(const double* __restrict__ sol, const double* __restrict__ ssum,
+                            double inv_n, double step, int64_t n, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  z[i] += step * (sol[i] - ssum[0] * inv_n);
+  z[n + i] += step * sol[n + i];
+}
+
+// mu = s + g/2, nu = -(s - g/2)
+__global__ void k_mu_nu(const double* __restrict__ z, int64_t n, double* __restrict__ mu,
+                        double* __restrict__ nu) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  mu[i] = z[i] + 0.5 * z[n + i];
+  nu[i] = -(z[i] - 0.5 * z[n + i]);
 }
 
 __global__ void k_axpy2(double* __restrict__ y, const double* __restrict__ x, double s,
@@ -1188,7 +1438,7 @@ __global__ void k_final(const double* __restrict__ an, const double* __restrict_
 bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
                       const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
                       double* x_out, double* mu_out, double* nu_out, double* A_out,
-                      QpResult& res, Arena& ws, hipStream_t s) {
+                      double* zdual, int warm_level, QpResult& res, Arena& ws, hipStream_t s) {
   const int64_t n = m->n_cells;
   const int64_t n2 = 2 * n;
   const double scale = m->bmax;
@@ -1244,9 +1494,20 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   fill_f64(Q.t, 0.0, nnz, s);
   {
     ::bchar::ProfScope ps_("k_fine_weights", s);
-    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, nnz, fine.w0);
+    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, 0.0, nnz, fine.w0);
   }
   BCHAR_HIP(hipGetLastError());
+  double dmax = 0;
+  {
+    double* dtmp = ws.get<double>(n2);
+    double* stmp = ws.get<double>(n2);
+    {
+      ::bchar::ProfScope ps_("k_level_diag", s);
+      k_level_diag<<<gn2, kT, 0, s>>>(fine.ptr, fine.w0, nullptr, n2, 0.0, 1.0, 0, dtmp, stmp);
+    }
+    red.maxabs(dtmp, n2, 0);
+    dmax = red.fetch(0);
+  }
   Hierarchy H;
   const double th0 = trace_enabled() ? wall_seconds() : 0.0;
   build_hierarchy(H, fine, row_ptr, col, Q.a, n, ws, s);
@@ -1257,7 +1518,6 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     for (auto& L : H.lv) fprintf(stderr, " %lld/%lld", (long long)L.n, (long long)L.ne);
     fprintf(stderr, "\n");
   }
-  for (size_t l = 1; l < H.lv.size(); ++l) H.lv[l].tau = 0.0;
   Level& L0 = H.lv[0];
 
   ZPrecond P;
@@ -1297,31 +1557,71 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   double fn = 0;
   for (level = 0; level <= max_level && !converged; ++level) {
     const double lo = lo_levels[level], hi = hi_levels[level];
-    fill_f64(Q.t, 0.0, nnz, s);
-    fill_f64(mu_out, 0.0, n, s);
-    fill_f64(nu_out, 0.0, n, s);
+    bool warm = o.warm_start && warm_level == level;
+   for (;;) {  // a warm start that fails is retried from zero
+    if (warm) {
+      // t from the previous solve's per-cell multipliers (same mesh)
+      ::bchar::ProfScope ps_("k_t_from_z", s);
+      k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
+    } else {
+      fill_f64(Q.t, 0.0, nnz, s);
+      fill_f64(zdual, 0.0, n2, s);
+    }
+    // From zero: smoothing Newton, i.e. Newton steps on the dual of the
+    // problem with clip replaced by clip_eps, whose Jacobian weights
+    // a_k^2 clip_eps'(t_k) are positive, so that entries on the box keep the
+    // cells coupled; eps starts at 0.1 and is cut tenfold whenever the
+    // iterate is within eps of the smoothed problem's solution (residual at
+    // most eps), and set to 0 below 1e-18, where clip_eps and clip agree in
+    // binary64 except within about eps of a bound.  From a warm start, whose
+    // entries are mostly on the right side of the box already, plain
+    // semismooth Newton (eps = 0).  Convergence is judged on the residual of
+    // clip itself.
+    double eps = -1.0;
     for (int it = 0; it < o.qp_max_newton; ++it) {
       {
         ::bchar::ProfScope ps_("k_residual", s);
         k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
-                                     Q.rr, Q.ss, n, Q.F);
+                                     0.0, Q.rr, Q.ss, n, Q.F);
       }
       red.maxabs(Q.F, n2, 0);
-      fn = red.fetch(0);
-      if (!(fn == fn)) break;
-      if (fn <= tol) {
+      const double ft = red.fetch(0);
+      fn = ft;
+      if (!(ft == ft)) break;
+      if (ft <= tol) {
         converged = true;
         break;
+      }
+      if (eps < 0.0) eps = (level == 2 || warm) ? 0.0 : 0.1;
+      while (eps > 0.0) {
+        {
+          ::bchar::ProfScope ps_("k_residual", s);
+          k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo,
+                                       hi, eps, Q.rr, Q.ss, n, Q.F);
+        }
+        red.maxabs(Q.F, n2, 0);
+        fn = red.fetch(0);
+        if (fn > eps) break;
+        eps *= 0.1;
+        if (eps < 1e-18) {
+          eps = 0.0;
+          {
+            ::bchar::ProfScope ps_("k_residual", s);
+            k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo,
+                                         hi, 0.0, Q.rr, Q.ss, n, Q.F);
+          }
+          fn = ft;
+        }
       }
       ++res.newton;
       // Newton matrix weights, per-cell blocks and the hierarchy values
       {
         ::bchar::ProfScope ps_("k_fine_weights", s);
-        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, nnz, L0.w);
+        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, eps, nnz, L0.w);
       }
       {
         ::bchar::ProfScope ps_("k_zcells", s);
-        k_zcells<<<gn, kT, 0, s>>>(P.Z, 1e-14);
+        k_zcells<<<gn, kT, 0, s>>>(P.Z, 1e-14, H.mu);
       }
       BCHAR_HIP(hipGetLastError());
       refresh_hierarchy(H, s);
@@ -1377,9 +1677,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         BCHAR_HIP(hipGetLastError());
       }
       res.cg += k;
-      if (trace_enabled())
-        fprintf(stderr, "[bchar]   level %d newton %d: |F| %.3e, cg %d, t %.3f s\n", level, it,
-                fn, k, wall_seconds());
+      if (trace_enabled()) {
+        red.maxabs(cr, n2, 11);
+        fprintf(stderr,
+                "[bchar]   level %d newton %d%s: |F| %.3e (eps %.1e: %.3e), cg %d (|r| %.3e of "
+                "%.3e), t %.3f s\n",
+                level, it, warm ? " (warm)" : "", ft, eps, fn, k, red.fetch(11), cg_tol,
+                wall_seconds());
+      }
       // dual direction and entry increments
       red.sum(cx, n, 13);
       {
@@ -1388,60 +1693,104 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
                                       dmu, dnu, Q.dt);
       }
       BCHAR_HIP(hipGetLastError());
-      // slope = F . d  and  d . (rr; ss)
-      red.dot(Q.F, dmu, n, 0);
-      red.dot(Q.F + n, dnu, n, 1);
-      red.dot(Q.rr, dmu, n, 2);
-      red.dot(Q.ss, dnu, n, 3);
-      double hs[4];
-      BCHAR_HIP(hipMemcpyAsync(hs, red.out, sizeof(hs), hipMemcpyDeviceToHost, s));
-      BCHAR_HIP(hipStreamSynchronize(s));
-      const double slope = hs[0] + hs[1];
-      const double drs = hs[2] + hs[3];
-      if (!(slope < 0.0)) break;
-      double step = 1.0;
-      while (true) {
+      // line search on phi(step) = theta(y + step d), convex and piecewise
+      // quadratic: phi'(0) = F . d < 0 and phi' is nondecreasing, so any
+      // step with phi'(step) <= 0 decreases theta.  The full step is taken
+      // when phi'(1) <= 0; otherwise the minimiser along d is bracketed by
+      // quartering and located by regula falsi (Illinois) on phi', which is
+      // piecewise linear.  Directions along which the entries on the box
+      // leave theta without curvature are long, and the minimiser can lie
+      // many orders of magnitude below 1.
+      auto dphi = [&](double al) {
         {
-          ::bchar::ProfScope ps_("k_dtheta_part", s);
-          k_dtheta_part<<<kRedBlocks, kT, 0, s>>>(Q.t, Q.dt, step, lo, hi, nnz, red.part);
+          ::bchar::ProfScope ps_("k_dphi_part", s);
+          k_dphi_part<<<kRedBlocks, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, al,
+                                                lo, hi, eps, Q.rr, Q.ss, dmu, dnu, n, red.part);
         }
         {
           ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-          k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 14);
+          k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 4);
         }
-        const double dth = red.fetch(14) - step * drs;
-        if (dth <= 1e-4 * step * slope) break;
-        if (step == 1.0) {
-          // near the solution the dual function changes by less than its
-          // rounding; accept a full step that halves the residual
-          {
-            ::bchar::ProfScope ps_("k_residual", s);
-            k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, 1.0, lo, hi,
-                                         Q.rr, Q.ss, n, cq);
-          }
-          red.maxabs(cq, n2, 14);
-          if (red.fetch(14) < 0.5 * fn) break;
-        }
-        step *= 0.5;
-        if (step < 1e-12) break;
+        BCHAR_HIP(hipGetLastError());
+        return red.fetch(4);
+      };
+      const double slope = dphi(0.0);
+      if (!(slope < 0.0)) {
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: slope %.3e\n", slope);
+        break;
       }
-      if (step < 1e-12) break;
+      double step = 1.0;
+      const double g1 = dphi(1.0);
+      int evals = 2;
+      bool full = g1 <= 0.0;
+      if (!full && fn < 1e-6) {
+        // near the solution phi'(1) is of the order of its rounding; take a
+        // full step that halves the residual
+        {
+          ::bchar::ProfScope ps_("k_residual", s);
+          k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, 1.0, lo, hi,
+                                       eps, Q.rr, Q.ss, n, cq);
+        }
+        red.maxabs(cq, n2, 14);
+        full = red.fetch(14) < 0.5 * fn;
+      }
+      if (!full) {
+        double a_lo = 0.0, g_lo = slope, a_hi = 1.0, g_hi = g1;
+        for (double al = 0.25; al >= 1e-40; al *= 0.25) {
+          const double g = dphi(al);
+          ++evals;
+          if (g <= 0.0) {
+            a_lo = al;
+            g_lo = g;
+            break;
+          }
+          a_hi = al;
+          g_hi = g;
+        }
+        if (a_lo == 0.0) {
+          if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no decrease along d\n");
+          break;
+        }
+        int side = 0;
+        for (int r = 0; r < 12 && g_lo < 0.1 * slope; ++r) {
+          double m = a_lo + (a_hi - a_lo) * (g_lo / (g_lo - g_hi));
+          if (!(m > a_lo && m < a_hi)) break;
+          const double g = dphi(m);
+          ++evals;
+          if (g <= 0.0) {
+            a_lo = m;
+            g_lo = g;
+            if (side == -1) g_hi *= 0.5;
+            side = -1;
+          } else {
+            a_hi = m;
+            g_hi = g;
+            if (side == 1) g_lo *= 0.5;
+            side = 1;
+          }
+        }
+        step = a_lo;
+      }
+      if (trace_enabled())
+        fprintf(stderr, "[bchar]   step %.3e (%d evaluations) slope %.3e\n", step, evals, slope);
       {
         ::bchar::ProfScope ps_("k_axpy2", s);
         k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, step, nnz);
       }
       {
-        ::bchar::ProfScope ps_("k_axpy2", s);
-        k_axpy2<<<gn, kT, 0, s>>>(mu_out, dmu, step, n);
-      }
-      {
-        ::bchar::ProfScope ps_("k_axpy2", s);
-        k_axpy2<<<gn, kT, 0, s>>>(nu_out, dnu, step, n);
+        ::bchar::ProfScope ps_("k_zdual_acc", s);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, step, n, zdual);
       }
       BCHAR_HIP(hipGetLastError());
       red.maxabs(Q.t, nnz, 15);
-      if (!(red.fetch(15) <= 1e12)) break;
+      if (!(red.fetch(15) <= 1e12)) {
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: |t| %.3e\n", red.fetch(15));
+        break;
+      }
     }
+    if (converged || !warm) break;
+    warm = false;
+   }
     if (converged) break;
   }
   res.residual = fn;
@@ -1450,6 +1799,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     return max_level == 0 ? BCHAR_E_QP_INFEASIBLE : BCHAR_E_QP_NOT_CONVERGED;
   }
   res.level = level;
+  {
+    ::bchar::ProfScope ps_("k_mu_nu", s);
+    k_mu_nu<<<gn, kT, 0, s>>>(zdual, n, mu_out, nu_out);
+  }
   const double lo = lo_levels[level], hi = hi_levels[level];
   int32_t* counts = ws.get<int32_t>(2);
   fill_i32(counts, 0, 2, s);
