@@ -144,6 +144,7 @@ typedef struct {
   int qp_cg;                   /* CG iterations (all levels)              */
   int64_t n_at_lower;          /* entries with 1 + x = 0                  */
   int64_t n_at_upper;          /* entries with 1 + x = 2                  */
+  int qp_ipm;                  /* interior-point iterations (all levels)  */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */

@@ -155,11 +155,12 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
                 t->zdual.as<double>(), t->warm_level, qr, ws, s);
   t->warm_level = rc == BCHAR_OK ? qr.level : -1;
   if (tr)
-    fprintf(stderr, "[bchar] qp: %.3f ms (level %d, newton %d, cg %d, residual %.3e)\n",
-            1e3 * (wall_seconds() - t0), qr.level, qr.newton, qr.cg, qr.residual);
+    fprintf(stderr, "[bchar] qp: %.3f ms (level %d, ipm %d, newton %d, cg %d, residual %.3e)\n",
+            1e3 * (wall_seconds() - t0), qr.level, qr.ipm, qr.newton, qr.cg, qr.residual);
   st.qp_level = qr.level;
   st.qp_newton = qr.newton;
   st.qp_cg = qr.cg;
+  st.qp_ipm = qr.ipm;
   st.qp_residual = qr.residual;
   st.n_at_lower = qr.at_lower;
   st.n_at_upper = qr.at_upper;

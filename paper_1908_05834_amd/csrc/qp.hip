@@ -8,24 +8,30 @@
 // Method: the minimiser is unique; it is reached through the dual.  With
 // multipliers mu (rows) and nu (columns), x_k = clip(a_k (mu_i + nu_j)).
 // The dual function is convex and C^1 with gradient F = constraint
-// residual; a damped semismooth Newton method minimises it.  Each Newton
-// step solves J d = -F with J = A_hat diag(free) A_hat^T, a weighted
-// bipartite graph Laplacian once the column multipliers change sign
-// (L (d_mu; -d_nu) = (-F_row; F_col)), by preconditioned conjugate
-// gradients.  t_k = a_k (mu_i + nu_j) is carried per entry and updated by
-// increments, since weakly coupled cells give multipliers of very
-// different sizes.  The step length comes from Armijo backtracking on the
-// change of the dual function, summed entry by entry.
+// residual.  Semismooth Newton on it converges fast from a good start but
+// crawls from a poor one: entries pinned to the box give it no curvature,
+// cells of a mesh that barely move link to their neighbours only through
+// such entries, some of them tiny, and the multipliers that pin them must
+// grow to about 1 / a_k.  So a level with a bound first runs a primal-dual
+// interior point (Mehrotra predictor-corrector), whose Newton systems keep
+// every entry with a positive weight, and semismooth Newton finishes from
+// its t; a rebuild first tries semismooth Newton from the previous
+// multipliers.  Every Newton system is a weighted bipartite graph
+// Laplacian L (d_mu; -d_nu) = (-F_row; F_col), solved by preconditioned
+// conjugate gradients in per-cell coordinates.  t_k = a_k (mu_i + nu_j) is
+// carried per entry and updated by increments, since the multipliers span
+// many orders of magnitude.
 //
 // Preconditioner: one symmetric two-grid cycle on the bipartite graph
 // (weighted Jacobi smoothing; each row node joins the column node it is
 // most strongly coupled to, which turns the graph into a graph on cells),
 // then a V-cycle of aggregation multigrid on the cell graph: pairwise
 // matching along strong couplings (w_pq >= beta max(w_p., w_q.)), Galerkin
-// coarse operators, l1-Jacobi smoothing, a dense Cholesky solve on the
-// coarsest level.  The aggregation is fixed once per solve from the
-// all-free weights a_k^2; each Newton step refreshes the weights of every
-// level (entries on the box weigh 0).  Weights span many decades on these
+// coarse operators, l1-Jacobi smoothing, a dense solve on the coarsest
+// level.  The aggregation is fixed once per solve from the all-free
+// weights a_k^2; each Newton system refreshes the weights of every level
+// (entries on the box weigh 0 in semismooth Newton, a_k^2 D_k in the
+// interior point).  Weights span many decades on these
 // matrices (cells that barely move couple to their neighbours by slivers),
 // which is why plain Jacobi-preconditioned CG does not converge here.
 #include <algorithm>
@@ -42,6 +48,8 @@ constexpr int kT = 256;   // threads per block for vector kernels
 constexpr int kRedBlocks = 512;
 constexpr int kMaxCoarse = 512;    // dense coarsest solve
 constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
+constexpr int kIpmMaxIter = 100;   // interior-point iterations per box level
+constexpr int kWarmNewton = 12;    // semismooth steps tried from a warm start
 
 // ====================================================================== reductions
 
@@ -1199,79 +1207,43 @@ __device__ __forceinline__ double clipv(double v, double lo, double hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// Smoothed clip.  max(0, u) is replaced by the Chen-Harker-Kanzow-Smale
-// function p(u) = (u + sqrt(u^2 + 4 eps^2)) / 2, so that
-//   clip_eps(t) = lo + p(t - lo) - p(t - hi) = hi - p(hi - t) + p(lo - t),
-// strictly increasing for eps > 0 and equal to clip for eps = 0.  p and p'
-// are evaluated without cancellation (for u < 0, p = 2 eps^2 / (s - u) and
-// p' = 2 eps^2 / (s (s - u))), and the form used on each half of the box
-// keeps the far bound's term tiny, so that an entry far outside the box
-// gets its bound to the last bit.
-__device__ __forceinline__ double smax0(double u, double eps) {
-  const double e2 = 2.0 * eps * eps;
-  const double s = sqrt(u * u + 2.0 * e2);
-  return u >= 0.0 ? 0.5 * (u + s) : e2 / (s - u);
-}
-__device__ __forceinline__ double dsmax0(double u, double eps) {
-  const double e2 = 2.0 * eps * eps;
-  const double s = sqrt(u * u + 2.0 * e2);
-  return u >= 0.0 ? 0.5 * (1.0 + u / s) : e2 / (s * (s - u));
-}
-__device__ __forceinline__ double clip_s(double t, double lo, double hi, double eps) {
-  if (eps == 0.0) return clipv(t, lo, hi);
-  const bool bl = !isinf(lo), bh = !isinf(hi);
-  if (!bl && !bh) return t;
-  if (!bh) return lo + smax0(t - lo, eps);
-  if (!bl) return hi - smax0(hi - t, eps);
-  return t <= 0.5 * (lo + hi) ? lo + smax0(t - lo, eps) - smax0(t - hi, eps)
-                              : hi - smax0(hi - t, eps) + smax0(lo - t, eps);
-}
-// derivative of clip_s in t (for eps = 0: 1 strictly inside the box, else 0)
-__device__ __forceinline__ double dclip_s(double t, double lo, double hi, double eps) {
-  if (eps == 0.0) return (t > lo && t < hi) ? 1.0 : 0.0;
-  const bool bl = !isinf(lo), bh = !isinf(hi);
-  if (!bl && !bh) return 1.0;
-  if (!bh) return dsmax0(t - lo, eps);
-  if (!bl) return dsmax0(hi - t, eps);
-  return t <= 0.5 * (lo + hi) ? dsmax0(t - lo, eps) - dsmax0(t - hi, eps)
-                              : dsmax0(hi - t, eps) - dsmax0(lo - t, eps);
-}
-
-// F = [sum_row a clip_eps(t + step dt) - rr ; sum_col ... - ss]
+// F = [sum_row a clip(t + step dt) - rr ; sum_col ... - ss]
 __global__ void k_residual(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
                            const int32_t* __restrict__ cpos, const double* __restrict__ a,
                            const double* __restrict__ ac, const double* __restrict__ t,
                            const double* __restrict__ dt, double step, double lo, double hi,
-                           double eps, const double* __restrict__ rr,
-                           const double* __restrict__ ss, int64_t n, double* __restrict__ F) {
+                           const double* __restrict__ rr, const double* __restrict__ ss,
+                           int64_t n, double* __restrict__ F) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   CSum r, c;
   r.add(-rr[i]);
   for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
     const double tk = dt ? t[k] + step * dt[k] : t[k];
-    r.add(a[k] * clip_s(tk, lo, hi, eps));
+    r.add(a[k] * clipv(tk, lo, hi));
   }
   c.add(-ss[i]);
   for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
     const int32_t k = cpos[e];
     const double tk = dt ? t[k] + step * dt[k] : t[k];
-    c.add(ac[e] * clip_s(tk, lo, hi, eps));
+    c.add(ac[e] * clipv(tk, lo, hi));
   }
   F[i] = r.value();
   F[n + i] = c.value();
 }
 
-// fine bipartite weights a_k^2 clip_eps'(t_k) in graph order: row part is
-// CSR order, column part is CSC order
+// fine bipartite weights a_k^2 * free_k in graph order: row part is CSR
+// order, column part is CSC order
 __global__ void k_fine_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
-                               const double* __restrict__ t, double lo, double hi, double eps,
-                               int64_t nnz, double* __restrict__ w) {
+                               const double* __restrict__ t, double lo, double hi, int64_t nnz,
+                               double* __restrict__ w) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  w[k] = (a[k] * a[k]) * dclip_s(t[k], lo, hi, eps);
+  const double tk = t[k];
+  w[k] = (tk > lo && tk < hi) ? a[k] * a[k] : 0.0;
   const int32_t kp = cpos[k];
-  w[nnz + k] = (a[kp] * a[kp]) * dclip_s(t[kp], lo, hi, eps);
+  const double tp = t[kp];
+  w[nnz + k] = (tp > lo && tp < hi) ? a[kp] * a[kp] : 0.0;
 }
 
 __global__ void k_fine_graph(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
@@ -1357,7 +1329,7 @@ __global__ void __launch_bounds__(kT) k_dphi_part(
     const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
     const int32_t* __restrict__ cpos, const double* __restrict__ a,
     const double* __restrict__ ac, const double* __restrict__ t, const double* __restrict__ dt,
-    double step, double lo, double hi, double eps, const double* __restrict__ rr,
+    double step, double lo, double hi, const double* __restrict__ rr,
     const double* __restrict__ ss, const double* __restrict__ dmu,
     const double* __restrict__ dnu, int64_t n, double* __restrict__ part) {
   __shared__ double sh[32];
@@ -1367,11 +1339,11 @@ __global__ void __launch_bounds__(kT) k_dphi_part(
     CSum r, c;
     r.add(-rr[i]);
     for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k)
-      r.add(a[k] * clip_s(t[k] + step * dt[k], lo, hi, eps));
+      r.add(a[k] * clipv(t[k] + step * dt[k], lo, hi));
     c.add(-ss[i]);
     for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
       const int32_t k = cpos[e];
-      c.add(ac[e] * clip_s(t[k] + step * dt[k], lo, hi, eps));
+      c.add(ac[e] * clipv(t[k] + step * dt[k], lo, hi));
     }
     acc.add(dmu[i] * r.value());
     acc.add(dnu[i] * c.value());
@@ -1431,6 +1403,207 @@ __global__ void k_final(const double* __restrict__ an, const double* __restrict_
   A[k] = an[k] * (1.0 + xk);
   if (xk == lo) atomicAdd(&counts[0], 1);
   if (xk == hi) atomicAdd(&counts[1], 1);
+}
+
+// ====================================================================== interior point
+//
+// Primal-dual interior-point iteration (Mehrotra predictor-corrector) on
+//   min 1/2 x^T x,  sum_row a x = rr,  sum_col a x = ss,  lo <= x <= hi,
+// with slacks sl = x - lo, su = hi - x and bound multipliers zl, zu >= 0.
+// Eliminating dx = D (B^T dy + h), D = 1 / (1 + zl / sl + zu / su), leaves
+// the normal equations B D B^T dy = -(B (x + D h) - r): the weighted
+// bipartite Laplacian of the Newton systems with weights a_k^2 D_k, all
+// positive, solved by the same preconditioned CG.  B^T dy = dt is the
+// change of t, carried per entry as in the semismooth iteration, so that
+// the interior point's t seeds it.
+
+struct IpmArrays {
+  double *x, *sl, *su, *zl, *zu;   // iterate
+  double *D, *h, *dxa;             // scaling, right-hand side, predictor dx
+  double *dx, *dzl, *dzu;          // step
+  double lo, hi;
+  int has_hi;                      // level 0: both bounds; level 1: lower only
+};
+
+// D and the per-block complementarity sums sl zl + su zu
+__global__ void __launch_bounds__(kT) k_ipm_prep(IpmArrays I, int64_t nnz,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kT) {
+    const double sl = I.sl[k], zl = I.zl[k];
+    double sig = zl / sl;
+    acc.add(sl * zl);
+    if (I.has_hi) {
+      const double su = I.su[k], zu = I.zu[k];
+      sig += zu / su;
+      acc.add(su * zu);
+    }
+    I.D[k] = 1.0 / (1.0 + sig);
+  }
+  CSum r = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r.hi;
+    part[2 * blockIdx.x + 1] = r.lo;
+  }
+}
+
+// complementarity targets: sl dzl + zl dx = cl, su dzu - zu dx = cu.
+// Predictor: cl = -sl zl, cu = -su zu.  Corrector: sigma mu minus those
+// and the predictor's second-order terms.
+struct IpmTargets {
+  double cl, cu;
+};
+__device__ __forceinline__ IpmTargets ipm_targets(const IpmArrays& I, int64_t k, int corr,
+                                                  double smu) {
+  const double sl = I.sl[k], zl = I.zl[k];
+  IpmTargets c;
+  c.cu = 0.0;
+  if (!corr) {
+    c.cl = -sl * zl;
+    if (I.has_hi) c.cu = -I.su[k] * I.zu[k];
+  } else {
+    const double dxa = I.dxa[k];
+    const double dzla = -zl - zl * dxa / sl;
+    c.cl = smu - sl * zl - dxa * dzla;
+    if (I.has_hi) {
+      const double su = I.su[k], zu = I.zu[k];
+      const double dzua = -zu + zu * dxa / su;
+      c.cu = smu - su * zu + dxa * dzua;
+    }
+  }
+  return c;
+}
+
+// h = -(x - t - zl + zu) + cl / sl - cu / su
+__global__ void k_ipm_h(IpmArrays I, const double* __restrict__ t, int corr, double smu,
+                        int64_t nnz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const IpmTargets c = ipm_targets(I, k, corr, smu);
+  double h = t[k] - I.x[k] + I.zl[k] + c.cl / I.sl[k];
+  if (I.has_hi) h += -I.zu[k] - c.cu / I.su[k];
+  I.h[k] = h;
+}
+
+// fine weights a_k^2 D_k in graph order (CSR part, CSC part)
+__global__ void k_ipm_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
+                              const double* __restrict__ D, int64_t nnz,
+                              double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  w[k] = (a[k] * a[k]) * D[k];
+  const int32_t kp = cpos[k];
+  w[nnz + k] = (a[kp] * a[kp]) * D[kp];
+}
+
+// per cell: rp = B x - r and fv = B (x + D h) - r (row part, then column part)
+__global__ void k_ipm_rhs(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
+                          const int32_t* __restrict__ cpos, const double* __restrict__ a,
+                          const double* __restrict__ ac, IpmArrays I,
+                          const double* __restrict__ rr, const double* __restrict__ ss,
+                          int64_t n, double* __restrict__ rp, double* __restrict__ fv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CSum r0, r1, c0, c1;
+  r0.add(-rr[i]);
+  r1.add(-rr[i]);
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    r0.add(a[k] * I.x[k]);
+    r1.add(a[k] * I.x[k]);
+    r1.add(a[k] * (I.D[k] * I.h[k]));
+  }
+  c0.add(-ss[i]);
+  c1.add(-ss[i]);
+  for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
+    const int32_t k = cpos[e];
+    c0.add(ac[e] * I.x[k]);
+    c1.add(ac[e] * I.x[k]);
+    c1.add(ac[e] * (I.D[k] * I.h[k]));
+  }
+  rp[i] = r0.value();
+  rp[n + i] = c0.value();
+  fv[i] = r1.value();
+  fv[n + i] = c1.value();
+}
+
+// step from dt = B^T dy: dx, dzl, dzu, and per block the largest inverse
+// step to the boundary, max(-dx / sl, dx / su) and max(-dzl / zl, -dzu / zu)
+__global__ void __launch_bounds__(kT) k_ipm_dir(IpmArrays I, const double* __restrict__ dt,
+                                                int corr, double smu, int64_t nnz,
+                                                double* __restrict__ part) {
+  __shared__ double sh[16];
+  double ip = 0.0, id = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kT) {
+    const IpmTargets c = ipm_targets(I, k, corr, smu);
+    const double sl = I.sl[k], zl = I.zl[k];
+    const double dx = I.D[k] * (dt[k] + I.h[k]);
+    const double dzl = (c.cl - zl * dx) / sl;
+    I.dx[k] = dx;
+    I.dzl[k] = dzl;
+    if (!corr) I.dxa[k] = dx;
+    ip = fmax(ip, -dx / sl);
+    id = fmax(id, -dzl / zl);
+    if (I.has_hi) {
+      const double su = I.su[k], zu = I.zu[k];
+      const double dzu = (c.cu + zu * dx) / su;
+      I.dzu[k] = dzu;
+      ip = fmax(ip, dx / su);
+      id = fmax(id, -dzu / zu);
+    }
+  }
+  ip = block_max(ip, sh);
+  __syncthreads();
+  id = block_max(id, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ip;
+    part[kRedBlocks + blockIdx.x] = id;
+  }
+}
+
+// complementarity after the predictor step (ap, ad), per block
+__global__ void __launch_bounds__(kT) k_ipm_muaff(IpmArrays I, double ap, double ad,
+                                                  int64_t nnz, double* __restrict__ part) {
+  __shared__ double sh[32];
+  CSum acc;
+  for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kT) {
+    const double dx = I.dx[k];
+    acc.add((I.sl[k] + ap * dx) * (I.zl[k] + ad * I.dzl[k]));
+    if (I.has_hi) acc.add((I.su[k] - ap * dx) * (I.zu[k] + ad * I.dzu[k]));
+  }
+  CSum r = block_csum(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r.hi;
+    part[2 * blockIdx.x + 1] = r.lo;
+  }
+}
+
+__global__ void k_ipm_update(IpmArrays I, double* __restrict__ t, const double* __restrict__ dt,
+                             double ap, double ad, int64_t nnz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double dx = I.dx[k];
+  I.x[k] += ap * dx;
+  I.sl[k] += ap * dx;
+  I.zl[k] += ad * I.dzl[k];
+  if (I.has_hi) {
+    I.su[k] -= ap * dx;
+    I.zu[k] += ad * I.dzu[k];
+  }
+  t[k] += ad * dt[k];
+}
+
+__global__ void k_ipm_init(IpmArrays I, int64_t nnz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  I.x[k] = 0.0;
+  I.sl[k] = -I.lo;
+  I.zl[k] = 1.0;
+  I.su[k] = I.has_hi ? I.hi : 1.0;
+  I.zu[k] = I.has_hi ? 1.0 : 0.0;
 }
 
 // ====================================================================== solver
@@ -1494,7 +1667,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   fill_f64(Q.t, 0.0, nnz, s);
   {
     ::bchar::ProfScope ps_("k_fine_weights", s);
-    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, 0.0, nnz, fine.w0);
+    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, nnz, fine.w0);
   }
   BCHAR_HIP(hipGetLastError());
   double dmax = 0;
@@ -1547,152 +1720,115 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   double *cx = ws.get<double>(n2), *cr = ws.get<double>(n2), *cz = ws.get<double>(n2),
          *cp = ws.get<double>(n2), *cq = ws.get<double>(n2);
 
-  const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
-  const double hi_levels[3] = {1.0, HUGE_VAL, HUGE_VAL};
-  const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : 2;
   const double tol = o.qp_tol;
   res = QpResult{};
-  bool converged = false;
-  int level = 0;
-  double fn = 0;
-  for (level = 0; level <= max_level && !converged; ++level) {
-    const double lo = lo_levels[level], hi = hi_levels[level];
-    bool warm = o.warm_start && warm_level == level;
-   for (;;) {  // a warm start that fails is retried from zero
-    if (warm) {
-      // t from the previous solve's per-cell multipliers (same mesh)
-      ::bchar::ProfScope ps_("k_t_from_z", s);
-      k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
-    } else {
-      fill_f64(Q.t, 0.0, nnz, s);
-      fill_f64(zdual, 0.0, n2, s);
+
+  // Newton matrix values: per-cell blocks and every level of the hierarchy,
+  // from the fine weights in L0.w
+  auto refresh = [&]() {
+    {
+      ::bchar::ProfScope ps_("k_zcells", s);
+      k_zcells<<<gn, kT, 0, s>>>(P.Z, 1e-14, H.mu);
     }
-    // From zero: smoothing Newton, i.e. Newton steps on the dual of the
-    // problem with clip replaced by clip_eps, whose Jacobian weights
-    // a_k^2 clip_eps'(t_k) are positive, so that entries on the box keep the
-    // cells coupled; eps starts at 0.1 and is cut tenfold whenever the
-    // iterate is within eps of the smoothed problem's solution (residual at
-    // most eps), and set to 0 below 1e-18, where clip_eps and clip agree in
-    // binary64 except within about eps of a bound.  From a warm start, whose
-    // entries are mostly on the right side of the box already, plain
-    // semismooth Newton (eps = 0).  Convergence is judged on the residual of
-    // clip itself.
-    double eps = -1.0;
-    for (int it = 0; it < o.qp_max_newton; ++it) {
+    BCHAR_HIP(hipGetLastError());
+    refresh_hierarchy(H, s);
+  };
+
+  // Preconditioned CG on J d = -fv (fv: row part, then column part), in
+  // the per-cell coordinates with the constant-s direction removed.  Leaves
+  // the per-cell solution in cx, the multiplier direction in dmu, dnu and
+  // the entry increments a_k (dmu_K + dnu_M) in Q.dt; returns iterations.
+  auto pcg = [&](const double* fv, double cg_tol) -> int {
+    {
+      ::bchar::ProfScope ps_("k_zrhs", s);
+      k_zrhs<<<gn, kT, 0, s>>>(fv, n, cr);
+    }
+    red.sum(cr, n, 12);
+    {
+      ::bchar::ProfScope ps_("k_sub_scalar", s);
+      k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, 1.0 / (double)n, n);
+    }
+    fill_f64(cx, 0.0, n2, s);
+    // scalars: out[8] = rz, out[9] = pq, out[10] = rz_new, out[11] = max |r|
+    zprecondition(P, cr, cz, s);
+    BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+    red.dot(cr, cz, n2, 8);
+    int k = 0;
+    for (k = 0; k < o.qp_max_cg; ++k) {
+      {
+        ::bchar::ProfScope ps_("k_zop", s);
+        k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq);
+      }
+      red.dot(cp, cq, n2, 9);
+      {
+        ::bchar::ProfScope ps_("k_cg_update", s);
+        k_cg_update<<<gn2, kT, 0, s>>>(red.out + 8, n2, cx, cr, cp, cq);
+      }
+      BCHAR_HIP(hipGetLastError());
+      if ((k % 4) == 3 || k + 1 == o.qp_max_cg) {
+        red.maxabs(cr, n2, 11);
+        if (red.fetch(11) <= cg_tol) {
+          ++k;
+          break;
+        }
+      }
+      zprecondition(P, cr, cz, s);
+      red.dot(cr, cz, n2, 10);
+      {
+        ::bchar::ProfScope ps_("k_cg_dir", s);
+        k_cg_dir<<<gn2, kT, 0, s>>>(red.out + 8, n2, cz, cp);
+      }
+      {
+        ::bchar::ProfScope ps_("k_copy_scalar", s);
+        k_copy_scalar<<<1, 64, 0, s>>>(red.out, 10, 8);
+      }
+      BCHAR_HIP(hipGetLastError());
+    }
+    res.cg += k;
+    red.sum(cx, n, 13);
+    {
+      ::bchar::ProfScope ps_("k_zdual_dir", s);
+      k_zdual_dir<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, cx, red.out + 13, 1.0 / (double)n, n,
+                                    dmu, dnu, Q.dt);
+    }
+    BCHAR_HIP(hipGetLastError());
+    return k;
+  };
+
+  // ---------------------------------------------------------------- semismooth Newton
+  // From the current t (and the per-cell multipliers in zdual that produce
+  // it): Newton steps on the dual function with the generalised Jacobian
+  // (entries on the box weigh 0) and a line search on its directional
+  // derivative.  Returns true once max |F| <= tol; fn holds the last
+  // residual.
+  double fn = 0.0;
+  auto ssn = [&](double lo, double hi, int max_it, const char* tag) -> bool {
+    for (int it = 0; it < max_it; ++it) {
       {
         ::bchar::ProfScope ps_("k_residual", s);
         k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
-                                     0.0, Q.rr, Q.ss, n, Q.F);
+                                     Q.rr, Q.ss, n, Q.F);
       }
       red.maxabs(Q.F, n2, 0);
-      const double ft = red.fetch(0);
-      fn = ft;
-      if (!(ft == ft)) break;
-      if (ft <= tol) {
-        converged = true;
-        break;
-      }
-      if (eps < 0.0) eps = (level == 2 || warm) ? 0.0 : 0.1;
-      while (eps > 0.0) {
-        {
-          ::bchar::ProfScope ps_("k_residual", s);
-          k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo,
-                                       hi, eps, Q.rr, Q.ss, n, Q.F);
-        }
-        red.maxabs(Q.F, n2, 0);
-        fn = red.fetch(0);
-        if (fn > eps) break;
-        eps *= 0.1;
-        if (eps < 1e-18) {
-          eps = 0.0;
-          {
-            ::bchar::ProfScope ps_("k_residual", s);
-            k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo,
-                                         hi, 0.0, Q.rr, Q.ss, n, Q.F);
-          }
-          fn = ft;
-        }
-      }
+      fn = red.fetch(0);
+      if (!(fn == fn)) return false;
+      if (fn <= tol) return true;
       ++res.newton;
-      // Newton matrix weights, per-cell blocks and the hierarchy values
       {
         ::bchar::ProfScope ps_("k_fine_weights", s);
-        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, eps, nnz, L0.w);
+        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, nnz, L0.w);
       }
-      {
-        ::bchar::ProfScope ps_("k_zcells", s);
-        k_zcells<<<gn, kT, 0, s>>>(P.Z, 1e-14, H.mu);
-      }
-      BCHAR_HIP(hipGetLastError());
-      refresh_hierarchy(H, s);
-      // right-hand side with the constant-s direction removed
-      {
-        ::bchar::ProfScope ps_("k_zrhs", s);
-        k_zrhs<<<gn, kT, 0, s>>>(Q.F, n, cr);
-      }
-      red.sum(cr, n, 12);
-      {
-        ::bchar::ProfScope ps_("k_sub_scalar", s);
-        k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, 1.0 / (double)n, n);
-      }
-      fill_f64(cx, 0.0, n2, s);
-      // inexact Newton: relative inner tolerance on the y-space residual
-      // (near-exact solves once Newton needs many steps, as on faces of the
-      // box where the multipliers of the pinned entries grow without bound)
+      refresh();
+      // inexact Newton: relative inner tolerance on the y-space residual,
+      // near-exact once many steps were needed
       const double eta = it < 30 ? std::min(0.1, std::sqrt(fn)) * 0.1 : 1e-6;
       const double cg_tol = std::max(eta * fn, 0.1 * tol);
-      // scalars: out[8] = rz, out[9] = pq, out[10] = rz_new, out[11] = max |r|
-      zprecondition(P, cr, cz, s);
-      BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
-      red.dot(cr, cz, n2, 8);
-      int k = 0;
-      for (k = 0; k < o.qp_max_cg; ++k) {
-        {
-          ::bchar::ProfScope ps_("k_zop", s);
-          k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq);
-        }
-        red.dot(cp, cq, n2, 9);
-        {
-          ::bchar::ProfScope ps_("k_cg_update", s);
-          k_cg_update<<<gn2, kT, 0, s>>>(red.out + 8, n2, cx, cr, cp, cq);
-        }
-        BCHAR_HIP(hipGetLastError());
-        if ((k % 4) == 3 || k + 1 == o.qp_max_cg) {
-          red.maxabs(cr, n2, 11);
-          if (red.fetch(11) <= cg_tol) {
-            ++k;
-            break;
-          }
-        }
-        zprecondition(P, cr, cz, s);
-        red.dot(cr, cz, n2, 10);
-        {
-          ::bchar::ProfScope ps_("k_cg_dir", s);
-          k_cg_dir<<<gn2, kT, 0, s>>>(red.out + 8, n2, cz, cp);
-        }
-        {
-          ::bchar::ProfScope ps_("k_copy_scalar", s);
-          k_copy_scalar<<<1, 64, 0, s>>>(red.out, 10, 8);
-        }
-        BCHAR_HIP(hipGetLastError());
-      }
-      res.cg += k;
+      const int k = pcg(Q.F, cg_tol);
       if (trace_enabled()) {
         red.maxabs(cr, n2, 11);
-        fprintf(stderr,
-                "[bchar]   level %d newton %d%s: |F| %.3e (eps %.1e: %.3e), cg %d (|r| %.3e of "
-                "%.3e), t %.3f s\n",
-                level, it, warm ? " (warm)" : "", ft, eps, fn, k, red.fetch(11), cg_tol,
-                wall_seconds());
+        fprintf(stderr, "[bchar]   newton %d%s: |F| %.3e, cg %d (|r| %.3e of %.3e), t %.3f s\n",
+                it, tag, fn, k, red.fetch(11), cg_tol, wall_seconds());
       }
-      // dual direction and entry increments
-      red.sum(cx, n, 13);
-      {
-        ::bchar::ProfScope ps_("k_zdual_dir", s);
-        k_zdual_dir<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, cx, red.out + 13, 1.0 / (double)n, n,
-                                      dmu, dnu, Q.dt);
-      }
-      BCHAR_HIP(hipGetLastError());
       // line search on phi(step) = theta(y + step d), convex and piecewise
       // quadratic: phi'(0) = F . d < 0 and phi' is nondecreasing, so any
       // step with phi'(step) <= 0 decreases theta.  The full step is taken
@@ -1705,7 +1841,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         {
           ::bchar::ProfScope ps_("k_dphi_part", s);
           k_dphi_part<<<kRedBlocks, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, al,
-                                                lo, hi, eps, Q.rr, Q.ss, dmu, dnu, n, red.part);
+                                                lo, hi, Q.rr, Q.ss, dmu, dnu, n, red.part);
         }
         {
           ::bchar::ProfScope ps_("k_reduce_final_sum", s);
@@ -1717,7 +1853,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       const double slope = dphi(0.0);
       if (!(slope < 0.0)) {
         if (trace_enabled()) fprintf(stderr, "[bchar]   stop: slope %.3e\n", slope);
-        break;
+        return false;
       }
       double step = 1.0;
       const double g1 = dphi(1.0);
@@ -1729,7 +1865,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         {
           ::bchar::ProfScope ps_("k_residual", s);
           k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, 1.0, lo, hi,
-                                       eps, Q.rr, Q.ss, n, cq);
+                                       Q.rr, Q.ss, n, cq);
         }
         red.maxabs(cq, n2, 14);
         full = red.fetch(14) < 0.5 * fn;
@@ -1749,21 +1885,21 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         }
         if (a_lo == 0.0) {
           if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no decrease along d\n");
-          break;
+          return false;
         }
         int side = 0;
         for (int r = 0; r < 12 && g_lo < 0.1 * slope; ++r) {
-          double m = a_lo + (a_hi - a_lo) * (g_lo / (g_lo - g_hi));
-          if (!(m > a_lo && m < a_hi)) break;
-          const double g = dphi(m);
+          double mid = a_lo + (a_hi - a_lo) * (g_lo / (g_lo - g_hi));
+          if (!(mid > a_lo && mid < a_hi)) break;
+          const double g = dphi(mid);
           ++evals;
           if (g <= 0.0) {
-            a_lo = m;
+            a_lo = mid;
             g_lo = g;
             if (side == -1) g_hi *= 0.5;
             side = -1;
           } else {
-            a_hi = m;
+            a_hi = mid;
             g_hi = g;
             if (side == 1) g_lo *= 0.5;
             side = 1;
@@ -1785,12 +1921,175 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       red.maxabs(Q.t, nnz, 15);
       if (!(red.fetch(15) <= 1e12)) {
         if (trace_enabled()) fprintf(stderr, "[bchar]   stop: |t| %.3e\n", red.fetch(15));
-        break;
+        return false;
       }
     }
-    if (converged || !warm) break;
-    warm = false;
-   }
+    return false;
+  };
+
+  // ---------------------------------------------------------------- interior point
+  // From x = 0, zl = zu = 1, t = 0.  Returns true once max |B x - r| and
+  // the mean complementarity are both at most 1e-10, leaving t and zdual
+  // for the semismooth iteration to finish; false when the complementarity
+  // grows by 1e8 (the box admits no solution), on a NaN, or after
+  // kIpmMaxIter iterations.
+  IpmArrays I{};
+  I.x = ws.get<double>(nnz + 1);
+  I.sl = ws.get<double>(nnz + 1);
+  I.su = ws.get<double>(nnz + 1);
+  I.zl = ws.get<double>(nnz + 1);
+  I.zu = ws.get<double>(nnz + 1);
+  I.D = ws.get<double>(nnz + 1);
+  I.h = ws.get<double>(nnz + 1);
+  I.dxa = ws.get<double>(nnz + 1);
+  I.dx = ws.get<double>(nnz + 1);
+  I.dzl = ws.get<double>(nnz + 1);
+  I.dzu = ws.get<double>(nnz + 1);
+  double* rp = ws.get<double>(n2);
+  auto ipm = [&](double lo, double hi) -> bool {
+    I.lo = lo;
+    I.hi = hi;
+    I.has_hi = std::isinf(hi) ? 0 : 1;
+    const double m_pairs = (double)nnz * (I.has_hi ? 2.0 : 1.0);
+    {
+      ::bchar::ProfScope ps_("k_ipm_init", s);
+      k_ipm_init<<<gz, kT, 0, s>>>(I, nnz);
+    }
+    fill_f64(Q.t, 0.0, nnz, s);
+    fill_f64(zdual, 0.0, n2, s);
+    BCHAR_HIP(hipGetLastError());
+    double mu0 = -1.0;
+    auto steps = [&](double* ap, double* ad) {
+      {
+        ::bchar::ProfScope ps_("k_reduce_final_max", s);
+        k_reduce_final_max<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 2);
+        k_reduce_final_max<<<1, 64, 0, s>>>(red.part + kRedBlocks, kRedBlocks, red.out + 3);
+      }
+      double v[2];
+      BCHAR_HIP(hipMemcpyAsync(v, red.out + 2, sizeof(v), hipMemcpyDeviceToHost, s));
+      BCHAR_HIP(hipStreamSynchronize(s));
+      *ap = v[0] > 0.0 ? 1.0 / v[0] : HUGE_VAL;
+      *ad = v[1] > 0.0 ? 1.0 / v[1] : HUGE_VAL;
+    };
+    for (int it = 0; it < kIpmMaxIter; ++it) {
+      ++res.ipm;
+      {
+        ::bchar::ProfScope ps_("k_ipm_prep", s);
+        k_ipm_prep<<<kRedBlocks, kT, 0, s>>>(I, nnz, red.part);
+      }
+      {
+        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+        k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 0);
+      }
+      {
+        ::bchar::ProfScope ps_("k_ipm_h", s);
+        k_ipm_h<<<gz, kT, 0, s>>>(I, Q.t, 0, 0.0, nnz);
+      }
+      {
+        ::bchar::ProfScope ps_("k_ipm_rhs", s);
+        k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
+      }
+      BCHAR_HIP(hipGetLastError());
+      red.maxabs(rp, n2, 1);
+      red.maxabs(Q.F, n2, 5);
+      double v[6];
+      BCHAR_HIP(hipMemcpyAsync(v, red.out, sizeof(v), hipMemcpyDeviceToHost, s));
+      BCHAR_HIP(hipStreamSynchronize(s));
+      const double mu = v[0] / m_pairs, fp = v[1], fv = v[5];
+      if (mu0 < 0.0) mu0 = mu;
+      fn = fp;
+      if (trace_enabled())
+        fprintf(stderr, "[bchar]   ipm %d: |B x - r| %.3e, mu %.3e, t %.3f s\n", it, fp, mu,
+                wall_seconds());
+      if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return false;
+      if (fp <= 1e-10 && mu <= 1e-10) return true;
+      {
+        ::bchar::ProfScope ps_("k_ipm_weights", s);
+        k_ipm_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, I.D, nnz, L0.w);
+      }
+      refresh();
+      const double cg_tol = std::max(1e-2 * std::min(fv, mu), 1e-15);
+      // predictor (affine scaling)
+      pcg(Q.F, cg_tol);
+      {
+        ::bchar::ProfScope ps_("k_ipm_dir", s);
+        k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 0, 0.0, nnz, red.part);
+      }
+      double ap, ad;
+      steps(&ap, &ad);
+      ap = std::min(1.0, ap);
+      ad = std::min(1.0, ad);
+      {
+        ::bchar::ProfScope ps_("k_ipm_muaff", s);
+        k_ipm_muaff<<<kRedBlocks, kT, 0, s>>>(I, ap, ad, nnz, red.part);
+      }
+      {
+        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+        k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 4);
+      }
+      const double mua = red.fetch(4) / m_pairs;
+      const double sig = std::pow(std::max(mua, 0.0) / mu, 3.0);
+      const double smu = sig * mu;
+      // corrector (centring and second-order terms)
+      {
+        ::bchar::ProfScope ps_("k_ipm_h", s);
+        k_ipm_h<<<gz, kT, 0, s>>>(I, Q.t, 1, smu, nnz);
+      }
+      {
+        ::bchar::ProfScope ps_("k_ipm_rhs", s);
+        k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
+      }
+      pcg(Q.F, cg_tol);
+      {
+        ::bchar::ProfScope ps_("k_ipm_dir", s);
+        k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 1, smu, nnz, red.part);
+      }
+      steps(&ap, &ad);
+      ap = std::min(1.0, 0.995 * ap);
+      ad = std::min(1.0, 0.995 * ad);
+      {
+        ::bchar::ProfScope ps_("k_ipm_update", s);
+        k_ipm_update<<<gz, kT, 0, s>>>(I, Q.t, Q.dt, ap, ad, nnz);
+      }
+      {
+        ::bchar::ProfScope ps_("k_zdual_acc", s);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, ad, n, zdual);
+      }
+      BCHAR_HIP(hipGetLastError());
+    }
+    return false;
+  };
+
+  // ---------------------------------------------------------------- box levels
+  // Level 0 is the paper's box, level 1 keeps x >= -1 only, level 2 keeps
+  // the equalities alone.  A level with a bound is solved by the interior
+  // point followed by semismooth Newton, or, when the previous solve of this
+  // transfer ended at the same level, by semismooth Newton from its
+  // multipliers first (kWarmNewton steps at most).  An interior point that
+  // fails declares the level infeasible.
+  const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
+  const double hi_levels[3] = {1.0, HUGE_VAL, HUGE_VAL};
+  const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : 2;
+  bool converged = false;
+  int level = 0;
+  for (level = 0; level <= max_level; ++level) {
+    const double lo = lo_levels[level], hi = hi_levels[level];
+    if (o.warm_start && warm_level == level) {
+      {
+        ::bchar::ProfScope ps_("k_t_from_z", s);
+        k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
+      }
+      BCHAR_HIP(hipGetLastError());
+      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), " (warm)");
+      if (converged) break;
+    }
+    if (level == 2) {
+      fill_f64(Q.t, 0.0, nnz, s);
+      fill_f64(zdual, 0.0, n2, s);
+      converged = ssn(lo, hi, o.qp_max_newton, "");
+    } else if (ipm(lo, hi)) {
+      converged = ssn(lo, hi, o.qp_max_newton, " (after interior point)");
+    }
     if (converged) break;
   }
   res.residual = fn;
