@@ -49,7 +49,9 @@ constexpr int kRedBlocks = 512;
 constexpr int kMaxCoarse = 512;    // dense coarsest solve
 constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
 constexpr int kIpmMaxIter = 100;   // interior-point iterations per box level
-constexpr int kWarmNewton = 12;    // semismooth steps tried from a warm start
+constexpr double kIpmMuTight = 1e-13;  // complementarity of an accepted interior point
+constexpr int kWarmNewton = 8;     // semismooth steps tried from a warm start
+constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 
 // ====================================================================== reductions
 
@@ -1233,17 +1235,20 @@ __global__ void k_residual(const int32_t* __restrict__ rptr, const int32_t* __re
 }
 
 // fine bipartite weights a_k^2 * free_k in graph order: row part is CSR
-// order, column part is CSC order
+// order, column part is CSC order.  An entry counts as free within `band`
+// outside the box as well: entries at a kink (zero multiplier on an active
+// bound) then keep their cells coupled instead of splitting them into
+// pieces whose multipliers the Newton step would move without bound.
 __global__ void k_fine_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
-                               const double* __restrict__ t, double lo, double hi, int64_t nnz,
-                               double* __restrict__ w) {
+                               const double* __restrict__ t, double lo, double hi, double band,
+                               int64_t nnz, double* __restrict__ w) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
   const double tk = t[k];
-  w[k] = (tk > lo && tk < hi) ? a[k] * a[k] : 0.0;
+  w[k] = (tk > lo - band && tk < hi + band) ? a[k] * a[k] : 0.0;
   const int32_t kp = cpos[k];
   const double tp = t[kp];
-  w[nnz + k] = (tp > lo && tp < hi) ? a[kp] * a[kp] : 0.0;
+  w[nnz + k] = (tp > lo - band && tp < hi + band) ? a[kp] * a[kp] : 0.0;
 }
 
 __global__ void k_fine_graph(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
@@ -1393,16 +1398,19 @@ __global__ void k_axpy2(double* __restrict__ y, const double* __restrict__ x, do
   if (i < n) y[i] += s * x[i];
 }
 
-__global__ void k_final(const double* __restrict__ an, const double* __restrict__ t, double lo,
-                        double hi, int64_t nnz, double* __restrict__ x, double* __restrict__ A,
+// x = clip(t) (semismooth answer) or the interior point's x (xi non-null);
+// counts the entries within `thr` of each bound
+__global__ void k_final(const double* __restrict__ an, const double* __restrict__ t,
+                        const double* __restrict__ xi, double lo, double hi, double thr,
+                        int64_t nnz, double* __restrict__ x, double* __restrict__ A,
                         int32_t* __restrict__ counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  const double xk = clipv(t[k], lo, hi);
+  const double xk = xi ? xi[k] : clipv(t[k], lo, hi);
   x[k] = xk;
   A[k] = an[k] * (1.0 + xk);
-  if (xk == lo) atomicAdd(&counts[0], 1);
-  if (xk == hi) atomicAdd(&counts[1], 1);
+  if (xk - lo <= thr) atomicAdd(&counts[0], 1);
+  if (hi - xk <= thr) atomicAdd(&counts[1], 1);
 }
 
 // ====================================================================== interior point
@@ -1667,7 +1675,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   fill_f64(Q.t, 0.0, nnz, s);
   {
     ::bchar::ProfScope ps_("k_fine_weights", s);
-    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, nnz, fine.w0);
+    k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, 0.0, nnz, fine.w0);
   }
   BCHAR_HIP(hipGetLastError());
   double dmax = 0;
@@ -1802,7 +1810,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // derivative.  Returns true once max |F| <= tol; fn holds the last
   // residual.
   double fn = 0.0;
-  auto ssn = [&](double lo, double hi, int max_it, const char* tag) -> bool {
+  auto ssn = [&](double lo, double hi, int max_it, int patience, const char* tag) -> bool {
+    int short_steps = 0;
     for (int it = 0; it < max_it; ++it) {
       {
         ::bchar::ProfScope ps_("k_residual", s);
@@ -1816,7 +1825,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       ++res.newton;
       {
         ::bchar::ProfScope ps_("k_fine_weights", s);
-        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, nnz, L0.w);
+        // kink band: ten times the residual, at most 1e-2
+        k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, lo, hi, std::min(1e-2, 10.0 * fn),
+                                         nnz, L0.w);
       }
       refresh();
       // inexact Newton: relative inner tolerance on the y-space residual,
@@ -1909,6 +1920,13 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       if (trace_enabled())
         fprintf(stderr, "[bchar]   step %.3e (%d evaluations) slope %.3e\n", step, evals, slope);
+      // steps far below 1 mean directions dominated by multipliers that the
+      // entries on the box leave without curvature: give up after
+      // `patience` of them (0: never)
+      if (step < 1e-3 && patience > 0 && ++short_steps >= patience) {
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: short steps\n");
+        return false;
+      }
       {
         ::bchar::ProfScope ps_("k_axpy2", s);
         k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, step, nnz);
@@ -1928,11 +1946,13 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   };
 
   // ---------------------------------------------------------------- interior point
-  // From x = 0, zl = zu = 1, t = 0.  Returns true once max |B x - r| and
-  // the mean complementarity are both at most 1e-10, leaving t and zdual
-  // for the semismooth iteration to finish; false when the complementarity
+  // From x = 0, zl = zu = 1, t = 0.  Returns 2 once max |B x - r| <= tol
+  // and the mean complementarity is at most kIpmMuTight (its x is then an
+  // answer in its own right, within about mu / z of the minimiser), 1 when
+  // it stalls after reaching 1e-10 on both, 0 when the complementarity
   // grows by 1e8 (the box admits no solution), on a NaN, or after
-  // kIpmMaxIter iterations.
+  // kIpmMaxIter iterations otherwise.  t and zdual are left for the
+  // semismooth iteration to finish from.
   IpmArrays I{};
   I.x = ws.get<double>(nnz + 1);
   I.sl = ws.get<double>(nnz + 1);
@@ -1946,7 +1966,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   I.dzl = ws.get<double>(nnz + 1);
   I.dzu = ws.get<double>(nnz + 1);
   double* rp = ws.get<double>(n2);
-  auto ipm = [&](double lo, double hi) -> bool {
+  double fp_ipm = HUGE_VAL;
+  auto ipm = [&](double lo, double hi) -> int {
     I.lo = lo;
     I.hi = hi;
     I.has_hi = std::isinf(hi) ? 0 : 1;
@@ -1958,7 +1979,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     fill_f64(Q.t, 0.0, nnz, s);
     fill_f64(zdual, 0.0, n2, s);
     BCHAR_HIP(hipGetLastError());
-    double mu0 = -1.0;
+    double mu0 = -1.0, fp_best = HUGE_VAL;
+    int stall = 0;
     auto steps = [&](double* ap, double* ad) {
       {
         ::bchar::ProfScope ps_("k_reduce_final_max", s);
@@ -2001,8 +2023,17 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (trace_enabled())
         fprintf(stderr, "[bchar]   ipm %d: |B x - r| %.3e, mu %.3e, t %.3f s\n", it, fp, mu,
                 wall_seconds());
-      if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return false;
-      if (fp <= 1e-10 && mu <= 1e-10) return true;
+      if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return 0;
+      fp_ipm = fp;
+      if (fp <= tol && mu <= kIpmMuTight) return 2;
+      if (fp <= 1e-10 && mu <= 1e-10) {
+        // stall: no halving of |B x - r| over three iterations
+        if (fp > 0.5 * fp_best && ++stall >= 3) return 1;
+      }
+      if (fp < 0.5 * fp_best) {
+        fp_best = fp;
+        stall = 0;
+      }
       {
         ::bchar::ProfScope ps_("k_ipm_weights", s);
         k_ipm_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, I.D, nnz, L0.w);
@@ -2057,20 +2088,22 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       BCHAR_HIP(hipGetLastError());
     }
-    return false;
+    return fp_best <= 1e-10 ? 1 : 0;
   };
 
   // ---------------------------------------------------------------- box levels
   // Level 0 is the paper's box, level 1 keeps x >= -1 only, level 2 keeps
   // the equalities alone.  A level with a bound is solved by the interior
-  // point followed by semismooth Newton, or, when the previous solve of this
-  // transfer ended at the same level, by semismooth Newton from its
-  // multipliers first (kWarmNewton steps at most).  An interior point that
-  // fails declares the level infeasible.
+  // point followed by semismooth Newton (kPolishNewton steps at most), or,
+  // when the previous solve of this transfer ended at the same level, by
+  // semismooth Newton from its multipliers first (kWarmNewton steps at
+  // most).  The answer is clip(t) when semismooth Newton reaches the
+  // tolerance, else the interior point's x if it reached it.  An interior
+  // point that fails declares the level infeasible.
   const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
   const double hi_levels[3] = {1.0, HUGE_VAL, HUGE_VAL};
   const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : 2;
-  bool converged = false;
+  bool converged = false, ipm_answer = false;
   int level = 0;
   for (level = 0; level <= max_level; ++level) {
     const double lo = lo_levels[level], hi = hi_levels[level];
@@ -2080,15 +2113,23 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
       }
       BCHAR_HIP(hipGetLastError());
-      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), " (warm)");
+      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2, " (warm)");
       if (converged) break;
     }
     if (level == 2) {
       fill_f64(Q.t, 0.0, nnz, s);
       fill_f64(zdual, 0.0, n2, s);
-      converged = ssn(lo, hi, o.qp_max_newton, "");
-    } else if (ipm(lo, hi)) {
-      converged = ssn(lo, hi, o.qp_max_newton, " (after interior point)");
+      converged = ssn(lo, hi, o.qp_max_newton, 0, "");
+    } else {
+      const int r = ipm(lo, hi);
+      if (r > 0) {
+        converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), 2,
+                        " (after interior point)");
+        if (!converged && r == 2) {
+          converged = ipm_answer = true;
+          fn = fp_ipm;
+        }
+      }
     }
     if (converged) break;
   }
@@ -2107,7 +2148,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   fill_i32(counts, 0, 2, s);
   {
     ::bchar::ProfScope ps_("k_final", s);
-    k_final<<<gz, kT, 0, s>>>(AN, Q.t, lo, hi, nnz, x_out, A_out, counts);
+    k_final<<<gz, kT, 0, s>>>(AN, Q.t, ipm_answer ? I.x : nullptr, lo, hi,
+                              ipm_answer ? 1e-12 : 0.0, nnz, x_out, A_out, counts);
   }
   BCHAR_HIP(hipGetLastError());
   int32_t hc[2];
