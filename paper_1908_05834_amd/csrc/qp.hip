@@ -55,25 +55,28 @@ constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 
 // ====================================================================== reductions
 
+// Final combine of the per-block partials by one wave: lane i takes the
+// partials i, i + 64, ... in order, then a fixed butterfly; launched with
+// 64 threads.  The order is fixed, so the result is reproducible.
 __global__ void k_reduce_final_sum(const double* __restrict__ part, int np,
                                    double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
   CSum acc;
-  for (int i = 0; i < np; ++i) {
+  for (int i = threadIdx.x; i < np; i += kWave) {
     CSum o;
     o.hi = part[2 * i];
     o.lo = part[2 * i + 1];
     acc.add(o);
   }
-  out[0] = acc.value();
+  wave_csum(acc);
+  if (threadIdx.x == 0) out[0] = acc.value();
 }
 
 __global__ void k_reduce_final_max(const double* __restrict__ part, int np,
                                    double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
   double m = 0;
-  for (int i = 0; i < np; ++i) m = fmax(m, part[i]);
-  out[0] = m;
+  for (int i = threadIdx.x; i < np; i += kWave) m = fmax(m, part[i]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) out[0] = m;
 }
 
 // dot(a, b) over n, compensated, deterministic (fixed grid)
@@ -184,6 +187,7 @@ struct Level {
 // (k_fused_cycle): their descriptions live in device memory.
 constexpr int kFusedMaxNodes = 8192;
 constexpr int kFusedMaxLevels = 48;
+constexpr int kFusedLds = 7168;     // doubles of LDS for the fused levels' x and a scratch
 
 struct FusedLevels {
   int count;                          // fused levels, the last is the coarsest
@@ -202,6 +206,10 @@ struct FusedLevels {
   double* x[kFusedMaxLevels];
   double* x2[kFusedMaxLevels];
   const double* G;
+  int off[kFusedMaxLevels];           // offset of each level's x in the x store
+  int total, maxn;                    // sum and maximum of n over the fused levels
+  int lds;                            // x store in LDS (else gx, global)
+  double* gx;                         // global x store, total + maxn doubles
 };
 
 // ---------------------------------------------------------------------- level kernels
@@ -579,39 +587,44 @@ __device__ __forceinline__ double lap_resid(const int32_t* ptr, const int32_t* n
 
 // The V-cycle below and including the first fused level, in one workgroup.
 // On entry F->b[0] holds that level's right-hand side; on exit F->x[0]
-// holds the cycle's result.  Every dependent phase is separated by a
-// workgroup barrier.
+// holds the cycle's result.  The iterates of every fused level live in LDS
+// when they fit (F->lds), so that the gathers x[nbr[e]] of the smoothing
+// sweeps, the part of a sweep that waits on memory, hit LDS; the graphs
+// and right-hand sides stay in global memory (independent loads).  Every
+// dependent phase is separated by a workgroup barrier.
 __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
+  __shared__ double sh[kFusedLds];
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int L = F->count;
-  double* cur[kFusedMaxLevels];
-  double* oth[kFusedMaxLevels];
-  for (int l = 0; l < L; ++l) {
-    cur[l] = F->x[l];
-    oth[l] = F->x2[l];
-  }
-  // downward: pre-smoothing and restriction of the residual
-  for (int l = 0; l + 1 < L; ++l) {
+  double* xs = F->lds ? sh : F->gx;
+  double* sc = xs + F->total;
+  // one damped Jacobi sweep of level l on x, through the scratch
+  auto sweep = [&](int l, double* x) {
     const int n = F->n[l];
     const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
     const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
-    for (int p = tid; p < n; p += nt) cur[l][p] = sd[p] * b[p];
+    for (int p = tid; p < n; p += nt) sc[p] = x[p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, x, p);
     __syncthreads();
-    for (int k = 1; k < F->pre; ++k) {
-      for (int p = tid; p < n; p += nt)
-        oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
-      __syncthreads();
-      double* t = cur[l];
-      cur[l] = oth[l];
-      oth[l] = t;
-    }
+    for (int p = tid; p < n; p += nt) x[p] = sc[p];
+    __syncthreads();
+  };
+  // downward: pre-smoothing and restriction of the residual
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = F->n[l];
+    double* x = xs + F->off[l];
+    const double *sd = F->sdinv[l], *b = F->b[l];
+    for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
+    __syncthreads();
+    for (int k = 1; k < F->pre; ++k) sweep(l, x);
+    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
+    const double *w = F->w[l], *dg = F->diag[l];
     const int nc = F->n[l + 1];
     for (int C = tid; C < nc; C += nt) {
       double acc = 0;
       for (int32_t m = F->mptr[l][C]; m < F->mptr[l][C + 1]; ++m)
-        acc += lap_resid(ptr, nbr, w, dg, b, cur[l], F->mem[l][m]);
+        acc += lap_resid(ptr, nbr, w, dg, b, x, F->mem[l][m]);
       F->b[l + 1][C] = acc;
     }
     __syncthreads();
@@ -621,6 +634,7 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     const int l = L - 1;
     const int n = F->n[l];
     const double* b = F->b[l];
+    double* x = xs + F->off[l];
     if (F->dense) {
       double sb = 0;
       for (int p = tid; p < n; p += nt) sb += b[p];
@@ -629,47 +643,30 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       for (int i = tid; i < n; i += nt) {
         double acc = 0;
         for (int j = 0; j < n; ++j) acc += F->G[i * n + j] * (b[j] - bmean);
-        cur[l][i] = acc;
+        x[i] = acc;
         sx += acc;
       }
       const double xmean = block_sum_1024(sx, red) / n;
-      for (int i = tid; i < n; i += nt) cur[l][i] -= xmean;
+      for (int i = tid; i < n; i += nt) x[i] -= xmean;
       __syncthreads();
     } else {
-      const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
-      const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l];
-      for (int p = tid; p < n; p += nt) cur[l][p] = sd[p] * b[p];
+      const double* sd = F->sdinv[l];
+      for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
       __syncthreads();
-      for (int k = 1; k < F->coarse_sweeps; ++k) {
-        for (int p = tid; p < n; p += nt)
-          oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
-        __syncthreads();
-        double* t = cur[l];
-        cur[l] = oth[l];
-        oth[l] = t;
-      }
+      for (int k = 1; k < F->coarse_sweeps; ++k) sweep(l, x);
     }
   }
   // upward: prolongation and post-smoothing
   for (int l = L - 2; l >= 0; --l) {
     const int n = F->n[l];
-    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l], *agg = F->agg[l];
-    const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
-    const double* e = cur[l + 1];
-    for (int p = tid; p < n; p += nt) cur[l][p] += e[agg[p]];
+    const int32_t* agg = F->agg[l];
+    double* x = xs + F->off[l];
+    const double* e = xs + F->off[l + 1];
+    for (int p = tid; p < n; p += nt) x[p] += e[agg[p]];
     __syncthreads();
-    for (int k = 0; k < F->post; ++k) {
-      for (int p = tid; p < n; p += nt)
-        oth[l][p] = cur[l][p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, cur[l], p);
-      __syncthreads();
-      double* t = cur[l];
-      cur[l] = oth[l];
-      oth[l] = t;
-    }
+    for (int k = 0; k < F->post; ++k) sweep(l, x);
   }
-  if (cur[0] != F->x[0]) {
-    for (int p = tid; p < F->n[0]; p += nt) F->x[0][p] = cur[0][p];
-  }
+  for (int p = tid; p < F->n[0]; p += nt) F->x[0][p] = xs[p];
 }
 
 // ====================================================================== hierarchy
@@ -840,12 +837,20 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   H.coarse_n = (int)last.n;
   H.dense = last.n <= kMaxCoarse;
   if (H.dense) H.G = ws.get<double>((size_t)last.n * last.n + 1);
-  // the cell levels from the first one with at most kFusedMaxNodes nodes
-  // down to the coarsest run in one workgroup
+  // the coarsest cell levels run in one workgroup: as many as keep their
+  // iterates (plus a scratch of the largest) within kFusedLds doubles of
+  // LDS; if even the coarsest does not fit, the levels of at most
+  // kFusedMaxNodes nodes with a global store
   size_t first = H.lv.size() - 1;
-  while (first > 1 && H.lv[first - 1].n <= kFusedMaxNodes &&
-         H.lv.size() - (first - 1) <= (size_t)kFusedMaxLevels)
+  int64_t total = H.lv[first].n, maxn = H.lv[first].n;
+  const bool lds = total + maxn <= kFusedLds;
+  while (first > 1 && H.lv.size() - (first - 1) <= (size_t)kFusedMaxLevels) {
+    const int64_t nn = H.lv[first - 1].n;
+    if (lds ? total + nn + std::max(maxn, nn) > kFusedLds : nn > kFusedMaxNodes) break;
+    total += nn;
+    maxn = std::max(maxn, nn);
     --first;
+  }
   H.fused_first = first;
   FusedLevels hf{};
   hf.count = (int)(H.lv.size() - first);
@@ -854,8 +859,14 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   hf.post = H.post;
   hf.coarse_sweeps = H.coarse_sweeps;
   hf.G = H.G;
-  for (int k = 0; k < hf.count; ++k) {
+  hf.total = (int)total;
+  hf.maxn = (int)maxn;
+  hf.lds = lds ? 1 : 0;
+  hf.gx = lds ? nullptr : ws.get<double>((size_t)(total + maxn));
+  for (int k = 0, o = 0; k < hf.count; ++k) {
     Level& Lk = H.lv[first + k];
+    hf.off[k] = o;
+    o += (int)Lk.n;
     hf.n[k] = (int)Lk.n;
     hf.ptr[k] = Lk.ptr;
     hf.nbr[k] = Lk.nbr;
@@ -2026,22 +2037,21 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return 0;
       fp_ipm = fp;
       if (fp <= tol && mu <= kIpmMuTight) return 2;
-      if (fp <= 1e-10 && mu <= 1e-10) {
-        // stall: no halving of |B x - r| over three iterations
-        if (fp > 0.5 * fp_best && ++stall >= 3) return 1;
+      if (fp_best <= 1e-10 && mu <= 1e-10 && fp > 0.5 * fp_best) {
+        // stalled: |B x - r| no longer halves
+        if (++stall >= 2) return 1;
       }
-      if (fp < 0.5 * fp_best) {
-        fp_best = fp;
-        stall = 0;
-      }
+      if (fp < fp_best) fp_best = fp;
       {
         ::bchar::ProfScope ps_("k_ipm_weights", s);
         k_ipm_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, I.D, nnz, L0.w);
       }
       refresh();
       const double cg_tol = std::max(1e-2 * std::min(fv, mu), 1e-15);
-      // predictor (affine scaling)
-      pcg(Q.F, cg_tol);
+      // predictor (affine scaling).  Once the normal equations are too
+      // ill-conditioned for CG to reach its tolerance the step would spoil
+      // the iterate: hand it over as it is.
+      if (pcg(Q.F, cg_tol) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 0, 0.0, nnz, red.part);
@@ -2070,7 +2080,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         ::bchar::ProfScope ps_("k_ipm_rhs", s);
         k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
       }
-      pcg(Q.F, cg_tol);
+      if (pcg(Q.F, cg_tol) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 1, smu, nnz, red.part);
@@ -2128,6 +2138,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         if (!converged && r == 2) {
           converged = ipm_answer = true;
           fn = fp_ipm;
+        } else if (!converged) {
+          // the interior point stalled short of the tolerance: semismooth
+          // Newton without the step-count cap
+          converged = ssn(lo, hi, o.qp_max_newton, 0, " (after interior point)");
         }
       }
     }
