@@ -263,6 +263,26 @@ __global__ void k_smooth_first(const double* __restrict__ sdinv, const double* _
   if (p < n) x[p] = sdinv[p] * b[p];
 }
 
+// Row kernels of the cell levels give each node kNodeLanes lanes, which
+// stride its ~10 edges and combine with xor shuffles in a fixed order: the
+// gathers x[nbr[e]] of a node then wait on memory side by side instead of
+// one after another.
+constexpr int kNodeLanes = 4;
+
+// (L x)[p] - diag[p] x[p] summed over the lanes of node p's group
+__device__ __forceinline__ double lanes_offdiag(const int32_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ nbr,
+                                                const double* __restrict__ w,
+                                                const double* __restrict__ x, int64_t p,
+                                                int sub, bool live) {
+  double s = 0.0;
+  if (live)
+    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) s += w[e] * x[nbr[e]];
+  s += __shfl_xor(s, 1, kWave);
+  s += __shfl_xor(s, 2, kWave);
+  return s;
+}
+
 // xo = xi + sdinv (b - L xi)
 __global__ void __launch_bounds__(kT) k_smooth(const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ nbr,
@@ -272,29 +292,37 @@ __global__ void __launch_bounds__(kT) k_smooth(const int32_t* __restrict__ ptr,
                                                const double* __restrict__ b,
                                                const double* __restrict__ xi, int64_t n,
                                                double* __restrict__ xo) {
-  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (p >= n) return;
-  double s = diag[p] * xi[p];
-  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * xi[nbr[e]];
-  xo[p] = xi[p] + sdinv[p] * (b[p] - s);
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t p = g / kNodeLanes;
+  const int sub = (int)(g % kNodeLanes);
+  const bool live = p < n;
+  const double off = lanes_offdiag(ptr, nbr, w, xi, p, sub, live);
+  if (live && sub == 0) xo[p] = xi[p] + sdinv[p] * (b[p] - (diag[p] * xi[p] - off));
 }
 
-// bc[C] = sum over members p of C of (b - L x)[p]
-__global__ void __launch_bounds__(kT) k_resid_restrict(
-    const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
-    const double* __restrict__ w, const double* __restrict__ diag,
-    const double* __restrict__ b, const double* __restrict__ x,
-    const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem, int64_t nc,
-    double* __restrict__ bc) {
-  const int64_t C = (int64_t)blockIdx.x * kT + threadIdx.x;
+// r = b - L x
+__global__ void __launch_bounds__(kT) k_resid(const int32_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ nbr,
+                                              const double* __restrict__ w,
+                                              const double* __restrict__ diag,
+                                              const double* __restrict__ b,
+                                              const double* __restrict__ x, int64_t n,
+                                              double* __restrict__ r) {
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t p = g / kNodeLanes;
+  const int sub = (int)(g % kNodeLanes);
+  const bool live = p < n;
+  const double off = lanes_offdiag(ptr, nbr, w, x, p, sub, live);
+  if (live && sub == 0) r[p] = b[p] - (diag[p] * x[p] - off);
+}
+
+// bc[C] = sum of r over the members of C
+__global__ void k_restrict(const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+                           const double* __restrict__ r, int64_t nc, double* __restrict__ bc) {
+  const int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= nc) return;
-  double acc = 0;
-  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) {
-    const int32_t p = mem[m];
-    double s = diag[p] * x[p];
-    for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
-    acc += b[p] - s;
-  }
+  double acc = 0.0;
+  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) acc += r[mem[m]];
   bc[C] = acc;
 }
 
@@ -639,12 +667,20 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       double sb = 0;
       for (int p = tid; p < n; p += nt) sb += b[p];
       const double bmean = block_sum_1024(sb, red) / n;
+      // x = G (b - mean b): 16 lanes per row, rows strided over the groups
+      constexpr int kRowLanes = 16;
+      const int sub = tid % kRowLanes;
       double sx = 0;
-      for (int i = tid; i < n; i += nt) {
+      // (the 16 lanes of a group share i, so each shuffle stays in a group
+      // whose lanes are all active)
+      for (int i = tid / kRowLanes; i < n; i += nt / kRowLanes) {
         double acc = 0;
-        for (int j = 0; j < n; ++j) acc += F->G[i * n + j] * (b[j] - bmean);
-        x[i] = acc;
-        sx += acc;
+        for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * (b[j] - bmean);
+        for (int o = kRowLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+        if (sub == 0) {
+          x[i] = acc;
+          sx += acc;
+        }
       }
       const double xmean = block_sum_1024(sx, red) / n;
       for (int i = tid; i < n; i += nt) x[i] -= xmean;
@@ -922,8 +958,8 @@ static void smooth_steps(Level& L, const double* b, double*& x, double*& x2, int
   for (; k < steps; ++k) {
     {
       ::bchar::ProfScope ps_("k_smooth", s);
-      k_smooth<<<blocks_for(L.n, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, b, x, L.n,
-                                                  x2);
+      k_smooth<<<blocks_for(L.n * kNodeLanes, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag,
+                                                               L.sdinv, b, x, L.n, x2);
     }
     std::swap(x, x2);
   }
@@ -947,10 +983,16 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   double* x = L.x;
   double* x2 = L.x2;
   smooth_steps(L, L.b, x, x2, pre, true, s);
+  // residual into the other buffer (free after the pre-smoothing), then
+  // summed over each aggregate
   {
-    ::bchar::ProfScope ps_("k_resid_restrict", s);
-    k_resid_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, x, L.mptr,
-                                                        L.mem, C.n, C.b);
+    ::bchar::ProfScope ps_("k_resid", s);
+    k_resid<<<blocks_for(L.n * kNodeLanes, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, x,
+                                                             L.n, x2);
+  }
+  {
+    ::bchar::ProfScope ps_("k_restrict", s);
+    k_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.mptr, L.mem, x2, C.n, C.b);
   }
   vcycle(H, l + 1, s);
   {
