@@ -187,7 +187,7 @@ struct Level {
 // (k_fused_cycle): their descriptions live in device memory.
 constexpr int kFusedMaxNodes = 8192;
 constexpr int kFusedMaxLevels = 48;
-constexpr int kFusedLds = 7168;     // doubles of LDS for the fused levels' x and a scratch
+constexpr int kFusedLds = 7168;     // doubles of LDS for two iterates of every fused level
 
 struct FusedLevels {
   int count;                          // fused levels, the last is the coarsest
@@ -207,9 +207,10 @@ struct FusedLevels {
   double* x2[kFusedMaxLevels];
   const double* G;
   int off[kFusedMaxLevels];           // offset of each level's x in the x store
-  int total, maxn;                    // sum and maximum of n over the fused levels
+  int ne[kFusedMaxLevels];            // edges of each fused level
+  int total;                          // sum of n over the fused levels
   int lds;                            // x store in LDS (else gx, global)
-  double* gx;                         // global x store, total + maxn doubles
+  double* gx;                         // global x store, 2 total doubles
 };
 
 // ---------------------------------------------------------------------- level kernels
@@ -615,11 +616,11 @@ __device__ __forceinline__ double lap_resid(const int32_t* ptr, const int32_t* n
 
 // The V-cycle below and including the first fused level, in one workgroup.
 // On entry F->b[0] holds that level's right-hand side; on exit F->x[0]
-// holds the cycle's result.  The iterates of every fused level live in LDS
+// holds the cycle's result.  Two iterates of every fused level live in LDS
 // when they fit (F->lds), so that the gathers x[nbr[e]] of the smoothing
-// sweeps, the part of a sweep that waits on memory, hit LDS; the graphs
-// and right-hand sides stay in global memory (independent loads).  Every
-// dependent phase is separated by a workgroup barrier.
+// sweeps hit LDS and a Jacobi sweep is one pass and one barrier; the
+// graphs and right-hand sides stay in global memory (independent loads).
+// Every dependent phase is separated by a workgroup barrier.
 __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
   __shared__ double sh[kFusedLds];
@@ -627,25 +628,55 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
   const int nt = blockDim.x;
   const int L = F->count;
   double* xs = F->lds ? sh : F->gx;
-  double* sc = xs + F->total;
-  // one damped Jacobi sweep of level l on x, through the scratch
-  auto sweep = [&](int l, double* x) {
+  // Touch every array the cycle reads, all threads at once and coalesced,
+  // before the first dependent phase: the kernels of the finer levels have
+  // streamed them out of L2 since the previous cycle, and each phase below
+  // would otherwise wait on memory two or three times in a row.
+  {
+    double acc = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const int n = F->n[l], ne = F->ne[l];
+      for (int p = tid; p < ne; p += nt) acc += F->w[l][p] + (double)F->nbr[l][p];
+      for (int p = tid; p <= n; p += nt) acc += (double)F->ptr[l][p];
+      for (int p = tid; p < n; p += nt) acc += F->diag[l][p] + F->sdinv[l][p];
+      if (l + 1 < L) {
+        for (int p = tid; p < n; p += nt) acc += (double)(F->agg[l][p] + F->mem[l][p]);
+        for (int p = tid; p <= F->n[l + 1]; p += nt) acc += (double)F->mptr[l][p];
+      }
+    }
+    if (F->dense) {
+      const int nn = F->n[L - 1] * F->n[L - 1];
+      for (int p = tid; p < nn; p += nt) acc += F->G[p];
+    }
+    // a store that never happens keeps the loads
+    if (acc == -1.0) red[0] = acc;
+  }
+  // level l's current iterate is xs + off[l] + (par[l] ? total : 0)
+  int par[kFusedMaxLevels];
+  for (int l = 0; l < L; ++l) par[l] = 0;
+  auto X = [&](int l) { return xs + F->off[l] + (par[l] ? F->total : 0); };
+  // one damped Jacobi sweep of level l into its other buffer
+  auto sweep = [&](int l) {
     const int n = F->n[l];
     const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
     const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
-    for (int p = tid; p < n; p += nt) sc[p] = x[p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, x, p);
-    __syncthreads();
-    for (int p = tid; p < n; p += nt) x[p] = sc[p];
+    const double* x = X(l);
+    double* y = xs + F->off[l] + (par[l] ? 0 : F->total);
+    for (int p = tid; p < n; p += nt) y[p] = x[p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, x, p);
+    par[l] ^= 1;
     __syncthreads();
   };
   // downward: pre-smoothing and restriction of the residual
   for (int l = 0; l + 1 < L; ++l) {
     const int n = F->n[l];
-    double* x = xs + F->off[l];
     const double *sd = F->sdinv[l], *b = F->b[l];
-    for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
+    {
+      double* x = X(l);
+      for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
+    }
     __syncthreads();
-    for (int k = 1; k < F->pre; ++k) sweep(l, x);
+    for (int k = 1; k < F->pre; ++k) sweep(l);
+    const double* x = X(l);
     const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
     const double *w = F->w[l], *dg = F->diag[l];
     const int nc = F->n[l + 1];
@@ -662,7 +693,7 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     const int l = L - 1;
     const int n = F->n[l];
     const double* b = F->b[l];
-    double* x = xs + F->off[l];
+    double* x = X(l);
     if (F->dense) {
       double sb = 0;
       for (int p = tid; p < n; p += nt) sb += b[p];
@@ -689,20 +720,23 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       const double* sd = F->sdinv[l];
       for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
       __syncthreads();
-      for (int k = 1; k < F->coarse_sweeps; ++k) sweep(l, x);
+      for (int k = 1; k < F->coarse_sweeps; ++k) sweep(l);
     }
   }
   // upward: prolongation and post-smoothing
   for (int l = L - 2; l >= 0; --l) {
     const int n = F->n[l];
     const int32_t* agg = F->agg[l];
-    double* x = xs + F->off[l];
-    const double* e = xs + F->off[l + 1];
+    double* x = X(l);
+    const double* e = X(l + 1);
     for (int p = tid; p < n; p += nt) x[p] += e[agg[p]];
     __syncthreads();
-    for (int k = 0; k < F->post; ++k) sweep(l, x);
+    for (int k = 0; k < F->post; ++k) sweep(l);
   }
-  for (int p = tid; p < F->n[0]; p += nt) F->x[0][p] = xs[p];
+  {
+    const double* x = X(0);
+    for (int p = tid; p < F->n[0]; p += nt) F->x[0][p] = x[p];
+  }
 }
 
 // ====================================================================== hierarchy
@@ -878,13 +912,12 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   // LDS; if even the coarsest does not fit, the levels of at most
   // kFusedMaxNodes nodes with a global store
   size_t first = H.lv.size() - 1;
-  int64_t total = H.lv[first].n, maxn = H.lv[first].n;
-  const bool lds = total + maxn <= kFusedLds;
+  int64_t total = H.lv[first].n;
+  const bool lds = 2 * total <= kFusedLds;
   while (first > 1 && H.lv.size() - (first - 1) <= (size_t)kFusedMaxLevels) {
     const int64_t nn = H.lv[first - 1].n;
-    if (lds ? total + nn + std::max(maxn, nn) > kFusedLds : nn > kFusedMaxNodes) break;
+    if (lds ? 2 * (total + nn) > kFusedLds : nn > kFusedMaxNodes) break;
     total += nn;
-    maxn = std::max(maxn, nn);
     --first;
   }
   H.fused_first = first;
@@ -896,13 +929,13 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   hf.coarse_sweeps = H.coarse_sweeps;
   hf.G = H.G;
   hf.total = (int)total;
-  hf.maxn = (int)maxn;
   hf.lds = lds ? 1 : 0;
-  hf.gx = lds ? nullptr : ws.get<double>((size_t)(total + maxn));
+  hf.gx = lds ? nullptr : ws.get<double>((size_t)(2 * total));
   for (int k = 0, o = 0; k < hf.count; ++k) {
     Level& Lk = H.lv[first + k];
     hf.off[k] = o;
     o += (int)Lk.n;
+    hf.ne[k] = (int)Lk.ne;
     hf.n[k] = (int)Lk.n;
     hf.ptr[k] = Lk.ptr;
     hf.nbr[k] = Lk.nbr;
@@ -2175,7 +2208,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     } else {
       const int r = ipm(lo, hi);
       if (r > 0) {
-        converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), 2,
+        // an interior point at the tolerance is an answer already: one
+        // short semismooth step is enough to give up on the exact one
+        converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
                         " (after interior point)");
         if (!converged && r == 2) {
           converged = ipm_answer = true;
