@@ -65,17 +65,19 @@ __global__ void __launch_bounds__(256) k_mass_part(const double* __restrict__ b,
   }
 }
 
+// one wave: lane i combines the partials i, i + 64, ... in order, then a
+// fixed butterfly (reproducible)
 __global__ void k_mass_final(const double* __restrict__ part, int nparts,
                              double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   CSum acc;
-  for (int i = 0; i < nparts; ++i) {
+  for (int i = threadIdx.x; i < nparts; i += kWave) {
     CSum o;
     o.hi = part[2 * i];
     o.lo = part[2 * i + 1];
     acc.add(o);
   }
-  out[0] = acc.value();
+  wave_csum(acc);
+  if (threadIdx.x == 0) out[0] = acc.value();
 }
 
 double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_t s) {

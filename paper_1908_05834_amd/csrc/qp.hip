@@ -243,27 +243,6 @@ __global__ void k_node_count(const int32_t* __restrict__ mptr, const int32_t* __
   cnt[C] = c;
 }
 
-// y = L x  (L = diag - W)
-__global__ void __launch_bounds__(kT) k_lap(const int32_t* __restrict__ ptr,
-                                            const int32_t* __restrict__ nbr,
-                                            const double* __restrict__ w,
-                                            const double* __restrict__ diag,
-                                            const double* __restrict__ x, int64_t n,
-                                            double* __restrict__ y) {
-  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (p >= n) return;
-  double s = diag[p] * x[p];
-  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
-  y[p] = s;
-}
-
-// x = sdinv * b
-__global__ void k_smooth_first(const double* __restrict__ sdinv, const double* __restrict__ b,
-                               int64_t n, double* __restrict__ x) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) x[p] = sdinv[p] * b[p];
-}
-
 // Row kernels of the cell levels give each node kNodeLanes lanes, which
 // stride its ~10 edges and combine with xor shuffles in a fixed order: the
 // gathers x[nbr[e]] of a node then wait on memory side by side instead of
@@ -301,6 +280,33 @@ __global__ void __launch_bounds__(kT) k_smooth(const int32_t* __restrict__ ptr,
   if (live && sub == 0) xo[p] = xi[p] + sdinv[p] * (b[p] - (diag[p] * xi[p] - off));
 }
 
+// Two Jacobi sweeps from zero in one pass: x1 = sdinv b is formed where it
+// is gathered, xo = x1 + sdinv (b - L x1)
+__global__ void __launch_bounds__(kT) k_smooth_zero2(const int32_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ nbr,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ sdinv,
+                                                     const double* __restrict__ b, int64_t n,
+                                                     double* __restrict__ xo) {
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t p = g / kNodeLanes;
+  const int sub = (int)(g % kNodeLanes);
+  const bool live = p < n;
+  double s = 0.0;
+  if (live)
+    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) {
+      const int32_t q = nbr[e];
+      s += w[e] * (sdinv[q] * b[q]);
+    }
+  s += __shfl_xor(s, 1, kWave);
+  s += __shfl_xor(s, 2, kWave);
+  if (live && sub == 0) {
+    const double x1 = sdinv[p] * b[p];
+    xo[p] = x1 + sdinv[p] * (b[p] - (diag[p] * x1 - s));
+  }
+}
+
 // r = b - L x
 __global__ void __launch_bounds__(kT) k_resid(const int32_t* __restrict__ ptr,
                                               const int32_t* __restrict__ nbr,
@@ -327,10 +333,30 @@ __global__ void k_restrict(const int32_t* __restrict__ mptr, const int32_t* __re
   bc[C] = acc;
 }
 
-__global__ void k_prolong(const int32_t* __restrict__ agg, const double* __restrict__ xc,
-                          int64_t n, double* __restrict__ x) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) x[p] += xc[agg[p]];
+// Prolongation and the first post-smoothing sweep in one pass: y = x +
+// xc[agg] is formed where it is gathered, xo = y + sdinv (b - L y)
+__global__ void __launch_bounds__(kT) k_prolong_smooth(
+    const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
+    const double* __restrict__ w, const double* __restrict__ diag,
+    const double* __restrict__ sdinv, const double* __restrict__ b,
+    const double* __restrict__ x, const int32_t* __restrict__ agg,
+    const double* __restrict__ xc, int64_t n, double* __restrict__ xo) {
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t p = g / kNodeLanes;
+  const int sub = (int)(g % kNodeLanes);
+  const bool live = p < n;
+  double s = 0.0;
+  if (live)
+    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) {
+      const int32_t q = nbr[e];
+      s += w[e] * (x[q] + xc[agg[q]]);
+    }
+  s += __shfl_xor(s, 1, kWave);
+  s += __shfl_xor(s, 2, kWave);
+  if (live && sub == 0) {
+    const double y = x[p] + xc[agg[p]];
+    xo[p] = y + sdinv[p] * (b[p] - (diag[p] * y - s));
+  }
 }
 
 // coarse weights: sum of the fine edge weights of each coarse entry
@@ -747,7 +773,7 @@ struct Hierarchy {
   double* G = nullptr;   // inverse of the shifted coarsest matrix
   int coarse_n = 0;
   bool dense = false;
-  int fine_pre = 2, fine_post = 2, pre = 2, post = 2;
+  int pre = 2, post = 2;             // sweeps of the fused coarse levels
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
   FusedLevels* fused = nullptr;    // device copy
@@ -978,26 +1004,6 @@ static void refresh_hierarchy(Hierarchy& H, hipStream_t s) {
   }
 }
 
-static void smooth_steps(Level& L, const double* b, double*& x, double*& x2, int steps,
-                         bool from_zero, hipStream_t s) {
-  int k = 0;
-  if (from_zero && steps > 0) {
-    {
-      ::bchar::ProfScope ps_("k_smooth_first", s);
-      k_smooth_first<<<blocks_for(L.n, kT), kT, 0, s>>>(L.sdinv, b, L.n, x);
-    }
-    k = 1;
-  }
-  for (; k < steps; ++k) {
-    {
-      ::bchar::ProfScope ps_("k_smooth", s);
-      k_smooth<<<blocks_for(L.n * kNodeLanes, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag,
-                                                               L.sdinv, b, x, L.n, x2);
-    }
-    std::swap(x, x2);
-  }
-}
-
 // x_l = cycle(b_l); on return H.lv[l].x holds the result.
 static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   Level& L = H.lv[l];
@@ -1010,32 +1016,32 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
     BCHAR_HIP(hipGetLastError());
     return;
   }
+  // two damped Jacobi sweeps before and after the coarse correction, in
+  // five launches: both pre-sweeps, residual, restriction, prolongation
+  // with the first post-sweep, the second post-sweep (result in L.x)
   Level& C = H.lv[l + 1];
-  const int pre = l == 0 ? H.fine_pre : H.pre;
-  const int post = l == 0 ? H.fine_post : H.post;
-  double* x = L.x;
-  double* x2 = L.x2;
-  smooth_steps(L, L.b, x, x2, pre, true, s);
-  // residual into the other buffer (free after the pre-smoothing), then
-  // summed over each aggregate
+  const unsigned gl = blocks_for(L.n * kNodeLanes, kT);
+  {
+    ::bchar::ProfScope ps_("k_smooth_zero2", s);
+    k_smooth_zero2<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.n, L.x);
+  }
   {
     ::bchar::ProfScope ps_("k_resid", s);
-    k_resid<<<blocks_for(L.n * kNodeLanes, kT), kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, x,
-                                                             L.n, x2);
+    k_resid<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, L.x, L.n, L.x2);
   }
   {
     ::bchar::ProfScope ps_("k_restrict", s);
-    k_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.mptr, L.mem, x2, C.n, C.b);
+    k_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.mptr, L.mem, L.x2, C.n, C.b);
   }
   vcycle(H, l + 1, s);
   {
-    ::bchar::ProfScope ps_("k_prolong", s);
-    k_prolong<<<blocks_for(L.n, kT), kT, 0, s>>>(L.agg, C.x, L.n, x);
+    ::bchar::ProfScope ps_("k_prolong_smooth", s);
+    k_prolong_smooth<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.x, L.agg, C.x,
+                                        L.n, L.x2);
   }
-  smooth_steps(L, L.b, x, x2, post, false, s);
-  if (x != L.x) {
-    // keep the result in L.x
-    std::swap(L.x, L.x2);
+  {
+    ::bchar::ProfScope ps_("k_smooth", s);
+    k_smooth<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.x2, L.n, L.x);
   }
   BCHAR_HIP(hipGetLastError());
 }
@@ -1832,7 +1838,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // the per-cell coordinates with the constant-s direction removed.  Leaves
   // the per-cell solution in cx, the multiplier direction in dmu, dnu and
   // the entry increments a_k (dmu_K + dnu_M) in Q.dt; returns iterations.
-  auto pcg = [&](const double* fv, double cg_tol) -> int {
+  auto pcg = [&](const double* fv, double cg_tol, bool from_cx) -> int {
     {
       ::bchar::ProfScope ps_("k_zrhs", s);
       k_zrhs<<<gn, kT, 0, s>>>(fv, n, cr);
@@ -1842,7 +1848,19 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       ::bchar::ProfScope ps_("k_sub_scalar", s);
       k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, 1.0 / (double)n, n);
     }
-    fill_f64(cx, 0.0, n2, s);
+    if (from_cx) {
+      // start from the solution already in cx: r = rhs - J cx
+      {
+        ::bchar::ProfScope ps_("k_zop", s);
+        k_zop<<<gn, kT, 0, s>>>(P.Z, cx, cq);
+      }
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gn2, kT, 0, s>>>(cr, cq, -1.0, n2);
+      }
+    } else {
+      fill_f64(cx, 0.0, n2, s);
+    }
     // scalars: out[8] = rz, out[9] = pq, out[10] = rz_new, out[11] = max |r|
     zprecondition(P, cr, cz, s);
     BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
@@ -1920,7 +1938,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // near-exact once many steps were needed
       const double eta = it < 30 ? std::min(0.1, std::sqrt(fn)) * 0.1 : 1e-6;
       const double cg_tol = std::max(eta * fn, 0.1 * tol);
-      const int k = pcg(Q.F, cg_tol);
+      const int k = pcg(Q.F, cg_tol, false);
       if (trace_enabled()) {
         red.maxabs(cr, n2, 11);
         fprintf(stderr, "[bchar]   newton %d%s: |F| %.3e, cg %d (|r| %.3e of %.3e), t %.3f s\n",
@@ -2126,7 +2144,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // predictor (affine scaling).  Once the normal equations are too
       // ill-conditioned for CG to reach its tolerance the step would spoil
       // the iterate: hand it over as it is.
-      if (pcg(Q.F, cg_tol) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      if (pcg(Q.F, cg_tol, false) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 0, 0.0, nnz, red.part);
@@ -2155,7 +2173,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         ::bchar::ProfScope ps_("k_ipm_rhs", s);
         k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
       }
-      if (pcg(Q.F, cg_tol) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      // the corrector's system differs from the predictor's in the
+      // right-hand side only: start CG from the predictor's solution
+      if (pcg(Q.F, cg_tol, true) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 1, smu, nnz, red.part);
