@@ -29,15 +29,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+SRC = os.path.join(ROOT, "paper_1908_05834_amd", "csrc")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, n_cells, nnz, n_balls):
+def algorithmic_bytes(kernel, n_cells, nnz, n_balls, stats):
     """Bytes a launch of ``kernel`` must move at least (each array read or
     written once; gathers of vector entries counted once per cell)."""
+    if kernel == "k_fused_cycle":
+        # the coarsest levels of the preconditioner, one workgroup: their
+        # graphs, diagonals, right-hand sides, aggregation and the dense
+        # inverse, as counted by the library for the last solve
+        return stats["qp_coarse_bytes"]
     if kernel == "k_zsmooth":
         # per cell: s,g in (16), rhs (16), block inverse (24), shifts (16),
         # row_ptr and col_ptr (8), diagonal position (4), out (16); per
@@ -47,14 +53,57 @@ def algorithmic_bytes(kernel, n_cells, nnz, n_balls):
     if kernel == "k_zop":
         return n_cells * (16 + 16 + 8 + 4 + 16) + 2 * nnz * 12
     if kernel == "k_assemble":
-        # tracked centre and radius (32), 8 residing balls (32 each) read
-        # through the hash, phi (8), CSR out (12 per entry)
-        return n_balls * (32 + 32) + n_cells * 8 + nnz * 12
+        # two launches per build, a counting pass and a filling pass, both
+        # reading the tracked centre and radius (32 per ball), the residing
+        # balls through the hash (32 per ball) and phi (8 per cell); the
+        # filling pass writes the CSR entries (12 each): per launch, the
+        # inputs and half the output
+        return n_balls * (32 + 32) + n_cells * 8 + nnz * 12 // 2
     if kernel == "k_trace":
         # centre in, tracked centre and radius out, velocity lattice (24 B
         # per node, about one node per cell)
         return n_balls * (24 + 32) + n_cells * 24
     raise KeyError(kernel)
+
+
+def source_digest():
+    """Digest of the HIP sources: a measured traffic figure is valid only for
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(SRC)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(SRC, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 --pmc
+    measurement (profiles/traffic_<kernel>.json), or None when there is
+    none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration(mib):
+    """A plain device copy of ``mib`` MiB, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters against a kernel of known traffic."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8,
+                      "launches": 3}))
 
 
 def cpu_baseline(sample_n=16):
@@ -88,11 +137,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--roofline-kernel", default="k_zsmooth")
+    ap.add_argument("--roofline-kernel", default="k_fused_cycle")
+    ap.add_argument("--build-kernel", default="k_assemble")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     args = ap.parse_args()
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -149,20 +204,33 @@ def main():
     t1 = time.perf_counter()
     launches, kms = bchar.profile_read()
     bchar.profile_kernel(None)
+    # the build kernel, timed the same way over one more (untimed) step
+    bchar.profile_kernel(args.build_kernel)
+    T.rebuild(vels[total - 1], w["dt"], opts)
+    torch.cuda.synchronize()
+    b_launches, b_kms = bchar.profile_read()
+    bchar.profile_kernel(None)
 
     elapsed = t1 - t0
     n_cells = M.n_cells
     value = n_cells * args.steps / elapsed
     nnz = stats[-1]["nnz"]
     roof = None
-    if launches > 0:
-        avg_s = kms / 1e3 / launches
-        alg = algorithmic_bytes(args.roofline_kernel, n_cells, nnz, M.n_balls)
+    def roofline(kernel, n_launch, total_ms, st):
+        if n_launch <= 0:
+            return None
+        avg_s = total_ms / 1e3 / n_launch
+        alg = algorithmic_bytes(kernel, n_cells, st["nnz"], M.n_balls, st)
         achieved = alg / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": args.roofline_kernel, "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "launches": launches, "avg_us": avg_s * 1e6,
+        traffic = measured_traffic(kernel)
+        return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "launches": n_launch, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes_per_launch": alg}
+
+    if launches > 0:
+        roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
+    roof_build = roofline(args.build_kernel, b_launches, b_kms, T.stats)
     out = {
         "metric": "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency",
         "value": value,
@@ -185,6 +253,7 @@ def main():
         "mass_ok": bool(mass_err <= 1e-12),
         "max_rel_mass_err": mass_err,
         "roofline": roof,
+        "roofline_build": roof_build,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

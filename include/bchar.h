@@ -145,6 +145,9 @@ typedef struct {
   int64_t n_at_lower;          /* entries with 1 + x = 0                  */
   int64_t n_at_upper;          /* entries with 1 + x = 2                  */
   int qp_ipm;                  /* interior-point iterations (all levels)  */
+  int64_t qp_coarse_bytes;     /* bytes one cycle over the coarsest levels
+                                  of the preconditioner (one workgroup)
+                                  reads or writes at least              */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */

@@ -170,6 +170,7 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
 // QP (qp.hip)
 struct QpResult {
   int level = 0, newton = 0, cg = 0, ipm = 0;
+  int64_t coarse_bytes = 0;   // bytes one coarse-level cycle moves at least
   double residual = 0;
   int64_t at_lower = 0, at_upper = 0;
 };

@@ -777,6 +777,7 @@ struct Hierarchy {
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
   FusedLevels* fused = nullptr;    // device copy
+  int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least once
 };
 
 static void level_refresh_diag(Level& L, double mu, hipStream_t s) {
@@ -975,6 +976,16 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     hf.x[k] = Lk.x;
     hf.x2[k] = Lk.x2;
   }
+  // bytes one fused cycle must move: each level's graph (index and weight
+  // per edge, row pointers), diagonal, smoother step, right-hand side and
+  // aggregation, the coarsest inverse, and the result
+  H.fused_bytes = 8 * H.lv[first].n;
+  for (int k = 0; k < hf.count; ++k) {
+    const int64_t nk = hf.n[k], ek = hf.ne[k];
+    H.fused_bytes += 12 * ek + 4 * (nk + 1) + 24 * nk;
+    if (k + 1 < hf.count) H.fused_bytes += 8 * nk + 4 * (hf.n[k + 1] + 1);
+  }
+  if (H.dense) H.fused_bytes += 8 * (int64_t)H.coarse_n * H.coarse_n;
   H.fused = ws.get<FusedLevels>(1);
   BCHAR_HIP(hipMemcpyAsync(H.fused, &hf, sizeof(hf), hipMemcpyHostToDevice, s));
   BCHAR_HIP(hipStreamSynchronize(s));
@@ -1822,6 +1833,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 
   const double tol = o.qp_tol;
   res = QpResult{};
+  res.coarse_bytes = H.fused_bytes;
 
   // Newton matrix values: per-cell blocks and every level of the hierarchy,
   // from the fine weights in L0.w
