@@ -21,6 +21,15 @@ Conventions shared with the inputs (not with the HIP path):
     equal-area disk).
 
   Within a cell, ``subcell`` balls are numbered s = sx + 2 sy (+ 4 sz).
+
+* A simplicial mesh is ``{"kind": "simplex", "vertices", "cells", "phi"}``:
+  vertex coordinates (n_vertices, dim), the dim + 1 vertex ids of every cell
+  (triangles in 2D, tetrahedra in 3D) and the porosity per cell.  The paper
+  gives no ball packing for such cells (its open problem in the
+  conclusion); each cell gets one ball at its centroid whose measure equals
+  |K| (``"equal_measure"``, rho_K = 1 up to rounding).  The domain is the
+  bounding box of the vertices.  phi(x) during tracking is phi of the cell
+  containing x clamped into that box, located by ``locate_points``.
 """
 
 from __future__ import annotations
@@ -36,6 +45,123 @@ LAYOUTS = ("subcell", "inscribed", "equal_measure")
 # --------------------------------------------------------------------------
 # Mesh and balls (Sec. 3, eq. def:porous.density)
 # --------------------------------------------------------------------------
+
+def is_simplex(mesh):
+    return mesh.get("kind", "cartesian") == "simplex"
+
+
+def mesh_dim(mesh):
+    return int(np.asarray(mesh["vertices"]).shape[1]) if is_simplex(mesh) else len(mesh["n"])
+
+
+def mesh_n_cells(mesh):
+    return int(np.asarray(mesh["cells"]).shape[0]) if is_simplex(mesh) else int(np.prod(mesh["n"]))
+
+
+def domain_box(mesh):
+    """(lo, hi) corners of the domain box."""
+    if is_simplex(mesh):
+        V = np.asarray(mesh["vertices"], dtype=np.float64)
+        return V.min(axis=0), V.max(axis=0)
+    lo = np.asarray(mesh["origin"], dtype=np.float64)
+    return lo, lo + np.asarray(mesh["n"], dtype=np.float64) * np.asarray(mesh["h"], dtype=np.float64)
+
+
+def _orient(a, b, c, d=None):
+    """Signed d! |simplex| of the points a, b, c (2D) or a, b, c, d (3D),
+    arrays of shape (..., dim): the determinant of the edge vectors from a,
+    expanded along the first edge, each operation rounded on its own in the
+    order written."""
+    e1, e2 = b - a, c - a
+    if d is None:
+        return e1[..., 0] * e2[..., 1] - e1[..., 1] * e2[..., 0]
+    e3 = d - a
+    m0 = e2[..., 1] * e3[..., 2] - e2[..., 2] * e3[..., 1]
+    m1 = e2[..., 0] * e3[..., 2] - e2[..., 2] * e3[..., 0]
+    m2 = e2[..., 0] * e3[..., 1] - e2[..., 1] * e3[..., 0]
+    return (e1[..., 0] * m0 - e1[..., 1] * m1) + e1[..., 2] * m2
+
+
+def simplex_volumes(vertices, cells):
+    """|K| = |det(v1 - v0, ..., vd - v0)| / d!."""
+    V = np.asarray(vertices, dtype=np.float64)
+    C = np.asarray(cells, dtype=np.int64)
+    P = [V[C[:, i]] for i in range(C.shape[1])]
+    if V.shape[1] == 2:
+        return np.abs(_orient(P[0], P[1], P[2])) / 2.0
+    return np.abs(_orient(P[0], P[1], P[2], P[3])) / 6.0
+
+
+def simplex_centroids(vertices, cells):
+    """(((v0 + v1) + v2) (+ v3)) / (dim + 1), summed in vertex order."""
+    V = np.asarray(vertices, dtype=np.float64)
+    C = np.asarray(cells, dtype=np.int64)
+    acc = V[C[:, 0]] + V[C[:, 1]]
+    for i in range(2, C.shape[1]):
+        acc = acc + V[C[:, i]]
+    return acc / float(C.shape[1])
+
+
+def simplex_ball_layout(mesh):
+    """One ball per simplex at its centroid with |B| = |K| (2D sqrt(|K|/pi),
+    3D cbrt(3 |K| / (4 pi))).  Returns centres, radii, cell."""
+    V = np.asarray(mesh["vertices"], dtype=np.float64)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    dim = V.shape[1]
+    vol = simplex_volumes(V, C)
+    centres = simplex_centroids(V, C)
+    if dim == 2:
+        radii = np.sqrt(vol / math.pi)
+    else:
+        radii = np.cbrt(3.0 * vol / (4.0 * math.pi))
+    return centres, radii, np.arange(C.shape[0], dtype=np.int64)
+
+
+def locate_points(points, mesh, chunk=2048):
+    """Cell of a simplicial mesh holding each point.
+
+    Candidates are the cells whose bounding box (min and max of the vertex
+    coordinates) contains the point, closed.  The point lies in a cell when,
+    for every vertex, the orientation of the cell with that vertex replaced
+    by the point (``_orient``) is zero or has the sign of the cell's own
+    orientation; the lowest-numbered such candidate is taken.  If rounding
+    leaves a point in none, the candidate whose centroid is nearest is
+    taken (squared distance summed over the axes in order, the lowest
+    number on ties).  Brute force over all cells, in chunks of points."""
+    V = np.asarray(mesh["vertices"], dtype=np.float64)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    X = np.asarray(points, dtype=np.float64)
+    dim = V.shape[1]
+    P = [V[C[:, i]] for i in range(dim + 1)]
+    blo = np.minimum.reduce(P)
+    bhi = np.maximum.reduce(P)
+    own = _orient(*P)
+    cen = simplex_centroids(V, C)
+    out = np.empty(X.shape[0], dtype=np.int64)
+    for s0 in range(0, X.shape[0], chunk):
+        x = X[s0:s0 + chunk][:, None, :]                       # (m, 1, dim)
+        cand = np.all((x >= blo[None]) & (x <= bhi[None]), axis=2)   # (m, nc)
+        inside = cand & (own[None] != 0.0)
+        for i in range(dim + 1):
+            Q = [np.broadcast_to(p[None], (x.shape[0],) + p.shape) for p in P]
+            Q[i] = np.broadcast_to(x, Q[0].shape)
+            o = _orient(*Q)
+            inside &= np.where(own[None] > 0.0, o >= 0.0, o <= 0.0)
+        for r in range(x.shape[0]):
+            hit = np.nonzero(inside[r])[0]
+            if hit.size:
+                out[s0 + r] = hit[0]
+                continue
+            cids = np.nonzero(cand[r])[0]
+            if cids.size == 0:
+                raise ValueError("point outside every cell's bounding box")
+            dx = x[r, 0] - cen[cids]
+            d2 = dx[:, 0] * dx[:, 0] + dx[:, 1] * dx[:, 1]
+            if dim == 3:
+                d2 = d2 + dx[:, 2] * dx[:, 2]
+            out[s0 + r] = cids[int(np.argmin(d2))]
+    return out
+
 
 def cell_index_grid(n):
     """Integer (i, j[, k]) of every cell, x-fastest, shape (n_cells, dim)."""
@@ -182,7 +308,13 @@ def speed(points, mesh, vel):
     phi = np.asarray(mesh["phi"], dtype=np.float64)
     if phi_is_constant(phi):
         return u / phi[0]
-    cid = cell_of_point(points, mesh["n"], mesh["origin"], mesh["h"])
+    if is_simplex(mesh):
+        # the cell of the point clamped into the domain box (a cardinal
+        # point of a boundary ball starts outside it)
+        lo, hi = domain_box(mesh)
+        cid = locate_points(np.minimum(np.maximum(points, lo), hi), mesh)
+    else:
+        cid = cell_of_point(points, mesh["n"], mesh["origin"], mesh["h"])
     return u / phi[cid][:, None]
 
 
@@ -207,8 +339,7 @@ def trace_points(points, mesh, vel, dt, substeps=1):
     """
     X = np.array(points, dtype=np.float64, copy=True)
     dim = X.shape[1]
-    lo = np.asarray(mesh["origin"], dtype=np.float64)
-    hi = lo + np.asarray(mesh["n"], dtype=np.float64) * np.asarray(mesh["h"], dtype=np.float64)
+    lo, hi = domain_box(mesh)
     tau = float(dt) / int(substeps)
     for _ in range(int(substeps)):
         k1 = speed(X, mesh, vel)

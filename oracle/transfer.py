@@ -164,22 +164,28 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
                    traced_override=None, qp_tol=1e-14):
     """Transfer matrix of one time step: Algorithm 1 of Sec. 3.3.
 
-    ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) and ``phi``
-    (per cell).  ``vel``: velocity lattice dict (``m``, ``origin``,
+    ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) or ``kind =
+    "simplex"``, ``vertices``, ``cells``, and ``phi`` (per cell).  ``vel``: velocity lattice dict (``m``, ``origin``,
     ``spacing``, ``u``).  Returns a dict holding every intermediate stage.
     ``traced_override`` replaces the tracked centres (to compare the
     later stages on identical geometry).
     """
-    n = tuple(int(v) for v in mesh["n"])
-    dim = len(n)
-    nc = int(np.prod(n))
-    h = tuple(float(v) for v in mesh["h"])
+    dim = geo.mesh_dim(mesh)
+    nc = geo.mesh_n_cells(mesh)
     phi = np.asarray(mesh["phi"], dtype=np.float64)
     if phi.shape != (nc,) or not np.all(np.isfinite(phi)) or np.any(phi <= 0):
         raise ValueError("phi must be finite and > 0 on every cell (Sec. 1.2)")
-    kvol = geo.cell_volume(h)
-    centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
-    rho = geo.porous_density(nc, np.full(nc, kvol), radii, bcell, dim)
+    if geo.is_simplex(mesh):
+        if layout != "equal_measure":
+            raise ValueError("simplicial meshes take the equal_measure layout")
+        kvol = geo.simplex_volumes(mesh["vertices"], mesh["cells"])
+        centres, radii, bcell = geo.simplex_ball_layout(mesh)
+    else:
+        n = tuple(int(v) for v in mesh["n"])
+        h = tuple(float(v) for v in mesh["h"])
+        kvol = np.full(nc, geo.cell_volume(h))
+        centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
+    rho = geo.porous_density(nc, kvol, radii, bcell, dim)
     b = phi * kvol                      # |K|_phi = b_loc = b_glob (eq. exactVol_traceback)
     out = {"centres": centres, "radii": radii, "ball_cell": bcell, "rho": rho, "b": b,
            "cell_vol": kvol}

@@ -12,6 +12,9 @@ the HIP path and the CPU oracle receive what it produces.
   ``(dim, prod(m))`` stored x-fastest.  For a Cartesian mesh the lattice
   nodes are the mesh vertices, so the Q1 interpolant of the nodal values is
   a piecewise polynomial on the mesh as the scheme assumes.
+* A simplicial mesh is a dict ``{"kind": "simplex", "vertices", "cells",
+  "phi"}``: vertex coordinates (n_vertices, dim), the dim + 1 vertex ids of
+  every triangle or tetrahedron, and the porosity per cell.
 * A time-dependent field is sampled at the middle of each time interval.
 """
 
@@ -40,7 +43,79 @@ def cartesian_mesh(n, length=1.0, origin=None, phi=None):
             "phi": np.ascontiguousarray(phi, dtype=np.float64)}
 
 
+def simplex_mesh(vertices, cells, phi=None):
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    C = np.ascontiguousarray(cells, dtype=np.int32)
+    if phi is None:
+        phi = np.ones(C.shape[0])
+    return {"kind": "simplex", "vertices": V, "cells": C,
+            "phi": np.ascontiguousarray(phi, dtype=np.float64)}
+
+
+def _grid_vertices(n, jitter, seed):
+    """(n+1)^dim vertices of the unit square/cube, x-fastest; interior
+    vertices moved by U(-jitter, jitter) h per axis (seeded)."""
+    dim = len(n)
+    m = tuple(v + 1 for v in n)
+    h = tuple(1.0 / v for v in n)
+    V = lattice_nodes(m, (0.0,) * dim, h)
+    if jitter > 0:
+        ids = np.arange(V.shape[0])
+        rem = ids.copy()
+        interior = np.ones(V.shape[0], dtype=bool)
+        for a in range(dim):
+            i = rem % m[a]
+            rem //= m[a]
+            interior &= (i > 0) & (i < m[a] - 1)
+        rng = np.random.default_rng(seed)
+        J = rng.uniform(-jitter, jitter, size=V.shape) * np.asarray(h)
+        V[interior] += J[interior]
+    return V, m
+
+
+def kuhn_tets(n, jitter=0.1, seed=1908, phi=None):
+    """n^3 cubes of the unit cube, each split into the 6 Kuhn tetrahedra
+    (corner 000 to corner 111 along the 6 orders of the axes), interior
+    vertices jittered by up to ``jitter`` h."""
+    n3 = (int(n),) * 3
+    V, m = _grid_vertices(n3, jitter, seed)
+    ijk = np.stack(np.meshgrid(*(np.arange(v) for v in n3), indexing="ij"), -1)
+    ijk = ijk.transpose(2, 1, 0, 3).reshape(-1, 3)          # x fastest
+    def vid(off):
+        q = ijk + np.asarray(off)
+        return q[:, 0] + m[0] * (q[:, 1] + m[1] * q[:, 2])
+    cells = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        p = [0, 0, 0]
+        path = [vid(p)]
+        for a in perm:
+            p[a] = 1
+            path.append(vid(tuple(p)))
+        cells.append(np.stack(path, 1))
+    C = np.stack(cells, 1).reshape(-1, 4)                  # cube-major
+    return simplex_mesh(V, C, phi)
+
+
+def triangulated_square(n, jitter=0.1, seed=1908, phi=None):
+    """n^2 squares of the unit square, each split along its diagonal from
+    corner 00 to corner 11; interior vertices jittered by up to ``jitter`` h."""
+    n2 = (int(n),) * 2
+    V, m = _grid_vertices(n2, jitter, seed)
+    j, i = np.meshgrid(np.arange(n2[1]), np.arange(n2[0]), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    v00 = i + m[0] * j
+    v10, v01, v11 = v00 + 1, v00 + m[0], v00 + m[0] + 1
+    C = np.stack([np.stack([v00, v10, v11], 1), np.stack([v00, v01, v11], 1)], 1).reshape(-1, 3)
+    return simplex_mesh(V, C, phi)
+
+
+def n_cells(mesh):
+    return int(mesh["cells"].shape[0]) if mesh.get("kind") == "simplex" else int(np.prod(mesh["n"]))
+
+
 def cell_centroids(mesh):
+    if mesh.get("kind") == "simplex":
+        return mesh["vertices"][mesh["cells"]].mean(axis=1)
     n, o, h = mesh["n"], mesh["origin"], mesh["h"]
     dim = len(n)
     ids = np.arange(int(np.prod(n)))
@@ -61,6 +136,16 @@ def lattice_nodes(m, origin, spacing):
         out[:, a] = origin[a] + (rem % m[a]) * spacing[a]
         rem //= m[a]
     return out
+
+
+def sample_velocity_grid(n, field, t=0.0):
+    """Lattice of (n+1)^dim nodes on the unit square/cube (the unjittered
+    vertex grid of ``kuhn_tets`` / ``triangulated_square``)."""
+    m = tuple(int(v) + 1 for v in n)
+    h = tuple(1.0 / int(v) for v in n)
+    pts = lattice_nodes(m, (0.0,) * len(n), h)
+    u = np.ascontiguousarray(np.asarray(field(pts, t), dtype=np.float64).T)
+    return {"m": m, "origin": (0.0,) * len(n), "spacing": h, "u": u}
 
 
 def sample_velocity(mesh, field, t=0.0):
@@ -172,7 +257,7 @@ def disk_indicator(mesh, centre, radius):
 
 
 def uniform_c(mesh, seed):
-    return np.random.default_rng(seed).uniform(0.0, 1.0, int(np.prod(mesh["n"])))
+    return np.random.default_rng(seed).uniform(0.0, 1.0, n_cells(mesh))
 
 
 def lognormal_phi(n_cells, seed, sigma=0.5, lo=0.05, hi=1.0):
@@ -223,3 +308,24 @@ def porous_swirl_hex(n=32, seed=5834, steps=20):
     c0 = uniform_c(mesh, 33)
     return {"name": f"porous_swirl_hex_{n}^3", "mesh": mesh, "vel_fn": vel_fn, "c0": c0,
             "dt": dt, "steps": steps, "time_dependent": True}
+
+
+def jittered_tets(n=96, jitter=0.1, seed=1908, phi_seed=5834, cfl=4.0, steps=20):
+    """3D unstructured workload: n^3 cubes split into 6 Kuhn tetrahedra
+    (6 n^3 cells), interior vertices jittered by up to 10 % of h, phi =
+    clip(exp(0.5 Z), 0.05, 1) per cell, the swirl scaled so that the largest
+    nodal |u| dt / h is ``cfl``, c^0 ~ U[0,1], dt = 1/128."""
+    nc = 6 * n ** 3
+    mesh = kuhn_tets(n, jitter, seed, phi=lognormal_phi(nc, phi_seed))
+    dt = 1.0 / 128.0
+    h = 1.0 / n
+    probe = sample_velocity_grid((n, n, n), lambda p, t: swirl_3d(p, t), 0.0)
+    umax = float(np.max(np.sqrt(np.sum(probe["u"] ** 2, axis=0))))
+    amp = cfl * h / (umax * dt)
+
+    def vel_fn(step):
+        return sample_velocity_grid((n, n, n), lambda p, t: swirl_3d(p, t, amplitude=amp),
+                                    (step + 0.5) * dt)
+    c0 = uniform_c(mesh, 33)
+    return {"name": f"jittered_tets_{n}", "mesh": mesh, "vel_fn": vel_fn, "c0": c0, "dt": dt,
+            "steps": steps, "time_dependent": True}
