@@ -90,15 +90,39 @@ typedef struct bchar_mesh_s* bchar_mesh;
 typedef struct bchar_transfer_s* bchar_transfer;
 
 /* Cartesian mesh of the box [origin, origin + n*h] (Sec. 1.2).          */
+/* Mesh kinds.  CARTESIAN: n[a] cells of size h[a] from origin (cell ids
+ * x-fastest).  SIMPLEX: triangles (2D) or tetrahedra (3D) given by their
+ * vertices; the domain is the bounding box of the vertices, which the cells
+ * must cover; the paper gives no ball packing for such cells, each gets one
+ * ball at its centroid (((v0 + v1) + v2) (+ v3)) / (dim + 1) with |B| = |K|
+ * (layout EQUAL_MEASURE only), |K| = |det(v1 - v0, ...)| / dim!.  phi(x)
+ * during tracking is phi of the cell holding x clamped into the domain box:
+ * among the cells whose bounding box holds x, the lowest-numbered one whose
+ * orientation tests (each vertex replaced by x) all agree in sign with the
+ * cell's own orientation or vanish; if rounding leaves none, the one whose
+ * centroid is nearest (lowest number on ties).                          */
+enum { BCHAR_MESH_CARTESIAN = 0, BCHAR_MESH_SIMPLEX = 1 };
+
 typedef struct {
   int dim;               /* 2 or 3                                        */
-  int64_t n[3];          /* cells per axis (n[2] ignored in 2D), each >= 1 */
-  double origin[3];      /* lower corner                                  */
-  double h[3];           /* cell size per axis, > 0                       */
-  const double* phi;     /* porosity per cell, n0*n1*n2 values, each finite
-                            and > 0 (Sec. 1.2); copied at creation        */
+  int64_t n[3];          /* CARTESIAN: cells per axis (n[2] ignored in 2D),
+                            each >= 1                                     */
+  double origin[3];      /* CARTESIAN: lower corner                       */
+  double h[3];           /* CARTESIAN: cell size per axis, > 0            */
+  const double* phi;     /* porosity per cell (n0*n1*n2 or n_simplices
+                            values), each finite and > 0 (Sec. 1.2);
+                            copied at creation                            */
   int phi_mem;           /* BCHAR_MEM_HOST or BCHAR_MEM_DEVICE            */
   int layout;            /* BCHAR_LAYOUT_*                                */
+  int kind;              /* BCHAR_MESH_CARTESIAN (0) or BCHAR_MESH_SIMPLEX */
+  int64_t n_vertices;    /* SIMPLEX: vertices, >= dim + 1                 */
+  int64_t n_simplices;   /* SIMPLEX: cells, >= 1                          */
+  const double* vertices;/* SIMPLEX, host: n_vertices * dim coordinates,
+                            vertex-major (x, y[, z] of vertex 0, ...);
+                            copied at creation                            */
+  const int32_t* cells;  /* SIMPLEX, host: n_simplices * (dim + 1) vertex
+                            ids, each in [0, n_vertices), non-degenerate
+                            cells; copied at creation                     */
 } bchar_mesh_desc;
 
 /* Velocity u^{(n+1)} frozen over the time step (Sec. 1.2, eq. hyp:un) as

@@ -104,7 +104,7 @@ def simplex_centroids(vertices, cells):
 
 def simplex_ball_layout(mesh):
     """One ball per simplex at its centroid with |B| = |K| (2D sqrt(|K|/pi),
-    3D cbrt(3 |K| / (4 pi))).  Returns centres, radii, cell."""
+    3D (3 |K| / (4 pi))^(1/3)).  Returns centres, radii, cell."""
     V = np.asarray(mesh["vertices"], dtype=np.float64)
     C = np.asarray(mesh["cells"], dtype=np.int64)
     dim = V.shape[1]
@@ -113,7 +113,9 @@ def simplex_ball_layout(mesh):
     if dim == 2:
         radii = np.sqrt(vol / math.pi)
     else:
-        radii = np.cbrt(3.0 * vol / (4.0 * math.pi))
+        # the C library's pow, element by element (as for the Cartesian
+        # equal-measure ball)
+        radii = np.array([math.pow(3.0 * v / (4.0 * math.pi), 1.0 / 3.0) for v in vol])
     return centres, radii, np.arange(C.shape[0], dtype=np.int64)
 
 

@@ -33,6 +33,7 @@ FP64, FP32_VOLUME = 0, 1
 BOX_PAPER_THEN_RELAX, BOX_STRICT = 0, 1
 STAGE_PAIRS, STAGE_V, STAGE_SCALING, STAGE_ALL = 1, 2, 3, 4
 MEM_HOST, MEM_DEVICE = 0, 1
+MESH_CARTESIAN, MESH_SIMPLEX = 0, 1
 
 LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
            "equal_measure": LAYOUT_EQUAL_MEASURE}
@@ -41,7 +42,8 @@ LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
 class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("origin", C.c_double * 3),
                 ("h", C.c_double * 3), ("phi", C.c_void_p), ("phi_mem", C.c_int),
-                ("layout", C.c_int)]
+                ("layout", C.c_int), ("kind", C.c_int), ("n_vertices", C.c_int64),
+                ("n_simplices", C.c_int64), ("vertices", C.c_void_p), ("cells", C.c_void_p)]
 
 
 class Velocity(C.Structure):
@@ -167,17 +169,34 @@ def opts_default(**kw):
 # ---------------------------------------------------------------- handles
 
 class Mesh:
-    """bchar_mesh_create on a Cartesian mesh dict (``inputs.cartesian_mesh``)."""
+    """bchar_mesh_create on a Cartesian mesh dict (``inputs.cartesian_mesh``)
+    or a simplicial one (``inputs.kuhn_tets``, ``inputs.triangulated_square``:
+    layout ``"equal_measure"``)."""
 
     def __init__(self, mesh, layout="subcell", stream=None):
-        n = tuple(int(v) for v in mesh["n"])
-        self.dim = len(n)
         d = MeshDesc()
-        d.dim = self.dim
-        for a in range(3):
-            d.n[a] = n[a] if a < self.dim else 1
-            d.origin[a] = mesh["origin"][a] if a < self.dim else 0.0
-            d.h[a] = mesh["h"][a] if a < self.dim else 1.0
+        if mesh.get("kind") == "simplex":
+            V = np.ascontiguousarray(mesh["vertices"], dtype=np.float64)
+            Cc = np.ascontiguousarray(mesh["cells"], dtype=np.int32)
+            self.dim = V.shape[1]
+            self._geom_host = (V, Cc)
+            d.dim = self.dim
+            d.kind = MESH_SIMPLEX
+            d.n_vertices = V.shape[0]
+            d.n_simplices = Cc.shape[0]
+            d.vertices = V.ctypes.data_as(C.c_void_p)
+            d.cells = Cc.ctypes.data_as(C.c_void_p)
+            for a in range(3):
+                d.n[a], d.origin[a], d.h[a] = 1, 0.0, 1.0
+        else:
+            n = tuple(int(v) for v in mesh["n"])
+            self.dim = len(n)
+            d.dim = self.dim
+            d.kind = MESH_CARTESIAN
+            for a in range(3):
+                d.n[a] = n[a] if a < self.dim else 1
+                d.origin[a] = mesh["origin"][a] if a < self.dim else 0.0
+                d.h[a] = mesh["h"][a] if a < self.dim else 1.0
         phi = np.ascontiguousarray(mesh["phi"], dtype=np.float64)
         self._phi_host = phi
         d.phi = phi.ctypes.data_as(C.c_void_p)

@@ -18,6 +18,175 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// ---- simplicial meshes (host side, at creation)
+
+// d! times the signed measure of (a, b, c[, d]), the same expansion and
+// operation order as the device's point location
+double orient_host(int dim, const double* a, const double* b, const double* c,
+                   const double* d) {
+#pragma clang fp contract(off)
+  double e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0}, e3[3] = {0, 0, 0};
+  for (int k = 0; k < dim; ++k) {
+    e1[k] = b[k] - a[k];
+    e2[k] = c[k] - a[k];
+    if (dim == 3) e3[k] = d[k] - a[k];
+  }
+  if (dim == 2) return e1[0] * e2[1] - e1[1] * e2[0];
+  const double m0 = e2[1] * e3[2] - e2[2] * e3[1];
+  const double m1 = e2[0] * e3[2] - e2[2] * e3[0];
+  const double m2 = e2[0] * e3[1] - e2[1] * e3[0];
+  return (e1[0] * m0 - e1[1] * m1) + e1[2] * m2;
+}
+
+struct SimplexHost {
+  int dim = 0;
+  int64_t nv = 0, nc = 0;
+  std::vector<double> vtx;       // SoA, dim * nv
+  std::vector<int32_t> cells;    // (dim + 1) * nc
+  std::vector<double> vol, cen, rad, bvol, rho;   // cen SoA dim * nc
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  double rmax = 0;
+};
+
+// |K| = |orient| / dim!, centroid (((v0 + v1) + v2) (+ v3)) / (dim + 1), the
+// ball with |B| = |K| (radius sqrt(|K| / pi) or pow(3 |K| / (4 pi), 1 / 3)),
+// rho_K = |K| / |B|, and the domain box
+void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
+#pragma clang fp contract(off)
+  const int dim = d->dim;
+  h.dim = dim;
+  h.nv = d->n_vertices;
+  h.nc = d->n_simplices;
+  h.vtx.resize((size_t)dim * h.nv);
+  for (int a = 0; a < 3; ++a) {
+    h.lo[a] = a < dim ? HUGE_VAL : 0.0;
+    h.hi[a] = a < dim ? -HUGE_VAL : 0.0;
+  }
+  for (int64_t v = 0; v < h.nv; ++v)
+    for (int a = 0; a < dim; ++a) {
+      const double x = d->vertices[v * dim + a];
+      BCHAR_REQUIRE(std::isfinite(x), BCHAR_E_INVALID_ARG, "vertex coordinates must be finite");
+      h.vtx[(size_t)a * h.nv + v] = x;
+      h.lo[a] = std::min(h.lo[a], x);
+      h.hi[a] = std::max(h.hi[a], x);
+    }
+  h.cells.assign(d->cells, d->cells + (size_t)(dim + 1) * h.nc);
+  h.vol.resize(h.nc);
+  h.cen.resize((size_t)dim * h.nc);
+  h.rad.resize(h.nc);
+  h.bvol.resize(h.nc);
+  h.rho.resize(h.nc);
+  for (int64_t K = 0; K < h.nc; ++K) {
+    double p[4][3] = {{0}};
+    for (int i = 0; i <= dim; ++i) {
+      const int32_t q = h.cells[(size_t)K * (dim + 1) + i];
+      BCHAR_REQUIRE(q >= 0 && q < h.nv, BCHAR_E_INVALID_ARG, "cell vertex id out of range");
+      for (int a = 0; a < dim; ++a) p[i][a] = h.vtx[(size_t)a * h.nv + q];
+    }
+    const double o = orient_host(dim, p[0], p[1], p[2], p[dim == 3 ? 3 : 2]);
+    const double v = std::fabs(o) / (dim == 2 ? 2.0 : 6.0);
+    BCHAR_REQUIRE(v > 0, BCHAR_E_INVALID_ARG, "degenerate simplex");
+    h.vol[K] = v;
+    for (int a = 0; a < dim; ++a) {
+      double acc = p[0][a] + p[1][a];
+      for (int i = 2; i <= dim; ++i) acc = acc + p[i][a];
+      h.cen[(size_t)a * h.nc + K] = acc / (double)(dim + 1);
+    }
+    const double r =
+        dim == 2 ? std::sqrt(v / kPi) : std::pow(3.0 * v / (4.0 * kPi), 1.0 / 3.0);
+    h.rad[K] = r;
+    h.bvol[K] = dim == 2 ? kPi * r * r : 4.0 / 3.0 * kPi * r * r * r;
+    h.rho[K] = v / h.bvol[K];
+    h.rmax = std::max(h.rmax, r);
+  }
+}
+
+// Device copies, and (when phi varies, so that tracking needs it) the
+// uniform grid of side (|box| / n_cells)^(1/dim) listing, per grid cell
+// and in ascending order, the cells whose bounding box meets it.
+void simplex_upload(bchar_mesh_s* m, const SimplexHost& h, const std::vector<double>& b,
+                    const std::vector<double>& /*phi*/, hipStream_t s) {
+  const int dim = h.dim;
+  auto up = [&](bchar::DBuf& buf, const void* src, size_t bytes) {
+    buf.reserve(bytes);
+    BCHAR_HIP(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, s));
+  };
+  std::vector<float> cen32(h.cen.size());
+  for (size_t i = 0; i < h.cen.size(); ++i) cen32[i] = (float)h.cen[i];
+  up(m->cen, h.cen.data(), sizeof(double) * h.cen.size());
+  up(m->cen32, cen32.data(), sizeof(float) * cen32.size());
+  up(m->rad, h.rad.data(), sizeof(double) * h.nc);
+  up(m->bvol, h.bvol.data(), sizeof(double) * h.nc);
+  up(m->rho, h.rho.data(), sizeof(double) * h.nc);
+  up(m->b, b.data(), sizeof(double) * h.nc);
+  up(m->vtx, h.vtx.data(), sizeof(double) * h.vtx.size());
+  up(m->cells, h.cells.data(), sizeof(int32_t) * h.cells.size());
+  m->n_vertices = h.nv;
+  m->rmax = h.rmax;
+  std::vector<int32_t> start, list;
+  double side = 1.0;
+  int64_t nb[3] = {1, 1, 1};
+  if (!m->phi_const) {
+    double boxvol = 1.0;
+    for (int a = 0; a < dim; ++a) boxvol *= std::max(h.hi[a] - h.lo[a], 1e-300);
+    side = std::pow(boxvol / (double)h.nc, 1.0 / dim);
+    int64_t ng = 1;
+    for (int a = 0; a < dim; ++a) {
+      nb[a] = std::max<int64_t>(1, (int64_t)std::ceil((h.hi[a] - h.lo[a]) / side));
+      ng *= nb[a];
+    }
+    BCHAR_REQUIRE(ng < ((int64_t)1 << 31), BCHAR_E_UNSUPPORTED, "location grid too large");
+    const double inv = 1.0 / side;
+    auto range = [&](int64_t K, int64_t lo_i[3], int64_t hi_i[3]) {
+      for (int a = 0; a < 3; ++a) {
+        lo_i[a] = 0;
+        hi_i[a] = 0;
+      }
+      for (int a = 0; a < dim; ++a) {
+        double lo = HUGE_VAL, hi = -HUGE_VAL;
+        for (int i = 0; i <= dim; ++i) {
+          const double x = h.vtx[(size_t)a * h.nv + h.cells[(size_t)K * (dim + 1) + i]];
+          lo = std::min(lo, x);
+          hi = std::max(hi, x);
+        }
+        int64_t l = (int64_t)std::floor((lo - h.lo[a]) * inv);
+        int64_t u = (int64_t)std::floor((hi - h.lo[a]) * inv);
+        lo_i[a] = std::min(std::max<int64_t>(l, 0), nb[a] - 1);
+        hi_i[a] = std::min(std::max<int64_t>(u, 0), nb[a] - 1);
+      }
+    };
+    std::vector<int64_t> cnt(ng + 1, 0);
+    for (int64_t K = 0; K < h.nc; ++K) {
+      int64_t l[3], u[3];
+      range(K, l, u);
+      for (int64_t k = l[2]; k <= u[2]; ++k)
+        for (int64_t j = l[1]; j <= u[1]; ++j)
+          for (int64_t i = l[0]; i <= u[0]; ++i) ++cnt[i + nb[0] * (j + nb[1] * k) + 1];
+    }
+    for (int64_t g = 0; g < ng; ++g) cnt[g + 1] += cnt[g];
+    BCHAR_REQUIRE(cnt[ng] < ((int64_t)1 << 31), BCHAR_E_UNSUPPORTED, "location lists too long");
+    start.assign(cnt.begin(), cnt.end());
+    list.resize(cnt[ng]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t K = 0; K < h.nc; ++K) {
+      int64_t l[3], u[3];
+      range(K, l, u);
+      for (int64_t k = l[2]; k <= u[2]; ++k)
+        for (int64_t j = l[1]; j <= u[1]; ++j)
+          for (int64_t i = l[0]; i <= u[0]; ++i)
+            list[pos[i + nb[0] * (j + nb[1] * k)]++] = (int32_t)K;
+    }
+  } else {
+    start.assign(2, 0);
+    list.assign(1, 0);
+  }
+  m->pl_inv = 1.0 / side;
+  for (int a = 0; a < 3; ++a) m->pl_nb[a] = nb[a];
+  up(m->pl_start, start.data(), sizeof(int32_t) * start.size());
+  up(m->pl_list, list.data(), sizeof(int32_t) * list.size());
+  BCHAR_HIP(hipStreamSynchronize(s));
+}
+
 template <class F>
 bchar_status guarded(F&& f) {
   try {
@@ -238,6 +407,8 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
   return guarded([&]() -> bchar_status {
     BCHAR_REQUIRE(d != nullptr && out != nullptr, BCHAR_E_INVALID_ARG, "NULL argument");
     BCHAR_REQUIRE(d->dim == 2 || d->dim == 3, BCHAR_E_INVALID_ARG, "dim must be 2 or 3");
+    BCHAR_REQUIRE(d->kind == BCHAR_MESH_CARTESIAN || d->kind == BCHAR_MESH_SIMPLEX,
+                  BCHAR_E_INVALID_ARG, "unknown mesh kind");
     BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_EQUAL_MEASURE,
                   BCHAR_E_INVALID_ARG, "unknown layout");
     BCHAR_REQUIRE(d->phi != nullptr, BCHAR_E_INVALID_ARG, "phi is NULL");
@@ -248,44 +419,70 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
     try {
       m->dim = d->dim;
       m->layout = d->layout;
+      m->kind = d->kind;
+      const int dim = d->dim;
       int64_t nc = 1;
-      double hmin = 1e300;
-      m->cell_vol = 1.0;
-      for (int a = 0; a < 3; ++a) {
-        if (a < d->dim) {
-          BCHAR_REQUIRE(d->n[a] >= 1, BCHAR_E_INVALID_ARG, "n must be >= 1");
-          BCHAR_REQUIRE(d->h[a] > 0 && std::isfinite(d->h[a]) && std::isfinite(d->origin[a]),
-                        BCHAR_E_INVALID_ARG, "h must be finite and > 0");
-          m->n[a] = d->n[a];
-          m->h[a] = d->h[a];
-          m->origin[a] = d->origin[a];
-          nc *= d->n[a];
-          hmin = std::min(hmin, d->h[a]);
-          m->cell_vol *= d->h[a];
-        } else {
-          m->n[a] = 1;
-          m->h[a] = 1;
-          m->origin[a] = 0;
+      bchar::UniformBalls ub{};
+      std::vector<double> kvol;   // simplex: |K| per cell
+      SimplexHost sh;
+      if (d->kind == BCHAR_MESH_CARTESIAN) {
+        double hmin = 1e300;
+        ub.cell_vol = 1.0;
+        for (int a = 0; a < 3; ++a) {
+          if (a < dim) {
+            BCHAR_REQUIRE(d->n[a] >= 1, BCHAR_E_INVALID_ARG, "n must be >= 1");
+            BCHAR_REQUIRE(d->h[a] > 0 && std::isfinite(d->h[a]) && std::isfinite(d->origin[a]),
+                          BCHAR_E_INVALID_ARG, "h must be finite and > 0");
+            m->n[a] = d->n[a];
+            m->h[a] = d->h[a];
+            m->origin[a] = d->origin[a];
+            nc *= d->n[a];
+            hmin = std::min(hmin, d->h[a]);
+            ub.cell_vol *= d->h[a];
+          } else {
+            m->n[a] = 1;
+            m->h[a] = 1;
+            m->origin[a] = 0;
+          }
+          m->box_lo[a] = m->origin[a];
+          m->box_hi[a] = m->origin[a] + (double)m->n[a] * m->h[a];
         }
-      }
-      m->n_cells = nc;
-      if (d->layout == BCHAR_LAYOUT_SUBCELL) {
-        m->nbpc = 1 << d->dim;
-        m->r = hmin / 4.0;
-      } else if (d->layout == BCHAR_LAYOUT_INSCRIBED) {
-        m->nbpc = 1;
-        m->r = hmin / 2.0;
+        m->n_cells = nc;
+        if (d->layout == BCHAR_LAYOUT_SUBCELL) {
+          m->nbpc = 1 << dim;
+          ub.r = hmin / 4.0;
+        } else if (d->layout == BCHAR_LAYOUT_INSCRIBED) {
+          m->nbpc = 1;
+          ub.r = hmin / 2.0;
+        } else {
+          m->nbpc = 1;
+          ub.r = dim == 2 ? std::sqrt(ub.cell_vol / kPi)
+                          : std::pow(3.0 * ub.cell_vol / (4.0 * kPi), 1.0 / 3.0);
+        }
+        ub.ball_vol = dim == 2 ? kPi * ub.r * ub.r : 4.0 / 3.0 * kPi * ub.r * ub.r * ub.r;
+        // rho_K sum_s |B_{K,s}|_phi = |K|_phi with |B|_phi = phi_K |B|
+        ub.rho = ub.cell_vol / (m->nbpc * ub.ball_vol);
       } else {
+        BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE, BCHAR_E_INVALID_ARG,
+                      "simplicial meshes take the EQUAL_MEASURE layout");
+        BCHAR_REQUIRE(d->vertices != nullptr && d->cells != nullptr, BCHAR_E_INVALID_ARG,
+                      "vertices or cells is NULL");
+        BCHAR_REQUIRE(d->n_vertices >= dim + 1 && d->n_simplices >= 1 &&
+                          d->n_simplices < ((int64_t)1 << 31) - 1,
+                      BCHAR_E_INVALID_ARG, "n_vertices / n_simplices");
+        nc = d->n_simplices;
+        m->n_cells = nc;
         m->nbpc = 1;
-        m->r = d->dim == 2 ? std::sqrt(m->cell_vol / kPi)
-                           : std::cbrt(3.0 * m->cell_vol / (4.0 * kPi));
+        simplex_geometry(d, sh);
+        for (int a = 0; a < 3; ++a) {
+          m->box_lo[a] = sh.lo[a];
+          m->box_hi[a] = sh.hi[a];
+        }
+        kvol = sh.vol;
       }
       m->n_balls = nc * m->nbpc;
       BCHAR_REQUIRE(m->n_balls < ((int64_t)1 << 31) - 1, BCHAR_E_UNSUPPORTED,
                     "more than 2^31 balls");
-      m->ball_vol = d->dim == 2 ? kPi * m->r * m->r : 4.0 / 3.0 * kPi * m->r * m->r * m->r;
-      // rho_K sum_s |B_{K,s}|_phi = |K|_phi with |B|_phi = phi_K |B|
-      m->rho = m->cell_vol / (m->nbpc * m->ball_vol);
       // phi: validate on the host
       std::vector<double> hphi(nc);
       if (d->phi_mem == BCHAR_MEM_HOST) {
@@ -305,11 +502,22 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
       }
       m->phi_const = same;
       m->phi0 = hphi[0];
-      m->bmax = pmax * m->cell_vol;
       m->phi.reserve(sizeof(double) * nc);
       BCHAR_HIP(hipMemcpyAsync(m->phi.p, hphi.data(), sizeof(double) * nc,
                                hipMemcpyHostToDevice, s));
-      bchar::mesh_build_device(m, s);
+      if (d->kind == BCHAR_MESH_CARTESIAN) {
+        m->bmax = pmax * ub.cell_vol;
+        bchar::mesh_build_cartesian(m, ub, s);
+      } else {
+        std::vector<double> b(nc);
+        m->bmax = 0;
+        for (int64_t K = 0; K < nc; ++K) {
+          b[K] = hphi[K] * kvol[K];
+          m->bmax = std::max(m->bmax, b[K]);
+        }
+        simplex_upload(m, sh, b, hphi, s);
+        bchar::mesh_build_hash(m, s);
+      }
     } catch (...) {
       bchar_mesh_destroy(m);
       throw;
@@ -330,6 +538,14 @@ bchar_status bchar_mesh_destroy(bchar_mesh m) {
   m->bk_cen.release();
   m->bk_cen32.release();
   m->bk_ball.release();
+  m->bk_rad.release();
+  m->rho.release();
+  m->rad.release();
+  m->bvol.release();
+  m->vtx.release();
+  m->cells.release();
+  m->pl_start.release();
+  m->pl_list.release();
   m->ws.release();
   m->scratch_small.release();
   delete m;
@@ -572,10 +788,10 @@ bchar_status bchar_mesh_export_balls(bchar_mesh m, double* centres, double* radi
     if (centres)
       BCHAR_HIP(hipMemcpy(centres, m->cen.p, sizeof(double) * m->dim * m->n_balls,
                           hipMemcpyDeviceToHost));
-    for (int64_t b = 0; b < m->n_balls; ++b) {
-      if (radii) radii[b] = m->r;
-      if (cell) cell[b] = (int32_t)(b / m->nbpc);
-    }
+    if (radii)
+      BCHAR_HIP(hipMemcpy(radii, m->rad.p, sizeof(double) * m->n_balls, hipMemcpyDeviceToHost));
+    if (cell)
+      for (int64_t b = 0; b < m->n_balls; ++b) cell[b] = (int32_t)(b / m->nbpc);
     return BCHAR_OK;
   });
 }

@@ -5,7 +5,10 @@
 //          velocity frozen (multilinear lattice interpolation), v = u/phi,
 //          result clamped into the domain box.  With non-constant phi the
 //          2d points C +- r e_a are tracked too and r_hat is the mean of
-//          their distances to the tracked centre (eq. rTrackedBall).
+//          their distances to the tracked centre (eq. rTrackedBall); phi(x)
+//          is that of the Cartesian cell floor((x - o) / h), or, on a
+//          simplicial mesh, of the cell located through a uniform grid of
+//          cell lists (the rule is stated in bchar.h).
 // assemble: one wavefront per tracked cell K.  Lanes are split into
 //          n_balls_per_cell groups; the lanes of a group share the 3^d (or
 //          (2w+1)^d) hash buckets around that ball's tracked centre.  For
@@ -38,7 +41,109 @@ struct PhiView {
   T phi0;
   int64_t n[3];
   T org[3], h[3];
+  // simplicial meshes (simplex != 0): vertices SoA, (dim+1) ids per cell,
+  // centroids (ball centres, SoA), the domain box and the location grid
+  int simplex;
+  const double* vtx;
+  int64_t n_vertices;
+  const int32_t* cells;
+  const double* cen;
+  int64_t n_cells;
+  double box_lo[3], box_hi[3];
+  double pl_inv;
+  int64_t pl_nb[3];
+  const int32_t* pl_start;
+  const int32_t* pl_list;
 };
+
+// d! times the signed measure of the simplex (a, b, c[, d]): the
+// determinant of the edges from a expanded along the first edge, each
+// operation rounded on its own in the order written.
+template <int DIM>
+__device__ __forceinline__ double orient(const double* a, const double* b, const double* c,
+                                         const double* d) {
+#pragma clang fp contract(off)
+  double e1[3], e2[3], e3[3];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    e1[k] = b[k] - a[k];
+    e2[k] = c[k] - a[k];
+    if (DIM == 3) e3[k] = d[k] - a[k];
+  }
+  if (DIM == 2) return e1[0] * e2[1] - e1[1] * e2[0];
+  const double m0 = e2[1] * e3[2] - e2[2] * e3[1];
+  const double m1 = e2[0] * e3[2] - e2[2] * e3[0];
+  const double m2 = e2[0] * e3[1] - e2[1] * e3[0];
+  return (e1[0] * m0 - e1[1] * m1) + e1[2] * m2;
+}
+
+// Cell of a simplicial mesh holding x (already inside the domain box):
+// among the cells listed in x's grid cell whose bounding box holds x, the
+// lowest-numbered one whose orientation tests with each vertex replaced by
+// x agree in sign with its own orientation or vanish; else the one whose
+// centroid is nearest (lowest number on ties).
+template <int DIM, class T>
+__device__ int64_t locate(const PhiView<T>& P, const double x[3]) {
+#pragma clang fp contract(off)
+  int64_t g = 0, stride = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    int64_t i = (int64_t)floor((x[a] - P.box_lo[a]) * P.pl_inv);
+    i = i < 0 ? 0 : (i >= P.pl_nb[a] ? P.pl_nb[a] - 1 : i);
+    g += i * stride;
+    stride *= P.pl_nb[a];
+  }
+  int64_t best = -1;
+  double best_d2 = 0.0;
+  for (int32_t e = P.pl_start[g]; e < P.pl_start[g + 1]; ++e) {
+    const int32_t K = P.pl_list[e];
+    double v[DIM + 1][3];
+    bool in_box = true;
+#pragma unroll
+    for (int i = 0; i <= DIM; ++i) {
+      const int32_t q = P.cells[(int64_t)K * (DIM + 1) + i];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) v[i][a] = P.vtx[a * P.n_vertices + q];
+      if (DIM == 2) v[i][2] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      double lo = v[0][a], hi = v[0][a];
+#pragma unroll
+      for (int i = 1; i <= DIM; ++i) {
+        lo = v[i][a] < lo ? v[i][a] : lo;
+        hi = v[i][a] > hi ? v[i][a] : hi;
+      }
+      in_box = in_box && x[a] >= lo && x[a] <= hi;
+    }
+    if (!in_box) continue;
+    const double own = orient<DIM>(v[0], v[1], v[2], v[DIM == 3 ? 3 : 2]);
+    bool inside = own != 0.0;
+#pragma unroll
+    for (int i = 0; i <= DIM; ++i) {
+      if (!inside) break;
+      const double* w[4] = {v[0], v[1], v[2], v[DIM == 3 ? 3 : 2]};
+      w[i] = x;
+      const double o = orient<DIM>(w[0], w[1], w[2], w[3]);
+      inside = own > 0.0 ? o >= 0.0 : o <= 0.0;
+    }
+    if (inside) return K;
+    // fallback candidate: nearest centroid
+    double d = x[0] - P.cen[K];
+    double d2 = d * d;
+    d = x[1] - P.cen[P.n_cells + K];
+    d2 = d2 + d * d;
+    if (DIM == 3) {
+      d = x[2] - P.cen[2 * P.n_cells + K];
+      d2 = d2 + d * d;
+    }
+    if (best < 0 || d2 < best_d2) {
+      best = K;
+      best_d2 = d2;
+    }
+  }
+  return best < 0 ? 0 : best;
+}
 
 // Multilinear interpolation, written as the sum over the 2^d lattice
 // corners of (product of the per-axis weights f or 1 - f) times the nodal
@@ -90,6 +195,15 @@ __device__ __forceinline__ void speed(const VelocityView<T>& V, const PhiView<T>
   T ph;
   if (P.constant) {
     ph = P.phi0;
+  } else if (P.simplex) {
+    // the cell of x clamped into the domain box
+    double q[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double xa = (double)x[a];
+      q[a] = xa < P.box_lo[a] ? P.box_lo[a] : (xa > P.box_hi[a] ? P.box_hi[a] : xa);
+    }
+    ph = (T)P.phi[locate<DIM, T>(P, q)];
   } else {
     int64_t cid = 0, stride = 1;
 #pragma unroll
@@ -140,8 +254,9 @@ __device__ __forceinline__ void rk4_back(const VelocityView<T>& V, const PhiView
 
 template <int DIM, class T>
 __global__ void k_trace(VelocityView<T> V, PhiView<T> P, const double* __restrict__ cen,
-                        int64_t n_balls, T r, T tau, int substeps, T lo0, T lo1, T lo2, T hi0,
-                        T hi1, T hi2, double* __restrict__ tracked, double* __restrict__ r_hat) {
+                        const double* __restrict__ rad, int64_t n_balls, T tau, int substeps,
+                        T lo0, T lo1, T lo2, T hi0, T hi1, T hi2, double* __restrict__ tracked,
+                        double* __restrict__ r_hat) {
 #pragma clang fp contract(off)
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_balls) return;
@@ -154,6 +269,7 @@ __global__ void k_trace(VelocityView<T> V, PhiView<T> P, const double* __restric
   rk4_back<DIM, T>(V, P, X, tau, substeps, lo, hi);
 #pragma unroll
   for (int a = 0; a < DIM; ++a) tracked[a * n_balls + b] = (double)X[a];
+  const T r = (T)rad[b];
   if (P.constant) {
     r_hat[b] = (double)r;
     return;
@@ -201,17 +317,29 @@ static void launch_trace(const bchar_mesh_s* m, const bchar_velocity& u, double 
   P.phi = m->phi.as<double>();
   P.constant = m->phi_const;
   P.phi0 = (T)m->phi0;
+  P.simplex = m->kind == BCHAR_MESH_SIMPLEX ? 1 : 0;
+  P.vtx = m->vtx.as<double>();
+  P.n_vertices = m->n_vertices;
+  P.cells = m->cells.as<int32_t>();
+  P.cen = m->cen.as<double>();
+  P.n_cells = m->n_cells;
+  P.pl_inv = m->pl_inv;
+  P.pl_start = m->pl_start.as<int32_t>();
+  P.pl_list = m->pl_list.as<int32_t>();
   T lo[3], hi[3];
   for (int a = 0; a < 3; ++a) {
-    lo[a] = (T)m->origin[a];
-    hi[a] = (T)(m->origin[a] + (double)m->n[a] * m->h[a]);
+    P.box_lo[a] = m->box_lo[a];
+    P.box_hi[a] = m->box_hi[a];
+    P.pl_nb[a] = m->pl_nb[a];
+    lo[a] = (T)m->box_lo[a];
+    hi[a] = (T)m->box_hi[a];
   }
   const T tau = (T)(dt / substeps);
   {
     ::bchar::ProfScope ps_("k_trace", s);
     k_trace<DIM, T><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(
-        V, P, m->cen.as<double>(), m->n_balls, (T)m->r, tau, substeps, lo[0], lo[1], lo[2], hi[0],
-        hi[1], hi[2], tracked, r_hat);
+        V, P, m->cen.as<double>(), m->rad.as<double>(), m->n_balls, tau, substeps, lo[0], lo[1],
+        lo[2], hi[0], hi[1], hi[2], tracked, r_hat);
   }
   BCHAR_HIP(hipGetLastError());
 }
@@ -297,9 +425,9 @@ struct AsmParams {
   double org[3];
   double inv_hs;
   double hs;
-  double r;               // residing radius
-  double rho;             // porous density (uniform)
-  double ball_vol;        // |B_{K,s}|
+  double rmax;            // largest residing radius
+  const double* rho;      // per cell, porous density
+  const double* bvol;     // per ball, |B_{K,s}|
   const double* phi;      // per cell
   const double* tracked;  // dim * n_balls
   const double* r_hat;    // n_balls
@@ -307,6 +435,7 @@ struct AsmParams {
   const double* bk_cen;   // dim * n_balls, bucket order
   const float* bk_cen32;
   const int32_t* bk_ball;
+  const double* bk_rad;   // n_balls, bucket order
   // outputs
   int32_t* row_cnt;       // count pass: unique M per row
   int32_t* pair_cnt;      // count pass: pairs per row
@@ -319,8 +448,8 @@ struct AsmParams {
   int32_t* flags;         // [0] first void ball (min), [1] overflow
 };
 
-// Predicate ((dx*dx + dy*dy) + dz*dz) < (ra + rb)^2, rounded once per
-// operation (no contraction into FMA) so that it is reproducible.
+// Predicate ((dx*dx + dy*dy) + dz*dz) < (ra + rb)^2 (rs = ra + rb), rounded
+// once per operation (no contraction into FMA) so that it is reproducible.
 template <int DIM, class T>
 __device__ __forceinline__ bool overlap(const T p[3], const T c[3], T rs, T& d2) {
 #pragma clang fp contract(off)
@@ -371,15 +500,13 @@ __global__ void __launch_bounds__(64) k_assemble(AsmParams P) {
 #pragma unroll
   for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
   const T ra = (T)P.r_hat[b];
-  const T rb = (T)P.r;
-  const T rs = ra + rb;
-  // buckets that can hold a centre within ra + rb of p (range widened by a
-  // relative 1e-6 so that binary32 rounding of the predicate cannot reach
+  // buckets that can hold a centre within ra + r_max of p (range widened by
+  // a relative 1e-6 so that binary32 rounding of the predicate cannot reach
   // past it; the predicate alone decides)
   int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
-  search_range<DIM>(P, p, (double)ra + P.r, blo, side);
+  search_range<DIM>(P, p, (double)ra + P.rmax, blo, side);
   const int nq = (int)(side[0] * side[1] * side[2]);
-  const double mass = P.rho * P.phi[K] * P.ball_vol;   // rho_K phi_K |B_{K,s}|
+  const double mass = P.rho[K] * P.phi[K] * P.bvol[b];   // rho_K phi_K |B_{K,s}|
 
   // pass 1: number of overlaps and S = sum omega for this lane's buckets
   int cnt = 0;
@@ -395,10 +522,11 @@ __global__ void __launch_bounds__(64) k_assemble(AsmParams P) {
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
         c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
+      const T rb = (T)P.bk_rad[e];
       T d2;
-      if (!overlap<DIM, T>(p, c, rs, d2)) continue;
+      if (!overlap<DIM, T>(p, c, ra + rb, d2)) continue;
       const int64_t M = P.bk_ball[e] / nbpc;
-      const double om = P.rho * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
+      const double om = P.rho[M] * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
       S += om;
       ++cnt;
     }
@@ -428,11 +556,12 @@ __global__ void __launch_bounds__(64) k_assemble(AsmParams P) {
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
         c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
+      const T rb = (T)P.bk_rad[e];
       T d2;
-      if (!overlap<DIM, T>(p, c, rs, d2)) continue;
+      if (!overlap<DIM, T>(p, c, ra + rb, d2)) continue;
       const int32_t rb_id = P.bk_ball[e];
       const int32_t M = rb_id / nbpc;
-      const double om = P.rho * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
+      const double om = P.rho[M] * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
       s_key[off] = M;
       s_val[off] = share * om;
       if (FILL) s_pb[off] = rb_id;
@@ -509,10 +638,8 @@ __global__ void k_ball_counts(AsmParams P, int32_t* __restrict__ ball_cnt) {
   T p[3] = {0, 0, 0};
   for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
   const T ra = (T)P.r_hat[b];
-  const T rb = (T)P.r;
-  const T rs = ra + rb;
   int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
-  search_range<DIM>(P, p, (double)ra + P.r, blo, side);
+  search_range<DIM>(P, p, (double)ra + P.rmax, blo, side);
   const int nq = (int)(side[0] * side[1] * side[2]);
   int cnt = 0;
   for (int q = 0; q < nq; ++q) {
@@ -525,7 +652,7 @@ __global__ void k_ball_counts(AsmParams P, int32_t* __restrict__ ball_cnt) {
       for (int a = 0; a < DIM; ++a)
         c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
       T d2;
-      if (overlap<DIM, T>(p, c, rs, d2)) ++cnt;
+      if (overlap<DIM, T>(p, c, ra + (T)P.bk_rad[e], d2)) ++cnt;
     }
   }
   ball_cnt[b] = cnt;
@@ -572,13 +699,13 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.nbpc = m->nbpc;
   for (int a = 0; a < 3; ++a) {
     P.nbk[a] = m->nbk[a];
-    P.org[a] = m->origin[a];
+    P.org[a] = m->box_lo[a];
   }
   P.inv_hs = 1.0 / m->hs;
   P.hs = m->hs;
-  P.r = m->r;
-  P.rho = m->rho;
-  P.ball_vol = m->ball_vol;
+  P.rmax = m->rmax;
+  P.rho = m->rho.as<double>();
+  P.bvol = m->bvol.as<double>();
   P.phi = m->phi.as<double>();
   P.tracked = tracked;
   P.r_hat = r_hat;
@@ -586,6 +713,7 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.bk_cen = m->bk_cen.as<double>();
   P.bk_cen32 = m->bk_cen32.as<float>();
   P.bk_ball = m->bk_ball.as<int32_t>();
+  P.bk_rad = m->bk_rad.as<double>();
   P.row_cnt = ws.get<int32_t>(nc + 1);
   P.pair_cnt = ws.get<int32_t>(nc + 1);
   P.flags = ws.get<int32_t>(2);

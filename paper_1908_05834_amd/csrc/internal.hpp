@@ -68,24 +68,35 @@ struct Arena {
 
 struct bchar_mesh_s {
   int dim = 0;
+  int kind = 0;                // BCHAR_MESH_CARTESIAN or BCHAR_MESH_SIMPLEX
   int64_t n[3] = {1, 1, 1};
   double origin[3] = {0, 0, 0};
   double h[3] = {1, 1, 1};
+  double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};   // domain box
   int layout = 0;
   int64_t n_cells = 0, n_balls = 0;
   int nbpc = 1;                // balls per cell
-  double cell_vol = 0;         // |K|
-  double r = 0;                // radius of every ball
-  double ball_vol = 0;         // |B|
-  double rho = 0;              // porous density (same on every cell)
+  double rmax = 0;             // largest ball radius
   bool phi_const = true;
   double phi0 = 1;
   double bmax = 0;             // max |K|_phi
   // device arrays
   bchar::DBuf phi;             // n_cells
   bchar::DBuf b;               // n_cells, |K|_phi
+  bchar::DBuf rho;             // n_cells, porous density rho_K
+  bchar::DBuf rad;             // n_balls, radius
+  bchar::DBuf bvol;            // n_balls, |B|
   bchar::DBuf cen;             // dim * n_balls, ball order, fp64
   bchar::DBuf cen32;           // dim * n_balls, fp32
+  // simplicial meshes: vertices (SoA), cells ((dim+1) ids per cell) and a
+  // uniform grid listing the cells whose bounding box meets each grid cell
+  int64_t n_vertices = 0;
+  bchar::DBuf vtx;             // dim * n_vertices
+  bchar::DBuf cells;           // int32 (dim + 1) * n_cells, cell-major
+  double pl_inv = 0;           // 1 / grid side
+  int64_t pl_nb[3] = {1, 1, 1};
+  bchar::DBuf pl_start;        // int32 [grid cells + 1]
+  bchar::DBuf pl_list;         // int32 cell ids, ascending within a grid cell
   // spatial hash of the residing balls
   double hs = 0;               // bucket side
   int64_t nbk[3] = {1, 1, 1};
@@ -94,6 +105,7 @@ struct bchar_mesh_s {
   bchar::DBuf bk_cen;          // fp64 dim * n_balls, bucket order
   bchar::DBuf bk_cen32;        // fp32 dim * n_balls, bucket order
   bchar::DBuf bk_ball;         // int32 n_balls: ball id of each bucket slot
+  bchar::DBuf bk_rad;          // fp64 n_balls, radius, bucket order
   // scratch reused by builds
   bchar::Arena ws;
   bchar::DBuf scratch_small;   // small device scalars
@@ -136,7 +148,17 @@ void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // mesh (mesh.hip)
-void mesh_build_device(bchar_mesh_s* m, hipStream_t s);
+// Cartesian layouts: every ball of radius r and measure ball_vol, rho and
+// |K| the same on every cell
+struct UniformBalls {
+  double r, ball_vol, rho, cell_vol;
+};
+// centres, radii, measures, rho and |K|_phi of a Cartesian layout on the
+// device, then the hash
+void mesh_build_cartesian(bchar_mesh_s* m, const UniformBalls& u, hipStream_t s);
+// the spatial hash of the balls already in cen / rad (side 2 rmax over the
+// domain box)
+void mesh_build_hash(bchar_mesh_s* m, hipStream_t s);
 
 // tracking + V (build.hip)
 struct BuildOut {

@@ -1,12 +1,14 @@
 // Mesh-static data: balls of every cell (Sec. 3) and the spatial hash.
 //
 // The balls of a Cartesian cell follow the layout chosen at creation
-// (see bchar.h).  Residing balls are bucketed on a uniform grid of side
-// hs = 2 r, so that every ball overlapping a tracked ball of radius
-// r_hat <= r lies in the 3^d buckets around the tracked centre; larger
-// tracked radii widen the searched block (build.hip).  Bucket contents are
-// stored contiguously in bucket order (SoA, binary64 and binary32 copies)
-// so that a query streams them.
+// (see bchar.h); those of a simplicial mesh come from the host (one
+// centroid ball per cell).  Residing balls are bucketed on a uniform grid
+// of side hs = 2 r_max over the domain box, so that every ball overlapping
+// a tracked ball of radius r_hat <= r_max lies in the 3^d buckets around
+// the tracked centre; larger tracked radii widen the searched block
+// (build.hip).  Bucket contents (centres, binary64 and binary32, and
+// radii) are stored contiguously in bucket order (SoA) so that a query
+// streams them.
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -65,8 +67,9 @@ __global__ void k_bucket_of(int dim, int64_t n_balls, const double* __restrict__
 
 __global__ void k_gather_bucketed(int dim, int64_t n_balls, const int32_t* __restrict__ perm,
                                   const double* __restrict__ cen,
-                                  const float* __restrict__ cen32, double* __restrict__ bk,
-                                  float* __restrict__ bk32) {
+                                  const float* __restrict__ cen32,
+                                  const double* __restrict__ rad, double* __restrict__ bk,
+                                  float* __restrict__ bk32, double* __restrict__ bkr) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_balls) return;
   const int64_t b = perm[p];
@@ -74,6 +77,7 @@ __global__ void k_gather_bucketed(int dim, int64_t n_balls, const int32_t* __res
     bk[a * n_balls + p] = cen[a * n_balls + b];
     bk32[a * n_balls + p] = cen32[a * n_balls + b];
   }
+  bkr[p] = rad[b];
 }
 
 __global__ void k_porous_volume(const double* __restrict__ phi, double vol, int64_t n,
@@ -82,7 +86,7 @@ __global__ void k_porous_volume(const double* __restrict__ phi, double vol, int6
   if (i < n) b[i] = phi[i] * vol;
 }
 
-void mesh_build_device(bchar_mesh_s* m, hipStream_t s) {
+void mesh_build_cartesian(bchar_mesh_s* m, const UniformBalls& u, hipStream_t s) {
   const int64_t nb = m->n_balls;
   m->cen.reserve(sizeof(double) * m->dim * nb);
   m->cen32.reserve(sizeof(float) * m->dim * nb);
@@ -93,21 +97,31 @@ void mesh_build_device(bchar_mesh_s* m, hipStream_t s) {
         m->h[1], m->h[2], m->cen.as<double>(), m->cen32.as<float>());
   }
   BCHAR_HIP(hipGetLastError());
-
   m->b.reserve(sizeof(double) * m->n_cells);
   {
     ::bchar::ProfScope ps_("k_porous_volume", s);
     k_porous_volume<<<blocks_for(m->n_cells, 256), 256, 0, s>>>(
-        m->phi.as<double>(), m->cell_vol, m->n_cells, m->b.as<double>());
+        m->phi.as<double>(), u.cell_vol, m->n_cells, m->b.as<double>());
   }
   BCHAR_HIP(hipGetLastError());
+  m->rad.reserve(sizeof(double) * nb);
+  m->bvol.reserve(sizeof(double) * nb);
+  m->rho.reserve(sizeof(double) * m->n_cells);
+  fill_f64(m->rad.as<double>(), u.r, nb, s);
+  fill_f64(m->bvol.as<double>(), u.ball_vol, nb, s);
+  fill_f64(m->rho.as<double>(), u.rho, m->n_cells, s);
+  m->rmax = u.r;
+  mesh_build_hash(m, s);
+}
 
-  // uniform bucket grid of side 2r over the domain box
-  m->hs = 2.0 * m->r;
+void mesh_build_hash(bchar_mesh_s* m, hipStream_t s) {
+  const int64_t nb = m->n_balls;
+  // uniform bucket grid of side 2 r_max over the domain box
+  m->hs = 2.0 * m->rmax;
   m->n_buckets = 1;
   for (int a = 0; a < 3; ++a) {
     if (a < m->dim) {
-      double L = (double)m->n[a] * m->h[a];
+      double L = m->box_hi[a] - m->box_lo[a];
       int64_t c = (int64_t)ceil(L / m->hs);
       m->nbk[a] = c < 1 ? 1 : c;
     } else {
@@ -122,7 +136,7 @@ void mesh_build_device(bchar_mesh_s* m, hipStream_t s) {
   {
     ::bchar::ProfScope ps_("k_bucket_of", s);
     k_bucket_of<<<blocks_for(nb, 256), 256, 0, s>>>(
-        m->dim, nb, m->cen.as<double>(), m->origin[0], m->origin[1], m->origin[2], 1.0 / m->hs,
+        m->dim, nb, m->cen.as<double>(), m->box_lo[0], m->box_lo[1], m->box_lo[2], 1.0 / m->hs,
         m->nbk[0], m->nbk[1], m->nbk[2], key);
   }
   BCHAR_HIP(hipGetLastError());
@@ -132,11 +146,13 @@ void mesh_build_device(bchar_mesh_s* m, hipStream_t s) {
               m->ws, s);
   m->bk_cen.reserve(sizeof(double) * m->dim * nb);
   m->bk_cen32.reserve(sizeof(float) * m->dim * nb);
+  m->bk_rad.reserve(sizeof(double) * nb);
   {
     ::bchar::ProfScope ps_("k_gather_bucketed", s);
     k_gather_bucketed<<<blocks_for(nb, 256), 256, 0, s>>>(
         m->dim, nb, m->bk_ball.as<int32_t>(), m->cen.as<double>(), m->cen32.as<float>(),
-        m->bk_cen.as<double>(), m->bk_cen32.as<float>());
+        m->rad.as<double>(), m->bk_cen.as<double>(), m->bk_cen32.as<float>(),
+        m->bk_rad.as<double>());
   }
   BCHAR_HIP(hipGetLastError());
   BCHAR_HIP(hipStreamSynchronize(s));

@@ -57,11 +57,22 @@ def _case(name):
     if name == "porous3d_subcell":
         w = inputs.porous_swirl_hex(8)
         return w["mesh"], w["vel_fn"](0), 0.05, "subcell"
+    if name in ("tets", "tets_porous"):
+        phi = inputs.lognormal_phi(6 * 4 ** 3, 21) if name == "tets_porous" else None
+        mesh = inputs.kuhn_tets(4, 0.1, 8, phi=phi)
+        vel = inputs.sample_velocity_grid((4, 4, 4), lambda p, t: inputs.swirl_3d(p, t))
+        return mesh, vel, 0.05, "equal_measure"
+    if name in ("tris", "tris_porous"):
+        phi = inputs.lognormal_phi(2 * 10 ** 2, 22) if name == "tris_porous" else None
+        mesh = inputs.triangulated_square(10, 0.1, 6, phi=phi)
+        vel = inputs.sample_velocity_grid((10, 10), inputs.rotation_stretch_2d)
+        return mesh, vel, 0.3, "equal_measure"
     raise KeyError(name)
 
 
 GEOM_CASES = ["rot2d_subcell", "solid_equal", "solid_inscribed", "swirl3d_subcell_8",
-              "swirl3d_inscribed_12", "porous2d_subcell", "porous3d_subcell"]
+              "swirl3d_inscribed_12", "porous2d_subcell", "porous3d_subcell",
+              "tets", "tets_porous", "tris", "tris_porous"]
 
 
 def _tracked_tensors(torch, T):
@@ -93,14 +104,17 @@ def test_pairs_pattern_and_v(env, name, precision):
 
 
 @pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_16", "porous2d_subcell",
-                                  "porous3d_subcell"])
+                                  "porous3d_subcell", "tets", "tets_porous", "tris_porous"])
 def test_tracking(env, name):
     torch, bchar = env
     _say(f"[gpu] tracking {name}")
     mesh, vel, dt, layout = _case(name)
     M = bchar.Mesh(mesh, layout)
     U = bchar.VelocityLattice(vel)
-    C, r, _ = ogeo.ball_layout(mesh["n"], mesh["origin"], mesh["h"], layout)
+    if ogeo.is_simplex(mesh):
+        C, r, _ = ogeo.simplex_ball_layout(mesh)
+    else:
+        C, r, _ = ogeo.ball_layout(mesh["n"], mesh["origin"], mesh["h"], layout)
     want = ogeo.trace_points(C, mesh, vel, dt)
     want_r = ogeo.tracked_radius(C, r, want, mesh, vel, dt)
     porous = not np.all(mesh["phi"] == mesh["phi"][0])
@@ -145,7 +159,8 @@ def _full(env, name, precision="fp64"):
 
 @pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_8", "swirl3d_subcell_16",
                                   "solid_equal", "solid_inscribed", "porous2d_subcell",
-                                  "porous3d_subcell", "swirl3d_inscribed_12"])
+                                  "porous3d_subcell", "swirl3d_inscribed_12", "tets",
+                                  "tets_porous", "tris", "tris_porous"])
 def test_full_step(env, name):
     _say(f"[gpu] full step {name}")
     torch, bchar, mesh, ref, M, T = _full(env, name)
@@ -180,7 +195,8 @@ def test_full_step(env, name):
     assert chk["ok"]
 
 
-@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_16", "porous3d_subcell"])
+@pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_16", "porous3d_subcell",
+                                  "tets", "tets_porous"])
 def test_full_step_fp32(env, name):
     _say(f"[gpu] full step fp32 {name}")
     torch, bchar, mesh, ref, M, T = _full(env, name, "fp32")
@@ -221,3 +237,25 @@ def test_solid_body_ten_steps(env):
     _say(f"    c rel err after 10 steps {err:.3e}")
     assert err <= 1e-10
     assert abs(M.mass(c) - m0) <= 1e-12 * abs(m0)
+
+
+def test_simplex_mesh_checks(env):
+    """Simplicial meshes: the layout must be equal_measure, degenerate cells
+    and out-of-range vertex ids are rejected, ball measures equal |K|."""
+    torch, bchar = env
+    m = inputs.kuhn_tets(2, 0.1, 3)
+    with pytest.raises(bchar.BcharError):
+        bchar.Mesh(m, "subcell")
+    bad = dict(m)
+    bad["cells"] = m["cells"].copy()
+    bad["cells"][0, 1] = bad["cells"][0, 0]
+    with pytest.raises(bchar.BcharError):
+        bchar.Mesh(bad, "equal_measure")
+    bad["cells"] = m["cells"].copy()
+    bad["cells"][3, 2] = m["vertices"].shape[0]
+    with pytest.raises(bchar.BcharError):
+        bchar.Mesh(bad, "equal_measure")
+    M = bchar.Mesh(m, "equal_measure")
+    c, r, cell = M.export_balls()
+    oc, orad, _ = ogeo.simplex_ball_layout(m)
+    assert np.array_equal(r, orad) and np.array_equal(c, oc)
