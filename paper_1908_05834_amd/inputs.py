@@ -313,14 +313,15 @@ def porous_swirl_hex(n=32, seed=5834, steps=20):
 def jittered_tets(n=96, jitter=0.1, seed=1908, phi_seed=5834, cfl=4.0, steps=20):
     """3D unstructured workload: n^3 cubes split into 6 Kuhn tetrahedra
     (6 n^3 cells), interior vertices jittered by up to 10 % of h, phi =
-    clip(exp(0.5 Z), 0.05, 1) per cell, the swirl scaled so that the largest
-    nodal |u| dt / h is ``cfl``, c^0 ~ U[0,1], dt = 1/128."""
+    clip(exp(0.5 Z), 0.05, 1) per cell, the swirl scaled so that the CFL
+    number of the characteristic speed, dt max over cell centroids of
+    (|u| / phi_K) / h, is ``cfl``; c^0 ~ U[0,1], dt = 1/128."""
     nc = 6 * n ** 3
     mesh = kuhn_tets(n, jitter, seed, phi=lognormal_phi(nc, phi_seed))
     dt = 1.0 / 128.0
     h = 1.0 / n
-    probe = sample_velocity_grid((n, n, n), lambda p, t: swirl_3d(p, t), 0.0)
-    umax = float(np.max(np.sqrt(np.sum(probe["u"] ** 2, axis=0))))
+    u0 = swirl_3d(cell_centroids(mesh), 0.0)
+    umax = float(np.max(np.sqrt(np.sum(u0 ** 2, axis=1)) / mesh["phi"]))
     amp = cfl * h / (umax * dt)
 
     def vel_fn(step):
