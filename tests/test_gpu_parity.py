@@ -259,3 +259,39 @@ def test_simplex_mesh_checks(env):
     c, r, cell = M.export_balls()
     oc, orad, _ = ogeo.simplex_ball_layout(m)
     assert np.array_equal(r, orad) and np.array_equal(c, oc)
+
+
+def test_unstructured_properties(env):
+    """The unstructured workload (jittered Kuhn tetrahedra, lognormal
+    porosity, CFL 4 on u / phi, FP32 volumes) at 24^3 x 6 cells, two steps:
+    properties that hold at any size -- porous mass to 1e-12, constants to
+    1e-12, both marginals of A equal |K|_phi."""
+    torch, bchar = env
+    _say("[gpu] unstructured 24^3 x 6 tets, 2 steps")
+    w = inputs.jittered_tets(24, steps=2)
+    mesh = w["mesh"]
+    M = bchar.Mesh(mesh, "equal_measure")
+    o = bchar.opts_default(precision=bchar.FP32_VOLUME)
+    c = torch.as_tensor(w["c0"], device="cuda")
+    nxt = torch.empty_like(c)
+    m0 = M.mass(c)
+    T = None
+    for s in range(w["steps"]):
+        U = bchar.VelocityLattice(w["vel_fn"](s))
+        if T is None:
+            T = bchar.Transfer.build(M, U, w["dt"], o)
+        else:
+            T.rebuild(U, w["dt"], o)
+        T.step(c, nxt)
+        c, nxt = nxt, c
+        _say(f"    step {s}: {T.stats}")
+        assert abs(M.mass(c) - m0) <= 1e-12 * abs(m0)
+    rp, col, A = T.export_csr(bchar.STAGE_ALL)
+    nc = rp.size - 1
+    rows = otr.csr_rows(rp)
+    b = mesh["phi"] * ogeo.simplex_volumes(mesh["vertices"], mesh["cells"])
+    assert np.max(np.abs(np.bincount(rows, weights=A, minlength=nc) - b)) <= 2e-13 * b.max()
+    assert np.max(np.abs(np.bincount(col, weights=A, minlength=nc) - b)) <= 2e-13 * b.max()
+    ones = torch.ones(nc, dtype=torch.float64, device="cuda")
+    T.step(ones, nxt)
+    assert torch.max(torch.abs(nxt - 1.0)).item() <= 1e-12
