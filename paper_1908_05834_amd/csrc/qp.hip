@@ -773,7 +773,7 @@ struct Hierarchy {
   double* G = nullptr;   // inverse of the shifted coarsest matrix
   int coarse_n = 0;
   bool dense = false;
-  int pre = 2, post = 2;             // sweeps of the fused coarse levels
+  int pre = 1, post = 1;             // sweeps of the fused coarse levels
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
   FusedLevels* fused = nullptr;    // device copy
