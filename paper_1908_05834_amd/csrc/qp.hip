@@ -50,8 +50,10 @@ constexpr int kMaxCoarse = 512;    // dense coarsest solve
 constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
 constexpr int kIpmMaxIter = 100;   // interior-point iterations per box level
 constexpr double kIpmMuTight = 1e-13;  // complementarity of an accepted interior point
+constexpr double kIpmWarmShift = 1e-3; // distance from the box of a warm interior point
 constexpr int kWarmNewton = 8;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
+constexpr int kPolishCG = 60;      // CG cap of those steps once the interior point met tol
 
 // ====================================================================== reductions
 
@@ -1707,6 +1709,24 @@ __global__ void k_ipm_update(IpmArrays I, double* __restrict__ t, const double* 
   t[k] += ad * dt[k];
 }
 
+// Warm start from multipliers: t = a (mu + nu) of the previous solve on
+// this matrix.  x = t moved at least theta inside the box, zl = (x - t)+ +
+// theta, zu = (t - x)+ + theta: dual feasible (x - t - zl + zu = 0) and
+// every slack and multiplier at least theta.
+__global__ void k_ipm_init_warm(IpmArrays I, const double* __restrict__ t, double theta,
+                                int64_t nnz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double tk = t[k];
+  double x = tk > I.lo + theta ? tk : I.lo + theta;
+  if (I.has_hi) x = x < I.hi - theta ? x : I.hi - theta;
+  I.x[k] = x;
+  I.sl[k] = x - I.lo;
+  I.zl[k] = (x > tk ? x - tk : 0.0) + theta;
+  I.su[k] = I.has_hi ? I.hi - x : 1.0;
+  I.zu[k] = I.has_hi ? (tk > x ? tk - x : 0.0) + theta : 0.0;
+}
+
 __global__ void k_ipm_init(IpmArrays I, int64_t nnz) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
@@ -1850,7 +1870,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // the per-cell coordinates with the constant-s direction removed.  Leaves
   // the per-cell solution in cx, the multiplier direction in dmu, dnu and
   // the entry increments a_k (dmu_K + dnu_M) in Q.dt; returns iterations.
-  auto pcg = [&](const double* fv, double cg_tol, bool from_cx) -> int {
+  auto pcg = [&](const double* fv, double cg_tol, bool from_cx, int max_cg) -> int {
     {
       ::bchar::ProfScope ps_("k_zrhs", s);
       k_zrhs<<<gn, kT, 0, s>>>(fv, n, cr);
@@ -1878,7 +1898,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
     red.dot(cr, cz, n2, 8);
     int k = 0;
-    for (k = 0; k < o.qp_max_cg; ++k) {
+    for (k = 0; k < max_cg; ++k) {
       {
         ::bchar::ProfScope ps_("k_zop", s);
         k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq);
@@ -1889,7 +1909,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_cg_update<<<gn2, kT, 0, s>>>(red.out + 8, n2, cx, cr, cp, cq);
       }
       BCHAR_HIP(hipGetLastError());
-      if ((k % 4) == 3 || k + 1 == o.qp_max_cg) {
+      if ((k % 4) == 3 || k + 1 == max_cg) {
         red.maxabs(cr, n2, 11);
         if (red.fetch(11) <= cg_tol) {
           ++k;
@@ -1926,7 +1946,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // derivative.  Returns true once max |F| <= tol; fn holds the last
   // residual.
   double fn = 0.0;
-  auto ssn = [&](double lo, double hi, int max_it, int patience, const char* tag) -> bool {
+  auto ssn = [&](double lo, double hi, int max_it, int patience, int max_cg,
+                 const char* tag) -> bool {
     int short_steps = 0;
     for (int it = 0; it < max_it; ++it) {
       {
@@ -1950,7 +1971,12 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // near-exact once many steps were needed
       const double eta = it < 30 ? std::min(0.1, std::sqrt(fn)) * 0.1 : 1e-6;
       const double cg_tol = std::max(eta * fn, 0.1 * tol);
-      const int k = pcg(Q.F, cg_tol, false);
+      const int k = pcg(Q.F, cg_tol, false, max_cg);
+      if (k >= max_cg && patience > 0) {
+        // a capped attempt whose linear system CG cannot solve is hopeless
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: CG did not converge\n");
+        return false;
+      }
       if (trace_enabled()) {
         red.maxabs(cr, n2, 11);
         fprintf(stderr, "[bchar]   newton %d%s: |F| %.3e, cg %d (|r| %.3e of %.3e), t %.3f s\n",
@@ -2062,7 +2088,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   };
 
   // ---------------------------------------------------------------- interior point
-  // From x = 0, zl = zu = 1, t = 0.  Returns 2 once max |B x - r| <= tol
+  // From x = 0, zl = zu = 1, t = 0, or (warm) from the current t.  Returns 2 once max |B x - r| <= tol
   // and the mean complementarity is at most kIpmMuTight (its x is then an
   // answer in its own right, within about mu / z of the minimiser), 1 when
   // it stalls after reaching 1e-10 on both, 0 when the complementarity
@@ -2083,17 +2109,23 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   I.dzu = ws.get<double>(nnz + 1);
   double* rp = ws.get<double>(n2);
   double fp_ipm = HUGE_VAL;
-  auto ipm = [&](double lo, double hi) -> int {
+  auto ipm = [&](double lo, double hi, bool warm) -> int {
     I.lo = lo;
     I.hi = hi;
     I.has_hi = std::isinf(hi) ? 0 : 1;
     const double m_pairs = (double)nnz * (I.has_hi ? 2.0 : 1.0);
-    {
-      ::bchar::ProfScope ps_("k_ipm_init", s);
-      k_ipm_init<<<gz, kT, 0, s>>>(I, nnz);
+    if (warm) {
+      // from the current t and zdual
+      ::bchar::ProfScope ps_("k_ipm_init_warm", s);
+      k_ipm_init_warm<<<gz, kT, 0, s>>>(I, Q.t, kIpmWarmShift, nnz);
+    } else {
+      {
+        ::bchar::ProfScope ps_("k_ipm_init", s);
+        k_ipm_init<<<gz, kT, 0, s>>>(I, nnz);
+      }
+      fill_f64(Q.t, 0.0, nnz, s);
+      fill_f64(zdual, 0.0, n2, s);
     }
-    fill_f64(Q.t, 0.0, nnz, s);
-    fill_f64(zdual, 0.0, n2, s);
     BCHAR_HIP(hipGetLastError());
     double mu0 = -1.0, fp_best = HUGE_VAL;
     int stall = 0;
@@ -2156,7 +2188,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // predictor (affine scaling).  Once the normal equations are too
       // ill-conditioned for CG to reach its tolerance the step would spoil
       // the iterate: hand it over as it is.
-      if (pcg(Q.F, cg_tol, false) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      if (pcg(Q.F, cg_tol, false, o.qp_max_cg) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 0, 0.0, nnz, red.part);
@@ -2187,7 +2219,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       // the corrector's system differs from the predictor's in the
       // right-hand side only: start CG from the predictor's solution
-      if (pcg(Q.F, cg_tol, true) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      if (pcg(Q.F, cg_tol, true, o.qp_max_cg) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 1, smu, nnz, red.part);
@@ -2230,19 +2262,23 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
       }
       BCHAR_HIP(hipGetLastError());
-      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2, " (warm)");
+      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2, o.qp_max_cg, " (warm)");
       if (converged) break;
     }
+    const bool warm = o.warm_start && warm_level == level;
     if (level == 2) {
       fill_f64(Q.t, 0.0, nnz, s);
       fill_f64(zdual, 0.0, n2, s);
-      converged = ssn(lo, hi, o.qp_max_newton, 0, "");
+      converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, "");
     } else {
-      const int r = ipm(lo, hi);
+      // a warm interior point that fails is retried from zero
+      int r = warm ? ipm(lo, hi, true) : 0;
+      if (r == 0) r = ipm(lo, hi, false);
       if (r > 0) {
         // an interior point at the tolerance is an answer already: one
         // short semismooth step is enough to give up on the exact one
         converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
+                        r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
                         " (after interior point)");
         if (!converged && r == 2) {
           converged = ipm_answer = true;
@@ -2250,7 +2286,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         } else if (!converged) {
           // the interior point stalled short of the tolerance: semismooth
           // Newton without the step-count cap
-          converged = ssn(lo, hi, o.qp_max_newton, 0, " (after interior point)");
+          converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, " (after interior point)");
         }
       }
     }
