@@ -190,6 +190,7 @@ struct Level {
 constexpr int kFusedMaxNodes = 8192;
 constexpr int kFusedMaxLevels = 48;
 constexpr int kFusedLds = 7168;     // doubles of LDS for two iterates of every fused level
+constexpr int kFusedLdsTotal = 20464;  // doubles of LDS of the fused cycle (160 KiB with red)
 
 struct FusedLevels {
   int count;                          // fused levels, the last is the coarsest
@@ -213,6 +214,11 @@ struct FusedLevels {
   int total;                          // sum of n over the fused levels
   int lds;                            // x store in LDS (else gx, global)
   double* gx;                         // global x store, 2 total doubles
+  // levels whose graph is copied into LDS at the start of the cycle (row
+  // pointers and neighbours as 16-bit, weights as binary64), with the byte
+  // offsets of those arrays past the x store
+  int gl[kFusedMaxLevels];
+  int gptr[kFusedMaxLevels], gnbr[kFusedMaxLevels], gw[kFusedMaxLevels];
 };
 
 // ---------------------------------------------------------------------- level kernels
@@ -633,12 +639,14 @@ __device__ __forceinline__ double block_sum_1024(double v, double* red) {
   return r;
 }
 
-// (b - L x)[p] for one node
-__device__ __forceinline__ double lap_resid(const int32_t* ptr, const int32_t* nbr,
-                                            const double* w, const double* diag, const double* b,
+// (b - L x)[p] for one node (graph indices 32-bit in global memory or
+// 16-bit in LDS)
+template <class I>
+__device__ __forceinline__ double lap_resid(const I* ptr, const I* nbr, const double* w,
+                                            const double* diag, const double* b,
                                             const double* x, int p) {
   double s = diag[p] * x[p];
-  for (int32_t e = ptr[p]; e < ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
+  for (int e = (int)ptr[p]; e < (int)ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
   return b[p] - s;
 }
 
@@ -651,21 +659,33 @@ __device__ __forceinline__ double lap_resid(const int32_t* ptr, const int32_t* n
 // Every dependent phase is separated by a workgroup barrier.
 __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
-  __shared__ double sh[kFusedLds];
+  __shared__ double sh[kFusedLdsTotal];
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int L = F->count;
   double* xs = F->lds ? sh : F->gx;
-  // Touch every array the cycle reads, all threads at once and coalesced,
-  // before the first dependent phase: the kernels of the finer levels have
-  // streamed them out of L2 since the previous cycle, and each phase below
-  // would otherwise wait on memory two or three times in a row.
+  unsigned char* gbase = reinterpret_cast<unsigned char*>(sh + (F->lds ? 2 * F->total : 0));
+  // Graphs of the levels marked gl: copied into LDS (all threads, coalesced
+  // reads).  The other levels' arrays are touched once, so that they are in
+  // L2 before the dependent phases below: the kernels of the finer levels
+  // have streamed them out since the previous cycle.
   {
     double acc = 0.0;
     for (int l = 0; l < L; ++l) {
       const int n = F->n[l], ne = F->ne[l];
-      for (int p = tid; p < ne; p += nt) acc += F->w[l][p] + (double)F->nbr[l][p];
-      for (int p = tid; p <= n; p += nt) acc += (double)F->ptr[l][p];
+      if (F->gl[l]) {
+        uint16_t* p16 = reinterpret_cast<uint16_t*>(gbase + F->gptr[l]);
+        uint16_t* n16 = reinterpret_cast<uint16_t*>(gbase + F->gnbr[l]);
+        double* w = reinterpret_cast<double*>(gbase + F->gw[l]);
+        for (int p = tid; p <= n; p += nt) p16[p] = (uint16_t)F->ptr[l][p];
+        for (int e = tid; e < ne; e += nt) {
+          n16[e] = (uint16_t)F->nbr[l][e];
+          w[e] = F->w[l][e];
+        }
+      } else {
+        for (int p = tid; p < ne; p += nt) acc += F->w[l][p] + (double)F->nbr[l][p];
+        for (int p = tid; p <= n; p += nt) acc += (double)F->ptr[l][p];
+      }
       for (int p = tid; p < n; p += nt) acc += F->diag[l][p] + F->sdinv[l][p];
       if (l + 1 < L) {
         for (int p = tid; p < n; p += nt) acc += (double)(F->agg[l][p] + F->mem[l][p]);
@@ -679,18 +699,27 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     // a store that never happens keeps the loads
     if (acc == -1.0) red[0] = acc;
   }
+  __syncthreads();
   // level l's current iterate is xs + off[l] + (par[l] ? total : 0)
   int par[kFusedMaxLevels];
   for (int l = 0; l < L; ++l) par[l] = 0;
   auto X = [&](int l) { return xs + F->off[l] + (par[l] ? F->total : 0); };
+  // (b - L x)[p] of level l, from the graph wherever it lives
+  auto resid = [&](int l, const double* x, int p) {
+    if (F->gl[l])
+      return lap_resid(reinterpret_cast<const uint16_t*>(gbase + F->gptr[l]),
+                       reinterpret_cast<const uint16_t*>(gbase + F->gnbr[l]),
+                       reinterpret_cast<const double*>(gbase + F->gw[l]), F->diag[l], F->b[l],
+                       x, p);
+    return lap_resid(F->ptr[l], F->nbr[l], F->w[l], F->diag[l], F->b[l], x, p);
+  };
   // one damped Jacobi sweep of level l into its other buffer
   auto sweep = [&](int l) {
     const int n = F->n[l];
-    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
-    const double *w = F->w[l], *dg = F->diag[l], *sd = F->sdinv[l], *b = F->b[l];
+    const double* sd = F->sdinv[l];
     const double* x = X(l);
     double* y = xs + F->off[l] + (par[l] ? 0 : F->total);
-    for (int p = tid; p < n; p += nt) y[p] = x[p] + sd[p] * lap_resid(ptr, nbr, w, dg, b, x, p);
+    for (int p = tid; p < n; p += nt) y[p] = x[p] + sd[p] * resid(l, x, p);
     par[l] ^= 1;
     __syncthreads();
   };
@@ -705,13 +734,11 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     __syncthreads();
     for (int k = 1; k < F->pre; ++k) sweep(l);
     const double* x = X(l);
-    const int32_t *ptr = F->ptr[l], *nbr = F->nbr[l];
-    const double *w = F->w[l], *dg = F->diag[l];
     const int nc = F->n[l + 1];
     for (int C = tid; C < nc; C += nt) {
       double acc = 0;
       for (int32_t m = F->mptr[l][C]; m < F->mptr[l][C + 1]; ++m)
-        acc += lap_resid(ptr, nbr, w, dg, b, x, F->mem[l][m]);
+        acc += resid(l, x, F->mem[l][m]);
       F->b[l + 1][C] = acc;
     }
     __syncthreads();
@@ -727,11 +754,11 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       for (int p = tid; p < n; p += nt) sb += b[p];
       const double bmean = block_sum_1024(sb, red) / n;
       // x = G (b - mean b): 16 lanes per row, rows strided over the groups
+      // (the 16 lanes of a group share i, so each shuffle stays in a group
+      // whose lanes are all active)
       constexpr int kRowLanes = 16;
       const int sub = tid % kRowLanes;
       double sx = 0;
-      // (the 16 lanes of a group share i, so each shuffle stays in a group
-      // whose lanes are all active)
       for (int i = tid / kRowLanes; i < n; i += nt / kRowLanes) {
         double acc = 0;
         for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * (b[j] - bmean);
@@ -960,6 +987,28 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   hf.total = (int)total;
   hf.lds = lds ? 1 : 0;
   hf.gx = lds ? nullptr : ws.get<double>((size_t)(2 * total));
+  // graphs in LDS, from the coarsest level up, while they fit past the
+  // iterates (16-bit indices need fewer than 65536 nodes and edges a level)
+  {
+    const int64_t avail = lds ? 8 * (int64_t)(kFusedLdsTotal - 2 * total) : 0;
+    int64_t used = 0;
+    for (int k = (int)(H.lv.size() - first) - 1; k >= 0; --k) {
+      const Level& Lk = H.lv[first + k];
+      const int64_t pb = ((2 * (Lk.n + 1) + 7) / 8) * 8;
+      const int64_t nbb = ((2 * Lk.ne + 7) / 8) * 8;
+      const int64_t need = pb + nbb + 8 * Lk.ne;
+      const bool fits = lds && Lk.n < 65535 && Lk.ne < 65535 && used + need <= avail;
+      hf.gl[k] = fits ? 1 : 0;
+      if (!fits) {
+        for (int j = k - 1; j >= 0; --j) hf.gl[j] = 0;
+        break;
+      }
+      hf.gptr[k] = (int)used;
+      hf.gnbr[k] = (int)(used + pb);
+      hf.gw[k] = (int)(used + pb + nbb);
+      used += need;
+    }
+  }
   for (int k = 0, o = 0; k < hf.count; ++k) {
     Level& Lk = H.lv[first + k];
     hf.off[k] = o;
