@@ -417,6 +417,12 @@ __device__ __forceinline__ T lens(T r1, T r2, T d) {
 // ---------------------------------------------------------------- assembly
 
 constexpr int kCap = 1024;   // candidate shares per tracked cell held in LDS
+constexpr int kXcds = 8;     // accelerator complex dies of the MI355X
+
+// one workgroup per cell, padded to a multiple of the XCD count
+static inline int64_t xcd_grid(int64_t n_cells) {
+  return ((n_cells + kXcds - 1) / kXcds) * kXcds;
+}
 
 struct AsmParams {
   int64_t n_cells, n_balls;
@@ -487,7 +493,12 @@ __global__ void __launch_bounds__(64) k_assemble(AsmParams P) {
   __shared__ double s_val[kCap];
   __shared__ int32_t s_first[kCap];
   __shared__ int32_t s_pb[FILL ? kCap : 1];
-  const int64_t K = blockIdx.x;
+  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, each
+  // with its own L2; give XCD j the j-th contiguous chunk of cells so that
+  // neighbouring cells, which read the same hash buckets, share an L2
+  const int64_t chunk = (P.n_cells + kXcds - 1) / kXcds;
+  const int64_t K = (int64_t)(blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
+  if (K >= P.n_cells) return;
   const int lane = threadIdx.x;
   const int nbpc = P.nbpc;
   const int spb = kWave / nbpc;         // lanes per tracked ball
@@ -663,12 +674,12 @@ static void launch_assemble(AsmParams& P, bool fill, hipStream_t s) {
   if (fill)
     {
       ::bchar::ProfScope ps_("k_assemble", s);
-      k_assemble<DIM, T, true><<<(unsigned)P.n_cells, 64, 0, s>>>(P);
+      k_assemble<DIM, T, true><<<(unsigned)xcd_grid(P.n_cells), 64, 0, s>>>(P);
     }
   else
     {
       ::bchar::ProfScope ps_("k_assemble", s);
-      k_assemble<DIM, T, false><<<(unsigned)P.n_cells, 64, 0, s>>>(P);
+      k_assemble<DIM, T, false><<<(unsigned)xcd_grid(P.n_cells), 64, 0, s>>>(P);
     }
   BCHAR_HIP(hipGetLastError());
 }
