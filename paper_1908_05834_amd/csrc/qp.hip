@@ -51,9 +51,12 @@ constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
 constexpr int kIpmMaxIter = 100;   // interior-point iterations per box level
 constexpr double kIpmMuTight = 1e-13;  // complementarity of an accepted interior point
 constexpr double kIpmWarmShift = 1e-3; // distance from the box of a warm interior point
-constexpr int kWarmNewton = 8;     // semismooth steps tried from a warm start
+constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relative to
+constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
+constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
-constexpr int kPolishCG = 60;      // CG cap of those steps once the interior point met tol
+constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those after an
+                                   // interior point that met tol
 
 // ====================================================================== reductions
 
@@ -2158,7 +2161,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   I.dzu = ws.get<double>(nnz + 1);
   double* rp = ws.get<double>(n2);
   double fp_ipm = HUGE_VAL;
-  auto ipm = [&](double lo, double hi, bool warm) -> int {
+  auto ipm = [&](double lo, double hi, bool warm, double cg_rel) -> int {
     I.lo = lo;
     I.hi = hi;
     I.has_hi = std::isinf(hi) ? 0 : 1;
@@ -2233,7 +2236,11 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_ipm_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, I.D, nnz, L0.w);
       }
       refresh();
-      const double cg_tol = std::max(1e-2 * std::min(fv, mu), 1e-15);
+      // inexact directions: the CG residual of the normal equations is kept
+      // below cg_rel times both the right-hand side and the complementarity
+      // mu, the scale at which the iterate itself is still inexact (the step
+      // is re-measured at the next iterate, and the exit test above is exact)
+      const double cg_tol = std::max(cg_rel * std::min(fv, mu), 1e-15);
       // predictor (affine scaling).  Once the normal equations are too
       // ill-conditioned for CG to reach its tolerance the step would spoil
       // the iterate: hand it over as it is.
@@ -2294,8 +2301,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // the equalities alone.  A level with a bound is solved by the interior
   // point followed by semismooth Newton (kPolishNewton steps at most), or,
   // when the previous solve of this transfer ended at the same level, by
-  // semismooth Newton from its multipliers first (kWarmNewton steps at
-  // most).  The answer is clip(t) when semismooth Newton reaches the
+  // semismooth Newton from its multipliers first (kWarmNewton steps of at
+  // most kPolishCG CG iterations each).  The answer is clip(t) when semismooth Newton reaches the
   // tolerance, else the interior point's x if it reached it.  An interior
   // point that fails declares the level infeasible.
   const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
@@ -2311,7 +2318,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
       }
       BCHAR_HIP(hipGetLastError());
-      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2, o.qp_max_cg, " (warm)");
+      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2,
+                      std::min(kPolishCG, o.qp_max_cg), " (warm)");
       if (converged) break;
     }
     const bool warm = o.warm_start && warm_level == level;
@@ -2320,9 +2328,11 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       fill_f64(zdual, 0.0, n2, s);
       converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, "");
     } else {
-      // a warm interior point that fails is retried from zero
-      int r = warm ? ipm(lo, hi, true) : 0;
-      if (r == 0) r = ipm(lo, hi, false);
+      // a warm or loose interior point that fails is retried from zero,
+      // then with near-exact directions
+      int r = warm ? ipm(lo, hi, true, kIpmCgLoose) : 0;
+      if (r == 0) r = ipm(lo, hi, false, kIpmCgLoose);
+      if (r == 0) r = ipm(lo, hi, false, kIpmCgTight);
       if (r > 0) {
         // an interior point at the tolerance is an answer already: one
         // short semismooth step is enough to give up on the exact one
