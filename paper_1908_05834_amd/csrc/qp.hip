@@ -649,8 +649,32 @@ __device__ __forceinline__ double lap_resid(const I* ptr, const I* nbr, const do
                                             const double* diag, const double* b,
                                             const double* x, int p) {
   double s = diag[p] * x[p];
-  for (int e = (int)ptr[p]; e < (int)ptr[p + 1]; ++e) s -= w[e] * x[nbr[e]];
+  int e = (int)ptr[p];
+  const int end = (int)ptr[p + 1];
+  // four edges a round, their loads issued together (same summation order)
+  for (; e + 4 <= end; e += 4) {
+    const int q0 = (int)nbr[e], q1 = (int)nbr[e + 1], q2 = (int)nbr[e + 2], q3 = (int)nbr[e + 3];
+    const double w0 = w[e], w1 = w[e + 1], w2 = w[e + 2], w3 = w[e + 3];
+    const double x0 = x[q0], x1 = x[q1], x2 = x[q2], x3 = x[q3];
+    s -= w0 * x0;
+    s -= w1 * x1;
+    s -= w2 * x2;
+    s -= w3 * x3;
+  }
+  for (; e < end; ++e) s -= w[e] * x[nbr[e]];
   return b[p] - s;
+}
+
+// Sum of a[tid], a[tid + nt], ... (a touch that brings the array into the
+// caches), four loads a round.
+template <class T>
+__device__ __forceinline__ double touch_sum(const T* a, int n, int tid, int nt) {
+  double acc = 0;
+  int p = tid;
+  for (; p + 3 * nt < n; p += 4 * nt)
+    acc += (double)a[p] + (double)a[p + nt] + (double)a[p + 2 * nt] + (double)a[p + 3 * nt];
+  for (; p < n; p += nt) acc += (double)a[p];
+  return acc;
 }
 
 // The V-cycle below and including the first fused level, in one workgroup.
@@ -680,25 +704,38 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
         uint16_t* p16 = reinterpret_cast<uint16_t*>(gbase + F->gptr[l]);
         uint16_t* n16 = reinterpret_cast<uint16_t*>(gbase + F->gnbr[l]);
         double* w = reinterpret_cast<double*>(gbase + F->gw[l]);
-        for (int p = tid; p <= n; p += nt) p16[p] = (uint16_t)F->ptr[l][p];
-        for (int e = tid; e < ne; e += nt) {
-          n16[e] = (uint16_t)F->nbr[l][e];
-          w[e] = F->w[l][e];
+        const int32_t *gp = F->ptr[l], *gn = F->nbr[l];
+        const double* gw = F->w[l];
+        for (int p = tid; p <= n; p += nt) p16[p] = (uint16_t)gp[p];
+        // four elements a round, loads first
+        int e = tid;
+        for (; e + 3 * nt < ne; e += 4 * nt) {
+          const int32_t a0 = gn[e], a1 = gn[e + nt], a2 = gn[e + 2 * nt], a3 = gn[e + 3 * nt];
+          const double v0 = gw[e], v1 = gw[e + nt], v2 = gw[e + 2 * nt], v3 = gw[e + 3 * nt];
+          n16[e] = (uint16_t)a0;
+          n16[e + nt] = (uint16_t)a1;
+          n16[e + 2 * nt] = (uint16_t)a2;
+          n16[e + 3 * nt] = (uint16_t)a3;
+          w[e] = v0;
+          w[e + nt] = v1;
+          w[e + 2 * nt] = v2;
+          w[e + 3 * nt] = v3;
+        }
+        for (; e < ne; e += nt) {
+          n16[e] = (uint16_t)gn[e];
+          w[e] = gw[e];
         }
       } else {
-        for (int p = tid; p < ne; p += nt) acc += F->w[l][p] + (double)F->nbr[l][p];
-        for (int p = tid; p <= n; p += nt) acc += (double)F->ptr[l][p];
+        acc += touch_sum(F->w[l], ne, tid, nt) + touch_sum(F->nbr[l], ne, tid, nt);
+        acc += touch_sum(F->ptr[l], n + 1, tid, nt);
       }
-      for (int p = tid; p < n; p += nt) acc += F->diag[l][p] + F->sdinv[l][p];
+      acc += touch_sum(F->diag[l], n, tid, nt) + touch_sum(F->sdinv[l], n, tid, nt);
       if (l + 1 < L) {
-        for (int p = tid; p < n; p += nt) acc += (double)(F->agg[l][p] + F->mem[l][p]);
-        for (int p = tid; p <= F->n[l + 1]; p += nt) acc += (double)F->mptr[l][p];
+        acc += touch_sum(F->agg[l], n, tid, nt) + touch_sum(F->mem[l], n, tid, nt);
+        acc += touch_sum(F->mptr[l], F->n[l + 1] + 1, tid, nt);
       }
     }
-    if (F->dense) {
-      const int nn = F->n[L - 1] * F->n[L - 1];
-      for (int p = tid; p < nn; p += nt) acc += F->G[p];
-    }
+    if (F->dense) acc += touch_sum(F->G, F->n[L - 1] * F->n[L - 1], tid, nt);
     // a store that never happens keeps the loads
     if (acc == -1.0) red[0] = acc;
   }
@@ -726,23 +763,43 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     par[l] ^= 1;
     __syncthreads();
   };
-  // downward: pre-smoothing and restriction of the residual
+  // downward: pre-smoothing (the first sweep from zero is x = sdinv b) and
+  // restriction of the residual.  The residual of every node is formed in
+  // parallel into the level's spare buffer, then summed per aggregate (in
+  // member order) by the coarse node's thread, which also starts the next
+  // level's smoothing.
+  {
+    const double *sd = F->sdinv[0], *b = F->b[0];
+    double* x = X(0);
+    for (int p = tid; p < F->n[0]; p += nt) x[p] = sd[p] * b[p];
+  }
+  __syncthreads();
   for (int l = 0; l + 1 < L; ++l) {
     const int n = F->n[l];
-    const double *sd = F->sdinv[l], *b = F->b[l];
-    {
-      double* x = X(l);
-      for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
-    }
-    __syncthreads();
     for (int k = 1; k < F->pre; ++k) sweep(l);
     const double* x = X(l);
+    double* r = xs + F->off[l] + (par[l] ? 0 : F->total);
+    for (int p = tid; p < n; p += nt) r[p] = resid(l, x, p);
+    __syncthreads();
     const int nc = F->n[l + 1];
+    const int32_t *mptr = F->mptr[l], *mem = F->mem[l];
+    const double* sdc = F->sdinv[l + 1];
+    double* bc = F->b[l + 1];
+    double* xc = X(l + 1);
     for (int C = tid; C < nc; C += nt) {
       double acc = 0;
-      for (int32_t m = F->mptr[l][C]; m < F->mptr[l][C + 1]; ++m)
-        acc += resid(l, x, F->mem[l][m]);
-      F->b[l + 1][C] = acc;
+      int m = mptr[C];
+      const int me = mptr[C + 1];
+      for (; m + 4 <= me; m += 4) {
+        const int p0 = mem[m], p1 = mem[m + 1], p2 = mem[m + 2], p3 = mem[m + 3];
+        acc += r[p0];
+        acc += r[p1];
+        acc += r[p2];
+        acc += r[p3];
+      }
+      for (; m < me; ++m) acc += r[mem[m]];
+      bc[C] = acc;
+      xc[C] = sdc[C] * acc;
     }
     __syncthreads();
   }
@@ -775,9 +832,7 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       for (int i = tid; i < n; i += nt) x[i] -= xmean;
       __syncthreads();
     } else {
-      const double* sd = F->sdinv[l];
-      for (int p = tid; p < n; p += nt) x[p] = sd[p] * b[p];
-      __syncthreads();
+      // x = sdinv b was set with the restriction
       for (int k = 1; k < F->coarse_sweeps; ++k) sweep(l);
     }
   }
