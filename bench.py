@@ -8,11 +8,18 @@ whole hot path: tracking, overlap search, lens volumes, V, the N = 10
 scaling sweeps, the bounded least-change problem, the update of c, and the
 porous mass (checked against the initial mass at every step).
 
+The velocity of every interval is prescribed (it does not depend on c), so
+the transfers of successive intervals are independent: the run first
+builds them one after another (per-step latency, reported under
+"sequential"), then ``--inflight`` of them at once, each on its own stream
+and host worker (bchar_build_transfer_batch), applying them in order.
+
 Prints one JSON line.  ``value`` counts cell updates per second over the
-timed steps; a run whose relative mass error exceeds 1e-12 at any step is
-reported with ``"mass_ok": false``.
+timed steps of the second run; a run whose relative mass error exceeds
+1e-12 at any step is reported with ``"mass_ok": false``.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 64] [--precision fp64|fp32]
+                    [--inflight D]
 """
 
 from __future__ import annotations
@@ -134,9 +141,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="transfers built at once on separate streams (1: one after another)")
     ap.add_argument("--roofline-kernel", default="k_fused_cycle")
     ap.add_argument("--build-kernel", default="k_assemble")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -151,6 +160,12 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    D = max(1, args.inflight)
+    if D > 1:
+        # one hardware queue per build stream, plus the default stream (set
+        # before the HIP runtime starts)
+        q = max(int(os.environ.get("GPU_MAX_HW_QUEUES", "4")), D + 2)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(q, 32))
 
     import numpy as np
     import torch
@@ -160,62 +175,118 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
 
     w = inputs.swirl_hex(args.n)
-    total = args.warmup + args.steps
     prec = bchar.FP64 if args.precision == "fp64" else bchar.FP32_VOLUME
     opts = bchar.opts_default(precision=prec)
     M = bchar.Mesh(w["mesh"], "subcell")
-    # every step's velocity lattice resident on the device before timing
-    vels = [bchar.VelocityLattice(w["vel_fn"](s % w["steps"])) for s in range(total)]
-    c = torch.as_tensor(w["c0"], device=dev)
-    nxt = torch.empty_like(c)
-    m0 = M.mass(c)
-    tw = time.perf_counter()
-    T = bchar.Transfer.build(M, vels[0], w["dt"], opts)
-    T.step(c, nxt)
-    c, nxt = nxt, c
-    torch.cuda.synchronize()
-    log(f"warmup step 0: {time.perf_counter() - tw:.3f} s, {T.stats}")
-    for s in range(1, args.warmup):
-        tw = time.perf_counter()
-        T.rebuild(vels[s], w["dt"], opts)
-        T.step(c, nxt)
-        c, nxt = nxt, c
-        torch.cuda.synchronize()
-        log(f"warmup step {s}: {time.perf_counter() - tw:.3f} s")
-
-    bchar.profile_kernel(args.roofline_kernel)
+    # phase 1: one build after another (per-step latency); phase 2: D builds
+    # at once (throughput, the reported value).  Every interval's velocity
+    # lattice is resident on the device before timing.
+    # Both runs time the same intervals (warmup .. warmup + steps - 1) when
+    # the warm-up spans whole batches.
+    seq_total = args.warmup + args.steps
+    warm_batches = max(1, math.ceil(args.warmup / D))
+    timed_batches = max(1, math.ceil(args.steps / D))
+    steps_timed = timed_batches * D if D > 1 else args.steps
+    pipe_first = max(0, args.warmup - warm_batches * D)
+    pipe_total = pipe_first + (warm_batches + timed_batches) * D if D > 1 else 0
+    vels = [bchar.VelocityLattice(w["vel_fn"](s % w["steps"]))
+            for s in range(max(seq_total, pipe_total))]
+    c0 = torch.as_tensor(w["c0"], device=dev)
+    m0 = M.mass(c0)
     mass_err = 0.0
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.warmup, total):
-        st = T.rebuild(vels[s], w["dt"], opts)
+
+    def apply(T, c, nxt):
+        nonlocal mass_err
         T.step(c, nxt)
-        c, nxt = nxt, c
-        m = M.mass(c)
-        mass_err = max(mass_err, abs(m - m0) / abs(m0))
-        stats.append(st)
-        log(f"step {s}: t = {time.perf_counter() - t0:.3f} s, newton {st['qp_newton']}, "
-            f"cg {st['qp_cg']}, level {st['qp_level']}, mass err {abs(m - m0) / abs(m0):.2e}")
+        m = M.mass(nxt)
+        e = abs(m - m0) / abs(m0)
+        mass_err = max(mass_err, e)
+        return nxt, c, e
+
+    # ---- phase 1: sequential
+    c, nxt = c0.clone(), torch.empty_like(c0)
+    T = None
+    lat = []
+    seq_stats = []
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches, kms = bchar.profile_read()
-    bchar.profile_kernel(None)
-    # the build kernel, timed the same way over one more (untimed) step
+    ts0 = time.perf_counter()
+    for s in range(seq_total):
+        tw = time.perf_counter()
+        if T is None:
+            T = bchar.Transfer.build(M, vels[s], w["dt"], opts)
+        else:
+            T.rebuild(vels[s], w["dt"], opts)
+        c, nxt, e = apply(T, c, nxt)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - tw
+        if s == args.warmup - 1 or (args.warmup == 0 and s == 0):
+            ts0 = time.perf_counter()
+        if s >= args.warmup:
+            lat.append(dt_s)
+            seq_stats.append(T.stats)
+        log(f"sequential step {s}: {dt_s:.3f} s, ipm {T.stats['qp_ipm']}, cg {T.stats['qp_cg']}, "
+            f"mass err {e:.2e}")
+    seq_elapsed = time.perf_counter() - ts0
+
+    # ---- phase 2: D transfers built at once (D = 1: the sequential run)
+    if D > 1:
+        streams = [torch.cuda.Stream() for _ in range(D)]
+        c, nxt = c0.clone(), torch.empty_like(c0)
+        Ts = [None] * D
+        last = None
+        stats = []
+        k = pipe_first
+
+        def batch(timed):
+            nonlocal Ts, last, k, c, nxt
+            jobs = [(Ts[j], M, vels[k + j], w["dt"], last) for j in range(D)]
+            Ts = bchar.build_batch(jobs, opts, streams)
+            for j in range(D):
+                c, nxt, e = apply(Ts[j], c, nxt)
+                if timed:
+                    stats.append(Ts[j].stats)
+            last = Ts[D - 1]
+            k += D
+
+        for _ in range(warm_batches):
+            batch(False)
+        torch.cuda.synchronize()
+        bchar.profile_kernel(args.roofline_kernel)
+        t0 = time.perf_counter()
+        for b in range(timed_batches):
+            batch(True)
+            log(f"batch {b}: t = {time.perf_counter() - t0:.3f} s, cg "
+                f"{[s_['qp_cg'] for s_ in stats[-D:]]}, mass err {mass_err:.2e}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        launches, kms = bchar.profile_read()
+        bchar.profile_kernel(None)
+        T_last = Ts[0]
+    else:
+        # the sequential run is the timed one; time the roofline kernel over
+        # one more pass of the same steps
+        stats = seq_stats
+        elapsed = seq_elapsed
+        bchar.profile_kernel(args.roofline_kernel)
+        for s in range(args.warmup, seq_total):
+            T.rebuild(vels[s], w["dt"], opts)
+        torch.cuda.synchronize()
+        launches, kms = bchar.profile_read()
+        bchar.profile_kernel(None)
+        T_last = T
+    # the build kernel, timed the same way over one more (untimed) build
     bchar.profile_kernel(args.build_kernel)
-    T.rebuild(vels[total - 1], w["dt"], opts)
+    T_last.rebuild(vels[0], w["dt"], opts)
     torch.cuda.synchronize()
     b_launches, b_kms = bchar.profile_read()
     bchar.profile_kernel(None)
 
-    elapsed = t1 - t0
     n_cells = M.n_cells
-    value = n_cells * args.steps / elapsed
+    value = n_cells * steps_timed / elapsed
     nnz = stats[-1]["nnz"]
-    roof = None
+
     def roofline(kernel, n_launch, total_ms, st):
         if n_launch <= 0:
             return None
@@ -228,17 +299,17 @@ def main():
                 "launches": n_launch, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes_per_launch": alg}
 
-    if launches > 0:
-        roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
-    roof_build = roofline(args.build_kernel, b_launches, b_kms, T.stats)
+    roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
+    roof_build = roofline(args.build_kernel, b_launches, b_kms, T_last.stats)
+    lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps_timed,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / steps_timed * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -247,11 +318,16 @@ def main():
         "config": {"workload": f"3D swirl, unit cube, {args.n}^3 hexahedra, 8 balls per cell, "
                                f"phi = 1, dt = 1/128, transfer rebuilt every step",
                    "n_cells": n_cells, "precision": args.precision, "nnz": nnz,
-                   "qp_newton_mean": float(np.mean([s_["qp_newton"] for s_ in stats])),
+                   "inflight_builds": D,
+                   "qp_ipm_mean": float(np.mean([s_["qp_ipm"] for s_ in stats])),
                    "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in stats])),
                    "qp_levels": sorted({s_["qp_level"] for s_ in stats})},
         "mass_ok": bool(mass_err <= 1e-12),
         "max_rel_mass_err": mass_err,
+        "sequential": {"value": n_cells * args.steps / seq_elapsed,
+                       "step_latency_ms_p50": float(np.percentile(lat_ms, 50)),
+                       "step_latency_ms_p99": float(np.percentile(lat_ms, 99)),
+                       "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in seq_stats]))},
         "roofline": roof,
         "roofline_build": roof_build,
         "cpu_baseline": None,

@@ -216,6 +216,45 @@ bchar_status bchar_build_transfer_tracked(bchar_mesh mesh, const double* tracked
 
 bchar_status bchar_transfer_destroy(bchar_transfer t);
 
+/* One job of bchar_build_transfer_batch: the transfer of one time step of
+ * one problem.                                                          */
+typedef struct {
+  bchar_transfer transfer;     /* in: a transfer to rebuild (its mesh is
+                                  used), or NULL to create one on `mesh`;
+                                  out: the transfer (NULL if a creation
+                                  failed)                                */
+  bchar_mesh mesh;             /* used when transfer is NULL              */
+  const bchar_velocity* u;     /* as for bchar_build_transfer             */
+  double dt;
+  bchar_transfer warm_from;    /* optional, rebuilds only: a transfer of
+                                  the same mesh whose last solve (ended
+                                  before the call) gives the warm start
+                                  instead of the job's own, e.g. the
+                                  latest interval already built; taken
+                                  before any job of the batch runs        */
+  bchar_status status;         /* out: the job's own status              */
+  bchar_stats stats;           /* out                                    */
+} bchar_build_job;
+
+/* Build the transfers of n_jobs independent jobs at once (Algorithm 1 for
+ * each, exactly as bchar_build_transfer / bchar_rebuild_transfer would):
+ * worker w < n_streams runs jobs w, w + n_streams, ... in that order on
+ * streams[w], from a host thread of its own, so that the latency-bound
+ * launches of several builds overlap on the device.  Jobs are
+ * independent problems, or time intervals of one problem whose velocity
+ * is prescribed ahead (the transfer of an interval depends on its
+ * velocity, not on the concentration).  Jobs may share a mesh (read only
+ * during builds); a transfer may appear in at most one job.  A rebuilt
+ * transfer warm-starts from its own previous solve.  Returns once every
+ * job has ended and every stream is synchronised: BCHAR_OK if all jobs
+ * succeeded, else the status of the first failed job (its message is the
+ * one bchar_last_error returns); every job's status is in its job.
+ * Errors: INVALID_ARG (NULL arrays, n_streams < 1, a transfer in two
+ * jobs), then the errors of bchar_build_transfer per job.              */
+bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
+                                        const bchar_opts* opts, void* const* streams,
+                                        int n_streams);
+
 /* One update (Sec. 2, eq. phys-inter-ELLAM): c_out = diag(|K|_phi)^-1 A c_in.
  * c_in, c_out: device, n_cells binary64 each, must not overlap.  Needs a
  * transfer built to BCHAR_STAGE_ALL.  Asynchronous on `stream`.         */

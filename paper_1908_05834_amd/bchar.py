@@ -103,6 +103,16 @@ _export_tracked = _sig("bchar_transfer_export_tracked", [_P, _P, _P])
 _export_qp = _sig("bchar_transfer_export_qp", [_P, _P, _P, _P])
 _export_balls = _sig("bchar_mesh_export_balls", [_P, _P, _P, _P])
 _profile_kernel = _sig("bchar_profile_kernel", [C.c_char_p])
+
+
+class BuildJob(C.Structure):
+    _fields_ = [("transfer", C.c_void_p), ("mesh", C.c_void_p), ("u", C.POINTER(Velocity)),
+                ("dt", C.c_double), ("warm_from", C.c_void_p), ("status", C.c_int),
+                ("stats", Stats)]
+
+
+_build_batch = _sig("bchar_build_transfer_batch", [C.POINTER(BuildJob), C.c_int, C.POINTER(Opts),
+                                                   C.POINTER(C.c_void_p), C.c_int])
 _profile_read = _sig("bchar_profile_read", [_i64p, C.POINTER(C.c_double)])
 
 EXPORTED = [
@@ -112,6 +122,7 @@ EXPORTED = [
     "bchar_last_error", "bchar_transfer_info", "bchar_transfer_export_csr",
     "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
     "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
+    "bchar_build_transfer_batch",
 ]
 
 
@@ -340,3 +351,47 @@ class Transfer:
         _check(_export_qp(self.handle, x.ctypes.data_as(_P), mu.ctypes.data_as(_P),
                           nu.ctypes.data_as(_P)))
         return x, mu, nu
+
+
+def _handle_value(h):
+    return h.value if isinstance(h, C.c_void_p) else h
+
+
+def build_batch(jobs, opts=None, streams=None):
+    """Build transfers of independent jobs at once (bchar_build_transfer_batch).
+
+    ``jobs``: a list of ``(transfer, mesh, velocity, dt)`` or ``(transfer,
+    mesh, velocity, dt, warm_from)``; ``transfer`` is a Transfer to rebuild,
+    or None to create one on ``mesh``; ``warm_from`` an optional Transfer of
+    the same mesh whose last solve warm-starts the job.  ``streams``:
+    torch streams (or raw handles), one host worker each.  Returns the list
+    of Transfer objects (the given ones, rebuilt, or new ones) after every
+    job ended; raises BcharError (first failed job) if any failed, once the
+    transfers that were created have been kept in their Transfer objects.
+    """
+    import torch
+    if streams is None:
+        streams = [torch.cuda.current_stream()]
+    o = opts if opts is not None else opts_default()
+    arr = (BuildJob * len(jobs))()
+    for i, job in enumerate(jobs):
+        tr, mesh, vel, dt = job[:4]
+        wf = job[4] if len(job) > 4 else None
+        arr[i].transfer = _handle_value(tr.handle) if tr is not None else None
+        arr[i].mesh = _handle_value(mesh.handle) if mesh is not None else None
+        arr[i].u = C.pointer(vel.struct)
+        arr[i].dt = float(dt)
+        arr[i].warm_from = _handle_value(wf.handle) if wf is not None else None
+    sp = (C.c_void_p * len(streams))(*[_stream_ptr(s).value for s in streams])
+    rc = _build_batch(arr, len(jobs), C.byref(o), sp, len(streams))
+    out = []
+    for i, job in enumerate(jobs):
+        tr, mesh = job[0], job[1]
+        st = arr[i].stats.as_dict()
+        if tr is None:
+            tr = Transfer(C.c_void_p(arr[i].transfer), mesh, st) if arr[i].transfer else None
+        else:
+            tr.stats = st
+        out.append(tr)
+    _check(rc)
+    return out

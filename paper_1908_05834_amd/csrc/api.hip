@@ -4,6 +4,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <set>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -245,7 +248,7 @@ void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
 bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_opts& o,
                                 hipStream_t s, bchar_stats* stats) {
   using namespace bchar;
-  Arena& ws = m->ws;
+  Arena& ws = t->ws;
   const bool tr = trace_enabled();
   double t0 = 0;
   if (tr) {
@@ -353,12 +356,12 @@ bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity
   validate_opts(o);
   validate_velocity(m, u);
   BCHAR_REQUIRE(dt > 0 && std::isfinite(dt), BCHAR_E_INVALID_ARG, "dt must be finite and > 0");
-  m->ws.reset();
+  t->ws.reset();
   t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
   t->r_hat.reserve(sizeof(double) * m->n_balls);
   const double t0 = trace_enabled() ? wall_seconds() : 0.0;
   trace_balls(m, *u, dt, o.rk_substeps, o.precision, t->tracked.as<double>(),
-              t->r_hat.as<double>(), m->ws, s);
+              t->r_hat.as<double>(), t->ws, s);
   if (trace_enabled()) {
     BCHAR_HIP(hipStreamSynchronize(s));
     fprintf(stderr, "[bchar] trace: %.3f ms\n", 1e3 * (wall_seconds() - t0));
@@ -578,6 +581,7 @@ static void transfer_free(bchar_transfer t) {
   t->r_hat.release();
   t->pair_a.release();
   t->pair_b.release();
+  t->ws.release();
 }
 
 bchar_status bchar_build_transfer(bchar_mesh m, const bchar_velocity* u, double dt,
@@ -634,7 +638,7 @@ bchar_status bchar_build_transfer_tracked(bchar_mesh m, const double* tracked,
     t->mesh = m;
     bchar_status rc;
     try {
-      m->ws.reset();
+      t->ws.reset();
       t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
       t->r_hat.reserve(sizeof(double) * m->n_balls);
       BCHAR_HIP(hipMemcpyAsync(t->tracked.p, tracked, sizeof(double) * m->dim * m->n_balls,
@@ -653,6 +657,76 @@ bchar_status bchar_build_transfer_tracked(bchar_mesh m, const double* tracked,
       return rc;
     }
     *out = t;
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
+                                        const bchar_opts* opts, void* const* streams,
+                                        int n_streams) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(n_jobs >= 0 && (n_jobs == 0 || jobs != nullptr) && n_streams >= 1 &&
+                      streams != nullptr,
+                  BCHAR_E_INVALID_ARG, "NULL argument or n_streams < 1");
+    std::set<bchar_transfer> seen;
+    for (int i = 0; i < n_jobs; ++i) {
+      BCHAR_REQUIRE(jobs[i].transfer != nullptr || jobs[i].mesh != nullptr,
+                    BCHAR_E_INVALID_ARG, "job without transfer and mesh");
+      if (jobs[i].transfer)
+        BCHAR_REQUIRE(seen.insert(jobs[i].transfer).second, BCHAR_E_INVALID_ARG,
+                      "a transfer appears in two jobs");
+    }
+    // warm starts from other transfers, taken before any job runs (the
+    // source may itself be rebuilt by a job of this batch)
+    {
+      hipStream_t s0 = as_stream(streams[0]);
+      bool copied = false;
+      for (int i = 0; i < n_jobs; ++i) {
+        bchar_transfer_s* dst = jobs[i].transfer;
+        const bchar_transfer_s* src = jobs[i].warm_from;
+        if (!src || !dst || src == dst) continue;
+        BCHAR_REQUIRE(src->mesh == dst->mesh, BCHAR_E_INVALID_ARG,
+                      "warm_from is a transfer of another mesh");
+        const size_t bytes = sizeof(double) * 2 * dst->mesh->n_cells;
+        if (src->warm_level < 0 || src->zdual.bytes < bytes) continue;
+        if (dst->zdual.bytes < bytes) dst->zdual.reserve(bytes);
+        BCHAR_HIP(hipMemcpyAsync(dst->zdual.p, src->zdual.p, bytes, hipMemcpyDeviceToDevice, s0));
+        dst->warm_level = src->warm_level;
+        copied = true;
+      }
+      if (copied) BCHAR_HIP(hipStreamSynchronize(s0));
+    }
+    int dev = 0;
+    BCHAR_HIP(hipGetDevice(&dev));
+    std::vector<std::string> msg(n_jobs);
+    const int workers = std::min(n_streams, std::max(n_jobs, 1));
+    std::vector<hipError_t> sync_err(workers, hipSuccess);
+    auto run = [&](int w) {
+      sync_err[w] = hipSetDevice(dev);
+      if (sync_err[w] != hipSuccess) {
+        for (int i = w; i < n_jobs; i += workers) jobs[i].status = BCHAR_E_DEVICE;
+        return;
+      }
+      for (int i = w; i < n_jobs; i += workers) {
+        bchar_build_job& J = jobs[i];
+        J.status = J.transfer ? bchar_rebuild_transfer(J.transfer, J.u, J.dt, opts, streams[w],
+                                                       &J.stats)
+                              : bchar_build_transfer(J.mesh, J.u, J.dt, opts, streams[w],
+                                                     &J.transfer, &J.stats);
+        if (J.status != BCHAR_OK) msg[i] = bchar_last_error();
+      }
+      sync_err[w] = hipStreamSynchronize(as_stream(streams[w]));
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < workers; ++w) pool.emplace_back(run, w);
+    run(0);
+    for (auto& th : pool) th.join();
+    for (int w = 0; w < workers; ++w) BCHAR_HIP(sync_err[w]);
+    for (int i = 0; i < n_jobs; ++i)
+      if (jobs[i].status != BCHAR_OK) {
+        bchar::set_error("job " + std::to_string(i) + ": " + msg[i]);
+        return jobs[i].status;
+      }
     return BCHAR_OK;
   });
 }

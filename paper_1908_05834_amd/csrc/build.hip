@@ -701,7 +701,7 @@ static void dispatch_assemble(int dim, int precision, AsmParams& P, bool fill, h
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
                         int precision, bool keep_pairs, bchar_transfer_s* t,
                         int64_t* first_void, hipStream_t s) {
-  Arena& ws = m->ws;
+  Arena& ws = t->ws;
   const int64_t nc = m->n_cells;
   BCHAR_REQUIRE(kWave % m->nbpc == 0, BCHAR_E_UNSUPPORTED, "balls per cell must divide 64");
   AsmParams P{};

@@ -106,7 +106,7 @@ struct bchar_mesh_s {
   bchar::DBuf bk_cen32;        // fp32 dim * n_balls, bucket order
   bchar::DBuf bk_ball;         // int32 n_balls: ball id of each bucket slot
   bchar::DBuf bk_rad;          // fp64 n_balls, radius, bucket order
-  // scratch reused by builds
+  // scratch of the mesh creation and of bchar_mass
   bchar::Arena ws;
   bchar::DBuf scratch_small;   // small device scalars
 };
@@ -128,6 +128,9 @@ struct bchar_transfer_s {
   bchar::DBuf r_hat;     // fp64 n_balls
   bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs)
   bchar_stats stats{};
+  // scratch of this transfer's builds (its own, so that builds of several
+  // transfers of one mesh may run at once on different streams)
+  bchar::Arena ws;
 };
 
 namespace bchar {

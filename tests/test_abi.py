@@ -38,3 +38,20 @@ def test_status_strings_and_defaults_without_device():
     assert bchar.status_string(bchar.E_VOID_ROW) == "void row"
     o = bchar.opts_default()
     assert o.n_sweeps == 10 and o.qp_tol == 1e-13 and o.precision == bchar.FP64
+
+
+def test_batch_build_rejects_bad_arguments_without_device():
+    import ctypes as C
+
+    from paper_1908_05834_amd import bchar
+    o = bchar.opts_default()
+    streams = (C.c_void_p * 1)(None)
+    jobs = (bchar.BuildJob * 2)()
+    # NULL job array, no streams, a job with neither transfer nor mesh, one
+    # transfer in two jobs: all refused before any device work
+    assert bchar._build_batch(None, 1, C.byref(o), streams, 1) == bchar.E_INVALID_ARG
+    assert bchar._build_batch(jobs, 1, C.byref(o), streams, 0) == bchar.E_INVALID_ARG
+    assert bchar._build_batch(jobs, 1, C.byref(o), streams, 1) == bchar.E_INVALID_ARG
+    jobs[0].transfer = jobs[1].transfer = 0x1000
+    assert bchar._build_batch(jobs, 2, C.byref(o), streams, 1) == bchar.E_INVALID_ARG
+    assert b"two jobs" in bchar._last_error()

@@ -1,0 +1,113 @@
+"""Concurrent builds (bchar_build_transfer_batch) give the same transfers as
+builds run alone: the kernels are deterministic and a job depends only on
+its own inputs and warm start, so every value must match bit for bit.  The
+transfers built alone are the ones the oracle parity tests check."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_05834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05834_amd import bchar
+    return torch, bchar
+
+
+def _same(bchar, Ta, Tb):
+    for stage in (bchar.STAGE_V, bchar.STAGE_SCALING, bchar.STAGE_ALL):
+        ra, ca, va = Ta.export_csr(stage)
+        rb, cb, vb = Tb.export_csr(stage)
+        assert np.array_equal(ra, rb) and np.array_equal(ca, cb)
+        assert np.array_equal(va.view(np.int64), vb.view(np.int64)), stage
+    for k in ("qp_level", "qp_cg", "qp_ipm", "qp_newton", "nnz", "n_pairs"):
+        assert Ta.stats[k] == Tb.stats[k], k
+
+
+def _problems(bchar):
+    w3 = inputs.swirl_hex(8)
+    m3 = bchar.Mesh(w3["mesh"], "subcell")
+    w2 = inputs.solid_body_32()
+    m2 = bchar.Mesh(w2["mesh"], "equal_measure")
+    tri = inputs.triangulated_square(10, 0.1, 6)
+    mt = bchar.Mesh(tri, "equal_measure")
+    vt = inputs.sample_velocity_grid((10, 10), inputs.rotation_stretch_2d)
+    return [(m3, bchar.VelocityLattice(w3["vel_fn"](0)), 0.05),
+            (m2, bchar.VelocityLattice(w2["vel_fn"](0)), w2["dt"]),
+            (mt, bchar.VelocityLattice(vt), 0.3)]
+
+
+def test_batch_builds_equal_builds_alone(env):
+    torch, bchar = env
+    probs = _problems(bchar)
+    alone = [bchar.Transfer.build(m, v, dt) for m, v, dt in probs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    _say("[gpu] batch of 3 jobs on 2 streams")
+    got = bchar.build_batch([(None, m, v, dt) for m, v, dt in probs], streams=streams)
+    for a, b in zip(alone, got):
+        _same(bchar, a, b)
+    # the same jobs again as rebuilds of the batch's transfers, each
+    # warm-started from its own first solve, against rebuilds alone
+    for a, (m, v, dt) in zip(alone, probs):
+        a.rebuild(v, dt)
+    torch.cuda.synchronize()
+    got = bchar.build_batch([(t, None, v, dt) for t, (m, v, dt) in zip(got, probs)],
+                            streams=streams)
+    for a, b in zip(alone, got):
+        _same(bchar, a, b)
+
+
+def test_batch_warm_from_another_transfer(env):
+    torch, bchar = env
+    w = inputs.swirl_hex(10)
+    M = bchar.Mesh(w["mesh"], "subcell")
+    u = [bchar.VelocityLattice(w["vel_fn"](s)) for s in range(4)]
+    dt = w["dt"] * 2
+    # alone: the interval-1 transfer warm-started from the interval-0 solve
+    ref = bchar.Transfer.build(M, u[0], dt)
+    ref.rebuild(u[1], dt)
+    ref2 = bchar.Transfer.build(M, u[0], dt)
+    ref2.rebuild(u[2], dt)
+    torch.cuda.synchronize()
+    # batch: A (last solve on interval 0) is itself rebuilt on interval 2
+    # while B (last solve on interval 3) takes A's interval-0 solve as its
+    # warm start for interval 1: the warm start is taken before A changes
+    A = bchar.Transfer.build(M, u[0], dt)
+    B = bchar.Transfer.build(M, u[3], dt)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    _say("[gpu] batch with warm_from")
+    A, B = bchar.build_batch([(A, None, u[2], dt), (B, None, u[1], dt, A)], streams=streams)
+    _same(bchar, ref, B)
+    _same(bchar, ref2, A)
+    # and the result is a valid step: mass and constants preserved
+    c0 = torch.as_tensor(inputs.uniform_c(w["mesh"], 5), device="cuda")
+    c1 = torch.empty_like(c0)
+    B.step(c0, c1)
+    m0, m1 = M.mass(c0), M.mass(c1)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+
+
+def test_batch_reports_the_failed_job(env):
+    torch, bchar = env
+    probs = _problems(bchar)
+    m, v, dt = probs[0]
+    # the second job is invalid (dt <= 0); the first still completes
+    jobs = [(None, m, v, dt), (None, m, v, -1.0)]
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.build_batch(jobs, streams=[torch.cuda.Stream()])
+    assert ei.value.status == bchar.E_INVALID_ARG
+    assert "job 1" in str(ei.value)
