@@ -238,9 +238,10 @@ typedef struct {
 
 /* Build the transfers of n_jobs independent jobs at once (Algorithm 1 for
  * each, exactly as bchar_build_transfer / bchar_rebuild_transfer would):
- * worker w < n_streams runs jobs w, w + n_streams, ... in that order on
- * streams[w], from a host thread of its own, so that the latency-bound
- * launches of several builds overlap on the device.  Jobs are
+ * min(n_streams, n_jobs) workers, worker w on streams[w] and a host thread
+ * of its own, each take the next job (in index order) whenever they are
+ * free, so that the latency-bound launches of several builds overlap on
+ * the device.  Jobs are
  * independent problems, or time intervals of one problem whose velocity
  * is prescribed ahead (the transfer of an interval depends on its
  * velocity, not on the concentration).  Jobs may share a mesh (read only

@@ -357,7 +357,7 @@ def _handle_value(h):
     return h.value if isinstance(h, C.c_void_p) else h
 
 
-def build_batch(jobs, opts=None, streams=None):
+def build_batch(jobs, opts=None, streams=None, check=True):
     """Build transfers of independent jobs at once (bchar_build_transfer_batch).
 
     ``jobs``: a list of ``(transfer, mesh, velocity, dt)`` or ``(transfer,
@@ -365,9 +365,10 @@ def build_batch(jobs, opts=None, streams=None):
     or None to create one on ``mesh``; ``warm_from`` an optional Transfer of
     the same mesh whose last solve warm-starts the job.  ``streams``:
     torch streams (or raw handles), one host worker each.  Returns the list
-    of Transfer objects (the given ones, rebuilt, or new ones) after every
-    job ended; raises BcharError (first failed job) if any failed, once the
-    transfers that were created have been kept in their Transfer objects.
+    of Transfer objects (the given ones, rebuilt, or new ones; None where a
+    creation failed) after every job ended; raises BcharError (first failed
+    job) if any failed, or with ``check=False`` returns ``(transfers,
+    statuses)`` instead.
     """
     import torch
     if streams is None:
@@ -393,5 +394,7 @@ def build_batch(jobs, opts=None, streams=None):
         else:
             tr.stats = st
         out.append(tr)
+    if not check:
+        return out, [arr[i].status for i in range(len(jobs))]
     _check(rc)
     return out

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <set>
 #include <string>
@@ -701,21 +702,25 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
     std::vector<std::string> msg(n_jobs);
     const int workers = std::min(n_streams, std::max(n_jobs, 1));
     std::vector<hipError_t> sync_err(workers, hipSuccess);
+    // jobs are taken in index order from a shared counter, each by the
+    // first worker that is free
+    std::atomic<int> next{0};
     auto run = [&](int w) {
       sync_err[w] = hipSetDevice(dev);
-      if (sync_err[w] != hipSuccess) {
-        for (int i = w; i < n_jobs; i += workers) jobs[i].status = BCHAR_E_DEVICE;
-        return;
-      }
-      for (int i = w; i < n_jobs; i += workers) {
+      for (int i = next++; i < n_jobs; i = next++) {
         bchar_build_job& J = jobs[i];
+        if (sync_err[w] != hipSuccess) {
+          J.status = BCHAR_E_DEVICE;
+          msg[i] = "hipSetDevice failed in a worker";
+          continue;
+        }
         J.status = J.transfer ? bchar_rebuild_transfer(J.transfer, J.u, J.dt, opts, streams[w],
                                                        &J.stats)
                               : bchar_build_transfer(J.mesh, J.u, J.dt, opts, streams[w],
                                                      &J.transfer, &J.stats);
         if (J.status != BCHAR_OK) msg[i] = bchar_last_error();
       }
-      sync_err[w] = hipStreamSynchronize(as_stream(streams[w]));
+      if (sync_err[w] == hipSuccess) sync_err[w] = hipStreamSynchronize(as_stream(streams[w]));
     };
     std::vector<std::thread> pool;
     for (int w = 1; w < workers; ++w) pool.emplace_back(run, w);

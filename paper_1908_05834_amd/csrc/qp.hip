@@ -51,6 +51,7 @@ constexpr int kAmgCap = 2048;      // candidate entries per coarse node (LDS)
 constexpr int kIpmMaxIter = 100;   // interior-point iterations per box level
 constexpr double kIpmMuTight = 1e-13;  // complementarity of an accepted interior point
 constexpr double kIpmWarmShift = 1e-3; // distance from the box of a warm interior point
+constexpr int kIpmInfeasIt = 10;       // iterations before the no-progress test
 constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relative to
 constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
@@ -2235,6 +2236,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     }
     BCHAR_HIP(hipGetLastError());
     double mu0 = -1.0, fp_best = HUGE_VAL;
+    std::vector<double> fp_hist;
     int stall = 0;
     auto steps = [&](double* ap, double* ad) {
       {
@@ -2279,6 +2281,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         fprintf(stderr, "[bchar]   ipm %d: |B x - r| %.3e, mu %.3e, t %.3f s\n", it, fp, mu,
                 wall_seconds());
       if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return 0;
+      // no progress on an infeasible box: after kIpmInfeasIt iterations the
+      // complementarity has not even halved and |B x - r| fell by less
+      // than 10 % over the last five
+      fp_hist.push_back(fp);
+      if (it >= kIpmInfeasIt && mu >= 0.5 * mu0 && fp >= 0.9 * fp_hist[it - 5]) {
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no progress (infeasible?)\n");
+        return 0;
+      }
       fp_ipm = fp;
       if (fp <= tol && mu <= kIpmMuTight) return 2;
       if (fp_best <= 1e-10 && mu <= 1e-10 && fp > 0.5 * fp_best) {

@@ -310,6 +310,39 @@ def porous_swirl_hex(n=32, seed=5834, steps=20):
             "dt": dt, "steps": steps, "time_dependent": True}
 
 
+def mixed_problem(p, n_lo=4.0e3, n_hi=2.0e5, steps=10):
+    """Problem ``p`` of a batch of independent small problems (seed p): a 2D
+    triangulated unit square (each of n^2 squares cut along the same
+    diagonal, 2 n^2 triangles, one centroid ball of equal measure) or a 3D
+    cube of n^3 hexahedra (8 sub-cell balls), with probability 1/2 each;
+    about N ~ logU[n_lo, n_hi] cells (n = round(sqrt(N / 2)) or
+    round(N^(1/3))); phi = 1; u the sum of four divergence-free Fourier
+    modes (seed p); dt such that dt max over cell centroids |u| / h is a
+    CFL number drawn from U[0.5, 4]; c^0 ~ U[0, 1]; the transfer is built
+    once and applied ``steps`` times (u does not depend on time)."""
+    rng = np.random.default_rng(p)
+    tri = bool(rng.random() < 0.5)
+    N = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+    cfl = float(rng.uniform(0.5, 4.0))
+    if tri:
+        n = max(2, int(round(math.sqrt(N / 2.0))))
+        mesh = triangulated_square(n, 0.0, p)
+        dim, layout = 2, "equal_measure"
+    else:
+        n = max(2, int(round(N ** (1.0 / 3.0))))
+        mesh = cartesian_mesh((n, n, n))
+        dim, layout = 3, "subcell"
+    field = fourier_modes_field(dim, seed=p)
+    u0 = field(cell_centroids(mesh))
+    umax = float(np.max(np.sqrt(np.sum(u0 ** 2, axis=1))))
+    h = 1.0 / n
+    dt = cfl * h / umax
+    vel = sample_velocity_grid((n,) * dim, field)
+    return {"name": f"mixed_{p}_{'tri' if tri else 'hex'}_{n}", "mesh": mesh, "layout": layout,
+            "vel": vel, "dt": dt, "cfl": cfl, "c0": uniform_c(mesh, 100000 + p),
+            "steps": steps, "time_dependent": False}
+
+
 def jittered_tets(n=96, jitter=0.1, seed=1908, phi_seed=5834, cfl=4.0, steps=20):
     """3D unstructured workload: n^3 cubes split into 6 Kuhn tetrahedra
     (6 n^3 cells), interior vertices jittered by up to 10 % of h, phi =

@@ -67,12 +67,17 @@ def _case(name):
         mesh = inputs.triangulated_square(10, 0.1, 6, phi=phi)
         vel = inputs.sample_velocity_grid((10, 10), inputs.rotation_stretch_2d)
         return mesh, vel, 0.3, "equal_measure"
+    if name in ("mixed_tri", "mixed_hex"):
+        # small members of the batch of independent problems (seed 3 is a
+        # triangulated square at CFL 3.3, seed 4 a hexahedral cube at CFL 3.9)
+        q = inputs.mixed_problem(3 if name == "mixed_tri" else 4, 400.0, 400.0)
+        return q["mesh"], q["vel"], q["dt"], q["layout"]
     raise KeyError(name)
 
 
 GEOM_CASES = ["rot2d_subcell", "solid_equal", "solid_inscribed", "swirl3d_subcell_8",
               "swirl3d_inscribed_12", "porous2d_subcell", "porous3d_subcell",
-              "tets", "tets_porous", "tris", "tris_porous"]
+              "tets", "tets_porous", "tris", "tris_porous", "mixed_tri", "mixed_hex"]
 
 
 def _tracked_tensors(torch, T):
@@ -160,7 +165,8 @@ def _full(env, name, precision="fp64"):
 @pytest.mark.parametrize("name", ["rot2d_subcell", "swirl3d_subcell_8", "swirl3d_subcell_16",
                                   "solid_equal", "solid_inscribed", "porous2d_subcell",
                                   "porous3d_subcell", "swirl3d_inscribed_12", "tets",
-                                  "tets_porous", "tris", "tris_porous"])
+                                  "tets_porous", "tris", "tris_porous", "mixed_tri",
+                                  "mixed_hex"])
 def test_full_step(env, name):
     _say(f"[gpu] full step {name}")
     torch, bchar, mesh, ref, M, T = _full(env, name)
