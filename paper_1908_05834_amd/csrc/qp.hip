@@ -2237,6 +2237,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     BCHAR_HIP(hipGetLastError());
     double mu0 = -1.0, fp_best = HUGE_VAL;
     std::vector<double> fp_hist;
+    const bool loose = cg_rel > kIpmCgTight;
     int stall = 0;
     auto steps = [&](double* ap, double* ad) {
       {
@@ -2289,6 +2290,12 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no progress (infeasible?)\n");
         return 0;
       }
+      // loose directions that no longer reduce |B x - r| (by 10 % over
+      // three iterations) hand over to a run with near-exact ones
+      if (loose && it >= 3 && fp >= 0.9 * fp_hist[it - 3]) {
+        if (trace_enabled()) fprintf(stderr, "[bchar]   stop: loose directions stall\n");
+        return 0;
+      }
       fp_ipm = fp;
       if (fp <= tol && mu <= kIpmMuTight) return 2;
       if (fp_best <= 1e-10 && mu <= 1e-10 && fp > 0.5 * fp_best) {
@@ -2309,7 +2316,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // predictor (affine scaling).  Once the normal equations are too
       // ill-conditioned for CG to reach its tolerance the step would spoil
       // the iterate: hand it over as it is.
-      if (pcg(Q.F, cg_tol, false, o.qp_max_cg) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      if (pcg(Q.F, cg_tol, false, o.qp_max_cg) >= o.qp_max_cg) {
+        if (fp_best <= 1e-10) return 1;
+        if (loose) return 0;   // too ill-conditioned for loose directions
+      }
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 0, 0.0, nnz, red.part);
@@ -2340,7 +2350,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       // the corrector's system differs from the predictor's in the
       // right-hand side only: start CG from the predictor's solution
-      if (pcg(Q.F, cg_tol, true, o.qp_max_cg) >= o.qp_max_cg && fp_best <= 1e-10) return 1;
+      if (pcg(Q.F, cg_tol, true, o.qp_max_cg) >= o.qp_max_cg) {
+        if (fp_best <= 1e-10) return 1;
+        if (loose) return 0;
+      }
       {
         ::bchar::ProfScope ps_("k_ipm_dir", s);
         k_ipm_dir<<<kRedBlocks, kT, 0, s>>>(I, Q.dt, 1, smu, nnz, red.part);
