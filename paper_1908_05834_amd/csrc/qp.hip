@@ -223,6 +223,10 @@ struct FusedLevels {
   // offsets of those arrays past the x store
   int gl[kFusedMaxLevels];
   int gptr[kFusedMaxLevels], gnbr[kFusedMaxLevels], gw[kFusedMaxLevels];
+  // the same bytes in global memory (rewritten whenever the weights
+  // change), so that the cycle copies them into LDS in one coalesced pass
+  double2* img;
+  int img_vec;                        // 16-byte vectors of the image
 };
 
 // ---------------------------------------------------------------------- level kernels
@@ -666,15 +670,34 @@ __device__ __forceinline__ double lap_resid(const I* ptr, const I* nbr, const do
   return b[p] - s;
 }
 
-// Sum of a[tid], a[tid + nt], ... (a touch that brings the array into the
-// caches), four loads a round.
+// The LDS image of the graphs of the levels marked gl (16-bit row pointers
+// and neighbours, binary64 weights, at the offsets gptr / gnbr / gw).
+__global__ void k_fused_image(const FusedLevels* __restrict__ F) {
+  unsigned char* img = reinterpret_cast<unsigned char*>(F->img);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ng = gridDim.x * blockDim.x;
+  for (int l = 0; l < F->count; ++l) {
+    if (!F->gl[l]) continue;
+    uint16_t* p16 = reinterpret_cast<uint16_t*>(img + F->gptr[l]);
+    uint16_t* n16 = reinterpret_cast<uint16_t*>(img + F->gnbr[l]);
+    double* w = reinterpret_cast<double*>(img + F->gw[l]);
+    const int32_t *gp = F->ptr[l], *gn = F->nbr[l];
+    const double* gw = F->w[l];
+    for (int p = g; p <= F->n[l]; p += ng) p16[p] = (uint16_t)gp[p];
+    for (int e = g; e < F->ne[l]; e += ng) {
+      n16[e] = (uint16_t)gn[e];
+      w[e] = gw[e];
+    }
+  }
+}
+
+// Value of element tid * stride of a[0, n) (0 past the end) plus the
+// elements (tid + k nt) * stride, k >= 1: one element per cache line of
+// the array, the first load of each thread issued without a loop.
 template <class T>
-__device__ __forceinline__ double touch_sum(const T* a, int n, int tid, int nt) {
-  double acc = 0;
-  int p = tid;
-  for (; p + 3 * nt < n; p += 4 * nt)
-    acc += (double)a[p] + (double)a[p + nt] + (double)a[p + 2 * nt] + (double)a[p + 3 * nt];
-  for (; p < n; p += nt) acc += (double)a[p];
+__device__ __forceinline__ double touch_lines(const T* a, int n, int stride, int tid, int nt) {
+  double acc = tid * stride < n ? (double)a[tid * stride] : 0.0;
+  for (int q = tid + nt; q * stride < n; q += nt) acc += (double)a[q * stride];
   return acc;
 }
 
@@ -687,56 +710,43 @@ __device__ __forceinline__ double touch_sum(const T* a, int n, int tid, int nt) 
 // Every dependent phase is separated by a workgroup barrier.
 __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
-  __shared__ double sh[kFusedLdsTotal];
+  __shared__ __attribute__((aligned(16))) double sh[kFusedLdsTotal];
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int L = F->count;
   double* xs = F->lds ? sh : F->gx;
   unsigned char* gbase = reinterpret_cast<unsigned char*>(sh + (F->lds ? 2 * F->total : 0));
-  // Graphs of the levels marked gl: copied into LDS (all threads, coalesced
-  // reads).  The other levels' arrays are touched once, so that they are in
+  // Graphs of the levels marked gl: copied into LDS from their image (one
+  // coalesced pass, four 16-byte vectors a round, loads first).  The other
+  // levels' arrays are touched once per 128-byte line, so that they are in
   // L2 before the dependent phases below: the kernels of the finer levels
   // have streamed them out since the previous cycle.
   {
+    const double2* src = F->img;
+    double2* dst = reinterpret_cast<double2*>(gbase);
+    const int nv = F->img_vec;
+    int i = tid;
+    for (; i + 3 * nt < nv; i += 4 * nt) {
+      const double2 a0 = src[i], a1 = src[i + nt], a2 = src[i + 2 * nt], a3 = src[i + 3 * nt];
+      dst[i] = a0;
+      dst[i + nt] = a1;
+      dst[i + 2 * nt] = a2;
+      dst[i + 3 * nt] = a3;
+    }
+    for (; i < nv; i += nt) dst[i] = src[i];
     double acc = 0.0;
     for (int l = 0; l < L; ++l) {
       const int n = F->n[l], ne = F->ne[l];
-      if (F->gl[l]) {
-        uint16_t* p16 = reinterpret_cast<uint16_t*>(gbase + F->gptr[l]);
-        uint16_t* n16 = reinterpret_cast<uint16_t*>(gbase + F->gnbr[l]);
-        double* w = reinterpret_cast<double*>(gbase + F->gw[l]);
-        const int32_t *gp = F->ptr[l], *gn = F->nbr[l];
-        const double* gw = F->w[l];
-        for (int p = tid; p <= n; p += nt) p16[p] = (uint16_t)gp[p];
-        // four elements a round, loads first
-        int e = tid;
-        for (; e + 3 * nt < ne; e += 4 * nt) {
-          const int32_t a0 = gn[e], a1 = gn[e + nt], a2 = gn[e + 2 * nt], a3 = gn[e + 3 * nt];
-          const double v0 = gw[e], v1 = gw[e + nt], v2 = gw[e + 2 * nt], v3 = gw[e + 3 * nt];
-          n16[e] = (uint16_t)a0;
-          n16[e + nt] = (uint16_t)a1;
-          n16[e + 2 * nt] = (uint16_t)a2;
-          n16[e + 3 * nt] = (uint16_t)a3;
-          w[e] = v0;
-          w[e + nt] = v1;
-          w[e + 2 * nt] = v2;
-          w[e + 3 * nt] = v3;
-        }
-        for (; e < ne; e += nt) {
-          n16[e] = (uint16_t)gn[e];
-          w[e] = gw[e];
-        }
-      } else {
-        acc += touch_sum(F->w[l], ne, tid, nt) + touch_sum(F->nbr[l], ne, tid, nt);
-        acc += touch_sum(F->ptr[l], n + 1, tid, nt);
-      }
-      acc += touch_sum(F->diag[l], n, tid, nt) + touch_sum(F->sdinv[l], n, tid, nt);
-      if (l + 1 < L) {
-        acc += touch_sum(F->agg[l], n, tid, nt) + touch_sum(F->mem[l], n, tid, nt);
-        acc += touch_sum(F->mptr[l], F->n[l + 1] + 1, tid, nt);
-      }
+      double t = touch_lines(F->diag[l], n, 16, tid, nt) + touch_lines(F->sdinv[l], n, 16, tid, nt);
+      if (l + 1 < L)
+        t += touch_lines(F->agg[l], n, 32, tid, nt) + touch_lines(F->mem[l], n, 32, tid, nt) +
+             touch_lines(F->mptr[l], F->n[l + 1] + 1, 32, tid, nt);
+      if (!F->gl[l])
+        t += touch_lines(F->w[l], ne, 16, tid, nt) + touch_lines(F->nbr[l], ne, 32, tid, nt) +
+             touch_lines(F->ptr[l], n + 1, 32, tid, nt);
+      acc += t;
     }
-    if (F->dense) acc += touch_sum(F->G, F->n[L - 1] * F->n[L - 1], tid, nt);
+    if (F->dense) acc += touch_lines(F->G, F->n[L - 1] * F->n[L - 1], 16, tid, nt);
     // a store that never happens keeps the loads
     if (acc == -1.0) red[0] = acc;
   }
@@ -865,6 +875,7 @@ struct Hierarchy {
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
   FusedLevels* fused = nullptr;    // device copy
+  bool fused_img = false;          // it has an LDS image to refresh
   int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least once
 };
 
@@ -1048,8 +1059,11 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   hf.gx = lds ? nullptr : ws.get<double>((size_t)(2 * total));
   // graphs in LDS, from the coarsest level up, while they fit past the
   // iterates (16-bit indices need fewer than 65536 nodes and edges a level)
+  int64_t img_bytes = 0;
   {
-    const int64_t avail = lds ? 8 * (int64_t)(kFusedLdsTotal - 2 * total) : 0;
+    // a multiple of 16 bytes, so that the image rounded up to whole
+    // 16-byte vectors still fits
+    const int64_t avail = lds ? (8 * (int64_t)(kFusedLdsTotal - 2 * total)) / 16 * 16 : 0;
     int64_t used = 0;
     for (int k = (int)(H.lv.size() - first) - 1; k >= 0; --k) {
       const Level& Lk = H.lv[first + k];
@@ -1067,7 +1081,10 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
       hf.gw[k] = (int)(used + pb + nbb);
       used += need;
     }
+    img_bytes = used;
   }
+  hf.img_vec = (int)((img_bytes + 15) / 16);
+  hf.img = hf.img_vec > 0 ? ws.get<double2>((size_t)hf.img_vec) : nullptr;
   for (int k = 0, o = 0; k < hf.count; ++k) {
     Level& Lk = H.lv[first + k];
     hf.off[k] = o;
@@ -1097,6 +1114,7 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   }
   if (H.dense) H.fused_bytes += 8 * (int64_t)H.coarse_n * H.coarse_n;
   H.fused = ws.get<FusedLevels>(1);
+  H.fused_img = hf.img_vec > 0;
   BCHAR_HIP(hipMemcpyAsync(H.fused, &hf, sizeof(hf), hipMemcpyHostToDevice, s));
   BCHAR_HIP(hipStreamSynchronize(s));
 }
@@ -1120,6 +1138,13 @@ static void refresh_hierarchy(Hierarchy& H, hipStream_t s) {
     {
       ::bchar::ProfScope ps_("k_coarse_inverse", s);
       k_coarse_inverse<<<1, 1024, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, (int)L.n, H.G);
+    }
+    BCHAR_HIP(hipGetLastError());
+  }
+  if (H.fused_img) {
+    {
+      ::bchar::ProfScope ps_("k_fused_image", s);
+      k_fused_image<<<64, kT, 0, s>>>(H.fused);
     }
     BCHAR_HIP(hipGetLastError());
   }
