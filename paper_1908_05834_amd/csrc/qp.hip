@@ -187,6 +187,12 @@ struct Level {
   int32_t* cedge = nullptr;    // this level's edge ids
   // vectors
   double *b = nullptr, *x = nullptr, *x2 = nullptr, *r = nullptr;
+  // restricted operator R L (row C: the residual of the aggregate C is
+  // sum_{p in C} b_p + sum_k ra_val[k] x[ra_col[k]]), with the
+  // contributions of every entry (fine edge e: + w_e; -1 - q: - diag_q)
+  int64_t nra = 0;
+  int32_t *ra_ptr = nullptr, *ra_col = nullptr, *ra_cptr = nullptr, *ra_code = nullptr;
+  double* ra_val = nullptr;
 };
 
 // Levels small enough for one workgroup run in a single launch
@@ -272,8 +278,19 @@ __device__ __forceinline__ double lanes_offdiag(const int32_t* __restrict__ ptr,
                                                 const double* __restrict__ x, int64_t p,
                                                 int sub, bool live) {
   double s = 0.0;
-  if (live)
-    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) s += w[e] * x[nbr[e]];
+  if (live) {
+    // two of the lane's edges a round, their loads issued together
+    const int32_t end = ptr[p + 1];
+    int32_t e = ptr[p] + sub;
+    for (; e + kNodeLanes < end; e += 2 * kNodeLanes) {
+      const int32_t q0 = nbr[e], q1 = nbr[e + kNodeLanes];
+      const double w0 = w[e], w1 = w[e + kNodeLanes];
+      const double x0 = x[q0], x1 = x[q1];
+      s += w0 * x0;
+      s += w1 * x1;
+    }
+    if (e < end) s += w[e] * x[nbr[e]];
+  }
   s += __shfl_xor(s, 1, kWave);
   s += __shfl_xor(s, 2, kWave);
   return s;
@@ -310,11 +327,21 @@ __global__ void __launch_bounds__(kT) k_smooth_zero2(const int32_t* __restrict__
   const int sub = (int)(g % kNodeLanes);
   const bool live = p < n;
   double s = 0.0;
-  if (live)
-    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) {
+  if (live) {
+    const int32_t end = ptr[p + 1];
+    int32_t e = ptr[p] + sub;
+    for (; e + kNodeLanes < end; e += 2 * kNodeLanes) {
+      const int32_t q0 = nbr[e], q1 = nbr[e + kNodeLanes];
+      const double w0 = w[e], w1 = w[e + kNodeLanes];
+      const double a0 = sdinv[q0] * b[q0], a1 = sdinv[q1] * b[q1];
+      s += w0 * a0;
+      s += w1 * a1;
+    }
+    if (e < end) {
       const int32_t q = nbr[e];
       s += w[e] * (sdinv[q] * b[q]);
     }
+  }
   s += __shfl_xor(s, 1, kWave);
   s += __shfl_xor(s, 2, kWave);
   if (live && sub == 0) {
@@ -337,6 +364,132 @@ __global__ void __launch_bounds__(kT) k_resid(const int32_t* __restrict__ ptr,
   const bool live = p < n;
   const double off = lanes_offdiag(ptr, nbr, w, x, p, sub, live);
   if (live && sub == 0) r[p] = b[p] - (diag[p] * x[p] - off);
+}
+
+// Residual and restriction in one pass through the restricted operator:
+// bc[C] = sum_{p in C} b_p + sum_k ra_val[k] x[ra_col[k]], kNodeLanes lanes
+// per coarse node (fixed order: lane-strided partial sums, then a
+// butterfly).
+__global__ void __launch_bounds__(kT) k_resid_restrict(
+    const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
+    const double* __restrict__ b, const int32_t* __restrict__ ra_ptr,
+    const int32_t* __restrict__ ra_col, const double* __restrict__ ra_val,
+    const double* __restrict__ x, int64_t nc, double* __restrict__ bc) {
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t C = g / kNodeLanes;
+  const int sub = (int)(g % kNodeLanes);
+  double s = 0.0;
+  if (C < nc) {
+    for (int32_t m = mptr[C] + sub; m < mptr[C + 1]; m += kNodeLanes) s += b[mem[m]];
+    const int32_t end = ra_ptr[C + 1];
+    int32_t k = ra_ptr[C] + sub;
+    for (; k + kNodeLanes < end; k += 2 * kNodeLanes) {
+      const int32_t q0 = ra_col[k], q1 = ra_col[k + kNodeLanes];
+      const double v0 = ra_val[k], v1 = ra_val[k + kNodeLanes];
+      const double x0 = x[q0], x1 = x[q1];
+      s += v0 * x0;
+      s += v1 * x1;
+    }
+    if (k < end) s += ra_val[k] * x[ra_col[k]];
+  }
+  s += __shfl_xor(s, 1, kWave);
+  s += __shfl_xor(s, 2, kWave);
+  if (C < nc && sub == 0) bc[C] = s;
+}
+
+// Values of the restricted operator from the level's weights and diagonal.
+__global__ void k_ra_values(const int32_t* __restrict__ ra_cptr,
+                            const int32_t* __restrict__ ra_code, const double* __restrict__ w,
+                            const double* __restrict__ diag, int64_t nra,
+                            double* __restrict__ ra_val) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nra) return;
+  double v = 0.0;
+  for (int32_t c = ra_cptr[r]; c < ra_cptr[r + 1]; ++c) {
+    const int32_t code = ra_code[c];
+    v += code >= 0 ? w[code] : -diag[-1 - code];
+  }
+  ra_val[r] = v;
+}
+
+// Pattern of the restricted operator, one coarse node per wave: the
+// candidates of each member p (p itself for its diagonal, then the far
+// ends of its edges), merged by fine node.  Count pass: row length and
+// candidate count.  Fill pass: ascending columns, and the candidates'
+// codes grouped by entry.
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_ra_pattern(
+    const int32_t* __restrict__ fptr, const int32_t* __restrict__ fnbr,
+    const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem, int64_t nc,
+    int32_t* __restrict__ row_cnt, int32_t* __restrict__ cand_cnt,
+    const int32_t* __restrict__ ra_ptr, const int32_t* __restrict__ cbase,
+    int32_t* __restrict__ ra_col, int32_t* __restrict__ ra_cptr, int32_t* __restrict__ ra_code,
+    int32_t* __restrict__ overflow) {
+  __shared__ int32_t s_key[kAmgCap];
+  __shared__ int32_t s_code[kAmgCap];
+  __shared__ int32_t s_first[kAmgCap];
+  const int64_t C = blockIdx.x;
+  const int lane = threadIdx.x;
+  int H = 0;
+  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) {
+    const int32_t p = mem[m];
+    const int32_t lo = fptr[p] - 1, hi = fptr[p + 1];
+    // slot lo is the diagonal of p, the others its edges
+    for (int32_t base = lo; base < hi; base += kWave) {
+      const int32_t e = base + lane;
+      const int keep = e < hi ? 1 : 0;
+      const int incl = wave_incl_scan_i(keep);
+      const int tot = __shfl(incl, kWave - 1, kWave);
+      if (keep && H + incl - 1 < kAmgCap) {
+        s_key[H + incl - 1] = e == lo ? p : fnbr[e];
+        s_code[H + incl - 1] = e == lo ? -1 - p : e;
+      }
+      H += tot;
+    }
+  }
+  if (H > kAmgCap) {
+    if (lane == 0) atomicMax(overflow, H);
+    return;
+  }
+  __syncthreads();
+  for (int e = lane; e < H; e += kWave) {
+    const int32_t k = s_key[e];
+    int first = 1;
+    for (int j = 0; j < e; ++j)
+      if (s_key[j] == k) {
+        first = 0;
+        break;
+      }
+    s_first[e] = first;
+  }
+  __syncthreads();
+  if (!FILL) {
+    int u = 0;
+    for (int e = lane; e < H; e += kWave) u += s_first[e];
+    u = wave_sum_i(u);
+    if (lane == 0) {
+      row_cnt[C] = u;
+      cand_cnt[C] = H;
+    }
+    return;
+  }
+  const int32_t rb = ra_ptr[C];
+  const int32_t cb = cbase[C];
+  for (int e = lane; e < H; e += kWave) {
+    const int32_t k = s_key[e];
+    int less = 0, before = 0, rank = 0;
+    for (int j = 0; j < H; ++j) {
+      const int32_t kj = s_key[j];
+      less += kj < k;
+      before += (kj == k) && (j < e);
+      rank += s_first[j] && kj < k;
+    }
+    ra_code[cb + less + before] = s_code[e];
+    if (s_first[e]) {
+      ra_col[rb + rank] = k;
+      ra_cptr[rb + rank] = cb + less;
+    }
+  }
 }
 
 // bc[C] = sum of r over the members of C
@@ -362,11 +515,22 @@ __global__ void __launch_bounds__(kT) k_prolong_smooth(
   const int sub = (int)(g % kNodeLanes);
   const bool live = p < n;
   double s = 0.0;
-  if (live)
-    for (int32_t e = ptr[p] + sub; e < ptr[p + 1]; e += kNodeLanes) {
+  if (live) {
+    const int32_t end = ptr[p + 1];
+    int32_t e = ptr[p] + sub;
+    for (; e + kNodeLanes < end; e += 2 * kNodeLanes) {
+      const int32_t q0 = nbr[e], q1 = nbr[e + kNodeLanes];
+      const double w0 = w[e], w1 = w[e + kNodeLanes];
+      const int32_t c0 = agg[q0], c1 = agg[q1];
+      const double y0 = x[q0] + xc[c0], y1 = x[q1] + xc[c1];
+      s += w0 * y0;
+      s += w1 * y1;
+    }
+    if (e < end) {
       const int32_t q = nbr[e];
       s += w[e] * (x[q] + xc[agg[q]]);
     }
+  }
   s += __shfl_xor(s, 1, kWave);
   s += __shfl_xor(s, 2, kWave);
   if (live && sub == 0) {
@@ -942,6 +1106,46 @@ static Level galerkin_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
   return Cl;
 }
 
+// Pattern of the restricted operator of level L (aggregates of L, nc of
+// them) and the codes its values are summed from.
+static void ra_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
+  int32_t* row_cnt = ws.get<int32_t>(nc + 1);
+  int32_t* cand_cnt = ws.get<int32_t>(nc + 1);
+  int32_t* overflow = ws.get<int32_t>(1);
+  fill_i32(overflow, 0, 1, s);
+  {
+    ::bchar::ProfScope ps_("k_ra_pattern", s);
+    k_ra_pattern<false><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.mptr, L.mem, nc, row_cnt,
+                                                    cand_cnt, nullptr, nullptr, nullptr,
+                                                    nullptr, nullptr, overflow);
+  }
+  BCHAR_HIP(hipGetLastError());
+  int32_t hov = 0;
+  BCHAR_HIP(hipMemcpyAsync(&hov, overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BCHAR_HIP(hipStreamSynchronize(s));
+  if (hov > 0)
+    throw Error{BCHAR_E_UNSUPPORTED,
+                "restriction: an aggregate has " + std::to_string(hov) + " candidate entries"};
+  L.ra_ptr = ws.get<int32_t>(nc + 1);
+  int32_t* cbase = ws.get<int32_t>(nc + 1);
+  L.nra = exclusive_scan_i32(row_cnt, L.ra_ptr, nc, ws, s);
+  const int64_t ncand = exclusive_scan_i32(cand_cnt, cbase, nc, ws, s);
+  L.ra_col = ws.get<int32_t>(L.nra + 1);
+  L.ra_cptr = ws.get<int32_t>(L.nra + 1);
+  L.ra_code = ws.get<int32_t>(ncand + 1);
+  L.ra_val = ws.get<double>(L.nra + 1);
+  {
+    ::bchar::ProfScope ps_("k_ra_pattern", s);
+    k_ra_pattern<true><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.mptr, L.mem, nc, nullptr,
+                                                   nullptr, L.ra_ptr, cbase, L.ra_col, L.ra_cptr,
+                                                   L.ra_code, overflow);
+  }
+  BCHAR_HIP(hipGetLastError());
+  // closing entry of the contribution pointer
+  BCHAR_HIP(hipMemcpyAsync(L.ra_cptr + L.nra, cbase + nc, sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+}
+
 static void alloc_level_vectors(Level& L, Arena& ws) {
   L.diag = ws.get<double>(L.n + 1);
   L.sdinv = ws.get<double>(L.n + 1);
@@ -1047,6 +1251,8 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     --first;
   }
   H.fused_first = first;
+  // the launched levels restrict their residual through R L
+  for (size_t l = 1; l < first; ++l) ra_pattern(H.lv[l], H.lv[l + 1].n, ws, s);
   FusedLevels hf{};
   hf.count = (int)(H.lv.size() - first);
   hf.dense = H.dense ? 1 : 0;
@@ -1132,6 +1338,14 @@ static void refresh_hierarchy(Hierarchy& H, hipStream_t s) {
       BCHAR_HIP(hipGetLastError());
     }
     level_refresh_diag(L, H.mu, s);
+    if (L.ra_val) {
+      {
+        ::bchar::ProfScope ps_("k_ra_values", s);
+        k_ra_values<<<blocks_for(L.nra, kT), kT, 0, s>>>(L.ra_cptr, L.ra_code, L.w, L.diag,
+                                                         L.nra, L.ra_val);
+      }
+      BCHAR_HIP(hipGetLastError());
+    }
   }
   if (H.dense) {
     Level& L = H.lv.back();
@@ -1163,7 +1377,7 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
     return;
   }
   // two damped Jacobi sweeps before and after the coarse correction, in
-  // five launches: both pre-sweeps, residual, restriction, prolongation
+  // four launches: both pre-sweeps, residual and restriction, prolongation
   // with the first post-sweep, the second post-sweep (result in L.x)
   Level& C = H.lv[l + 1];
   const unsigned gl = blocks_for(L.n * kNodeLanes, kT);
@@ -1172,12 +1386,9 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
     k_smooth_zero2<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.n, L.x);
   }
   {
-    ::bchar::ProfScope ps_("k_resid", s);
-    k_resid<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.b, L.x, L.n, L.x2);
-  }
-  {
-    ::bchar::ProfScope ps_("k_restrict", s);
-    k_restrict<<<blocks_for(C.n, kT), kT, 0, s>>>(L.mptr, L.mem, L.x2, C.n, C.b);
+    ::bchar::ProfScope ps_("k_resid_restrict", s);
+    k_resid_restrict<<<blocks_for(C.n * kNodeLanes, kT), kT, 0, s>>>(
+        L.mptr, L.mem, L.b, L.ra_ptr, L.ra_col, L.ra_val, L.x, C.n, C.b);
   }
   vcycle(H, l + 1, s);
   {
@@ -1259,15 +1470,40 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
                                             double& os, double& og) {
   const double sK = zs[K], gK = zg[K];
   double fr = 0, fc = 0, fd = 0;
-  for (int32_t k = Z.rptr[K]; k < Z.rptr[K + 1]; ++k) {
-    const int32_t M = Z.col[k];
-    if (M == (int32_t)K) {
-      fd = Z.w[k] * gK;
-    } else {
-      fr += Z.w[k] * ((sK - zs[M]) + 0.5 * (gK + zg[M]));
-    }
+  // two entries a round with their loads issued together (same order of
+  // accumulation as one at a time)
+  const int32_t kend = Z.rptr[K + 1];
+  int32_t k = Z.rptr[K];
+  for (; k + 1 < kend; k += 2) {
+    const int32_t M0 = Z.col[k], M1 = Z.col[k + 1];
+    const double w0 = Z.w[k], w1 = Z.w[k + 1];
+    const double s0 = zs[M0], g0 = zg[M0], s1 = zs[M1], g1 = zg[M1];
+    if (M0 == (int32_t)K)
+      fd = w0 * gK;
+    else
+      fr += w0 * ((sK - s0) + 0.5 * (gK + g0));
+    if (M1 == (int32_t)K)
+      fd = w1 * gK;
+    else
+      fr += w1 * ((sK - s1) + 0.5 * (gK + g1));
   }
-  for (int32_t e = Z.cptr[K]; e < Z.cptr[K + 1]; ++e) {
+  if (k < kend) {
+    const int32_t M = Z.col[k];
+    if (M == (int32_t)K)
+      fd = Z.w[k] * gK;
+    else
+      fr += Z.w[k] * ((sK - zs[M]) + 0.5 * (gK + zg[M]));
+  }
+  const int32_t eend = Z.cptr[K + 1];
+  int32_t e = Z.cptr[K];
+  for (; e + 1 < eend; e += 2) {
+    const int32_t I0 = Z.crow[e], I1 = Z.crow[e + 1];
+    const double w0 = Z.wc[e], w1 = Z.wc[e + 1];
+    const double s0 = zs[I0], g0 = zg[I0], s1 = zs[I1], g1 = zg[I1];
+    if (I0 != (int32_t)K) fc += w0 * ((s0 - sK) + 0.5 * (g0 + gK));
+    if (I1 != (int32_t)K) fc += w1 * ((s1 - sK) + 0.5 * (g1 + gK));
+  }
+  if (e < eend) {
     const int32_t I = Z.crow[e];
     if (I != (int32_t)K) fc += Z.wc[e] * ((zs[I] - sK) + 0.5 * (zg[I] + gK));
   }
