@@ -350,21 +350,6 @@ __global__ void __launch_bounds__(kT) k_smooth_zero2(const int32_t* __restrict__
   }
 }
 
-// r = b - L x
-__global__ void __launch_bounds__(kT) k_resid(const int32_t* __restrict__ ptr,
-                                              const int32_t* __restrict__ nbr,
-                                              const double* __restrict__ w,
-                                              const double* __restrict__ diag,
-                                              const double* __restrict__ b,
-                                              const double* __restrict__ x, int64_t n,
-                                              double* __restrict__ r) {
-  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const int64_t p = g / kNodeLanes;
-  const int sub = (int)(g % kNodeLanes);
-  const bool live = p < n;
-  const double off = lanes_offdiag(ptr, nbr, w, x, p, sub, live);
-  if (live && sub == 0) r[p] = b[p] - (diag[p] * x[p] - off);
-}
 
 // Residual and restriction in one pass through the restricted operator:
 // bc[C] = sum_{p in C} b_p + sum_k ra_val[k] x[ra_col[k]], kNodeLanes lanes
@@ -492,15 +477,6 @@ __global__ void __launch_bounds__(64) k_ra_pattern(
   }
 }
 
-// bc[C] = sum of r over the members of C
-__global__ void k_restrict(const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
-                           const double* __restrict__ r, int64_t nc, double* __restrict__ bc) {
-  const int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (C >= nc) return;
-  double acc = 0.0;
-  for (int32_t m = mptr[C]; m < mptr[C + 1]; ++m) acc += r[mem[m]];
-  bc[C] = acc;
-}
 
 // Prolongation and the first post-smoothing sweep in one pass: y = x +
 // xc[agg] is formed where it is gathered, xo = y + sdinv (b - L y)
