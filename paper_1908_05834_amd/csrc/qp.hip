@@ -1448,22 +1448,31 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
   double fr = 0, fc = 0, fd = 0;
   // two entries a round with their loads issued together (same order of
   // accumulation as one at a time)
+  constexpr int U = 4;
   const int32_t kend = Z.rptr[K + 1];
   int32_t k = Z.rptr[K];
-  for (; k + 1 < kend; k += 2) {
-    const int32_t M0 = Z.col[k], M1 = Z.col[k + 1];
-    const double w0 = Z.w[k], w1 = Z.w[k + 1];
-    const double s0 = zs[M0], g0 = zg[M0], s1 = zs[M1], g1 = zg[M1];
-    if (M0 == (int32_t)K)
-      fd = w0 * gK;
-    else
-      fr += w0 * ((sK - s0) + 0.5 * (gK + g0));
-    if (M1 == (int32_t)K)
-      fd = w1 * gK;
-    else
-      fr += w1 * ((sK - s1) + 0.5 * (gK + g1));
+  for (; k + U - 1 < kend; k += U) {
+    int32_t M[U];
+    double wv[U], sv[U], gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      M[u] = Z.col[k + u];
+      wv[u] = Z.w[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sv[u] = zs[M[u]];
+      gv[u] = zg[M[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (M[u] == (int32_t)K)
+        fd = wv[u] * gK;
+      else
+        fr += wv[u] * ((sK - sv[u]) + 0.5 * (gK + gv[u]));
+    }
   }
-  if (k < kend) {
+  for (; k < kend; ++k) {
     const int32_t M = Z.col[k];
     if (M == (int32_t)K)
       fd = Z.w[k] * gK;
@@ -1472,14 +1481,24 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
   }
   const int32_t eend = Z.cptr[K + 1];
   int32_t e = Z.cptr[K];
-  for (; e + 1 < eend; e += 2) {
-    const int32_t I0 = Z.crow[e], I1 = Z.crow[e + 1];
-    const double w0 = Z.wc[e], w1 = Z.wc[e + 1];
-    const double s0 = zs[I0], g0 = zg[I0], s1 = zs[I1], g1 = zg[I1];
-    if (I0 != (int32_t)K) fc += w0 * ((s0 - sK) + 0.5 * (g0 + gK));
-    if (I1 != (int32_t)K) fc += w1 * ((s1 - sK) + 0.5 * (g1 + gK));
+  for (; e + U - 1 < eend; e += U) {
+    int32_t I[U];
+    double wv[U], sv[U], gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      I[u] = Z.crow[e + u];
+      wv[u] = Z.wc[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sv[u] = zs[I[u]];
+      gv[u] = zg[I[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (I[u] != (int32_t)K) fc += wv[u] * ((sv[u] - sK) + 0.5 * (gv[u] + gK));
   }
-  if (e < eend) {
+  for (; e < eend; ++e) {
     const int32_t I = Z.crow[e];
     if (I != (int32_t)K) fc += Z.wc[e] * ((zs[I] - sK) + 0.5 * (zg[I] + gK));
   }
