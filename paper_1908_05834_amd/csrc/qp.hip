@@ -1506,14 +1506,28 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
   og = 0.5 * (fr + fc) + fd + Z.tau_g[K] * gK;
 }
 
+// out = J_z z; with `part`, also the compensated block sums of z . out
+// (one (hi, lo) pair per block, in block order)
 __global__ void __launch_bounds__(kT) k_zop(ZCells Z, const double* __restrict__ z,
-                                            double* __restrict__ out) {
+                                            double* __restrict__ out, double* __restrict__ part) {
+  __shared__ double sh[32];
   const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (K >= Z.n) return;
-  double os, og;
-  zapply_cell(Z, z, z + Z.n, K, os, og);
-  out[K] = os;
-  out[Z.n + K] = og;
+  CSum acc;
+  if (K < Z.n) {
+    double os, og;
+    zapply_cell(Z, z, z + Z.n, K, os, og);
+    out[K] = os;
+    out[Z.n + K] = og;
+    acc.add(z[K] * os);
+    acc.add(z[Z.n + K] * og);
+  }
+  if (part) {   // uniform over the grid: every thread reaches the barriers
+    const CSum t = block_csum(acc, sh);
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = t.hi;
+      part[2 * blockIdx.x + 1] = t.lo;
+    }
+  }
 }
 
 // x = omega B^-1 b
@@ -1526,18 +1540,35 @@ __global__ void k_zsmooth_first(ZCells Z, double omega, const double* __restrict
   x[Z.n + K] = omega * (Z.bi[3 * K + 1] * bs + Z.bi[3 * K + 2] * bg);
 }
 
-// xo = xi + omega B^-1 (b - J_z xi)
+// xo = xi + omega B^-1 (b - J_z xi); with `part`, also the compensated
+// block sums of b . xo (as k_zop)
 __global__ void __launch_bounds__(kT) k_zsmooth(ZCells Z, double omega,
                                                 const double* __restrict__ b,
                                                 const double* __restrict__ xi,
-                                                double* __restrict__ xo) {
+                                                double* __restrict__ xo,
+                                                double* __restrict__ part) {
+  __shared__ double sh[32];
   const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (K >= Z.n) return;
-  double os, og;
-  zapply_cell(Z, xi, xi + Z.n, K, os, og);
-  const double rs = b[K] - os, rg = b[Z.n + K] - og;
-  xo[K] = xi[K] + omega * (Z.bi[3 * K] * rs + Z.bi[3 * K + 1] * rg);
-  xo[Z.n + K] = xi[Z.n + K] + omega * (Z.bi[3 * K + 1] * rs + Z.bi[3 * K + 2] * rg);
+  CSum acc;
+  if (K < Z.n) {
+    double os, og;
+    zapply_cell(Z, xi, xi + Z.n, K, os, og);
+    const double bs = b[K], bg = b[Z.n + K];
+    const double rs = bs - os, rg = bg - og;
+    const double ys = xi[K] + omega * (Z.bi[3 * K] * rs + Z.bi[3 * K + 1] * rg);
+    const double yg = xi[Z.n + K] + omega * (Z.bi[3 * K + 1] * rs + Z.bi[3 * K + 2] * rg);
+    xo[K] = ys;
+    xo[Z.n + K] = yg;
+    acc.add(bs * ys);
+    acc.add(bg * yg);
+  }
+  if (part) {
+    const CSum t = block_csum(acc, sh);
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = t.hi;
+      part[2 * blockIdx.x + 1] = t.lo;
+    }
+  }
 }
 
 // r = b - J_z x
@@ -1588,8 +1619,11 @@ struct ZPrecond {
 };
 
 // z = M r: block-Jacobi smoothing in (s, g), coarse correction through
-// the cell hierarchy, block-Jacobi smoothing (symmetric)
-static void zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s) {
+// the cell hierarchy, block-Jacobi smoothing (symmetric).  With `part`
+// (and at least one post-sweep) the last sweep also leaves the block sums
+// of r . z there; returns whether it did.
+static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s,
+                          double* part = nullptr) {
   const int64_t n = P.Z.n;
   const unsigned gb = blocks_for(n, kT);
   double* x = P.x;
@@ -1601,7 +1635,7 @@ static void zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   for (int k = 1; k < P.pre; ++k) {
     {
       ::bchar::ProfScope ps_("k_zsmooth", s);
-      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, x2);
+      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, x2, nullptr);
     }
     std::swap(x, x2);
   }
@@ -1624,13 +1658,14 @@ static void zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
     double* out = (k + 1 == P.post) ? z : x2;
     {
       ::bchar::ProfScope ps_("k_zsmooth", s);
-      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, out);
+      k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, out, out == z ? part : nullptr);
     }
     if (out == x2) std::swap(x, x2);
   }
   if (P.post == 0)
     BCHAR_HIP(hipMemcpyAsync(z, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, s));
   BCHAR_HIP(hipGetLastError());
+  return part != nullptr && P.post > 0;
 }
 
 // ====================================================================== Newton kernels
@@ -1752,27 +1787,23 @@ __global__ void k_sub_scalar(double* __restrict__ v, const double* __restrict__ 
 }
 
 // CG vector updates with device scalars sc[0] = rz, sc[1] = pq
-__global__ void k_cg_update(const double* __restrict__ sc, int64_t n, double* __restrict__ x,
-                            double* __restrict__ r, const double* __restrict__ p,
-                            const double* __restrict__ q) {
+__global__ void k_cg_update(const double* __restrict__ rz, const double* __restrict__ pq,
+                            int64_t n, double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double alpha = sc[1] != 0.0 ? sc[0] / sc[1] : 0.0;
+  const double alpha = *pq != 0.0 ? *rz / *pq : 0.0;
   x[i] += alpha * p[i];
   r[i] -= alpha * q[i];
 }
 
-// p = z + (sc[2] / sc[0]) p
-__global__ void k_cg_dir(const double* __restrict__ sc, int64_t n, const double* __restrict__ z,
-                         double* __restrict__ p) {
+// p = z + (rz_new / rz_old) p
+__global__ void k_cg_dir(const double* __restrict__ rz_old, const double* __restrict__ rz_new,
+                         int64_t n, const double* __restrict__ z, double* __restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
+  const double beta = *rz_old != 0.0 ? *rz_new / *rz_old : 0.0;
   p[i] = z[i] + beta * p[i];
-}
-
-__global__ void k_copy_scalar(double* sc, int from, int to) {
-  if (threadIdx.x == 0) sc[to] = sc[from];
 }
 
 // dual direction from the (s, g) solution (mean of s removed) and the
@@ -2114,6 +2145,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   const unsigned gn = blocks_for(n, kT), gn2 = blocks_for(n2, kT), gz = blocks_for(nnz, kT);
 
   Reducer red{ws.get<double>(2 * kRedBlocks + 2), ws.get<double>(16), s};
+  double* zpart = ws.get<double>(2 * (size_t)blocks_for(n, kT) + 2);   // block sums
 
   QpArrays Q{};
   Q.n = n;
@@ -2248,7 +2280,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       // start from the solution already in cx: r = rhs - J cx
       {
         ::bchar::ProfScope ps_("k_zop", s);
-        k_zop<<<gn, kT, 0, s>>>(P.Z, cx, cq);
+        k_zop<<<gn, kT, 0, s>>>(P.Z, cx, cq, nullptr);
       }
       {
         ::bchar::ProfScope ps_("k_axpy2", s);
@@ -2257,20 +2289,28 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     } else {
       fill_f64(cx, 0.0, n2, s);
     }
-    // scalars: out[8] = rz, out[9] = pq, out[10] = rz_new, out[11] = max |r|
+    // scalars: r.z alternates between out[8] and out[10] (the current one
+    // and the next), out[9] = p.q, out[11] = max |r|; the dot products are
+    // summed from the block sums that k_zop and the last sweep of the
+    // preconditioner leave in zpart
     zprecondition(P, cr, cz, s);
     BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
     red.dot(cr, cz, n2, 8);
+    double* rz = red.out + 8;
+    double* rz_next = red.out + 10;
     int k = 0;
     for (k = 0; k < max_cg; ++k) {
       {
         ::bchar::ProfScope ps_("k_zop", s);
-        k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq);
+        k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq, zpart);
       }
-      red.dot(cp, cq, n2, 9);
+      {
+        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+        k_reduce_final_sum<<<1, 64, 0, s>>>(zpart, (int)gn, red.out + 9);
+      }
       {
         ::bchar::ProfScope ps_("k_cg_update", s);
-        k_cg_update<<<gn2, kT, 0, s>>>(red.out + 8, n2, cx, cr, cp, cq);
+        k_cg_update<<<gn2, kT, 0, s>>>(rz, red.out + 9, n2, cx, cr, cp, cq);
       }
       BCHAR_HIP(hipGetLastError());
       if ((k % 4) == 3 || k + 1 == max_cg) {
@@ -2280,16 +2320,17 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
           break;
         }
       }
-      zprecondition(P, cr, cz, s);
-      red.dot(cr, cz, n2, 10);
+      if (zprecondition(P, cr, cz, s, zpart)) {
+        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
+        k_reduce_final_sum<<<1, 64, 0, s>>>(zpart, (int)gn, rz_next);
+      } else {
+        red.dot(cr, cz, n2, (int)(rz_next - red.out));
+      }
       {
         ::bchar::ProfScope ps_("k_cg_dir", s);
-        k_cg_dir<<<gn2, kT, 0, s>>>(red.out + 8, n2, cz, cp);
+        k_cg_dir<<<gn2, kT, 0, s>>>(rz, rz_next, n2, cz, cp);
       }
-      {
-        ::bchar::ProfScope ps_("k_copy_scalar", s);
-        k_copy_scalar<<<1, 64, 0, s>>>(red.out, 10, 8);
-      }
+      std::swap(rz, rz_next);
       BCHAR_HIP(hipGetLastError());
     }
     res.cg += k;
