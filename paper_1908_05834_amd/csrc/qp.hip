@@ -61,20 +61,22 @@ constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those aft
 
 // ====================================================================== reductions
 
-// Final combine of the per-block partials by one wave: lane i takes the
-// partials i, i + 64, ... in order, then a fixed butterfly; launched with
-// 64 threads.  The order is fixed, so the result is reproducible.
-__global__ void k_reduce_final_sum(const double* __restrict__ part, int np,
-                                   double* __restrict__ out) {
+// Final combine of the per-block partials by one block of kFinalThreads:
+// thread i takes the partials i, i + kFinalThreads, ... in order, then a
+// fixed tree.  The order is fixed, so the result is reproducible.
+constexpr int kFinalThreads = 256;
+__global__ void __launch_bounds__(kFinalThreads) k_reduce_final_sum(
+    const double* __restrict__ part, int np, double* __restrict__ out) {
+  __shared__ double sh[32];
   CSum acc;
-  for (int i = threadIdx.x; i < np; i += kWave) {
+  for (int i = threadIdx.x; i < np; i += kFinalThreads) {
     CSum o;
     o.hi = part[2 * i];
     o.lo = part[2 * i + 1];
     acc.add(o);
   }
-  wave_csum(acc);
-  if (threadIdx.x == 0) out[0] = acc.value();
+  const CSum t = block_csum(acc, sh);
+  if (threadIdx.x == 0) out[0] = t.value();
 }
 
 __global__ void k_reduce_final_max(const double* __restrict__ part, int np,
@@ -135,7 +137,7 @@ struct Reducer {
     }
     {
       ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-      k_reduce_final_sum<<<1, 64, 0, s>>>(part, kRedBlocks, out + slot);
+      k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(part, kRedBlocks, out + slot);
     }
   }
   void sum(const double* a, int64_t n, int slot) {
@@ -145,7 +147,7 @@ struct Reducer {
     }
     {
       ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-      k_reduce_final_sum<<<1, 64, 0, s>>>(part, kRedBlocks, out + slot);
+      k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(part, kRedBlocks, out + slot);
     }
   }
   void maxabs(const double* a, int64_t n, int slot) {
@@ -313,53 +315,19 @@ __global__ void __launch_bounds__(kT) k_smooth(const int32_t* __restrict__ ptr,
   if (live && sub == 0) xo[p] = xi[p] + sdinv[p] * (b[p] - (diag[p] * xi[p] - off));
 }
 
-// Two Jacobi sweeps from zero in one pass: x1 = sdinv b is formed where it
-// is gathered, xo = x1 + sdinv (b - L x1)
-__global__ void __launch_bounds__(kT) k_smooth_zero2(const int32_t* __restrict__ ptr,
-                                                     const int32_t* __restrict__ nbr,
-                                                     const double* __restrict__ w,
-                                                     const double* __restrict__ diag,
-                                                     const double* __restrict__ sdinv,
-                                                     const double* __restrict__ b, int64_t n,
-                                                     double* __restrict__ xo) {
-  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const int64_t p = g / kNodeLanes;
-  const int sub = (int)(g % kNodeLanes);
-  const bool live = p < n;
-  double s = 0.0;
-  if (live) {
-    const int32_t end = ptr[p + 1];
-    int32_t e = ptr[p] + sub;
-    for (; e + kNodeLanes < end; e += 2 * kNodeLanes) {
-      const int32_t q0 = nbr[e], q1 = nbr[e + kNodeLanes];
-      const double w0 = w[e], w1 = w[e + kNodeLanes];
-      const double a0 = sdinv[q0] * b[q0], a1 = sdinv[q1] * b[q1];
-      s += w0 * a0;
-      s += w1 * a1;
-    }
-    if (e < end) {
-      const int32_t q = nbr[e];
-      s += w[e] * (sdinv[q] * b[q]);
-    }
-  }
-  s += __shfl_xor(s, 1, kWave);
-  s += __shfl_xor(s, 2, kWave);
-  if (live && sub == 0) {
-    const double x1 = sdinv[p] * b[p];
-    xo[p] = x1 + sdinv[p] * (b[p] - (diag[p] * x1 - s));
-  }
-}
 
 
 // Residual and restriction in one pass through the restricted operator:
 // bc[C] = sum_{p in C} b_p + sum_k ra_val[k] x[ra_col[k]], kNodeLanes lanes
 // per coarse node (fixed order: lane-strided partial sums, then a
-// butterfly).
+// butterfly); also the coarse level's first Jacobi sweep from zero,
+// x1 = sdc bc.
 __global__ void __launch_bounds__(kT) k_resid_restrict(
     const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
     const double* __restrict__ b, const int32_t* __restrict__ ra_ptr,
     const int32_t* __restrict__ ra_col, const double* __restrict__ ra_val,
-    const double* __restrict__ x, int64_t nc, double* __restrict__ bc) {
+    const double* __restrict__ x, int64_t nc, const double* __restrict__ sdc,
+    double* __restrict__ bc, double* __restrict__ x1) {
   const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
   const int64_t C = g / kNodeLanes;
   const int sub = (int)(g % kNodeLanes);
@@ -379,7 +347,10 @@ __global__ void __launch_bounds__(kT) k_resid_restrict(
   }
   s += __shfl_xor(s, 1, kWave);
   s += __shfl_xor(s, 2, kWave);
-  if (C < nc && sub == 0) bc[C] = s;
+  if (C < nc && sub == 0) {
+    bc[C] = s;
+    x1[C] = sdc[C] * s;
+  }
 }
 
 // Values of the restricted operator from the level's weights and diagonal.
@@ -1358,13 +1329,14 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   Level& C = H.lv[l + 1];
   const unsigned gl = blocks_for(L.n * kNodeLanes, kT);
   {
-    ::bchar::ProfScope ps_("k_smooth_zero2", s);
-    k_smooth_zero2<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.n, L.x);
+    // the first sweep (x1 = sdinv b, in L.x2) came with the restriction
+    ::bchar::ProfScope ps_("k_smooth", s);
+    k_smooth<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.x2, L.n, L.x);
   }
   {
     ::bchar::ProfScope ps_("k_resid_restrict", s);
     k_resid_restrict<<<blocks_for(C.n * kNodeLanes, kT), kT, 0, s>>>(
-        L.mptr, L.mem, L.b, L.ra_ptr, L.ra_col, L.ra_val, L.x, C.n, C.b);
+        L.mptr, L.mem, L.b, L.ra_ptr, L.ra_col, L.ra_val, L.x, C.n, C.sdinv, C.b, C.x2);
   }
   vcycle(H, l + 1, s);
   {
@@ -1585,8 +1557,10 @@ __global__ void __launch_bounds__(kT) k_zresid(ZCells Z, const double* __restric
 
 // coarse (cell) residual: y-space residual of the rows attached to M and
 // of column M, with r_row = r_s / 2 + r_g and r_col = r_s / 2 - r_g
+// (also the first Jacobi sweep of the cell level from zero, x1 = sdc bc)
 __global__ void k_zrestrict(const int32_t* __restrict__ mptr, const int32_t* __restrict__ mem,
-                            const double* __restrict__ r, int64_t n, double* __restrict__ bc) {
+                            const double* __restrict__ r, int64_t n, const double* __restrict__ sdc,
+                            double* __restrict__ bc, double* __restrict__ x1) {
   const int64_t M = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (M >= n) return;
   double acc = 0;
@@ -1598,6 +1572,7 @@ __global__ void k_zrestrict(const int32_t* __restrict__ mptr, const int32_t* __r
       acc += 0.5 * r[p - n] - r[p];   // r[n + (p - n)] is the g part of cell p - n
   }
   bc[M] = acc;
+  x1[M] = sdc[M] * acc;
 }
 
 // x += P e: row K takes e[best K], column K takes e[K]
@@ -1647,7 +1622,8 @@ static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   Level& L1 = P.H->lv[1];
   {
     ::bchar::ProfScope ps_("k_zrestrict", s);
-    k_zrestrict<<<blocks_for(n, kT), kT, 0, s>>>(L0.mptr, L0.mem, P.res, n, L1.b);
+    k_zrestrict<<<blocks_for(n, kT), kT, 0, s>>>(L0.mptr, L0.mem, P.res, n, L1.sdinv, L1.b,
+                                                  L1.x2);
   }
   vcycle(*P.H, 1, s);
   {
@@ -2306,7 +2282,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, 64, 0, s>>>(zpart, (int)gn, red.out + 9);
+        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(zpart, (int)gn, red.out + 9);
       }
       {
         ::bchar::ProfScope ps_("k_cg_update", s);
@@ -2322,7 +2298,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       if (zprecondition(P, cr, cz, s, zpart)) {
         ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, 64, 0, s>>>(zpart, (int)gn, rz_next);
+        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(zpart, (int)gn, rz_next);
       } else {
         red.dot(cr, cz, n2, (int)(rz_next - red.out));
       }
@@ -2403,7 +2379,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         }
         {
           ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-          k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 4);
+          k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(red.part, kRedBlocks, red.out + 4);
         }
         BCHAR_HIP(hipGetLastError());
         return red.fetch(4);
@@ -2556,7 +2532,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 0);
+        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(red.part, kRedBlocks, red.out + 0);
       }
       {
         ::bchar::ProfScope ps_("k_ipm_h", s);
@@ -2631,7 +2607,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, 64, 0, s>>>(red.part, kRedBlocks, red.out + 4);
+        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(red.part, kRedBlocks, red.out + 4);
       }
       const double mua = red.fetch(4) / m_pairs;
       const double sig = std::pow(std::max(mua, 0.0) / mu, 3.0);
