@@ -113,6 +113,75 @@ def copy_calibration(mib):
                       "launches": 3}))
 
 
+TRAFFIC_KERNELS = ("k_fused_cycle", "k_zsmooth", "k_assemble")
+
+
+def pmc_summary(prof_dir, counter, out):
+    """Sum one rocprofv3 --pmc counter (CSV output under ``prof_dir``) per
+    dispatch of the kernels whose traffic bench.py reports and of the
+    device copy used for calibration; write the per-dispatch means (KiB)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(prof_dir, "**", "*counter_collection*.csv"), recursive=True)
+    tot = {}
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                name = r.get("Kernel_Name", "")
+                key = next((k for k in TRAFFIC_KERNELS if k in name), None)
+                if key is None and "copy" in name.lower():
+                    key = "copy: " + name[:80]
+                if key is None:
+                    continue
+                d = tot.setdefault(key, {"dispatches": set(), "sum": 0.0})
+                d["dispatches"].add(r.get("Dispatch_Id"))
+                d["sum"] += float(r["Counter_Value"])
+    res = {k: {"dispatches": len(v["dispatches"]),
+               "kib_per_dispatch": v["sum"] / max(1, len(v["dispatches"]))} for k, v in tot.items()}
+    with open(out, "w") as fh:
+        json.dump({"counter": counter, "kernels": res}, fh, indent=1)
+    print(json.dumps(res))
+
+
+def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, workload):
+    """profiles/traffic_<kernel>.json from the four counter summaries: the
+    kernel's FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    same counter reads for a plain device copy of copy_mib MiB (read once,
+    written once)."""
+    def load(p):
+        with open(p) as fh:
+            return json.load(fh)["kernels"]
+    f, w, cf, cw = load(fetch), load(write), load(copy_fetch), load(copy_write)
+    copy_kib = copy_mib * 1024.0
+
+    def copy_of(d):
+        # the device copy: the copy kernel moving the most data
+        return max((v for k, v in d.items() if k.startswith("copy")),
+                   key=lambda v: v["kib_per_dispatch"])
+    ccf, ccw = copy_of(cf), copy_of(cw)
+    ff = copy_kib / ccf["kib_per_dispatch"]
+    wf = copy_kib / ccw["kib_per_dispatch"]
+    for k in TRAFFIC_KERNELS:
+        if k not in f or k not in w:
+            continue
+        rec = {"kernel": k, "workload": workload, "commands": commands,
+               "dispatches": f[k]["dispatches"],
+               "fetch_kib_per_dispatch": f[k]["kib_per_dispatch"],
+               "write_kib_per_dispatch": w[k]["kib_per_dispatch"],
+               "copy_calibration": {"copy_kib": copy_kib,
+                                    "fetch_kib_per_dispatch": ccf["kib_per_dispatch"],
+                                    "write_kib_per_dispatch": ccw["kib_per_dispatch"],
+                                    "fetch_factor": ff, "write_factor": wf},
+               "bytes_per_launch": 1024.0 * (f[k]["kib_per_dispatch"] * ff +
+                                             w[k]["kib_per_dispatch"] * wf),
+               "source_digest": source_digest()}
+        with open(os.path.join(ROOT, "profiles", f"traffic_{k}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(k, rec["bytes_per_launch"])
+
+
 def cpu_baseline(sample_n=16):
     """The oracle timed on the host: one full time step (build + apply) of
     the same swirl workload on a reduced sample_n^3 mesh, one thread."""
@@ -256,6 +325,7 @@ def main():
                     help="transfers built at once on separate streams (1: one after another)")
     ap.add_argument("--roofline-kernel", default="k_fused_cycle")
     ap.add_argument("--build-kernel", default="k_assemble")
+    ap.add_argument("--smoother-kernel", default="k_zsmooth")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -263,7 +333,27 @@ def main():
     ap.add_argument("--workload", choices=["swirl", "mixed"], default="swirl")
     ap.add_argument("--problems", type=int, default=32,
                     help="mixed workload: number of problems (seeds 0 .. problems-1)")
+    ap.add_argument("--pmc-sum", nargs=3, metavar=("PROF_DIR", "COUNTER", "OUT"),
+                    help="only summarise a rocprofv3 --pmc run (no device work)")
+    ap.add_argument("--traffic-json", nargs=5,
+                    metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "COPY_MIB"),
+                    help="only write profiles/traffic_<kernel>.json from four summaries")
     args = ap.parse_args()
+
+    if args.pmc_sum:
+        pmc_summary(*args.pmc_sum)
+        return
+    if args.traffic_json:
+        fe, wr, cfe, cwr, mib = args.traffic_json
+        cmd = "rocprofv3 --pmc {c} --output-format csv -d /tmp/pmc_{t} -o p -- python3 bench.py {a}"
+        run = "--steps 1 --warmup 1 --inflight 1 --no-cpu-baseline"
+        write_traffic(fe, wr, cfe, cwr, int(mib),
+                      [cmd.format(c="FETCH_SIZE", t="f", a=run),
+                       cmd.format(c="WRITE_SIZE", t="w", a=run),
+                       cmd.format(c="FETCH_SIZE", t="cf", a=f"--copy-calibration {mib}"),
+                       cmd.format(c="WRITE_SIZE", t="cw", a=f"--copy-calibration {mib}")],
+                      "3D swirl, 64^3 hexahedra, 8 balls per cell, FP64")
+        return
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -390,11 +480,16 @@ def main():
         launches, kms = bchar.profile_read()
         bchar.profile_kernel(None)
         T_last = T
-    # the build kernel, timed the same way over one more (untimed) build
+    # the build kernel and the fine-level smoother, timed the same way over
+    # one more (untimed) build each
     bchar.profile_kernel(args.build_kernel)
     T_last.rebuild(vels[0], w["dt"], opts)
     torch.cuda.synchronize()
     b_launches, b_kms = bchar.profile_read()
+    bchar.profile_kernel(args.smoother_kernel)
+    T_last.rebuild(vels[1], w["dt"], opts)
+    torch.cuda.synchronize()
+    z_launches, z_kms = bchar.profile_read()
     bchar.profile_kernel(None)
 
     n_cells = M.n_cells
@@ -415,6 +510,7 @@ def main():
 
     roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
     roof_build = roofline(args.build_kernel, b_launches, b_kms, T_last.stats)
+    roof_smoother = roofline(args.smoother_kernel, z_launches, z_kms, T_last.stats)
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency",
@@ -444,6 +540,7 @@ def main():
                        "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in seq_stats]))},
         "roofline": roof,
         "roofline_build": roof_build,
+        "roofline_smoother": roof_smoother,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
