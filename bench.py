@@ -46,6 +46,12 @@ def log(msg):
 def algorithmic_bytes(kernel, n_cells, nnz, n_balls, stats):
     """Bytes a launch of ``kernel`` must move at least (each array read or
     written once; gathers of vector entries counted once per cell)."""
+    if kernel == "k_smooth":
+        # one Jacobi sweep of a launched multigrid level (row pointers,
+        # neighbours and weights, diagonal, smoother step, right-hand side
+        # and iterate in, iterate out), mean over the sweeps of one cycle,
+        # as counted by the library for the last solve
+        return stats["qp_smooth_bytes"]
     if kernel == "k_fused_cycle":
         # the coarsest levels of the preconditioner, one workgroup: their
         # graphs, diagonals, right-hand sides, aggregation and the dense
@@ -113,7 +119,13 @@ def copy_calibration(mib):
                       "launches": 3}))
 
 
-TRAFFIC_KERNELS = ("k_fused_cycle", "k_zsmooth", "k_assemble")
+TRAFFIC_KERNELS = ("k_smooth", "k_fused_cycle", "k_zsmooth", "k_assemble")
+
+
+def kernel_base_name(name):
+    """'void bchar::k_assemble<3, double, true>(bchar::AsmParams)' -> 'k_assemble'."""
+    base = name.split("(")[0].split("<")[0].strip()
+    return base.split("::")[-1].split(" ")[-1]
 
 
 def pmc_summary(prof_dir, counter, out):
@@ -130,7 +142,8 @@ def pmc_summary(prof_dir, counter, out):
                 if r.get("Counter_Name") != counter:
                     continue
                 name = r.get("Kernel_Name", "")
-                key = next((k for k in TRAFFIC_KERNELS if k in name), None)
+                base = kernel_base_name(name)
+                key = base if base in TRAFFIC_KERNELS else None
                 if key is None and "copy" in name.lower():
                     key = "copy: " + name[:80]
                 if key is None:
@@ -323,9 +336,10 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--inflight", type=int, default=4,
                     help="transfers built at once on separate streams (1: one after another)")
-    ap.add_argument("--roofline-kernel", default="k_fused_cycle")
+    ap.add_argument("--roofline-kernel", default="k_smooth")
     ap.add_argument("--build-kernel", default="k_assemble")
     ap.add_argument("--smoother-kernel", default="k_zsmooth")
+    ap.add_argument("--coarse-kernel", default="k_fused_cycle")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -490,6 +504,11 @@ def main():
     T_last.rebuild(vels[1], w["dt"], opts)
     torch.cuda.synchronize()
     z_launches, z_kms = bchar.profile_read()
+    z_stats = T_last.stats
+    bchar.profile_kernel(args.coarse_kernel)
+    T_last.rebuild(vels[2], w["dt"], opts)
+    torch.cuda.synchronize()
+    c_launches, c_kms = bchar.profile_read()
     bchar.profile_kernel(None)
 
     n_cells = M.n_cells
@@ -510,7 +529,8 @@ def main():
 
     roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
     roof_build = roofline(args.build_kernel, b_launches, b_kms, T_last.stats)
-    roof_smoother = roofline(args.smoother_kernel, z_launches, z_kms, T_last.stats)
+    roof_smoother = roofline(args.smoother_kernel, z_launches, z_kms, z_stats)
+    roof_coarse = roofline(args.coarse_kernel, c_launches, c_kms, T_last.stats)
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency",
@@ -541,6 +561,7 @@ def main():
         "roofline": roof,
         "roofline_build": roof_build,
         "roofline_smoother": roof_smoother,
+        "roofline_coarse": roof_coarse,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -172,6 +172,9 @@ typedef struct {
   int64_t qp_coarse_bytes;     /* bytes one cycle over the coarsest levels
                                   of the preconditioner (one workgroup)
                                   reads or writes at least              */
+  int64_t qp_smooth_bytes;     /* bytes one Jacobi sweep of a launched
+                                  multigrid level reads or writes at least,
+                                  mean over the sweeps of one cycle       */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */

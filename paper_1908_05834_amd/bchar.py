@@ -63,7 +63,8 @@ class Stats(C.Structure):
                 ("first_void", C.c_int64), ("scaling_max_col_err", C.c_double),
                 ("qp_residual", C.c_double), ("qp_level", C.c_int), ("qp_newton", C.c_int),
                 ("qp_cg", C.c_int), ("n_at_lower", C.c_int64), ("n_at_upper", C.c_int64),
-                ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64)]
+                ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64),
+                ("qp_smooth_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -335,6 +335,7 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   st.qp_cg = qr.cg;
   st.qp_ipm = qr.ipm;
   st.qp_coarse_bytes = qr.coarse_bytes;
+  st.qp_smooth_bytes = qr.smooth_bytes;
   st.qp_residual = qr.residual;
   st.n_at_lower = qr.at_lower;
   st.n_at_upper = qr.at_upper;

@@ -196,6 +196,8 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
 struct QpResult {
   int level = 0, newton = 0, cg = 0, ipm = 0;
   int64_t coarse_bytes = 0;   // bytes one coarse-level cycle moves at least
+  int64_t smooth_bytes = 0;   // bytes a launched-level sweep moves at least, mean
+                              // over the sweeps of one cycle
   double residual = 0;
   int64_t at_lower = 0, at_upper = 0;
 };

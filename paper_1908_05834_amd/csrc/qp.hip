@@ -987,7 +987,8 @@ struct Hierarchy {
   size_t fused_first = 0;          // first level handled by k_fused_cycle
   FusedLevels* fused = nullptr;    // device copy
   bool fused_img = false;          // it has an LDS image to refresh
-  int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least once
+  int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least
+  int64_t smooth_bytes = 0;        // bytes of a launched-level sweep, mean per launch once
 };
 
 static void level_refresh_diag(Level& L, double mu, hipStream_t s) {
@@ -1200,6 +1201,14 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
   H.fused_first = first;
   // the launched levels restrict their residual through R L
   for (size_t l = 1; l < first; ++l) ra_pattern(H.lv[l], H.lv[l + 1].n, ws, s);
+  // one sweep (k_smooth) of level l reads the row pointers, neighbours and
+  // weights, the diagonal, smoother step, right-hand side and iterate, and
+  // writes the new iterate: 44 n + 12 ne bytes; two sweeps a level a cycle
+  H.smooth_bytes = 0;
+  if (first > 1) {
+    for (size_t l = 1; l < first; ++l) H.smooth_bytes += 44 * H.lv[l].n + 12 * H.lv[l].ne;
+    H.smooth_bytes /= (int64_t)(first - 1);
+  }
   FusedLevels hf{};
   hf.count = (int)(H.lv.size() - first);
   hf.dense = H.dense ? 1 : 0;
@@ -2226,6 +2235,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   const double tol = o.qp_tol;
   res = QpResult{};
   res.coarse_bytes = H.fused_bytes;
+  res.smooth_bytes = H.smooth_bytes;
 
   // Newton matrix values: per-cell blocks and every level of the hierarchy,
   // from the fine weights in L0.w
