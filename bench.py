@@ -410,7 +410,7 @@ def main():
     pipe_first = max(0, args.warmup - warm_batches * D)
     pipe_total = pipe_first + (warm_batches + timed_batches) * D if D > 1 else 0
     vels = [bchar.VelocityLattice(w["vel_fn"](s % w["steps"]))
-            for s in range(max(seq_total, pipe_total))]
+            for s in range(max(seq_total, pipe_total, 3))]
     c0 = torch.as_tensor(w["c0"], device=dev)
     m0 = M.mass(c0)
     mass_err = 0.0
