@@ -471,7 +471,10 @@ def main():
         for _ in range(warm_batches):
             batch(False)
         torch.cuda.synchronize()
-        bchar.profile_kernel(args.roofline_kernel)
+        # every 17th launch: the events barely disturb the run, and as 17 is
+        # prime the sample runs through the levels of a cycle (unless a cycle
+        # launches the kernel a multiple of 17 times)
+        bchar.profile_kernel_sampled(args.roofline_kernel, 17)
         t0 = time.perf_counter()
         for b in range(timed_batches):
             batch(True)

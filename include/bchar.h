@@ -302,6 +302,12 @@ bchar_status bchar_transfer_export_qp(bchar_transfer t, double* x, double* mu, d
  * benchmarks; a kernel that is not being timed pays nothing.            */
 bchar_status bchar_profile_kernel(const char* name);
 
+/* As bchar_profile_kernel, but time only every `every`-th launch of the
+ * kernel (every >= 1), so that a kernel launched very often can be timed
+ * with little disturbance; bchar_profile_read then counts the timed
+ * launches only.  Errors: INVALID_ARG (every < 1).                      */
+bchar_status bchar_profile_kernel_sampled(const char* name, int every);
+
 /* Launches timed since bchar_profile_kernel and their summed duration in
  * milliseconds (waits for the recorded events).                         */
 bchar_status bchar_profile_read(int64_t* launches, double* total_ms);

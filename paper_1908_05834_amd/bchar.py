@@ -104,6 +104,7 @@ _export_tracked = _sig("bchar_transfer_export_tracked", [_P, _P, _P])
 _export_qp = _sig("bchar_transfer_export_qp", [_P, _P, _P, _P])
 _export_balls = _sig("bchar_mesh_export_balls", [_P, _P, _P, _P])
 _profile_kernel = _sig("bchar_profile_kernel", [C.c_char_p])
+_profile_kernel_sampled = _sig("bchar_profile_kernel_sampled", [C.c_char_p, C.c_int])
 
 
 class BuildJob(C.Structure):
@@ -123,7 +124,7 @@ EXPORTED = [
     "bchar_last_error", "bchar_transfer_info", "bchar_transfer_export_csr",
     "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
     "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
-    "bchar_build_transfer_batch",
+    "bchar_build_transfer_batch", "bchar_profile_kernel_sampled",
 ]
 
 
@@ -159,6 +160,11 @@ def _dptr(t):
 def profile_kernel(name):
     """Time every later launch of kernel ``name`` with HIP events (None: off)."""
     _check(_profile_kernel(name.encode() if name else None))
+
+
+def profile_kernel_sampled(name, every):
+    """Time every ``every``-th launch of kernel ``name`` (None: off)."""
+    _check(_profile_kernel_sampled(name.encode() if name else None, int(every)))
 
 
 def profile_read():

@@ -277,6 +277,8 @@ namespace {
 struct ProfState {
   std::mutex mu;
   std::string target;     // kernel name being timed ("" = off)
+  int64_t every = 1;      // time every `every`-th launch of it
+  int64_t seen = 0;       // launches of it seen
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<hipEvent_t> free_events;
   int64_t launches = 0;
@@ -314,6 +316,7 @@ ProfScope::ProfScope(const char* name, hipStream_t st) : slot(-1), s(st) {
   ProfState& p = prof();
   if (p.target.empty() || p.target != name) return;
   std::lock_guard<std::mutex> g(p.mu);
+  if ((p.seen++ % p.every) != 0) return;
   hipEvent_t a = take_event(p), b = take_event(p);
   BCHAR_HIP(hipEventRecord(a, s));
   p.pending.push_back({a, b});
@@ -329,12 +332,18 @@ ProfScope::~ProfScope() {
 
 }  // namespace bchar
 
-extern "C" bchar_status bchar_profile_kernel(const char* name) {
+extern "C" bchar_status bchar_profile_kernel_sampled(const char* name, int every) {
+  if (every < 1) {
+    bchar::set_error("every must be >= 1");
+    return BCHAR_E_INVALID_ARG;
+  }
   try {
     bchar::ProfState& p = bchar::prof();
     std::lock_guard<std::mutex> g(p.mu);
     bchar::drain(p);
     p.target = name ? name : "";
+    p.every = every;
+    p.seen = 0;
     p.launches = 0;
     p.total_ms = 0;
     return BCHAR_OK;
@@ -342,6 +351,10 @@ extern "C" bchar_status bchar_profile_kernel(const char* name) {
     bchar::set_error(e.msg);
     return e.status;
   }
+}
+
+extern "C" bchar_status bchar_profile_kernel(const char* name) {
+  return bchar_profile_kernel_sampled(name, 1);
 }
 
 extern "C" bchar_status bchar_profile_read(int64_t* launches, double* total_ms) {
