@@ -327,6 +327,114 @@ def bench_mixed(args):
     print(json.dumps(out))
 
 
+def bench_serve(args):
+    """Requests arriving as a Poisson process (seeded) at ``--rate`` per
+    second: each takes a problem from a pool of ``--problems`` resident
+    meshes (inputs.mixed_problem), builds its transfer and applies it a
+    number of times drawn from U{1..50}; the server (bchar_server_*) runs
+    them with ``--inflight`` workers, then with one (the serial path) on the
+    same arrivals.  Reports cell-updates/s and the latency from arrival to
+    result (p50, p99)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1908_05834_amd import bchar, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    D = max(1, args.inflight)
+    pool = []
+    for p in range(args.problems):
+        q = inputs.mixed_problem(p)
+        M = bchar.Mesh(q["mesh"], q["layout"])
+        c0 = torch.as_tensor(q["c0"], device="cuda")
+        pool.append({"M": M, "U": bchar.VelocityLattice(q["vel"]), "dt": q["dt"], "c0": c0,
+                     "m0": M.mass(c0), "name": q["name"]})
+    rng = np.random.default_rng(args.seed)
+    gaps = rng.exponential(1.0 / args.rate, size=args.requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    which = rng.integers(0, len(pool), size=args.requests)
+    nsteps = rng.integers(1, 51, size=args.requests)
+
+    def run(workers, label):
+        srv = bchar.Server(workers, mem_budget=int(args.mem_budget_gib * (1 << 30)))
+        # warm-up: every pool problem once (worker buffers reach their size)
+        for q in pool:
+            out, tmp = torch.empty_like(q["c0"]), torch.empty_like(q["c0"])
+            srv.wait(srv.submit(q["M"], q["U"], q["dt"], 1, q["c0"], out, tmp))
+        results = [None] * args.requests
+        tickets = [None] * args.requests
+        bufs = [None] * args.requests
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for i in range(args.requests):
+                ready.acquire()
+                results[i] = srv.wait(tickets[i])
+                q = pool[which[i]]
+                m = q["M"].mass(bufs[i][0])
+                results[i]["mass_err"] = abs(m - q["m0"]) / abs(q["m0"])
+                bufs[i] = None
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(args.requests):
+            dly = t0 + arrivals[i] - time.perf_counter()
+            if dly > 0:
+                time.sleep(dly)
+            q = pool[which[i]]
+            out, tmp = torch.empty_like(q["c0"]), torch.empty_like(q["c0"])
+            bufs[i] = (out, tmp)
+            tickets[i] = srv.submit(q["M"], q["U"], q["dt"], int(nsteps[i]), q["c0"], out, tmp)
+            ready.release()
+            if i % 25 == 24:
+                log(f"  {label}: {i + 1} requests submitted at {time.perf_counter() - t0:.1f} s")
+        th.join()
+        srv.close()
+        ok = all(r["status"] == bchar.OK for r in results)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in results])
+        span = max(r["t_done"] for r in results) - min(r["t_submit"] for r in results)
+        cu = sum(pool[which[i]]["M"].n_cells * int(nsteps[i]) for i in range(args.requests))
+        merr = max(r["mass_err"] for r in results)
+        log(f"{label}: {span:.2f} s, p50 {np.percentile(lat, 50) * 1e3:.0f} ms, "
+            f"p99 {np.percentile(lat, 99) * 1e3:.0f} ms")
+        return {"value": cu / span, "seconds": span, "ok": ok, "mass_err": merr,
+                "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+                "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
+
+    par = run(D, f"{D} workers")
+    ser = run(1, "1 worker")
+    out = {
+        "metric": "B-char served cell-updates/s and p99 latency (arrival to result)",
+        "value": par["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": len(pool),
+        "ms_per_step": par["seconds"] / args.requests * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests, Poisson arrivals at {args.rate}/s "
+                               f"(seed {args.seed}), problems drawn from {len(pool)} resident "
+                               "meshes of the batch of independent problems, U{1..50} "
+                               "updates each",
+                   "workers": D, "mem_budget_gib": args.mem_budget_gib,
+                   "latency_ms_p50": par["latency_ms_p50"],
+                   "latency_ms_p99": par["latency_ms_p99"]},
+        "mass_ok": bool(par["ok"] and ser["ok"] and max(par["mass_err"], ser["mass_err"]) <= 1e-12),
+        "max_rel_mass_err": max(par["mass_err"], ser["mass_err"]),
+        "serial": ser,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,7 +452,12 @@ def main():
                     help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--workload", choices=["swirl", "mixed"], default="swirl")
+    ap.add_argument("--workload", choices=["swirl", "mixed", "serve"], default="swirl")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
+    ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
+    ap.add_argument("--seed", type=int, default=0, help="serve: arrival seed")
+    ap.add_argument("--mem-budget-gib", type=float, default=64.0,
+                    help="serve: device memory the requests in progress may take")
     ap.add_argument("--problems", type=int, default=32,
                     help="mixed workload: number of problems (seeds 0 .. problems-1)")
     ap.add_argument("--pmc-sum", nargs=3, metavar=("PROF_DIR", "COUNTER", "OUT"),
@@ -383,6 +496,9 @@ def main():
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(q, 32))
     if args.workload == "mixed":
         bench_mixed(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import numpy as np

@@ -259,6 +259,58 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
                                         const bchar_opts* opts, void* const* streams,
                                         int n_streams);
 
+/* ---- serving: a queue of independent requests ---------------------- */
+
+typedef struct bchar_server_s* bchar_server;
+
+/* One request: build the transfer of one time step dt of `mesh` with
+ * velocity u and apply it `steps` times to c_in; the result is written to
+ * c_out.  c_in, c_out and c_tmp are device arrays of n_cells binary64
+ * values that must not overlap; c_tmp (scratch) may be NULL when steps
+ * is 1; c_in is not written.  Everything the request points to must stay
+ * valid until the request has been waited for.                         */
+typedef struct {
+  bchar_mesh mesh;
+  const bchar_velocity* u;
+  double dt;
+  int steps;                   /* >= 1                                   */
+  const double* c_in;
+  double* c_out;
+  double* c_tmp;
+  int64_t bytes;               /* device memory the request may take
+                                  (admission); 0: 900 bytes per ball    */
+} bchar_request;
+
+typedef struct {
+  bchar_status status;         /* of the build (BCHAR_OK: c_out written) */
+  bchar_stats stats;
+  double t_submit, t_start, t_done;  /* host steady-clock seconds        */
+} bchar_request_result;
+
+/* A server with n_workers worker threads, worker w on streams[w] with a
+ * transfer of its own that every request it takes rebuilds (no device
+ * allocation once the largest request has been seen).  Requests are taken
+ * in submission order; the oldest waiting request starts only when the
+ * sum of `bytes` of the requests in progress plus its own stays within
+ * mem_budget bytes (0: no limit; a request larger than the budget runs
+ * alone).  Errors: INVALID_ARG.                                         */
+bchar_status bchar_server_create(int n_workers, void* const* streams, int64_t mem_budget,
+                                 const bchar_opts* opts, bchar_server* out);
+
+/* Queue a request (copied); *ticket identifies it.  Never blocks on the
+ * device.  Errors: INVALID_ARG (NULL pointers, steps < 1, c_tmp NULL with
+ * steps > 1, a server being destroyed).                                */
+bchar_status bchar_server_submit(bchar_server srv, const bchar_request* req, int64_t* ticket);
+
+/* Wait until request `ticket` has ended (its c_out is then final) and
+ * fill *res; a ticket can be waited for once.  Errors: INVALID_ARG
+ * (unknown ticket).                                                     */
+bchar_status bchar_server_wait(bchar_server srv, int64_t ticket, bchar_request_result* res);
+
+/* Finish the queued requests, stop the workers and free the server (the
+ * results not yet waited for are dropped).  NULL is a no-op.            */
+bchar_status bchar_server_destroy(bchar_server srv);
+
 /* One update (Sec. 2, eq. phys-inter-ELLAM): c_out = diag(|K|_phi)^-1 A c_in.
  * c_in, c_out: device, n_cells binary64 each, must not overlap.  Needs a
  * transfer built to BCHAR_STAGE_ALL.  Asynchronous on `stream`.         */

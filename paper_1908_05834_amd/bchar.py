@@ -113,6 +113,24 @@ class BuildJob(C.Structure):
                 ("stats", Stats)]
 
 
+class Request(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("u", C.POINTER(Velocity)), ("dt", C.c_double),
+                ("steps", C.c_int), ("c_in", C.c_void_p), ("c_out", C.c_void_p),
+                ("c_tmp", C.c_void_p), ("bytes", C.c_int64)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("stats", Stats), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+_server_create = _sig("bchar_server_create", [C.c_int, C.POINTER(C.c_void_p), C.c_int64,
+                                              C.POINTER(Opts), C.POINTER(C.c_void_p)])
+_server_submit = _sig("bchar_server_submit", [C.c_void_p, C.POINTER(Request),
+                                              C.POINTER(C.c_int64)])
+_server_wait = _sig("bchar_server_wait", [C.c_void_p, C.c_int64, C.POINTER(RequestResult)])
+_server_destroy = _sig("bchar_server_destroy", [C.c_void_p])
+
 _build_batch = _sig("bchar_build_transfer_batch", [C.POINTER(BuildJob), C.c_int, C.POINTER(Opts),
                                                    C.POINTER(C.c_void_p), C.c_int])
 _profile_read = _sig("bchar_profile_read", [_i64p, C.POINTER(C.c_double)])
@@ -125,6 +143,7 @@ EXPORTED = [
     "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
     "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
     "bchar_build_transfer_batch", "bchar_profile_kernel_sampled",
+    "bchar_server_create", "bchar_server_submit", "bchar_server_wait", "bchar_server_destroy",
 ]
 
 
@@ -405,3 +424,55 @@ def build_batch(jobs, opts=None, streams=None, check=True):
         return out, [arr[i].status for i in range(len(jobs))]
     _check(rc)
     return out
+
+
+class Server:
+    """A queue of independent requests (bchar_server_*): each request builds
+    the transfer of one step on a resident mesh and applies it ``steps``
+    times; ``workers`` host threads, each on its own stream."""
+
+    def __init__(self, workers, mem_budget=0, opts=None, streams=None):
+        import torch
+        self.streams = streams or [torch.cuda.Stream() for _ in range(workers)]
+        sp = (C.c_void_p * len(self.streams))(*[_stream_ptr(s).value for s in self.streams])
+        o = opts if opts is not None else opts_default()
+        h = C.c_void_p()
+        _check(_server_create(len(self.streams), sp, int(mem_budget), C.byref(o), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, mesh, velocity, dt, steps, c_in, c_out, c_tmp=None, nbytes=0):
+        """Queue a request; the tensors must stay alive until ``wait``."""
+        r = Request()
+        r.mesh = _handle_value(mesh.handle)
+        r.u = C.pointer(velocity.struct)
+        r.dt = float(dt)
+        r.steps = int(steps)
+        r.c_in = c_in.data_ptr()
+        r.c_out = c_out.data_ptr()
+        r.c_tmp = c_tmp.data_ptr() if c_tmp is not None else None
+        r.bytes = int(nbytes)
+        t = C.c_int64()
+        _check(_server_submit(self.handle, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (velocity, c_in, c_out, c_tmp)
+        return t.value
+
+    def wait(self, ticket):
+        """Block until the request ended: its status, stats and the host
+        clock at submission, start and end (seconds)."""
+        res = RequestResult()
+        _check(_server_wait(self.handle, int(ticket), C.byref(res)))
+        self._keep.pop(ticket, None)
+        return {"status": res.status, "stats": res.stats.as_dict(), "t_submit": res.t_submit,
+                "t_start": res.t_start, "t_done": res.t_done}
+
+    def close(self):
+        if self.handle:
+            _server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

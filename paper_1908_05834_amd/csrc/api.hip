@@ -4,6 +4,10 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -372,6 +376,83 @@ bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- serving
+
+struct bchar_server_s {
+  struct Item {
+    bchar_request req;
+    int64_t bytes = 0;
+    bool done = false;
+    bchar_request_result res{};
+  };
+  int dev = 0;
+  bchar_opts opts{};
+  int64_t budget = 0, in_use = 0;
+  int running = 0;                       // requests in progress
+  std::vector<hipStream_t> streams;
+  std::vector<bchar_transfer_s*> transfers;   // one per worker, rebuilt per request
+  std::mutex mu;
+  std::condition_variable cv;            // queue, memory and completions
+  std::deque<int64_t> queue;             // tickets waiting, in submission order
+  std::map<int64_t, Item> items;
+  int64_t next_ticket = 1;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+
+  void work(int w) {
+    (void)hipSetDevice(dev);
+    bchar_transfer_s* t = transfers[w];
+    hipStream_t s = streams[w];
+    for (;;) {
+      int64_t ticket = 0;
+      Item* it = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        // the oldest request starts once its bytes fit beside the running
+        // ones (alone if it does not fit at all)
+        cv.wait(lk, [&] {
+          if (queue.empty()) return stopping;
+          const Item& head = items[queue.front()];
+          return running == 0 || budget == 0 || in_use + head.bytes <= budget;
+        });
+        if (queue.empty()) return;
+        ticket = queue.front();
+        queue.pop_front();
+        it = &items[ticket];
+        in_use += it->bytes;
+        ++running;
+        it->res.t_start = bchar::wall_seconds();
+      }
+      const bchar_request& r = it->req;
+      bchar_status st = guarded([&]() -> bchar_status {
+        // the transfer follows the request's mesh; a multiplier warm start
+        // from another problem would be meaningless
+        t->mesh = r.mesh;
+        t->warm_level = -1;
+        bchar_status rc = do_build(r.mesh, t, r.u, r.dt, opts, s, &it->res.stats);
+        if (rc != BCHAR_OK) return rc;
+        const double* src = r.c_in;
+        for (int i = 0; i < r.steps; ++i) {
+          double* dst = ((r.steps - 1 - i) % 2 == 0) ? r.c_out : r.c_tmp;
+          bchar::apply_transfer(t, src, dst, s);
+          src = dst;
+        }
+        BCHAR_HIP(hipStreamSynchronize(s));
+        return BCHAR_OK;
+      });
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        it->res.status = st;
+        it->res.t_done = bchar::wall_seconds();
+        it->done = true;
+        in_use -= it->bytes;
+        --running;
+      }
+      cv.notify_all();
+    }
+  }
+};
 
 extern "C" {
 
@@ -874,6 +955,78 @@ bchar_status bchar_mesh_export_balls(bchar_mesh m, double* centres, double* radi
       for (int64_t b = 0; b < m->n_balls; ++b) cell[b] = (int32_t)(b / m->nbpc);
     return BCHAR_OK;
   });
+}
+
+bchar_status bchar_server_create(int n_workers, void* const* streams, int64_t mem_budget,
+                                 const bchar_opts* opts, bchar_server* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(out != nullptr && streams != nullptr && n_workers >= 1 && mem_budget >= 0,
+                  BCHAR_E_INVALID_ARG, "NULL argument, n_workers < 1 or mem_budget < 0");
+    auto* srv = new bchar_server_s();
+    opts_or_default(opts, srv->opts);
+    validate_opts(srv->opts);
+    BCHAR_HIP(hipGetDevice(&srv->dev));
+    srv->budget = mem_budget;
+    for (int w = 0; w < n_workers; ++w) {
+      srv->streams.push_back(as_stream(streams[w]));
+      srv->transfers.push_back(new bchar_transfer_s());
+    }
+    for (int w = 0; w < n_workers; ++w) srv->workers.emplace_back(&bchar_server_s::work, srv, w);
+    *out = srv;
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_server_submit(bchar_server srv, const bchar_request* req, int64_t* ticket) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(srv != nullptr && req != nullptr && ticket != nullptr, BCHAR_E_INVALID_ARG,
+                  "NULL argument");
+    BCHAR_REQUIRE(req->mesh != nullptr && req->u != nullptr && req->c_in != nullptr &&
+                      req->c_out != nullptr && req->steps >= 1 &&
+                      (req->steps == 1 || req->c_tmp != nullptr),
+                  BCHAR_E_INVALID_ARG, "request: NULL pointer, steps < 1 or no c_tmp");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    BCHAR_REQUIRE(!srv->stopping, BCHAR_E_INVALID_ARG, "server is being destroyed");
+    const int64_t id = srv->next_ticket++;
+    bchar_server_s::Item& it = srv->items[id];
+    it.req = *req;
+    it.bytes = req->bytes > 0 ? req->bytes : 900 * req->mesh->n_balls;
+    it.res.t_submit = bchar::wall_seconds();
+    srv->queue.push_back(id);
+    *ticket = id;
+    srv->cv.notify_all();
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_server_wait(bchar_server srv, int64_t ticket, bchar_request_result* res) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(srv != nullptr && res != nullptr, BCHAR_E_INVALID_ARG, "NULL argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto f = srv->items.find(ticket);
+    BCHAR_REQUIRE(f != srv->items.end(), BCHAR_E_INVALID_ARG, "unknown ticket");
+    srv->cv.wait(lk, [&] { return f->second.done; });
+    *res = f->second.res;
+    srv->items.erase(f);
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_server_destroy(bchar_server srv) {
+  if (!srv) return BCHAR_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+  }
+  srv->cv.notify_all();
+  for (auto& th : srv->workers) th.join();
+  for (auto* t : srv->transfers) {
+    transfer_free(t);
+    delete t;
+  }
+  delete srv;
+  return BCHAR_OK;
 }
 
 }  // extern "C"

@@ -55,3 +55,18 @@ def test_batch_build_rejects_bad_arguments_without_device():
     jobs[0].transfer = jobs[1].transfer = 0x1000
     assert bchar._build_batch(jobs, 2, C.byref(o), streams, 1) == bchar.E_INVALID_ARG
     assert b"two jobs" in bchar._last_error()
+
+
+def test_server_rejects_bad_arguments_without_device():
+    import ctypes as C
+
+    from paper_1908_05834_amd import bchar
+    h = C.c_void_p()
+    streams = (C.c_void_p * 1)(None)
+    # no streams, no workers, negative budget: refused before any device work
+    assert bchar._server_create(1, None, 0, None, C.byref(h)) == bchar.E_INVALID_ARG
+    assert bchar._server_create(0, streams, 0, None, C.byref(h)) == bchar.E_INVALID_ARG
+    assert bchar._server_create(1, streams, -1, None, C.byref(h)) == bchar.E_INVALID_ARG
+    t = C.c_int64()
+    assert bchar._server_submit(None, None, C.byref(t)) == bchar.E_INVALID_ARG
+    assert bchar._server_destroy(None) == bchar.OK

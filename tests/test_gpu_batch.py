@@ -111,3 +111,38 @@ def test_batch_reports_the_failed_job(env):
         bchar.build_batch(jobs, streams=[torch.cuda.Stream()])
     assert ei.value.status == bchar.E_INVALID_ARG
     assert "job 1" in str(ei.value)
+
+
+def test_server_requests_equal_runs_alone(env):
+    torch, bchar = env
+    probs = _problems(bchar)
+    steps = [3, 1, 4]
+    g = torch.Generator().manual_seed(7)
+    c0s = [torch.rand(m.n_cells, dtype=torch.float64, generator=g).cuda() for m, _, _ in probs]
+    want = []
+    for (m, v, dt), k, c0 in zip(probs, steps, c0s):
+        T = bchar.Transfer.build(m, v, dt)
+        c, nxt = c0.clone(), torch.empty_like(c0)
+        for _ in range(k):
+            T.step(c, nxt)
+            c, nxt = nxt, c
+        torch.cuda.synchronize()
+        want.append(c.cpu().numpy())
+        T.close()
+    _say("[gpu] server: 6 requests on 2 workers")
+    srv = bchar.Server(2)
+    pending = []
+    for rep in range(2):
+        for i, ((m, v, dt), k, c0) in enumerate(zip(probs, steps, c0s)):
+            out, tmp = torch.empty_like(c0), torch.empty_like(c0)
+            pending.append((i, out, srv.submit(m, v, dt, k, c0, out, tmp)))
+    for i, out, t in pending:
+        r = srv.wait(t)
+        assert r["status"] == bchar.OK
+        assert r["t_submit"] <= r["t_start"] <= r["t_done"]
+        got = out.cpu().numpy()
+        assert np.array_equal(got.view(np.int64), want[i].view(np.int64)), i
+        m = probs[i][0]
+        m0, m1 = m.mass(c0s[i]), m.mass(out)
+        assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    srv.close()
