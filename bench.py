@@ -79,15 +79,20 @@ def algorithmic_bytes(kernel, n_cells, nnz, n_balls, stats):
     raise KeyError(kernel)
 
 
-def source_digest():
-    """Digest of the HIP sources: a measured traffic figure is valid only for
-    the kernels it was measured on."""
+# the sources each measured kernel is compiled from (its file and the
+# headers every kernel file includes)
+KERNEL_SOURCES = {"k_smooth": "qp.hip", "k_zsmooth": "qp.hip", "k_fused_cycle": "qp.hip",
+                  "k_assemble": "build.hip"}
+
+
+def source_digest(kernel):
+    """Digest of the sources of ``kernel``: a measured traffic figure is
+    valid only for the code it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(SRC)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(SRC, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in (KERNEL_SOURCES[kernel], "device_util.hpp", "internal.hpp"):
+        with open(os.path.join(SRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -100,7 +105,7 @@ def measured_traffic(kernel):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_digest") != source_digest():
+    if rec.get("source_digest") != source_digest(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -189,7 +194,7 @@ def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, work
                                     "fetch_factor": ff, "write_factor": wf},
                "bytes_per_launch": 1024.0 * (f[k]["kib_per_dispatch"] * ff +
                                              w[k]["kib_per_dispatch"] * wf),
-               "source_digest": source_digest()}
+               "source_digest": source_digest(k)}
         with open(os.path.join(ROOT, "profiles", f"traffic_{k}.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
         print(k, rec["bytes_per_launch"])
