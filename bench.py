@@ -200,27 +200,35 @@ def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, work
         print(k, rec["bytes_per_launch"])
 
 
-def cpu_baseline(sample_n=16):
+def cpu_baseline(sample_n=16, workload="swirl"):
     """The oracle timed on the host: one full time step (build + apply) of
-    the same swirl workload on a reduced sample_n^3 mesh, one thread."""
+    the same workload on a reduced mesh (sample_n^3 hexahedra, or
+    sample_n^3 cubes of 6 tetrahedra), one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import transfer as otr
     from paper_1908_05834_amd import inputs
 
-    w = inputs.swirl_hex(sample_n)
+    if workload == "tets":
+        w = inputs.jittered_tets(sample_n, steps=1)
+        layout, prec, what = "equal_measure", "fp32", "jittered tetrahedra"
+        n_cells = 6 * sample_n ** 3
+    else:
+        w = inputs.swirl_hex(sample_n)
+        layout, prec, what = "subcell", "fp64", "hexahedra, 8 balls per cell"
+        n_cells = sample_n ** 3
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        T = otr.build_transfer(w["mesh"], w["vel_fn"](0), w["dt"], layout="subcell")
+        T = otr.build_transfer(w["mesh"], w["vel_fn"](0), w["dt"], layout=layout,
+                               precision=prec)
         c1 = otr.apply(T["row_ptr"], T["col"], T["A"], T["b"], w["c0"])
         t1 = time.perf_counter()
     assert np.all(np.isfinite(c1))
-    n_cells = sample_n ** 3
     return {"value": n_cells / (t1 - t0), "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one step (build + apply) of the swirl workload on {sample_n}^3 "
-                      f"hexahedra ({n_cells} cells, 8 balls per cell, FP64), "
+            "sample": f"one step (build + apply) of the {workload} workload on a "
+                      f"{sample_n}^3 grid ({n_cells} cells, {what}, {prec.upper()}), "
                       f"{t1 - t0:.2f} s single-threaded"}
 
 
@@ -445,8 +453,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--n", type=int, default=None,
+                    help="cells per axis (swirl: 64; tets: 96 cubes of 6 tetrahedra)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="swirl: fp64 by default; tets: fp32 (binary32 volumes)")
     ap.add_argument("--inflight", type=int, default=4,
                     help="transfers built at once on separate streams (1: one after another)")
     ap.add_argument("--roofline-kernel", default="k_smooth")
@@ -457,7 +467,7 @@ def main():
                     help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--workload", choices=["swirl", "mixed", "serve"], default="swirl")
+    ap.add_argument("--workload", choices=["swirl", "tets", "mixed", "serve"], default="swirl")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--seed", type=int, default=0, help="serve: arrival seed")
@@ -515,10 +525,27 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    w = inputs.swirl_hex(args.n)
+    if args.workload == "tets":
+        args.n = args.n or 96
+        args.precision = args.precision or "fp32"
+        w = inputs.jittered_tets(args.n, steps=max(args.warmup + args.steps, 3))
+        layout = "equal_measure"
+        workload = (f"3D jittered Kuhn tetrahedra, {args.n}^3 cubes x 6 = {6 * args.n ** 3} "
+                    f"cells, lognormal phi, swirl at CFL 4, one centroid ball per cell, "
+                    f"dt = 1/128, transfer rebuilt every step")
+        metric = (f"B-char cell-updates/s (3D tets {6 * args.n ** 3}) at 1e-12 mass err; "
+                  "served p99 latency")
+    else:
+        args.n = args.n or 64
+        args.precision = args.precision or "fp64"
+        w = inputs.swirl_hex(args.n)
+        layout = "subcell"
+        workload = (f"3D swirl, unit cube, {args.n}^3 hexahedra, 8 balls per cell, "
+                    f"phi = 1, dt = 1/128, transfer rebuilt every step")
+        metric = "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency"
     prec = bchar.FP64 if args.precision == "fp64" else bchar.FP32_VOLUME
     opts = bchar.opts_default(precision=prec)
-    M = bchar.Mesh(w["mesh"], "subcell")
+    M = bchar.Mesh(w["mesh"], layout)
     # phase 1: one build after another (per-step latency); phase 2: D builds
     # at once (throughput, the reported value).  Every interval's velocity
     # lattice is resident on the device before timing.
@@ -657,7 +684,7 @@ def main():
     roof_coarse = roofline(args.coarse_kernel, c_launches, c_kms, T_last.stats)
     lat_ms = np.array(lat) * 1e3
     out = {
-        "metric": "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency",
+        "metric": metric,
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -669,8 +696,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32 geometry + f64 adjustment",
         "data": "synthetic",
-        "config": {"workload": f"3D swirl, unit cube, {args.n}^3 hexahedra, 8 balls per cell, "
-                               f"phi = 1, dt = 1/128, transfer rebuilt every step",
+        "config": {"workload": workload,
                    "n_cells": n_cells, "precision": args.precision, "nnz": nnz,
                    "inflight_builds": D,
                    "qp_ipm_mean": float(np.mean([s_["qp_ipm"] for s_ in stats])),
@@ -689,7 +715,10 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        # the oracle's cost grows faster than linearly on tetrahedra: a
+        # 6^3-cube sample (1,296 cells) keeps it to seconds
+        out["cpu_baseline"] = cpu_baseline(
+            args.cpu_sample if args.workload == "swirl" else 6, args.workload)
     print(json.dumps(out))
 
 
