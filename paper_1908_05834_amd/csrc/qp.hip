@@ -1891,7 +1891,8 @@ __global__ void k_final(const double* __restrict__ an, const double* __restrict_
                         int32_t* __restrict__ counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  const double xk = xi ? xi[k] : clipv(t[k], lo, hi);
+  // the interior point's iterate stays in the box up to its rounding
+  const double xk = clipv(xi ? xi[k] : t[k], lo, hi);
   x[k] = xk;
   A[k] = an[k] * (1.0 + xk);
   if (xk - lo <= thr) atomicAdd(&counts[0], 1);
@@ -2131,6 +2132,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 
   Reducer red{ws.get<double>(2 * kRedBlocks + 2), ws.get<double>(16), s};
   double* zpart = ws.get<double>(2 * (size_t)blocks_for(n, kT) + 2);   // block sums
+  double* zsave = ws.get<double>(2 * (size_t)n + 1);   // interior-point multipliers
+  double* tsave = ws.get<double>((size_t)nnz + 1);
 
   QpArrays Q{};
   Q.n = n;
@@ -2696,13 +2699,22 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (r == 0) r = ipm(lo, hi, false, kIpmCgTight);
       if (r > 0) {
         // an interior point at the tolerance is an answer already: one
-        // short semismooth step is enough to give up on the exact one
+        // short semismooth step is enough to give up on the exact one.  Its
+        // multipliers are kept, so that an interior-point answer leaves
+        // the multipliers that go with its x (and the next solve's warm
+        // start) rather than those of an abandoned step.
+        if (r == 2) {
+          BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+          BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+        }
         converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
                         r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
                         " (after interior point)");
         if (!converged && r == 2) {
           converged = ipm_answer = true;
           fn = fp_ipm;
+          BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+          BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
         } else if (!converged) {
           // the interior point stalled short of the tolerance: semismooth
           // Newton without the step-count cap
