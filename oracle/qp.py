@@ -278,19 +278,13 @@ def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol):
     equals clip(a (mu_i + nu_j)) entrywise up to the rounding of the sum
     mu_i + nu_j (the multipliers of weakly coupled cells can be large, so
     the check allows 1e-12 of |a| (|mu_i| + |nu_j|)).  Returns the worst
-    violation of each condition and ``ok``; also ``stationarity_a``, the
-    largest |a| |clip(a (mu_i + nu_j)) - x| relative to ``scale``: what the
-    departure from that identity changes in the entries a (1 + x) of the
-    final matrix (an interior-point answer meets the identity only to its
-    complementarity)."""
+    violation of each condition and ``ok``."""
     As = np.asarray(a) / scale
     t = As * (mu[rows] + nu[cols])
     mag = np.abs(As) * (np.abs(mu[rows]) + np.abs(nu[cols]))
-    dev = np.abs(np.clip(t, lo, hi) - x)
-    stat = float(np.max(dev / (1.0 + mag), initial=0.0))
-    stat_a = float(np.max(np.abs(As) * dev, initial=0.0))
+    stat = float(np.max((np.abs(np.clip(t, lo, hi) - x)) / (1.0 + mag), initial=0.0))
     box = float(max(np.max(lo - x, initial=-np.inf), np.max(x - hi, initial=-np.inf), 0.0))
     r, s = constraint_rhs(rows, cols, As, np.asarray(b_row) / scale, np.asarray(b_col) / scale)
     prim = float(np.max(np.abs(residual(rows, cols, As, x, r, s)), initial=0.0))
-    return {"stationarity": stat, "stationarity_a": stat_a, "box": box, "primal": prim,
+    return {"stationarity": stat, "box": box, "primal": prim,
             "ok": stat <= 1e-12 and box == 0.0 and prim <= tol}

@@ -56,6 +56,8 @@ constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relati
 constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
+constexpr int kCrossoverSteps = 2; // fixed-side Newton steps from an interior point
+constexpr double kCrossoverRatio = 1e-3;  // slack / multiplier of a pinned entry
 constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those after an
                                    // interior point that met tol
 
@@ -1919,6 +1921,59 @@ struct IpmArrays {
   int has_hi;                      // level 0: both bounds; level 1: lower only
 };
 
+// Crossover from an interior point: the side of every entry, -1 on the
+// lower bound (its slack below `ratio` times its multiplier), +1 on the
+// upper bound, 0 free (degenerate entries, slack and multiplier alike
+// small, stay free).
+__global__ void k_xover_state(IpmArrays I, double ratio, int64_t nnz,
+                              int8_t* __restrict__ side) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  int8_t v = 0;
+  if (I.sl[k] < ratio * I.zl[k])
+    v = -1;
+  else if (I.has_hi && I.su[k] < ratio * I.zu[k])
+    v = 1;
+  side[k] = v;
+}
+
+// Residual with the sides fixed: x_k is the bound of a pinned entry and
+// t_k of a free one (k_residual with clip replaced by the sides).
+__global__ void k_residual_sides(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
+                                 const int32_t* __restrict__ cpos, const double* __restrict__ a,
+                                 const double* __restrict__ ac, const double* __restrict__ t,
+                                 const int8_t* __restrict__ side, double lo, double hi,
+                                 const double* __restrict__ rr, const double* __restrict__ ss,
+                                 int64_t n, double* __restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CSum r, c;
+  r.add(-rr[i]);
+  for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) {
+    const double xk = side[k] < 0 ? lo : (side[k] > 0 ? hi : t[k]);
+    r.add(a[k] * xk);
+  }
+  c.add(-ss[i]);
+  for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) {
+    const int32_t k = cpos[e];
+    const double xk = side[k] < 0 ? lo : (side[k] > 0 ? hi : t[k]);
+    c.add(ac[e] * xk);
+  }
+  F[i] = r.value();
+  F[n + i] = c.value();
+}
+
+// fine weights a_k^2 on the free entries (graph order, as k_fine_weights)
+__global__ void k_side_weights(const double* __restrict__ a, const int32_t* __restrict__ cpos,
+                               const int8_t* __restrict__ side, int64_t nnz,
+                               double* __restrict__ w) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  w[k] = side[k] == 0 ? a[k] * a[k] : 0.0;
+  const int32_t kp = cpos[k];
+  w[nnz + k] = side[kp] == 0 ? a[kp] * a[kp] : 0.0;
+}
+
 // D and the per-block complementarity sums sl zl + su zu
 __global__ void __launch_bounds__(kT) k_ipm_prep(IpmArrays I, int64_t nnz,
                                                  double* __restrict__ part) {
@@ -2660,6 +2715,57 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     return fp_best <= 1e-10 ? 1 : 0;
   };
 
+  // ---------------------------------------------------------------- crossover
+  // From an interior point at the tolerance: keep its split of the entries
+  // into those on a bound and the free ones, and solve the constraints for
+  // the multipliers with that split (linear in them: a Newton step is
+  // exact up to CG); accepted only if clip(t) then meets the tolerance, so
+  // that x = clip(t) is the exact minimiser.  The state is left as found
+  // when it fails.
+  int8_t* side = ws.get<int8_t>((size_t)nnz + 1);
+  auto crossover = [&](double lo, double hi) -> bool {
+    {
+      ::bchar::ProfScope ps_("k_xover_state", s);
+      k_xover_state<<<gz, kT, 0, s>>>(I, kCrossoverRatio, nnz, side);
+    }
+    BCHAR_HIP(hipGetLastError());
+    for (int it = 0; it < kCrossoverSteps; ++it) {
+      {
+        ::bchar::ProfScope ps_("k_residual_sides", s);
+        k_residual_sides<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, side, lo, hi,
+                                           Q.rr, Q.ss, n, Q.F);
+      }
+      {
+        ::bchar::ProfScope ps_("k_side_weights", s);
+        k_side_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, side, nnz, L0.w);
+      }
+      refresh();
+      pcg(Q.F, 0.1 * tol, false, o.qp_max_cg);
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, 1.0, nnz);
+      }
+      {
+        ::bchar::ProfScope ps_("k_zdual_acc", s);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, 1.0, n, zdual);
+      }
+      {
+        ::bchar::ProfScope ps_("k_residual", s);
+        k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
+                                     Q.rr, Q.ss, n, Q.F);
+      }
+      red.maxabs(Q.F, n2, 0);
+      const double f = red.fetch(0);
+      if (trace_enabled())
+        fprintf(stderr, "[bchar]   crossover %d: |F| of clip(t) %.3e\n", it, f);
+      if (f <= tol) {
+        fn = f;
+        return true;
+      }
+    }
+    return false;
+  };
+
   // ---------------------------------------------------------------- box levels
   // Level 0 is the paper's box, level 1 keeps x >= -1 only, level 2 keeps
   // the equalities alone.  A level with a bound is solved by the interior
@@ -2706,10 +2812,18 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         if (r == 2) {
           BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
           BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+          converged = crossover(lo, hi);
+          if (!converged) {
+            BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * n2, hipMemcpyDeviceToDevice,
+                                     s));
+            BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                                     s));
+          }
         }
-        converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
-                        r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
-                        " (after interior point)");
+        if (!converged)
+          converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
+                          r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
+                          " (after interior point)");
         if (!converged && r == 2) {
           converged = ipm_answer = true;
           fn = fp_ipm;
