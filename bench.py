@@ -249,7 +249,8 @@ def bench_mixed(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     D = max(1, args.inflight)
-    opts = bchar.opts_default()
+    # a void makes the library repeat the build with half the step
+    opts = bchar.opts_default(max_halvings=4)
     probs = []
     for p in range(args.problems):
         q = inputs.mixed_problem(p)
@@ -263,11 +264,11 @@ def bench_mixed(args):
     steps = probs[0]["steps"]
     mass_err = 0.0
 
-    def finish(q, T, k):
+    def finish(q, T):
         nonlocal mass_err
         c = q["c0_dev"].clone()
         nxt = torch.empty_like(c)
-        for _ in range(k):
+        for _ in range(steps):
             T.step(c, nxt)
             c, nxt = nxt, c
         m = q["M"].mass(c)
@@ -275,9 +276,6 @@ def bench_mixed(args):
         T.close()
 
     def run(depth):
-        # a job that meets a void row or column is built again with half the
-        # time step and applied twice as often (the remedy the method
-        # prescribes for voids), at most four times
         streams = [torch.cuda.Stream() for _ in range(depth)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -285,21 +283,12 @@ def bench_mixed(args):
         halvings = 0
         per_call = 64 if depth > 1 else 1
         for b0 in range(0, len(probs), per_call):
-            chunk = [(q, q["dt"], steps) for q in probs[b0:b0 + per_call]]
-            while chunk:
-                Ts, sts = bchar.build_batch([(None, q["M"], q["U"], dt) for q, dt, _ in chunk],
-                                            opts, streams, check=False)
-                again = []
-                for (q, dt, k), T, st in zip(chunk, Ts, sts):
-                    if st in (bchar.E_VOID_ROW, bchar.E_VOID_COLUMN) and k < 16 * steps:
-                        again.append((q, dt / 2, 2 * k))
-                        halvings += 1
-                        continue
-                    if st != bchar.OK:
-                        raise bchar.BcharError(st, f"problem {q['name']}")
-                    cg.append(T.stats["qp_cg"])
-                    finish(q, T, k)
-                chunk = again
+            chunk = probs[b0:b0 + per_call]
+            Ts = bchar.build_batch([(None, q["M"], q["U"], q["dt"]) for q in chunk], opts, streams)
+            for q, T in zip(chunk, Ts):
+                cg.append(T.stats["qp_cg"])
+                halvings += T.stats["dt_halvings"]
+                finish(q, T)
             if depth > 1 or b0 % 16 == 15:
                 log(f"  depth {depth}: problems up to {min(b0 + per_call, len(probs)) - 1} done "
                     f"at {time.perf_counter() - t0:.2f} s")

@@ -153,6 +153,14 @@ typedef struct {
                             transfer's previous solve (same mesh); the
                             solution is unique, only the iteration count
                             changes; a failed warm start is retried cold */
+  int max_halvings;      /* a build that meets a void row or column (no
+                            tracked ball in a residing cell, or none
+                            overlapping a tracked ball) is repeated with
+                            half the time step, at most this many times
+                            (default 0: report the void); the transfer then
+                            covers dt in 2^h sub-steps of dt / 2^h, which
+                            bchar_step applies in turn (stats.dt_halvings
+                            = h)                                         */
 } bchar_opts;
 
 typedef struct {
@@ -175,6 +183,8 @@ typedef struct {
   int64_t qp_smooth_bytes;     /* bytes one Jacobi sweep of a launched
                                   multigrid level reads or writes at least,
                                   mean over the sweeps of one cycle       */
+  int dt_halvings;             /* times the time step was halved after a
+                                  void (opts.max_halvings)                */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */
@@ -311,7 +321,8 @@ bchar_status bchar_server_wait(bchar_server srv, int64_t ticket, bchar_request_r
  * results not yet waited for are dropped).  NULL is a no-op.            */
 bchar_status bchar_server_destroy(bchar_server srv);
 
-/* One update (Sec. 2, eq. phys-inter-ELLAM): c_out = diag(|K|_phi)^-1 A c_in.
+/* One update (Sec. 2, eq. phys-inter-ELLAM): c_out = diag(|K|_phi)^-1 A c_in,
+ * applied 2^h times when the build halved the time step h times.
  * c_in, c_out: device, n_cells binary64 each, must not overlap.  Needs a
  * transfer built to BCHAR_STAGE_ALL.  Asynchronous on `stream`.         */
 bchar_status bchar_step(bchar_transfer t, const double* c_in, double* c_out, void* stream);

@@ -55,7 +55,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_sweeps", C.c_int), ("rk_substeps", C.c_int),
                 ("box_policy", C.c_int), ("stop_after", C.c_int), ("qp_tol", C.c_double),
                 ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int),
-                ("warm_start", C.c_int)]
+                ("warm_start", C.c_int), ("max_halvings", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -64,7 +64,7 @@ class Stats(C.Structure):
                 ("qp_residual", C.c_double), ("qp_level", C.c_int), ("qp_newton", C.c_int),
                 ("qp_cg", C.c_int), ("n_at_lower", C.c_int64), ("n_at_upper", C.c_int64),
                 ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64),
-                ("qp_smooth_bytes", C.c_int64)]
+                ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

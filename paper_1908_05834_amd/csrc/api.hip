@@ -233,6 +233,8 @@ void validate_opts(const bchar_opts& o) {
   BCHAR_REQUIRE(o.qp_tol > 0 && std::isfinite(o.qp_tol), BCHAR_E_INVALID_ARG, "opts.qp_tol");
   BCHAR_REQUIRE(o.qp_max_newton >= 1 && o.qp_max_cg >= 1, BCHAR_E_INVALID_ARG,
                 "opts.qp_max_newton / qp_max_cg");
+  BCHAR_REQUIRE(o.max_halvings >= 0 && o.max_halvings <= 20, BCHAR_E_INVALID_ARG,
+                "opts.max_halvings");
 }
 
 void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
@@ -356,12 +358,9 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   return BCHAR_OK;
 }
 
-bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity* u, double dt,
-                      const bchar_opts& o, hipStream_t s, bchar_stats* stats) {
+bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity* u,
+                        double dt, const bchar_opts& o, hipStream_t s, bchar_stats* stats) {
   using namespace bchar;
-  validate_opts(o);
-  validate_velocity(m, u);
-  BCHAR_REQUIRE(dt > 0 && std::isfinite(dt), BCHAR_E_INVALID_ARG, "dt must be finite and > 0");
   t->ws.reset();
   t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
   t->r_hat.reserve(sizeof(double) * m->n_balls);
@@ -373,6 +372,39 @@ bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity
     fprintf(stderr, "[bchar] trace: %.3f ms\n", 1e3 * (wall_seconds() - t0));
   }
   return build_from_tracked(m, t, o, s, stats);
+}
+
+// A void row or column is the method's sign that the step is too long for
+// the mesh: the build is repeated with half the step (the remedy the paper
+// gives), at most o.max_halvings times.
+bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity* u, double dt,
+                      const bchar_opts& o, hipStream_t s, bchar_stats* stats) {
+  validate_opts(o);
+  validate_velocity(m, u);
+  BCHAR_REQUIRE(dt > 0 && std::isfinite(dt), BCHAR_E_INVALID_ARG, "dt must be finite and > 0");
+  bchar_status rc = BCHAR_OK;
+  int h = 0;
+  for (;; ++h) {
+    rc = build_once(m, t, u, std::ldexp(dt, -h), o, s, stats);
+    if ((rc != BCHAR_E_VOID_ROW && rc != BCHAR_E_VOID_COLUMN) || h >= o.max_halvings) break;
+    if (bchar::trace_enabled())
+      fprintf(stderr, "[bchar] void: step halved to dt / %d\n", 1 << (h + 1));
+  }
+  t->substeps = 1 << h;
+  t->stats.dt_halvings = h;
+  if (stats) stats->dt_halvings = h;
+  return rc;
+}
+
+// The update applied t->substeps times, the last one into cout.
+void apply_substeps(bchar_transfer_s* t, const double* cin, double* cout, double* tmp,
+                    hipStream_t s) {
+  const double* src = cin;
+  for (int i = 0; i < t->substeps; ++i) {
+    double* dst = ((t->substeps - 1 - i) % 2 == 0) ? cout : tmp;
+    bchar::apply_transfer(t, src, dst, s);
+    src = dst;
+  }
 }
 
 }  // namespace
@@ -432,9 +464,13 @@ struct bchar_server_s {
         t->warm_level = -1;
         bchar_status rc = do_build(r.mesh, t, r.u, r.dt, opts, s, &it->res.stats);
         if (rc != BCHAR_OK) return rc;
+        // every update is t->substeps sub-steps after void halvings
+        const int k = r.steps * t->substeps;
+        BCHAR_REQUIRE(k == 1 || r.c_tmp != nullptr, BCHAR_E_INVALID_ARG,
+                      "request needs c_tmp (the step was halved)");
         const double* src = r.c_in;
-        for (int i = 0; i < r.steps; ++i) {
-          double* dst = ((r.steps - 1 - i) % 2 == 0) ? r.c_out : r.c_tmp;
+        for (int i = 0; i < k; ++i) {
+          double* dst = ((k - 1 - i) % 2 == 0) ? r.c_out : r.c_tmp;
           bchar::apply_transfer(t, src, dst, s);
           src = dst;
         }
@@ -665,6 +701,7 @@ static void transfer_free(bchar_transfer t) {
   t->pair_a.release();
   t->pair_b.release();
   t->ws.release();
+  t->cscratch.release();
 }
 
 bchar_status bchar_build_transfer(bchar_mesh m, const bchar_velocity* u, double dt,
@@ -836,7 +873,8 @@ bchar_status bchar_step(bchar_transfer t, const double* cin, double* cout, void*
     const double* ce = cin + n;
     BCHAR_REQUIRE(cout + n <= cin || ce <= cout, BCHAR_E_INVALID_ARG,
                   "c_in and c_out overlap");
-    bchar::apply_transfer(t, cin, cout, as_stream(stream));
+    if (t->substeps > 1) t->cscratch.reserve(sizeof(double) * n);
+    apply_substeps(t, cin, cout, t->cscratch.as<double>(), as_stream(stream));
     return BCHAR_OK;
   });
 }

@@ -131,6 +131,8 @@ struct bchar_transfer_s {
   // scratch of this transfer's builds (its own, so that builds of several
   // transfers of one mesh may run at once on different streams)
   bchar::Arena ws;
+  int substeps = 1;       // sub-steps of dt / substeps after void halvings
+  bchar::DBuf cscratch;   // fp64 n_cells, the update's intermediate vector
 };
 
 namespace bchar {

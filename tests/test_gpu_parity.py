@@ -301,3 +301,36 @@ def test_unstructured_properties(env):
     ones = torch.ones(nc, dtype=torch.float64, device="cuda")
     T.step(ones, nxt)
     assert torch.max(torch.abs(nxt - 1.0)).item() <= 1e-12
+
+
+def test_void_step_halving(env):
+    # a step too long for the mesh: some residing cell receives no tracked
+    # ball (a void column).  The library reports it, or with max_halvings
+    # builds the transfer of half the step and applies it twice, which must
+    # equal the oracle's transfer of dt / 2 applied twice
+    torch, bchar = env
+    _say("[gpu] void column, step halving")
+    q = inputs.mixed_problem(2, 400.0, 400.0)
+    mesh, vel, dt, layout = q["mesh"], q["vel"], q["dt"], q["layout"]
+    with pytest.raises(otr.VoidColumnError):
+        otr.build_transfer(mesh, vel, dt, layout=layout)
+    ref = otr.build_transfer(mesh, vel, dt / 2, layout=layout)
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build(M, U, dt)
+    assert ei.value.status == bchar.E_VOID_COLUMN
+    T = bchar.Transfer.build(M, U, dt, bchar.opts_default(max_halvings=3))
+    assert T.stats["dt_halvings"] == 1 and T.stats["qp_level"] == ref["qp"]["level"]
+    c0 = inputs.uniform_c(mesh, 11)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    half = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], c0)
+    want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], half)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
