@@ -161,6 +161,11 @@ typedef struct {
                             covers dt in 2^h sub-steps of dt / 2^h, which
                             bchar_step applies in turn (stats.dt_halvings
                             = h)                                         */
+  int cg_graphs;         /* non-zero (default): the conjugate-gradient
+                            iterations of the least-change solve are
+                            captured once per solve as HIP graphs of four
+                            iterations and replayed (same kernels, same
+                            results bit for bit; fewer host launches)    */
 } bchar_opts;
 
 typedef struct {

@@ -505,6 +505,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->qp_max_cg = 400;
   o->keep_pairs = 0;
   o->warm_start = 1;
+  o->cg_graphs = 1;
 }
 
 const char* bchar_status_string(bchar_status s) {

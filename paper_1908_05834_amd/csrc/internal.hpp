@@ -236,6 +236,18 @@ namespace bchar {
 bool trace_enabled();
 double wall_seconds();
 
+// Work replayed from a HIP graph cannot carry events: while a graph is
+// captured no launch is timed (mode off), and one replayed unit in `every`
+// (prof_unit_due) is launched eagerly instead, with every launch of the
+// timed kernel in it bracketed (mode all).  The mode is per thread.
+enum class ProfMode { normal, off, all };
+void prof_set_mode(ProfMode m);
+bool prof_unit_due();
+struct ProfModeGuard {
+  explicit ProfModeGuard(ProfMode m) { prof_set_mode(m); }
+  ~ProfModeGuard() { prof_set_mode(ProfMode::normal); }
+};
+
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s);
   ~ProfScope();

@@ -197,6 +197,13 @@ struct Level {
   int64_t nra = 0;
   int32_t *ra_ptr = nullptr, *ra_col = nullptr, *ra_cptr = nullptr, *ra_code = nullptr;
   double* ra_val = nullptr;
+  // the cycle's coarse level: `step` levels down, reached through the
+  // composed aggregation (cagg, cmptr, cmem; the level's own maps when
+  // step = 1).  Aggregation with piecewise-constant prolongation composes
+  // exactly: the Galerkin operator two levels down is that of the composed
+  // aggregates, so a cycle may pass over a level.
+  int step = 1;
+  int32_t *cagg = nullptr, *cmptr = nullptr, *cmem = nullptr;
 };
 
 // Levels small enough for one workgroup run in a single launch
@@ -708,6 +715,13 @@ __global__ void k_pair_agg(const int32_t* __restrict__ partner,
 // Inverse of the coarsest matrix plus a relative shift, by Gauss-Jordan
 // elimination in place (the matrix is symmetric positive definite, so no
 // pivoting), one workgroup.
+// aggregation two levels down: cagg[p] = agg1[agg0[p]]
+__global__ void k_compose_agg(const int32_t* __restrict__ agg0, const int32_t* __restrict__ agg1,
+                              int64_t n, int32_t* __restrict__ cagg) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) cagg[p] = agg1[agg0[p]];
+}
+
 __global__ void __launch_bounds__(1024) k_coarse_inverse(const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ nbr,
                                                          const double* __restrict__ w,
@@ -987,6 +1001,7 @@ struct Hierarchy {
   int pre = 1, post = 1;             // sweeps of the fused coarse levels
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
+  int skip = 1;                    // launched levels from this one pass over every other level
   FusedLevels* fused = nullptr;    // device copy
   bool fused_img = false;          // it has an LDS image to refresh
   int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least
@@ -1065,7 +1080,7 @@ static void ra_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
   fill_i32(overflow, 0, 1, s);
   {
     ::bchar::ProfScope ps_("k_ra_pattern", s);
-    k_ra_pattern<false><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.mptr, L.mem, nc, row_cnt,
+    k_ra_pattern<false><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.cmptr, L.cmem, nc, row_cnt,
                                                     cand_cnt, nullptr, nullptr, nullptr,
                                                     nullptr, nullptr, overflow);
   }
@@ -1086,7 +1101,7 @@ static void ra_pattern(Level& L, int64_t nc, Arena& ws, hipStream_t s) {
   L.ra_val = ws.get<double>(L.nra + 1);
   {
     ::bchar::ProfScope ps_("k_ra_pattern", s);
-    k_ra_pattern<true><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.mptr, L.mem, nc, nullptr,
+    k_ra_pattern<true><<<(unsigned)nc, 64, 0, s>>>(L.ptr, L.nbr, L.cmptr, L.cmem, nc, nullptr,
                                                    nullptr, L.ra_ptr, cbase, L.ra_col, L.ra_cptr,
                                                    L.ra_code, overflow);
   }
@@ -1201,16 +1216,40 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     --first;
   }
   H.fused_first = first;
-  // the launched levels restrict their residual through R L
-  for (size_t l = 1; l < first; ++l) ra_pattern(H.lv[l], H.lv[l + 1].n, ws, s);
-  // one sweep (k_smooth) of level l reads the row pointers, neighbours and
-  // weights, the diagonal, smoother step, right-hand side and iterate, and
-  // writes the new iterate: 44 n + 12 ne bytes; two sweeps a level a cycle
+  // the launched levels of the cycle: from level 1, passing over every
+  // other level (aggregates of about four nodes) while that lands at or
+  // above the fused levels; each restricts its residual through R L
+  int64_t launched = 0;
   H.smooth_bytes = 0;
-  if (first > 1) {
-    for (size_t l = 1; l < first; ++l) H.smooth_bytes += 44 * H.lv[l].n + 12 * H.lv[l].ne;
-    H.smooth_bytes /= (int64_t)(first - 1);
+  for (size_t l = 1; l < first;) {
+    Level& L = H.lv[l];
+    L.step = (H.skip > 0 && (int)l >= H.skip && l + 2 <= first) ? 2 : 1;
+    if (L.step == 2) {
+      L.cagg = ws.get<int32_t>(L.n + 1);
+      {
+        ::bchar::ProfScope ps_("k_compose_agg", s);
+        k_compose_agg<<<blocks_for(L.n, kT), kT, 0, s>>>(L.agg, H.lv[l + 1].agg, L.n, L.cagg);
+      }
+      BCHAR_HIP(hipGetLastError());
+      const int64_t nc2 = H.lv[l + 2].n;
+      L.cmptr = ws.get<int32_t>(nc2 + 1);
+      L.cmem = ws.get<int32_t>(L.n + 1);
+      bucket_sort(L.cagg, L.n, nc2, L.cmptr, L.cmem, ws, s);
+    } else {
+      L.cagg = L.agg;
+      L.cmptr = L.mptr;
+      L.cmem = L.mem;
+    }
+    ra_pattern(L, H.lv[l + L.step].n, ws, s);
+    // one sweep (k_smooth) of level l reads the row pointers, neighbours
+    // and weights, the diagonal, smoother step, right-hand side and
+    // iterate, and writes the new iterate: 44 n + 12 ne bytes; two sweeps
+    // a level a cycle
+    H.smooth_bytes += 44 * L.n + 12 * L.ne;
+    ++launched;
+    l += L.step;
   }
+  if (launched > 0) H.smooth_bytes /= launched;
   FusedLevels hf{};
   hf.count = (int)(H.lv.size() - first);
   hf.dense = H.dense ? 1 : 0;
@@ -1337,7 +1376,7 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   // two damped Jacobi sweeps before and after the coarse correction, in
   // four launches: both pre-sweeps, residual and restriction, prolongation
   // with the first post-sweep, the second post-sweep (result in L.x)
-  Level& C = H.lv[l + 1];
+  Level& C = H.lv[l + L.step];
   const unsigned gl = blocks_for(L.n * kNodeLanes, kT);
   {
     // the first sweep (x1 = sdinv b, in L.x2) came with the restriction
@@ -1347,12 +1386,12 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
   {
     ::bchar::ProfScope ps_("k_resid_restrict", s);
     k_resid_restrict<<<blocks_for(C.n * kNodeLanes, kT), kT, 0, s>>>(
-        L.mptr, L.mem, L.b, L.ra_ptr, L.ra_col, L.ra_val, L.x, C.n, C.sdinv, C.b, C.x2);
+        L.cmptr, L.cmem, L.b, L.ra_ptr, L.ra_col, L.ra_val, L.x, C.n, C.sdinv, C.b, C.x2);
   }
-  vcycle(H, l + 1, s);
+  vcycle(H, l + L.step, s);
   {
     ::bchar::ProfScope ps_("k_prolong_smooth", s);
-    k_prolong_smooth<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.x, L.agg, C.x,
+    k_prolong_smooth<<<gl, kT, 0, s>>>(L.ptr, L.nbr, L.w, L.diag, L.sdinv, L.b, L.x, L.cagg, C.x,
                                         L.n, L.x2);
   }
   {
@@ -2306,6 +2345,88 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     refresh_hierarchy(H, s);
   };
 
+  // One CG iteration split after its update: the update half (product
+  // J p, p.q, x/r update with r.z in rz) and units that run the next
+  // iteration's preconditioner (r.z into rz_next), direction and update.
+  auto cg_update_half = [&](const double* rzc, hipStream_t st) {
+    {
+      ::bchar::ProfScope ps_("k_zop", st);
+      k_zop<<<gn, kT, 0, st>>>(P.Z, cp, cq, zpart);
+    }
+    {
+      ::bchar::ProfScope ps_("k_reduce_final_sum", st);
+      k_reduce_final_sum<<<1, kFinalThreads, 0, st>>>(zpart, (int)gn, red.out + 9);
+    }
+    {
+      ::bchar::ProfScope ps_("k_cg_update", st);
+      k_cg_update<<<gn2, kT, 0, st>>>(rzc, red.out + 9, n2, cx, cr, cp, cq);
+    }
+    BCHAR_HIP(hipGetLastError());
+  };
+  // units, then (with `check`) the residual check's max |r| into out[11]
+  auto cg_units = [&](int units, double* a, double* b, bool check, hipStream_t st) {
+    Reducer rs = red;
+    rs.s = st;
+    for (int u = 0; u < units; ++u) {
+      if (zprecondition(P, cr, cz, st, zpart)) {
+        ::bchar::ProfScope ps_("k_reduce_final_sum", st);
+        k_reduce_final_sum<<<1, kFinalThreads, 0, st>>>(zpart, (int)gn, b);
+      } else {
+        rs.dot(cr, cz, n2, (int)(b - red.out));
+      }
+      {
+        ::bchar::ProfScope ps_("k_cg_dir", st);
+        k_cg_dir<<<gn2, kT, 0, st>>>(a, b, n2, cz, cp);
+      }
+      BCHAR_HIP(hipGetLastError());
+      cg_update_half(b, st);
+      std::swap(a, b);
+    }
+    if (check) rs.maxabs(cr, n2, 11);
+  };
+  // The iterations between two residual checks launch the same few dozen
+  // kernels with the same arguments every time (the hierarchy's buffers
+  // are fixed for the whole solve): they are captured once per solve and
+  // replayed, which takes the host's per-launch cost off the critical path.
+  // Graph 0 holds the three units after iteration 0, graph 1 the four
+  // between two later checks; each ends with the check's max |r|.
+  // Capture runs on a stream of its own (the solve's stream may be the
+  // null stream, which cannot be captured); the graphs replay on the
+  // solve's stream.
+  struct CgGraphs {
+    hipStream_t ls = nullptr;   // replays go to this stream
+    hipStream_t cs = nullptr;
+    hipGraph_t g[2] = {nullptr, nullptr};
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+    ~CgGraphs() {
+      // (every replay is followed by a read of its check; this also covers
+      // a replay an exception left behind)
+      if (x[0] || x[1]) (void)hipStreamSynchronize(ls);
+      for (int i = 0; i < 2; ++i) {
+        if (x[i]) (void)hipGraphExecDestroy(x[i]);
+        if (g[i]) (void)hipGraphDestroy(g[i]);
+      }
+      if (cs) (void)hipStreamDestroy(cs);
+    }
+  } G;
+  G.ls = s;
+  const bool graphs_ok = o.cg_graphs != 0;
+  auto capture_units = [&](int which, int units, double* a, double* b) {
+    ProfModeGuard g_(ProfMode::off);
+    if (!G.cs) BCHAR_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+    BCHAR_HIP(hipStreamBeginCapture(G.cs, hipStreamCaptureModeRelaxed));
+    try {
+      cg_units(units, a, b, true, G.cs);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(G.cs, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    BCHAR_HIP(hipStreamEndCapture(G.cs, &G.g[which]));
+    BCHAR_HIP(hipGraphInstantiateWithFlags(&G.x[which], G.g[which], 0));
+  };
+
   // Preconditioned CG on J d = -fv (fv: row part, then column part), in
   // the per-cell coordinates with the constant-s direction removed.  Leaves
   // the per-cell solution in cx, the multiplier direction in dmu, dnu and
@@ -2342,40 +2463,47 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     red.dot(cr, cz, n2, 8);
     double* rz = red.out + 8;
     double* rz_next = red.out + 10;
+    // iteration 0's update, then units of (preconditioner, direction,
+    // product, update) advancing one iteration each; after the update of
+    // iteration k the residual is checked when k % 4 == 3 or at the cap
+    cg_update_half(rz, s);
     int k = 0;
-    for (k = 0; k < max_cg; ++k) {
-      {
-        ::bchar::ProfScope ps_("k_zop", s);
-        k_zop<<<gn, kT, 0, s>>>(P.Z, cp, cq, zpart);
-      }
-      {
-        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(zpart, (int)gn, red.out + 9);
-      }
-      {
-        ::bchar::ProfScope ps_("k_cg_update", s);
-        k_cg_update<<<gn2, kT, 0, s>>>(rz, red.out + 9, n2, cx, cr, cp, cq);
-      }
-      BCHAR_HIP(hipGetLastError());
-      if ((k % 4) == 3 || k + 1 == max_cg) {
+    bool checked = false;   // a replayed graph has just checked iteration k
+    for (;;) {
+      if (!checked && ((k % 4) == 3 || k + 1 == max_cg)) {
         red.maxabs(cr, n2, 11);
-        if (red.fetch(11) <= cg_tol) {
+        if (red.fetch(11) <= cg_tol || k + 1 == max_cg) {
           ++k;
           break;
         }
       }
-      if (zprecondition(P, cr, cz, s, zpart)) {
-        ::bchar::ProfScope ps_("k_reduce_final_sum", s);
-        k_reduce_final_sum<<<1, kFinalThreads, 0, s>>>(zpart, (int)gn, rz_next);
-      } else {
-        red.dot(cr, cz, n2, (int)(rz_next - red.out));
+      // the next check falls on iteration k + 3 (from 0) or k + 4: replay
+      // those units from the graph when they all fit under the cap
+      const int next = (k == 0) ? 3 : 4;
+      if (graphs_ok && (k % 4) == ((k == 0) ? 0 : 3) && k + next < max_cg) {
+        const int which = (k == 0) ? 0 : 1;
+        // graph 0 starts from r.z in out[8], graph 1 from out[10]
+        BCHAR_REQUIRE(rz == red.out + (which ? 10 : 8), BCHAR_E_DEVICE, "cg graph parity");
+        if (prof_unit_due()) {
+          ProfModeGuard g_(ProfMode::all);
+          cg_units(next, rz, rz_next, true, s);
+        } else {
+          if (!G.x[which]) capture_units(which, next, rz, rz_next);
+          BCHAR_HIP(hipGraphLaunch(G.x[which], s));
+        }
+        if (next % 2) std::swap(rz, rz_next);
+        k += next;
+        if (red.fetch(11) <= cg_tol || k + 1 == max_cg) {
+          ++k;
+          break;
+        }
+        checked = true;
+        continue;
       }
-      {
-        ::bchar::ProfScope ps_("k_cg_dir", s);
-        k_cg_dir<<<gn2, kT, 0, s>>>(rz, rz_next, n2, cz, cp);
-      }
+      checked = false;
+      cg_units(1, rz, rz_next, false, s);
       std::swap(rz, rz_next);
-      BCHAR_HIP(hipGetLastError());
+      ++k;
     }
     res.cg += k;
     red.sum(cx, n, 13);

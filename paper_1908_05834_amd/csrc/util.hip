@@ -279,6 +279,7 @@ struct ProfState {
   std::string target;     // kernel name being timed ("" = off)
   int64_t every = 1;      // time every `every`-th launch of it
   int64_t seen = 0;       // launches of it seen
+  int64_t units = 0;      // replayable units seen
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<hipEvent_t> free_events;
   int64_t launches = 0;
@@ -312,11 +313,22 @@ void drain(ProfState& p) {
 }
 }  // namespace
 
+thread_local ProfMode t_mode = ProfMode::normal;
+
+void prof_set_mode(ProfMode m) { t_mode = m; }
+
+bool prof_unit_due() {
+  ProfState& p = prof();
+  if (p.target.empty()) return false;
+  std::lock_guard<std::mutex> g(p.mu);
+  return (p.units++ % p.every) == 0;
+}
+
 ProfScope::ProfScope(const char* name, hipStream_t st) : slot(-1), s(st) {
   ProfState& p = prof();
-  if (p.target.empty() || p.target != name) return;
+  if (t_mode == ProfMode::off || p.target.empty() || p.target != name) return;
   std::lock_guard<std::mutex> g(p.mu);
-  if ((p.seen++ % p.every) != 0) return;
+  if (t_mode != ProfMode::all && (p.seen++ % p.every) != 0) return;
   hipEvent_t a = take_event(p), b = take_event(p);
   BCHAR_HIP(hipEventRecord(a, s));
   p.pending.push_back({a, b});
@@ -344,6 +356,7 @@ extern "C" bchar_status bchar_profile_kernel_sampled(const char* name, int every
     p.target = name ? name : "";
     p.every = every;
     p.seen = 0;
+    p.units = 0;
     p.launches = 0;
     p.total_ms = 0;
     return BCHAR_OK;

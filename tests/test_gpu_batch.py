@@ -146,3 +146,43 @@ def test_server_requests_equal_runs_alone(env):
         m0, m1 = m.mass(c0s[i]), m.mass(out)
         assert abs(m1 - m0) <= 1e-12 * abs(m0)
     srv.close()
+
+
+def test_cg_graph_replay_equals_eager_launches(env):
+    """The CG iterations replayed from captured graphs (opts.cg_graphs)
+    launch the same kernels on the same buffers as the eager loop: the
+    transfers must agree bit for bit, on the null stream (captured on a
+    stream of the solve's own) and on a side stream, and with kernel timing
+    on, which runs one replay in `every` eagerly."""
+    torch, bchar = env
+    probs = _problems(bchar)
+    w = inputs.swirl_hex(16)
+    probs.append((bchar.Mesh(w["mesh"], "subcell"), bchar.VelocityLattice(w["vel_fn"](1)),
+                  w["dt"] * 2))
+    eager = bchar.opts_default(cg_graphs=0)
+    graph = bchar.opts_default(cg_graphs=1)
+    side = torch.cuda.Stream()
+    for i, (m, v, dt) in enumerate(probs):
+        _say(f"[gpu] cg graphs, problem {i}")
+        a = bchar.Transfer.build(m, v, dt, opts=eager)
+        b = bchar.Transfer.build(m, v, dt, opts=graph)
+        with torch.cuda.stream(side):
+            c = bchar.Transfer.build(m, v, dt, opts=graph, stream=side)
+        side.synchronize()
+        bchar.profile_kernel_sampled("k_zsmooth", 3)
+        try:
+            d = bchar.Transfer.build(m, v, dt, opts=graph)
+            torch.cuda.synchronize()
+            launches, ms = bchar.profile_read()
+        finally:
+            bchar.profile_kernel(None)
+        assert a.stats["qp_cg"] > 0
+        assert launches > 0 and ms > 0.0
+        for t in (b, c, d):
+            _same(bchar, a, t)
+        # a rebuild (warm start) through the graphs too
+        a.rebuild(v, dt, opts=eager)
+        b.rebuild(v, dt, opts=graph)
+        _same(bchar, a, b)
+        for t in (a, b, c, d):
+            t.close()
