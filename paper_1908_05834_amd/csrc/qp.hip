@@ -67,9 +67,8 @@ constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those aft
 // thread i takes the partials i, i + kFinalThreads, ... in order, then a
 // fixed tree.  The order is fixed, so the result is reproducible.
 constexpr int kFinalThreads = 256;
-__global__ void __launch_bounds__(kFinalThreads) k_reduce_final_sum(
-    const double* __restrict__ part, int np, double* __restrict__ out) {
-  __shared__ double sh[32];
+__device__ __forceinline__ double block_final_sum(const double* __restrict__ part, int np,
+                                                  double* sh) {
   CSum acc;
   for (int i = threadIdx.x; i < np; i += kFinalThreads) {
     CSum o;
@@ -77,8 +76,14 @@ __global__ void __launch_bounds__(kFinalThreads) k_reduce_final_sum(
     o.lo = part[2 * i + 1];
     acc.add(o);
   }
-  const CSum t = block_csum(acc, sh);
-  if (threadIdx.x == 0) out[0] = t.value();
+  return block_csum(acc, sh).value();
+}
+
+__global__ void __launch_bounds__(kFinalThreads) k_reduce_final_sum(
+    const double* __restrict__ part, int np, double* __restrict__ out) {
+  __shared__ double sh[32];
+  const double v = block_final_sum(part, np, sh);
+  if (threadIdx.x == 0) out[0] = v;
 }
 
 __global__ void k_reduce_final_max(const double* __restrict__ part, int np,
@@ -212,6 +217,9 @@ constexpr int kFusedMaxNodes = 8192;
 constexpr int kFusedMaxLevels = 48;
 constexpr int kFusedLds = 7168;     // doubles of LDS for two iterates of every fused level
 constexpr int kFusedLdsTotal = 20464;  // doubles of LDS of the fused cycle (160 KiB with red)
+constexpr int kFusedThreads = 1024;   // the fused cycle's workgroup
+constexpr int kTouchRound = 16;       // line loads a thread issues before using them
+constexpr int kTouchMax = 512;        // ranges of the touch table
 
 struct FusedLevels {
   int count;                          // fused levels, the last is the coarsest
@@ -244,6 +252,13 @@ struct FusedLevels {
   // change), so that the cycle copies them into LDS in one coalesced pass
   double2* img;
   int img_vec;                        // 16-byte vectors of the image
+  // the arrays the cycle reads from global memory, as ranges of at most
+  // kFusedThreads 128-byte lines (a multiple of kTouchRound of them, the
+  // padding empty): the cycle touches every line once before its
+  // dependent phases
+  int ntouch;
+  const unsigned char* tbase[kTouchMax];
+  int tlines[kTouchMax];
 };
 
 // ---------------------------------------------------------------------- level kernels
@@ -759,19 +774,30 @@ __global__ void __launch_bounds__(1024) k_coarse_inverse(const int32_t* __restri
     }
     __syncthreads();
   }
-}
-
-__device__ __forceinline__ double block_sum_1024(double v, double* red) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  v = wave_sum(v);
+  // the cycle applies P G P, P = I - 1 1^T / n (the mean-free part):
+  // G_ij - rowmean_i - colmean_j + mean
+  __shared__ double rmean[kMaxCoarse], cmean[kMaxCoarse];
+  for (int i = tid; i < n; i += nt) {
+    double sr = 0, sc = 0;
+    for (int j = 0; j < n; ++j) {
+      sr += G[i * n + j];
+      sc += G[j * n + i];
+    }
+    rmean[i] = sr / n;
+    cmean[i] = sc / n;
+  }
   __syncthreads();
-  if (lane == 0) red[wv] = v;
+  if (tid == 0) {
+    double t = 0;
+    for (int i = 0; i < n; ++i) t += rmean[i];
+    s_piv = t / n;
+  }
   __syncthreads();
-  double r = 0;
-  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r += red[i];
-  __syncthreads();
-  return r;
+  const double tmean = s_piv;
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, j = e % n;
+    G[e] = G[e] - rmean[i] - cmean[j] + tmean;
+  }
 }
 
 // (b - L x)[p] for one node (graph indices 32-bit in global memory or
@@ -818,16 +844,6 @@ __global__ void k_fused_image(const FusedLevels* __restrict__ F) {
   }
 }
 
-// Value of element tid * stride of a[0, n) (0 past the end) plus the
-// elements (tid + k nt) * stride, k >= 1: one element per cache line of
-// the array, the first load of each thread issued without a loop.
-template <class T>
-__device__ __forceinline__ double touch_lines(const T* a, int n, int stride, int tid, int nt) {
-  double acc = tid * stride < n ? (double)a[tid * stride] : 0.0;
-  for (int q = tid + nt; q * stride < n; q += nt) acc += (double)a[q * stride];
-  return acc;
-}
-
 // The V-cycle below and including the first fused level, in one workgroup.
 // On entry F->b[0] holds that level's right-hand side; on exit F->x[0]
 // holds the cycle's result.  Two iterates of every fused level live in LDS
@@ -835,7 +851,7 @@ __device__ __forceinline__ double touch_lines(const T* a, int n, int stride, int
 // sweeps hit LDS and a Jacobi sweep is one pass and one barrier; the
 // graphs and right-hand sides stay in global memory (independent loads).
 // Every dependent phase is separated by a workgroup barrier.
-__global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restrict__ F) {
+__global__ void __launch_bounds__(kFusedThreads) k_fused_cycle(const FusedLevels* __restrict__ F) {
   __shared__ double red[16];
   __shared__ __attribute__((aligned(16))) double sh[kFusedLdsTotal];
   const int tid = threadIdx.x;
@@ -861,21 +877,21 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
       dst[i + 3 * nt] = a3;
     }
     for (; i < nv; i += nt) dst[i] = src[i];
-    double acc = 0.0;
-    for (int l = 0; l < L; ++l) {
-      const int n = F->n[l], ne = F->ne[l];
-      double t = touch_lines(F->diag[l], n, 16, tid, nt) + touch_lines(F->sdinv[l], n, 16, tid, nt);
-      if (l + 1 < L)
-        t += touch_lines(F->agg[l], n, 32, tid, nt) + touch_lines(F->mem[l], n, 32, tid, nt) +
-             touch_lines(F->mptr[l], F->n[l + 1] + 1, 32, tid, nt);
-      if (!F->gl[l])
-        t += touch_lines(F->w[l], ne, 16, tid, nt) + touch_lines(F->nbr[l], ne, 32, tid, nt) +
-             touch_lines(F->ptr[l], n + 1, 32, tid, nt);
-      acc += t;
+    // thread tid reads line tid of every range, kTouchRound ranges' loads
+    // issued before any is used
+    int acc = 0;
+    for (int r = 0; r < F->ntouch; r += kTouchRound) {
+      int v[kTouchRound];
+#pragma unroll
+      for (int u = 0; u < kTouchRound; ++u)
+        v[u] = tid < F->tlines[r + u]
+                   ? *reinterpret_cast<const int*>(F->tbase[r + u] + (size_t)tid * 128)
+                   : 0;
+#pragma unroll
+      for (int u = 0; u < kTouchRound; ++u) acc += v[u];
     }
-    if (F->dense) acc += touch_lines(F->G, F->n[L - 1] * F->n[L - 1], 16, tid, nt);
     // a store that never happens keeps the loads
-    if (acc == -1.0) red[0] = acc;
+    if (acc == -1) red[0] = acc;
   }
   __syncthreads();
   // level l's current iterate is xs + off[l] + (par[l] ? total : 0)
@@ -948,26 +964,17 @@ __global__ void __launch_bounds__(1024) k_fused_cycle(const FusedLevels* __restr
     const double* b = F->b[l];
     double* x = X(l);
     if (F->dense) {
-      double sb = 0;
-      for (int p = tid; p < n; p += nt) sb += b[p];
-      const double bmean = block_sum_1024(sb, red) / n;
-      // x = G (b - mean b): 16 lanes per row, rows strided over the groups
-      // (the 16 lanes of a group share i, so each shuffle stays in a group
-      // whose lanes are all active)
+      // x = P G P b with P = I - 1 1^T / n folded into G: 16 lanes per row,
+      // rows strided over the groups (the 16 lanes of a group share i, so
+      // each shuffle stays in a group whose lanes are all active)
       constexpr int kRowLanes = 16;
       const int sub = tid % kRowLanes;
-      double sx = 0;
       for (int i = tid / kRowLanes; i < n; i += nt / kRowLanes) {
         double acc = 0;
-        for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * (b[j] - bmean);
+        for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * b[j];
         for (int o = kRowLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if (sub == 0) {
-          x[i] = acc;
-          sx += acc;
-        }
+        if (sub == 0) x[i] = acc;
       }
-      const double xmean = block_sum_1024(sx, red) / n;
-      for (int i = tid; i < n; i += nt) x[i] -= xmean;
       __syncthreads();
     } else {
       // x = sdinv b was set with the restriction
@@ -1316,6 +1323,43 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     if (k + 1 < hf.count) H.fused_bytes += 8 * nk + 4 * (hf.n[k + 1] + 1);
   }
   if (H.dense) H.fused_bytes += 8 * (int64_t)H.coarse_n * H.coarse_n;
+  {
+    hf.ntouch = 0;
+    auto touch = [&](const void* a, int64_t bytes) {
+      const unsigned char* base = static_cast<const unsigned char*>(a);
+      for (int64_t lines = (bytes + 127) / 128; lines > 0;) {
+        const int take = (int)std::min<int64_t>(lines, kFusedThreads);
+        if (hf.ntouch >= kTouchMax) throw Error{BCHAR_E_UNSUPPORTED, "fused cycle: touch table"};
+        hf.tbase[hf.ntouch] = base;
+        hf.tlines[hf.ntouch] = take;
+        ++hf.ntouch;
+        base += (int64_t)take * 128;
+        lines -= take;
+      }
+    };
+    for (int k = 0; k < hf.count; ++k) {
+      const int64_t nk = hf.n[k], ek = hf.ne[k];
+      touch(hf.diag[k], 8 * nk);
+      touch(hf.sdinv[k], 8 * nk);
+      if (k + 1 < hf.count) {
+        touch(hf.agg[k], 4 * nk);
+        touch(hf.mem[k], 4 * nk);
+        touch(hf.mptr[k], 4 * (hf.n[k + 1] + 1));
+      }
+      if (!hf.gl[k]) {
+        touch(hf.w[k], 8 * ek);
+        touch(hf.nbr[k], 4 * ek);
+        touch(hf.ptr[k], 4 * (nk + 1));
+      }
+    }
+    if (H.dense) touch(H.G, 8 * (int64_t)H.coarse_n * H.coarse_n);
+    while (hf.ntouch % kTouchRound) {
+      if (hf.ntouch >= kTouchMax) throw Error{BCHAR_E_UNSUPPORTED, "fused cycle: touch table"};
+      hf.tbase[hf.ntouch] = nullptr;
+      hf.tlines[hf.ntouch] = 0;
+      ++hf.ntouch;
+    }
+  }
   H.fused = ws.get<FusedLevels>(1);
   H.fused_img = hf.img_vec > 0;
   BCHAR_HIP(hipMemcpyAsync(H.fused, &hf, sizeof(hf), hipMemcpyHostToDevice, s));
@@ -1368,7 +1412,7 @@ static void vcycle(Hierarchy& H, size_t l, hipStream_t s) {
     // this level and all coarser ones: one workgroup, one launch
     {
       ::bchar::ProfScope ps_("k_fused_cycle", s);
-      k_fused_cycle<<<1, 1024, 0, s>>>(H.fused);
+      k_fused_cycle<<<1, kFusedThreads, 0, s>>>(H.fused);
     }
     BCHAR_HIP(hipGetLastError());
     return;
@@ -1463,10 +1507,12 @@ __global__ void k_zcells(ZCells Z, double rel, double mu) {
 }
 
 // out = J_z z for cell K
-__device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __restrict__ zs,
-                                            const double* __restrict__ zg, int64_t K,
-                                            double& os, double& og) {
-  const double sK = zs[K], gK = zg[K];
+// (J_z v) at cell K, the (s, g) values of v at a cell M given by val(M, s, g)
+template <class V>
+__device__ __forceinline__ void zapply_cell_v(const ZCells& Z, V val, int64_t K, double& os,
+                                              double& og) {
+  double sK, gK;
+  val((int32_t)K, sK, gK);
   double fr = 0, fc = 0, fd = 0;
   // two entries a round with their loads issued together (same order of
   // accumulation as one at a time)
@@ -1482,10 +1528,7 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
       wv[u] = Z.w[k + u];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      sv[u] = zs[M[u]];
-      gv[u] = zg[M[u]];
-    }
+    for (int u = 0; u < U; ++u) val(M[u], sv[u], gv[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (M[u] == (int32_t)K)
@@ -1496,10 +1539,13 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
   }
   for (; k < kend; ++k) {
     const int32_t M = Z.col[k];
-    if (M == (int32_t)K)
+    if (M == (int32_t)K) {
       fd = Z.w[k] * gK;
-    else
-      fr += Z.w[k] * ((sK - zs[M]) + 0.5 * (gK + zg[M]));
+    } else {
+      double sM, gM;
+      val(M, sM, gM);
+      fr += Z.w[k] * ((sK - sM) + 0.5 * (gK + gM));
+    }
   }
   const int32_t eend = Z.cptr[K + 1];
   int32_t e = Z.cptr[K];
@@ -1512,20 +1558,42 @@ __device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __res
       wv[u] = Z.wc[e + u];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      sv[u] = zs[I[u]];
-      gv[u] = zg[I[u]];
-    }
+    for (int u = 0; u < U; ++u) val(I[u], sv[u], gv[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (I[u] != (int32_t)K) fc += wv[u] * ((sv[u] - sK) + 0.5 * (gv[u] + gK));
   }
   for (; e < eend; ++e) {
     const int32_t I = Z.crow[e];
-    if (I != (int32_t)K) fc += Z.wc[e] * ((zs[I] - sK) + 0.5 * (zg[I] + gK));
+    if (I != (int32_t)K) {
+      double sI, gI;
+      val(I, sI, gI);
+      fc += Z.wc[e] * ((sI - sK) + 0.5 * (gI + gK));
+    }
   }
   os = fr - fc + Z.tau_s[K] * sK;
   og = 0.5 * (fr + fc) + fd + Z.tau_g[K] * gK;
+}
+
+__device__ __forceinline__ void zapply_cell(const ZCells& Z, const double* __restrict__ zs,
+                                            const double* __restrict__ zg, int64_t K,
+                                            double& os, double& og) {
+  zapply_cell_v(
+      Z,
+      [&](int32_t M, double& sv, double& gv) {
+        sv = zs[M];
+        gv = zg[M];
+      },
+      K, os, og);
+}
+
+// the first block-Jacobi sweep from zero at cell M: x1 = omega B^-1 b
+__device__ __forceinline__ void zfirst_sweep(const ZCells& Z, double omega,
+                                             const double* __restrict__ b, int32_t M, double& s,
+                                             double& g) {
+  const double bs = b[M], bg = b[Z.n + M];
+  s = omega * (Z.bi[3 * M] * bs + Z.bi[3 * M + 1] * bg);
+  g = omega * (Z.bi[3 * M + 1] * bs + Z.bi[3 * M + 2] * bg);
 }
 
 // out = J_z z; with `part`, also the compensated block sums of z . out
@@ -1557,9 +1625,26 @@ __global__ void k_zsmooth_first(ZCells Z, double omega, const double* __restrict
                                 double* __restrict__ x) {
   const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= Z.n) return;
+  zfirst_sweep(Z, omega, b, (int32_t)K, x[K], x[Z.n + K]);
+}
+
+// the first two sweeps from zero in one pass: x1 = omega B^-1 b is formed
+// wherever it is gathered, xo = x1 + omega B^-1 (b - J_z x1)
+__global__ void __launch_bounds__(kT) k_zsmooth_two(ZCells Z, double omega,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ xo) {
+  const int64_t K = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (K >= Z.n) return;
+  double os, og;
+  zapply_cell_v(
+      Z, [&](int32_t M, double& sv, double& gv) { zfirst_sweep(Z, omega, b, M, sv, gv); }, K,
+      os, og);
+  double xs, xg;
+  zfirst_sweep(Z, omega, b, (int32_t)K, xs, xg);
   const double bs = b[K], bg = b[Z.n + K];
-  x[K] = omega * (Z.bi[3 * K] * bs + Z.bi[3 * K + 1] * bg);
-  x[Z.n + K] = omega * (Z.bi[3 * K + 1] * bs + Z.bi[3 * K + 2] * bg);
+  const double rs = bs - os, rg = bg - og;
+  xo[K] = xs + omega * (Z.bi[3 * K] * rs + Z.bi[3 * K + 1] * rg);
+  xo[Z.n + K] = xg + omega * (Z.bi[3 * K + 1] * rs + Z.bi[3 * K + 2] * rg);
 }
 
 // xo = xi + omega B^-1 (b - J_z xi); with `part`, also the compensated
@@ -1653,11 +1738,16 @@ static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   const unsigned gb = blocks_for(n, kT);
   double* x = P.x;
   double* x2 = P.x2;
-  {
+  int k0 = 1;
+  if (P.pre >= 2) {
+    ::bchar::ProfScope ps_("k_zsmooth_two", s);
+    k_zsmooth_two<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x);
+    k0 = 2;
+  } else {
     ::bchar::ProfScope ps_("k_zsmooth_first", s);
     k_zsmooth_first<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x);
   }
-  for (int k = 1; k < P.pre; ++k) {
+  for (int k = k0; k < P.pre; ++k) {
     {
       ::bchar::ProfScope ps_("k_zsmooth", s);
       k_zsmooth<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x, x2, nullptr);
@@ -1812,15 +1902,41 @@ __global__ void k_sub_scalar(double* __restrict__ v, const double* __restrict__ 
   if (i < n) v[i] -= sum[0] * inv_n;
 }
 
-// CG vector updates with device scalars sc[0] = rz, sc[1] = pq
-__global__ void k_cg_update(const double* __restrict__ rz, const double* __restrict__ pq,
-                            int64_t n, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ q) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double alpha = *pq != 0.0 ? *rz / *pq : 0.0;
-  x[i] += alpha * p[i];
-  r[i] -= alpha * q[i];
+// CG vector updates (x += alpha p, r -= alpha q; p = z + beta p) with the
+// scalar they need summed from the block partials of the kernel before
+// (k_zop: p.q; the preconditioner's last sweep: r.z) inside the kernel:
+// every block sums all partials exactly as k_reduce_final_sum does (the
+// same bits), so no launch sits between.  A
+// grid of at most kCgBlocks blocks (grid-stride) keeps the repeated reads
+// of the partials small.
+constexpr int kCgBlocks = 512;
+
+__global__ void __launch_bounds__(kFinalThreads) k_cg_update_part(
+    const double* __restrict__ rz, const double* __restrict__ part, int np, int64_t n,
+    double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q) {
+  __shared__ double sh[32];
+  const double pq = block_final_sum(part, np, sh);
+  const double alpha = pq != 0.0 ? *rz / pq : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kFinalThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kFinalThreads + threadIdx.x; i < n; i += stride) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+// also stores the new r.z (block 0) for the next update
+__global__ void __launch_bounds__(kFinalThreads) k_cg_dir_part(
+    const double* __restrict__ rz_old, const double* __restrict__ part, int np,
+    double* __restrict__ rz_new, int64_t n, const double* __restrict__ z,
+    double* __restrict__ p) {
+  __shared__ double sh[32];
+  const double rzn = block_final_sum(part, np, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_new = rzn;
+  const double beta = *rz_old != 0.0 ? rzn / *rz_old : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kFinalThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kFinalThreads + threadIdx.x; i < n; i += stride)
+    p[i] = z[i] + beta * p[i];
 }
 
 // p = z + (rz_new / rz_old) p
@@ -2348,18 +2464,15 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // One CG iteration split after its update: the update half (product
   // J p, p.q, x/r update with r.z in rz) and units that run the next
   // iteration's preconditioner (r.z into rz_next), direction and update.
+  const unsigned gcg = std::min<unsigned>(gn2, kCgBlocks);
   auto cg_update_half = [&](const double* rzc, hipStream_t st) {
     {
       ::bchar::ProfScope ps_("k_zop", st);
       k_zop<<<gn, kT, 0, st>>>(P.Z, cp, cq, zpart);
     }
     {
-      ::bchar::ProfScope ps_("k_reduce_final_sum", st);
-      k_reduce_final_sum<<<1, kFinalThreads, 0, st>>>(zpart, (int)gn, red.out + 9);
-    }
-    {
-      ::bchar::ProfScope ps_("k_cg_update", st);
-      k_cg_update<<<gn2, kT, 0, st>>>(rzc, red.out + 9, n2, cx, cr, cp, cq);
+      ::bchar::ProfScope ps_("k_cg_update_part", st);
+      k_cg_update_part<<<gcg, kFinalThreads, 0, st>>>(rzc, zpart, (int)gn, n2, cx, cr, cp, cq);
     }
     BCHAR_HIP(hipGetLastError());
   };
@@ -2369,12 +2482,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     rs.s = st;
     for (int u = 0; u < units; ++u) {
       if (zprecondition(P, cr, cz, st, zpart)) {
-        ::bchar::ProfScope ps_("k_reduce_final_sum", st);
-        k_reduce_final_sum<<<1, kFinalThreads, 0, st>>>(zpart, (int)gn, b);
+        ::bchar::ProfScope ps_("k_cg_dir_part", st);
+        k_cg_dir_part<<<gcg, kFinalThreads, 0, st>>>(a, zpart, (int)gn, b, n2, cz, cp);
       } else {
         rs.dot(cr, cz, n2, (int)(b - red.out));
-      }
-      {
         ::bchar::ProfScope ps_("k_cg_dir", st);
         k_cg_dir<<<gn2, kT, 0, st>>>(a, b, n2, cz, cp);
       }
@@ -2455,9 +2566,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       fill_f64(cx, 0.0, n2, s);
     }
     // scalars: r.z alternates between out[8] and out[10] (the current one
-    // and the next), out[9] = p.q, out[11] = max |r|; the dot products are
-    // summed from the block sums that k_zop and the last sweep of the
-    // preconditioner leave in zpart
+    // and the next), out[11] = max |r|; p.q and the new r.z are summed
+    // inside the update kernels from the block sums that k_zop and the last
+    // sweep of the preconditioner leave in zpart
     zprecondition(P, cr, cz, s);
     BCHAR_HIP(hipMemcpyAsync(cp, cz, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
     red.dot(cr, cz, n2, 8);
