@@ -457,6 +457,8 @@ def main():
     ap.add_argument("--cg-graphs", type=int, choices=[0, 1], default=1,
                     help="replay the CG iterations from captured HIP graphs (1) or launch "
                          "every kernel from the host (0)")
+    ap.add_argument("--cycle-skip", type=int, choices=[0, 1], default=0,
+                    help="multigrid cycle visiting every other level (opts.cycle_skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--workload", choices=["swirl", "tets", "mixed", "serve"], default="swirl")
@@ -536,7 +538,8 @@ def main():
                     f"phi = 1, dt = 1/128, transfer rebuilt every step")
         metric = "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency"
     prec = bchar.FP64 if args.precision == "fp64" else bchar.FP32_VOLUME
-    opts = bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs)
+    opts = bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs,
+                              cycle_skip=args.cycle_skip)
     M = bchar.Mesh(w["mesh"], layout)
     # phase 1: one build after another (per-step latency); phase 2: D builds
     # at once (throughput, the reported value).  Every interval's velocity
@@ -691,6 +694,7 @@ def main():
         "config": {"workload": workload,
                    "n_cells": n_cells, "precision": args.precision, "nnz": nnz,
                    "inflight_builds": D, "cg_graphs": args.cg_graphs,
+                   "cycle_skip": args.cycle_skip,
                    "qp_ipm_mean": float(np.mean([s_["qp_ipm"] for s_ in stats])),
                    "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in stats])),
                    "qp_levels": sorted({s_["qp_level"] for s_ in stats})},

@@ -166,6 +166,13 @@ typedef struct {
                             captured once per solve as HIP graphs of four
                             iterations and replayed (same kernels, same
                             results bit for bit; fewer host launches)    */
+  int cycle_skip;        /* non-zero: the preconditioner's multigrid cycle
+                            visits every other level of the pairwise
+                            hierarchy (aggregates of about four nodes,
+                            exact Galerkin operators): half the launches
+                            per cycle, a weaker cycle.  Default 0 (every
+                            level); the same solution either way, only
+                            the iteration count and time change          */
 } bchar_opts;
 
 typedef struct {

@@ -1008,7 +1008,8 @@ struct Hierarchy {
   int pre = 1, post = 1;             // sweeps of the fused coarse levels
   int coarse_sweeps = 40;
   size_t fused_first = 0;          // first level handled by k_fused_cycle
-  int skip = 1;                    // launched levels from this one pass over every other level
+  int skip = 0;                    // launched levels from this one pass over every other
+                                   // level (0: every level is visited)
   FusedLevels* fused = nullptr;    // device copy
   bool fused_img = false;          // it has an LDS image to refresh
   int64_t fused_bytes = 0;         // bytes one fused cycle reads or writes at least
@@ -2407,6 +2408,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     dmax = red.fetch(0);
   }
   Hierarchy H;
+  H.skip = o.cycle_skip ? 1 : 0;
   const double th0 = trace_enabled() ? wall_seconds() : 0.0;
   build_hierarchy(H, fine, row_ptr, col, Q.a, n, ws, s);
   if (trace_enabled()) {

@@ -151,14 +151,14 @@ def test_scaling(env, name):
     assert err <= 1e-12
 
 
-def _full(env, name, precision="fp64"):
+def _full(env, name, precision="fp64", **opts):
     torch, bchar = env
     mesh, vel, dt, layout = _case(name)
     ref = otr.build_transfer(mesh, vel, dt, layout=layout, precision=precision)
     M = bchar.Mesh(mesh, layout)
     U = bchar.VelocityLattice(vel)
     prec = bchar.FP64 if precision == "fp64" else bchar.FP32_VOLUME
-    T = bchar.Transfer.build(M, U, dt, bchar.opts_default(precision=prec))
+    T = bchar.Transfer.build(M, U, dt, bchar.opts_default(precision=prec, **opts))
     return torch, bchar, mesh, ref, M, T
 
 
@@ -168,8 +168,20 @@ def _full(env, name, precision="fp64"):
                                   "tets_porous", "tris", "tris_porous", "mixed_tri",
                                   "mixed_hex"])
 def test_full_step(env, name):
-    _say(f"[gpu] full step {name}")
-    torch, bchar, mesh, ref, M, T = _full(env, name)
+    _check_full_step(env, name)
+
+
+# the cycle that visits every other level (opts.cycle_skip) is another
+# preconditioner for the same systems: the same solution to the same bar
+@pytest.mark.parametrize("name", ["swirl3d_subcell_16", "solid_inscribed", "tets", "tris",
+                                  "mixed_hex"])
+def test_full_step_cycle_skip(env, name):
+    _check_full_step(env, name, cycle_skip=1)
+
+
+def _check_full_step(env, name, **opts):
+    _say(f"[gpu] full step {name} {opts}")
+    torch, bchar, mesh, ref, M, T = _full(env, name, **opts)
     st = T.stats
     _say(f"    stats {st}; oracle level {ref['qp']['level']} it {ref['qp']['iterations']}")
     assert st["qp_level"] == ref["qp"]["level"]
