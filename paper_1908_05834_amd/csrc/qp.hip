@@ -774,30 +774,20 @@ __global__ void __launch_bounds__(1024) k_coarse_inverse(const int32_t* __restri
     }
     __syncthreads();
   }
-  // the cycle applies P G P, P = I - 1 1^T / n (the mean-free part):
-  // G_ij - rowmean_i - colmean_j + mean
-  __shared__ double rmean[kMaxCoarse], cmean[kMaxCoarse];
-  for (int i = tid; i < n; i += nt) {
-    double sr = 0, sc = 0;
-    for (int j = 0; j < n; ++j) {
-      sr += G[i * n + j];
-      sc += G[j * n + i];
-    }
-    rmean[i] = sr / n;
-    cmean[i] = sc / n;
-  }
+}
+
+// sum over the fused cycle's workgroup (every thread gets it)
+__device__ __forceinline__ double block_sum_fused(double v, double* red) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  v = wave_sum(v);
   __syncthreads();
-  if (tid == 0) {
-    double t = 0;
-    for (int i = 0; i < n; ++i) t += rmean[i];
-    s_piv = t / n;
-  }
+  if (lane == 0) red[wv] = v;
   __syncthreads();
-  const double tmean = s_piv;
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, j = e % n;
-    G[e] = G[e] - rmean[i] - cmean[j] + tmean;
-  }
+  double r = 0;
+  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r += red[i];
+  __syncthreads();
+  return r;
 }
 
 // (b - L x)[p] for one node (graph indices 32-bit in global memory or
@@ -964,17 +954,29 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused_cycle(const FusedLevels
     const double* b = F->b[l];
     double* x = X(l);
     if (F->dense) {
-      // x = P G P b with P = I - 1 1^T / n folded into G: 16 lanes per row,
-      // rows strided over the groups (the 16 lanes of a group share i, so
-      // each shuffle stays in a group whose lanes are all active)
+      // x = G (b - mean b), then its mean removed: G carries the nearly
+      // singular constant mode with a huge weight, which the mean-free
+      // right-hand side leaves out and the last step discards (folding the
+      // projections into G instead cancels catastrophically).  16 lanes per
+      // row, rows strided over the groups (the 16 lanes of a group share
+      // i, so each shuffle stays in a group whose lanes are all active)
+      double sb = 0;
+      for (int p = tid; p < n; p += nt) sb += b[p];
+      const double bmean = block_sum_fused(sb, red) / n;
       constexpr int kRowLanes = 16;
       const int sub = tid % kRowLanes;
+      double sx = 0;
       for (int i = tid / kRowLanes; i < n; i += nt / kRowLanes) {
         double acc = 0;
-        for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * b[j];
+        for (int j = sub; j < n; j += kRowLanes) acc += F->G[i * n + j] * (b[j] - bmean);
         for (int o = kRowLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if (sub == 0) x[i] = acc;
+        if (sub == 0) {
+          x[i] = acc;
+          sx += acc;
+        }
       }
+      const double xmean = block_sum_fused(sx, red) / n;
+      for (int i = tid; i < n; i += nt) x[i] -= xmean;
       __syncthreads();
     } else {
       // x = sdinv b was set with the restriction
