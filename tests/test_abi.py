@@ -70,3 +70,72 @@ def test_server_rejects_bad_arguments_without_device():
     t = C.c_int64()
     assert bchar._server_submit(None, None, C.byref(t)) == bchar.E_INVALID_ARG
     assert bchar._server_destroy(None) == bchar.OK
+
+
+def _struct_fields(name):
+    """Member names of `typedef struct { ... } name;` in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct\s*\{((?:(?!typedef).)*?)\}\s*" + name + r"\s*;", text,
+                  flags=re.S)
+    assert m, name
+    out = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if decl:
+            # every declarator of the line: `double a, b, c`, `int64_t n[3]`
+            out.extend(re.findall(r"(\w+)\s*(?:\[[^\]]*\])?\s*(?:,|$)", decl))
+    return out
+
+
+def test_binding_structs_mirror_the_header():
+    from paper_1908_05834_amd import bchar
+    pairs = [("bchar_mesh_desc", bchar.MeshDesc), ("bchar_velocity", bchar.Velocity),
+             ("bchar_opts", bchar.Opts), ("bchar_stats", bchar.Stats),
+             ("bchar_build_job", bchar.BuildJob), ("bchar_request", bchar.Request),
+             ("bchar_request_result", bchar.RequestResult)]
+    for cname, py in pairs:
+        assert [f for f, _ in py._fields_] == _struct_fields(cname), cname
+
+
+def test_option_defaults_of_the_solver():
+    from paper_1908_05834_amd import bchar
+    o = bchar.opts_default()
+    # CG iterations replayed from graphs, every multigrid level visited,
+    # voids reported rather than remedied
+    assert o.cg_graphs == 1 and o.cycle_skip == 0 and o.max_halvings == 0
+    assert o.warm_start == 1 and o.qp_max_cg == 400
+
+
+def test_binding_struct_offsets_match_the_c_compiler(tmp_path):
+    """sizeof and every member offset of the ctypes mirrors against what gcc
+    lays out for the header's structs."""
+    import shutil
+    import subprocess
+
+    import pytest
+
+    from paper_1908_05834_amd import bchar
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("bchar_mesh_desc", bchar.MeshDesc), ("bchar_velocity", bchar.Velocity),
+             ("bchar_opts", bchar.Opts), ("bchar_stats", bchar.Stats),
+             ("bchar_build_job", bchar.BuildJob), ("bchar_request", bchar.Request),
+             ("bchar_request_result", bchar.RequestResult)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bchar.h"', "int main(void) {"]
+    for cname, _ in pairs:
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in _struct_fields(cname):
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, py in pairs:
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
