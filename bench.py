@@ -86,13 +86,19 @@ KERNEL_SOURCES = {"k_smooth": "qp.hip", "k_zsmooth": "qp.hip", "k_fused_cycle": 
 
 
 def source_digest(kernel):
-    """Digest of the sources of ``kernel``: a measured traffic figure is
-    valid only for the code it was measured on."""
+    """Digest of the code of ``kernel``'s sources (comments and layout left
+    out): a measured traffic figure is valid only for the code it was
+    measured on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in (KERNEL_SOURCES[kernel], "device_util.hpp"):
-        with open(os.path.join(SRC, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(SRC, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = re.sub(r"\s+", " ", text)
+        h.update((f + text).encode())
     return h.hexdigest()[:16]
 
 

@@ -1226,9 +1226,10 @@ static void build_hierarchy(Hierarchy& H, Level fine, const int32_t* rptr, const
     --first;
   }
   H.fused_first = first;
-  // the launched levels of the cycle: from level 1, passing over every
-  // other level (aggregates of about four nodes) while that lands at or
-  // above the fused levels; each restricts its residual through R L
+  // the launched levels of the cycle: from level 1, every level, or with
+  // skip every other level (aggregates of about four nodes) while that
+  // lands at or above the fused levels; each restricts its residual
+  // through R L
   int64_t launched = 0;
   H.smooth_bytes = 0;
   for (size_t l = 1; l < first;) {
