@@ -186,3 +186,32 @@ def test_cg_graph_replay_equals_eager_launches(env):
         _same(bchar, a, b)
         for t in (a, b, c, d):
             t.close()
+
+
+def test_cg_graph_replay_at_small_iteration_caps(env):
+    """Where the cap on CG iterations cuts a replay short (caps 3, 6, 8: no
+    replay, the first replay then single iterations, both replays) the
+    graph path takes the same iterations as the eager loop: the same
+    transfer bit for bit, or the same error."""
+    torch, bchar = env
+    w = inputs.swirl_hex(8)
+    M = bchar.Mesh(w["mesh"], "subcell")
+    U = bchar.VelocityLattice(w["vel_fn"](2))
+    for cap in (3, 6, 8):
+        _say(f"[gpu] cg cap {cap}")
+        got = []
+        for graphs in (0, 1):
+            o = bchar.opts_default(cg_graphs=graphs, qp_max_cg=cap, qp_max_newton=60)
+            try:
+                got.append(("ok", bchar.Transfer.build(M, U, 0.05, opts=o)))
+            except bchar.BcharError as e:
+                st = e.stats or {}
+                got.append(("err", (e.status, st.get("qp_cg"), st.get("qp_ipm"),
+                                    st.get("qp_newton"), st.get("qp_level"))))
+        assert got[0][0] == got[1][0], cap
+        if got[0][0] == "ok":
+            _same(bchar, got[0][1], got[1][1])
+            for _, t in got:
+                t.close()
+        else:
+            assert got[0][1] == got[1][1], cap
