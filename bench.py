@@ -102,15 +102,22 @@ def source_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+# the workload the committed counter runs measure (the default bench run)
+TRAFFIC_WORKLOAD_KEY = "swirl-64-fp64"
+
+
+def measured_traffic(kernel, workload_key):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 --pmc
     measurement (profiles/traffic_<kernel>.json), or None when there is
-    none or the sources changed since it was taken."""
+    none, it was taken on another workload, or the sources changed since
+    it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    if rec.get("workload_key") != workload_key:
+        return None
     if rec.get("source_digest") != source_digest(kernel):
         return None
     return rec.get("bytes_per_launch")
@@ -190,7 +197,8 @@ def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, work
     for k in TRAFFIC_KERNELS:
         if k not in f or k not in w:
             continue
-        rec = {"kernel": k, "workload": workload, "commands": commands,
+        rec = {"kernel": k, "workload": workload, "workload_key": TRAFFIC_WORKLOAD_KEY,
+               "commands": commands,
                "dispatches": f[k]["dispatches"],
                "fetch_kib_per_dispatch": f[k]["kib_per_dispatch"],
                "write_kib_per_dispatch": w[k]["kib_per_dispatch"],
@@ -673,7 +681,7 @@ def main():
         avg_s = total_ms / 1e3 / n_launch
         alg = algorithmic_bytes(kernel, n_cells, st["nnz"], M.n_balls, st)
         achieved = alg / avg_s / 1e9
-        traffic = measured_traffic(kernel)
+        traffic = measured_traffic(kernel, f"{args.workload}-{args.n}-{args.precision}")
         return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches": n_launch, "avg_us": avg_s * 1e6,
