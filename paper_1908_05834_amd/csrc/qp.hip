@@ -58,6 +58,7 @@ constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 constexpr int kCrossoverSteps = 2; // fixed-side Newton steps from an interior point
 constexpr double kCrossoverRatio = 1e-3;  // slack / multiplier of a pinned entry
+constexpr int64_t kZsmoothTwoMaxCells = 1 << 20;  // k_zsmooth_two up to this size
 constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those after an
                                    // interior point that met tol
 
@@ -1743,7 +1744,10 @@ static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   double* x = P.x;
   double* x2 = P.x2;
   int k0 = 1;
-  if (P.pre >= 2) {
+  // one pass for the first two sweeps saves a launch where launches cost
+  // (up to ~10^6 cells); beyond, its wider gathers (b and B^-1 of every
+  // neighbour instead of its iterate) cost more than the pass it saves
+  if (P.pre >= 2 && n <= kZsmoothTwoMaxCells) {
     ::bchar::ProfScope ps_("k_zsmooth_two", s);
     k_zsmooth_two<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x);
     k0 = 2;
