@@ -102,8 +102,10 @@ def source_digest(kernel):
     return h.hexdigest()[:16]
 
 
-# the workload the committed counter runs measure (the default bench run)
-TRAFFIC_WORKLOAD_KEY = "swirl-64-fp64"
+def workload_key(workload, n, precision, cycle_skip):
+    """The configuration a traffic figure belongs to: workload, size,
+    precision and multigrid cycle (the cycle changes the launched levels)."""
+    return f"{workload}-{n}-{precision}-skip{int(cycle_skip)}"
 
 
 def measured_traffic(kernel, workload_key):
@@ -176,7 +178,7 @@ def pmc_summary(prof_dir, counter, out):
     print(json.dumps(res))
 
 
-def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, workload):
+def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, workload, key):
     """profiles/traffic_<kernel>.json from the four counter summaries: the
     kernel's FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
     same counter reads for a plain device copy of copy_mib MiB (read once,
@@ -197,7 +199,7 @@ def write_traffic(fetch, write, copy_fetch, copy_write, copy_mib, commands, work
     for k in TRAFFIC_KERNELS:
         if k not in f or k not in w:
             continue
-        rec = {"kernel": k, "workload": workload, "workload_key": TRAFFIC_WORKLOAD_KEY,
+        rec = {"kernel": k, "workload": workload, "workload_key": key,
                "commands": commands,
                "dispatches": f[k]["dispatches"],
                "fetch_kib_per_dispatch": f[k]["kib_per_dispatch"],
@@ -472,7 +474,10 @@ def main():
                     help="replay the CG iterations from captured HIP graphs (1) or launch "
                          "every kernel from the host (0)")
     ap.add_argument("--cycle-skip", type=int, choices=[0, 1], default=0,
-                    help="multigrid cycle visiting every other level (opts.cycle_skip)")
+                    help="multigrid cycle visiting every other level (opts.cycle_skip), "
+                         "with --tune 0")
+    ap.add_argument("--tune", type=int, choices=[0, 1], default=1,
+                    help="swirl/tets: choose cycle_skip by measuring both (bchar_tune_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--workload", choices=["swirl", "tets", "mixed", "serve"], default="swirl")
@@ -488,6 +493,8 @@ def main():
     ap.add_argument("--traffic-json", nargs=5,
                     metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "COPY_MIB"),
                     help="only write profiles/traffic_<kernel>.json from four summaries")
+    ap.add_argument("--traffic-cycle-skip", type=int, choices=[0, 1], default=0,
+                    help="with --traffic-json: the cycle the counter runs used")
     args = ap.parse_args()
 
     if args.pmc_sum:
@@ -496,13 +503,16 @@ def main():
     if args.traffic_json:
         fe, wr, cfe, cwr, mib = args.traffic_json
         cmd = "rocprofv3 --pmc {c} --output-format csv -d /tmp/pmc_{t} -o p -- python3 bench.py {a}"
-        run = "--steps 1 --warmup 1 --inflight 1 --no-cpu-baseline"
+        sk = args.traffic_cycle_skip
+        run = f"--steps 1 --warmup 1 --inflight 1 --no-cpu-baseline --tune 0 --cycle-skip {sk}"
         write_traffic(fe, wr, cfe, cwr, int(mib),
                       [cmd.format(c="FETCH_SIZE", t="f", a=run),
                        cmd.format(c="WRITE_SIZE", t="w", a=run),
                        cmd.format(c="FETCH_SIZE", t="cf", a=f"--copy-calibration {mib}"),
                        cmd.format(c="WRITE_SIZE", t="cw", a=f"--copy-calibration {mib}")],
-                      "3D swirl, 64^3 hexahedra, 8 balls per cell, FP64")
+                      "3D swirl, 64^3 hexahedra, 8 balls per cell, FP64"
+                      + (", cycle visiting every other level" if sk else ""),
+                      workload_key("swirl", 64, "fp64", sk))
         return
 
     if args.copy_calibration:
@@ -579,6 +589,20 @@ def main():
         e = abs(m - m0) / abs(m0)
         mass_err = max(mass_err, e)
         return nxt, c, e
+
+    # ---- autotuning (untimed): which multigrid cycle builds D transfers in
+    # flight fastest on this workload, measured by the library on the first
+    # intervals (bchar_tune_options), unless --tune 0 fixes it
+    tuned = None
+    if args.tune:
+        cands = [bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs, cycle_skip=v)
+                 for v in (0, 1)]
+        tune_streams = [torch.cuda.Stream() for _ in range(D)]
+        best, secs = bchar.tune_options([(M, vels[j % len(vels)], w["dt"]) for j in range(D)],
+                                        cands, tune_streams, rounds=2)
+        opts = cands[best]
+        tuned = {"option": "cycle_skip", "values": [0, 1], "seconds": secs, "chosen": best}
+        log(f"tuned: cycle_skip {best} ({secs[0]:.3f} s against {secs[1]:.3f} s)")
 
     # ---- phase 1: sequential
     c, nxt = c0.clone(), torch.empty_like(c0)
@@ -681,7 +705,8 @@ def main():
         avg_s = total_ms / 1e3 / n_launch
         alg = algorithmic_bytes(kernel, n_cells, st["nnz"], M.n_balls, st)
         achieved = alg / avg_s / 1e9
-        traffic = measured_traffic(kernel, f"{args.workload}-{args.n}-{args.precision}")
+        traffic = measured_traffic(kernel, workload_key(args.workload, args.n, args.precision,
+                                                        opts.cycle_skip))
         return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches": n_launch, "avg_us": avg_s * 1e6,
@@ -708,7 +733,7 @@ def main():
         "config": {"workload": workload,
                    "n_cells": n_cells, "precision": args.precision, "nnz": nnz,
                    "inflight_builds": D, "cg_graphs": args.cg_graphs,
-                   "cycle_skip": args.cycle_skip,
+                   "cycle_skip": int(opts.cycle_skip), "tuned": tuned,
                    "qp_ipm_mean": float(np.mean([s_["qp_ipm"] for s_ in stats])),
                    "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in stats])),
                    "qp_levels": sorted({s_["qp_level"] for s_ in stats})},

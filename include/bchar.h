@@ -281,6 +281,25 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
                                         const bchar_opts* opts, void* const* streams,
                                         int n_streams);
 
+/* Autotuning of the options for a workload: which of n_candidates option
+ * sets builds the given jobs fastest, measured.  The jobs (mesh, u, dt;
+ * transfer and warm_from must be NULL, nothing is written to them) are
+ * built once untimed, then `rounds` times per candidate as
+ * bchar_build_transfer_batch would on the same streams (new transfers,
+ * destroyed again), the candidates' order reversed every other round;
+ * the host clock times each batch, GPU work included.  On return *best is
+ * the candidate with the least summed time and seconds[c] (may be NULL)
+ * that sum, +inf for a candidate whose builds failed.  Every candidate
+ * yields the same transfers up to the solver's tolerance; only the time
+ * differs (e.g. cycle_skip, cg_graphs, precision).  Errors: INVALID_ARG
+ * (NULL arrays, a count < 1, a job with a transfer or without a mesh or
+ * velocity, an invalid candidate), the first failure if every candidate
+ * fails.                                                               */
+bchar_status bchar_tune_options(const bchar_build_job* jobs, int n_jobs,
+                                const bchar_opts* candidates, int n_candidates, int rounds,
+                                void* const* streams, int n_streams, int* best,
+                                double* seconds);
+
 /* ---- serving: a queue of independent requests ---------------------- */
 
 typedef struct bchar_server_s* bchar_server;

@@ -134,6 +134,9 @@ _server_destroy = _sig("bchar_server_destroy", [C.c_void_p])
 
 _build_batch = _sig("bchar_build_transfer_batch", [C.POINTER(BuildJob), C.c_int, C.POINTER(Opts),
                                                    C.POINTER(C.c_void_p), C.c_int])
+_tune_options = _sig("bchar_tune_options", [C.POINTER(BuildJob), C.c_int, C.POINTER(Opts), C.c_int,
+                                            C.c_int, C.POINTER(C.c_void_p), C.c_int, _ip,
+                                            C.POINTER(C.c_double)])
 _profile_read = _sig("bchar_profile_read", [_i64p, C.POINTER(C.c_double)])
 
 EXPORTED = [
@@ -145,6 +148,7 @@ EXPORTED = [
     "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
     "bchar_build_transfer_batch", "bchar_profile_kernel_sampled",
     "bchar_server_create", "bchar_server_submit", "bchar_server_wait", "bchar_server_destroy",
+    "bchar_tune_options",
 ]
 
 
@@ -425,6 +429,30 @@ def build_batch(jobs, opts=None, streams=None, check=True):
         return out, [arr[i].status for i in range(len(jobs))]
     _check(rc)
     return out
+
+
+def tune_options(jobs, candidates, streams=None, rounds=2):
+    """Which option set builds ``jobs`` fastest (bchar_tune_options).
+
+    ``jobs``: ``(mesh, velocity, dt)`` triples; ``candidates``: Opts;
+    ``streams``: torch streams (or raw handles), one worker each.  Returns
+    ``(best_index, seconds)`` with the summed wall time of every candidate
+    (inf where its builds failed)."""
+    import torch
+    if streams is None:
+        streams = [torch.cuda.current_stream()]
+    arr = (BuildJob * len(jobs))()
+    for i, (mesh, vel, dt) in enumerate(jobs):
+        arr[i].mesh = _handle_value(mesh.handle)
+        arr[i].u = C.pointer(vel.struct)
+        arr[i].dt = float(dt)
+    cands = (Opts * len(candidates))(*candidates)
+    sp = (C.c_void_p * len(streams))(*[_stream_ptr(s).value for s in streams])
+    best = C.c_int(-1)
+    secs = (C.c_double * len(candidates))()
+    _check(_tune_options(arr, len(jobs), cands, len(candidates), int(rounds), sp, len(streams),
+                         C.byref(best), secs))
+    return best.value, list(secs)
 
 
 class Server:

@@ -856,6 +856,64 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
   });
 }
 
+bchar_status bchar_tune_options(const bchar_build_job* jobs, int n_jobs,
+                                const bchar_opts* candidates, int n_candidates, int rounds,
+                                void* const* streams, int n_streams, int* best,
+                                double* seconds) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(jobs != nullptr && n_jobs >= 1 && candidates != nullptr && n_candidates >= 1 &&
+                      rounds >= 1 && streams != nullptr && n_streams >= 1 && best != nullptr,
+                  BCHAR_E_INVALID_ARG, "NULL argument or a count < 1");
+    for (int i = 0; i < n_jobs; ++i)
+      BCHAR_REQUIRE(jobs[i].transfer == nullptr && jobs[i].warm_from == nullptr &&
+                        jobs[i].mesh != nullptr && jobs[i].u != nullptr,
+                    BCHAR_E_INVALID_ARG, "a tuning job names a mesh and a velocity, no transfer");
+    for (int c = 0; c < n_candidates; ++c) validate_opts(candidates[c]);
+    std::vector<bchar_build_job> J(n_jobs);
+    // one batch: fresh transfers, built and destroyed; its status
+    auto batch = [&](const bchar_opts& o) -> bchar_status {
+      for (int i = 0; i < n_jobs; ++i) {
+        J[i] = jobs[i];
+        J[i].transfer = nullptr;
+      }
+      const bchar_status st = bchar_build_transfer_batch(J.data(), n_jobs, &o, streams, n_streams);
+      for (auto& j : J)
+        if (j.transfer) bchar_transfer_destroy(j.transfer);
+      return st;
+    };
+    // untimed: device buffers, code and caches warmed once
+    (void)batch(candidates[0]);
+    std::vector<double> total(n_candidates, 0.0);
+    std::vector<bchar_status> failed(n_candidates, BCHAR_OK);
+    std::string first_msg;
+    for (int r = 0; r < rounds; ++r)
+      for (int k = 0; k < n_candidates; ++k) {
+        const int c = (r % 2 == 0) ? k : n_candidates - 1 - k;
+        if (failed[c] != BCHAR_OK) continue;
+        const double t0 = bchar::wall_seconds();
+        const bchar_status st = batch(candidates[c]);
+        const double t = bchar::wall_seconds() - t0;
+        if (st != BCHAR_OK) {
+          failed[c] = st;
+          if (first_msg.empty()) first_msg = bchar_last_error();
+          continue;
+        }
+        total[c] += t;
+      }
+    int b = -1;
+    for (int c = 0; c < n_candidates; ++c) {
+      if (seconds) seconds[c] = failed[c] == BCHAR_OK ? total[c] : HUGE_VAL;
+      if (failed[c] == BCHAR_OK && (b < 0 || total[c] < total[b])) b = c;
+    }
+    if (b < 0) {
+      bchar::set_error("every candidate failed: " + first_msg);
+      return failed[0];
+    }
+    *best = b;
+    return BCHAR_OK;
+  });
+}
+
 bchar_status bchar_transfer_destroy(bchar_transfer t) {
   if (!t) return BCHAR_OK;
   (void)hipDeviceSynchronize();

@@ -139,3 +139,36 @@ def test_binding_struct_offsets_match_the_c_compiler(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_tuner_rejects_bad_arguments_without_device():
+    import ctypes as C
+
+    from paper_1908_05834_amd import bchar
+    cands = (bchar.Opts * 2)(bchar.opts_default(), bchar.opts_default(cycle_skip=1))
+    streams = (C.c_void_p * 1)(None)
+    jobs = (bchar.BuildJob * 1)()
+    best = C.c_int(-1)
+    secs = (C.c_double * 2)()
+    # NULL jobs, no candidates, zero rounds, a job without a mesh, a job
+    # naming a transfer, an invalid candidate: refused before device work
+    assert bchar._tune_options(None, 1, cands, 2, 1, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    jobs[0].mesh = 0x1000
+    jobs[0].u = C.cast(C.c_void_p(0x2000), C.POINTER(bchar.Velocity))
+    assert bchar._tune_options(jobs, 1, cands, 0, 1, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    assert bchar._tune_options(jobs, 1, cands, 2, 0, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    jobs[0].mesh = None
+    assert bchar._tune_options(jobs, 1, cands, 2, 1, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    jobs[0].mesh = 0x1000
+    jobs[0].transfer = 0x3000
+    assert bchar._tune_options(jobs, 1, cands, 2, 1, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    jobs[0].transfer = None
+    bad = (bchar.Opts * 1)(bchar.opts_default(n_sweeps=-1))
+    assert bchar._tune_options(jobs, 1, bad, 1, 1, streams, 1, C.byref(best), secs) == \
+        bchar.E_INVALID_ARG
+    assert best.value == -1

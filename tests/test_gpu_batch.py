@@ -215,3 +215,26 @@ def test_cg_graph_replay_at_small_iteration_caps(env):
                 t.close()
         else:
             assert got[0][1] == got[1][1], cap
+
+
+def test_tuner_picks_a_working_candidate(env):
+    """bchar_tune_options times every candidate on the same jobs and never
+    picks one whose builds fail; the transfers it builds are its own."""
+    torch, bchar = env
+    # a step too long for this mesh meets a void column: without halving the
+    # build fails, with it the build succeeds
+    q = inputs.mixed_problem(2, 400.0, 400.0)
+    M = bchar.Mesh(q["mesh"], q["layout"])
+    U = bchar.VelocityLattice(q["vel"])
+    jobs = [(M, U, q["dt"])] + [(m, v, dt) for m, v, dt in _problems(bchar)[:1]]
+    failing = bchar.opts_default()
+    cands = [failing, bchar.opts_default(max_halvings=3),
+             bchar.opts_default(max_halvings=3, cycle_skip=1)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    _say("[gpu] tuner over 3 candidates")
+    best, secs = bchar.tune_options(jobs, cands, streams, rounds=2)
+    _say(f"    best {best}, seconds {secs}")
+    assert best in (1, 2)
+    assert secs[0] == float("inf")
+    assert all(0.0 < s < float("inf") for s in secs[1:])
+    assert secs[best] == min(secs)
