@@ -593,13 +593,16 @@ def main():
     # ---- autotuning (untimed): which multigrid cycle builds D transfers in
     # flight fastest on this workload, measured by the library on the first
     # intervals (bchar_tune_options), unless --tune 0 fixes it
+    # one stream per build in flight, created once: the tuning and the
+    # in-flight phase share them (more streams than hardware queues would
+    # put two builds on one queue)
+    streams = [torch.cuda.Stream() for _ in range(D)]
     tuned = None
     if args.tune:
         cands = [bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs, cycle_skip=v)
                  for v in (0, 1)]
-        tune_streams = [torch.cuda.Stream() for _ in range(D)]
         best, secs = bchar.tune_options([(M, vels[j % len(vels)], w["dt"]) for j in range(D)],
-                                        cands, tune_streams, rounds=2)
+                                        cands, streams, rounds=2)
         opts = cands[best]
         tuned = {"option": "cycle_skip", "values": [0, 1], "seconds": secs, "chosen": best}
         log(f"tuned: cycle_skip {best} ({secs[0]:.3f} s against {secs[1]:.3f} s)")
@@ -631,7 +634,6 @@ def main():
 
     # ---- phase 2: D transfers built at once (D = 1: the sequential run)
     if D > 1:
-        streams = [torch.cuda.Stream() for _ in range(D)]
         c, nxt = c0.clone(), torch.empty_like(c0)
         Ts = [None] * D
         last = None
