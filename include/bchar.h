@@ -287,7 +287,9 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
  * built once untimed, then `rounds` times per candidate as
  * bchar_build_transfer_batch would on the same streams (new transfers,
  * destroyed again), the candidates' order reversed every other round;
- * the host clock times each batch, GPU work included.  On return *best is
+ * the host clock times each batch, GPU work included (destroying a batch's
+ * transfers synchronises the device, so concurrent work of the caller on
+ * the same device waits and is timed too).  On return *best is
  * the candidate with the least summed time and seconds[c] (may be NULL)
  * that sum, +inf for a candidate whose builds failed.  Every candidate
  * yields the same transfers up to the solver's tolerance; only the time
