@@ -251,7 +251,7 @@ struct ProfModeGuard {
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s);
   ~ProfScope();
-  int slot;
+  hipEvent_t end;   // recorded when the scope closes (null: not timed)
   hipStream_t s;
 };
 

@@ -252,6 +252,7 @@ double max_abs(const double* v, int64_t n, Arena& ws, hipStream_t s) {
 
 // ---------------------------------------------------------------- kernel timing
 
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -276,6 +277,7 @@ double wall_seconds() {
 namespace {
 struct ProfState {
   std::mutex mu;
+  std::atomic<bool> on{false};  // a kernel is being timed (target non-empty)
   std::string target;     // kernel name being timed ("" = off)
   int64_t every = 1;      // time every `every`-th launch of it
   int64_t seen = 0;       // launches of it seen
@@ -319,27 +321,28 @@ void prof_set_mode(ProfMode m) { t_mode = m; }
 
 bool prof_unit_due() {
   ProfState& p = prof();
-  if (p.target.empty()) return false;
+  if (!p.on.load(std::memory_order_relaxed)) return false;
   std::lock_guard<std::mutex> g(p.mu);
+  if (p.target.empty()) return false;
   return (p.units++ % p.every) == 0;
 }
 
-ProfScope::ProfScope(const char* name, hipStream_t st) : slot(-1), s(st) {
+// The target is only read under the lock; a disabled scope costs one
+// relaxed atomic load.
+ProfScope::ProfScope(const char* name, hipStream_t st) : end(nullptr), s(st) {
   ProfState& p = prof();
-  if (t_mode == ProfMode::off || p.target.empty() || p.target != name) return;
+  if (t_mode == ProfMode::off || !p.on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(p.mu);
+  if (p.target != name) return;
   if (t_mode != ProfMode::all && (p.seen++ % p.every) != 0) return;
   hipEvent_t a = take_event(p), b = take_event(p);
   BCHAR_HIP(hipEventRecord(a, s));
   p.pending.push_back({a, b});
-  slot = (int)p.pending.size() - 1;
+  end = b;
 }
 
 ProfScope::~ProfScope() {
-  if (slot < 0) return;
-  ProfState& p = prof();
-  std::lock_guard<std::mutex> g(p.mu);
-  (void)hipEventRecord(p.pending[slot].second, s);
+  if (end) (void)hipEventRecord(end, s);
 }
 
 }  // namespace bchar
@@ -354,6 +357,7 @@ extern "C" bchar_status bchar_profile_kernel_sampled(const char* name, int every
     std::lock_guard<std::mutex> g(p.mu);
     bchar::drain(p);
     p.target = name ? name : "";
+    p.on.store(!p.target.empty(), std::memory_order_relaxed);
     p.every = every;
     p.seen = 0;
     p.units = 0;
