@@ -228,9 +228,10 @@ namespace bchar {
 
 // ---------------------------------------------------------------- kernel timing
 //
-// When enabled for a kernel name, every launch of that kernel is bracketed
-// by two HIP events recorded on its stream; bchar_profile_read sums the
-// elapsed times.  Off by default: a disabled scope costs one string compare.
+// When enabled for a kernel name, every launch of that kernel (or every
+// `every`-th) is bracketed by two HIP events recorded on its stream;
+// bchar_profile_read sums the elapsed times.  Off by default: a disabled
+// scope costs one atomic load.
 // Opt-in progress trace on stderr (environment variable BCHAR_TRACE=1):
 // stage wall times of every build and the solver's iteration counts.
 bool trace_enabled();
