@@ -113,9 +113,7 @@ def simplex_ball_layout(mesh):
     if dim == 2:
         radii = np.sqrt(vol / math.pi)
     else:
-        # the C library's pow, element by element (as for the Cartesian
-        # equal-measure ball)
-        radii = np.array([math.pow(3.0 * v / (4.0 * math.pi), 1.0 / 3.0) for v in vol])
+        radii = np.cbrt(3.0 * vol / (4.0 * math.pi))
     return centres, radii, np.arange(C.shape[0], dtype=np.int64)
 
 
@@ -234,7 +232,7 @@ def ball_layout(n, origin, h, layout):
         if dim == 2:
             r = math.sqrt(vol / math.pi)
         else:
-            r = (3.0 * vol / (4.0 * math.pi)) ** (1.0 / 3.0)
+            r = float(np.cbrt(3.0 * vol / (4.0 * math.pi)))
         radii = np.full(nc, r)
         cell = np.arange(nc, dtype=np.int64)
     else:

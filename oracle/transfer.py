@@ -161,14 +161,15 @@ def mass(phi, cell_vol, c):
 
 def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
                    precision="fp64", box_policy="paper_then_relax", stop_after="all",
-                   traced_override=None, qp_tol=1e-14):
+                   traced_override=None, balls_override=None, qp_tol=1e-14):
     """Transfer matrix of one time step: Algorithm 1 of Sec. 3.3.
 
     ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) or ``kind =
     "simplex"``, ``vertices``, ``cells``, and ``phi`` (per cell).  ``vel``: velocity lattice dict (``m``, ``origin``,
     ``spacing``, ``u``).  Returns a dict holding every intermediate stage.
-    ``traced_override`` replaces the tracked centres (to compare the
-    later stages on identical geometry).
+    ``traced_override`` replaces the tracked centres and ``balls_override``
+    = (centres, radii) the residing balls of the layout (to compare the
+    later stages on identical geometry); rho_K follows the given radii.
     """
     dim = geo.mesh_dim(mesh)
     nc = geo.mesh_n_cells(mesh)
@@ -185,6 +186,9 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
         h = tuple(float(v) for v in mesh["h"])
         kvol = np.full(nc, geo.cell_volume(h))
         centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
+    if balls_override is not None:
+        centres = np.asarray(balls_override[0], dtype=np.float64).reshape(centres.shape)
+        radii = np.asarray(balls_override[1], dtype=np.float64).reshape(radii.shape)
     rho = geo.porous_density(nc, kvol, radii, bcell, dim)
     b = phi * kvol                      # |K|_phi = b_loc = b_glob (eq. exactVol_traceback)
     out = {"centres": centres, "radii": radii, "ball_cell": bcell, "rho": rho, "b": b,

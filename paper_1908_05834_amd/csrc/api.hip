@@ -57,7 +57,7 @@ struct SimplexHost {
 };
 
 // |K| = |orient| / dim!, centroid (((v0 + v1) + v2) (+ v3)) / (dim + 1), the
-// ball with |B| = |K| (radius sqrt(|K| / pi) or pow(3 |K| / (4 pi), 1 / 3)),
+// ball with |B| = |K| (radius sqrt(|K| / pi) or cbrt(3 |K| / (4 pi))),
 // rho_K = |K| / |B|, and the domain box
 void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
 #pragma clang fp contract(off)
@@ -101,7 +101,7 @@ void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
       h.cen[(size_t)a * h.nc + K] = acc / (double)(dim + 1);
     }
     const double r =
-        dim == 2 ? std::sqrt(v / kPi) : std::pow(3.0 * v / (4.0 * kPi), 1.0 / 3.0);
+        dim == 2 ? std::sqrt(v / kPi) : std::cbrt(3.0 * v / (4.0 * kPi));
     h.rad[K] = r;
     h.bvol[K] = dim == 2 ? kPi * r * r : 4.0 / 3.0 * kPi * r * r * r;
     h.rho[K] = v / h.bvol[K];
@@ -580,7 +580,7 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         } else {
           m->nbpc = 1;
           ub.r = dim == 2 ? std::sqrt(ub.cell_vol / kPi)
-                          : std::pow(3.0 * ub.cell_vol / (4.0 * kPi), 1.0 / 3.0);
+                          : std::cbrt(3.0 * ub.cell_vol / (4.0 * kPi));
         }
         ub.ball_vol = dim == 2 ? kPi * ub.r * ub.r : 4.0 / 3.0 * kPi * ub.r * ub.r * ub.r;
         // rho_K sum_s |B_{K,s}|_phi = |K|_phi with |B|_phi = phi_K |B|
