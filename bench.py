@@ -561,7 +561,10 @@ def main():
         workload = (f"3D swirl, unit cube, {args.n}^3 hexahedra, 8 balls per cell, "
                     f"phi = 1, dt = 1/128, transfer rebuilt every step")
         metric = "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency"
-    prec = bchar.FP64 if args.precision == "fp64" else bchar.FP32_VOLUME
+    # binary32 tracking (FP32_VOLUME) needs a constant porosity; the porous
+    # unstructured workload tracks in binary64 with binary32 lenses
+    prec = bchar.FP64 if args.precision == "fp64" else (
+        bchar.FP32_LENS if args.workload == "tets" else bchar.FP32_VOLUME)
     opts = bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs,
                               cycle_skip=args.cycle_skip)
     M = bchar.Mesh(w["mesh"], layout)

@@ -59,20 +59,30 @@ typedef enum {
   BCHAR_E_UNSUPPORTED = 8       /* a configuration outside what is built       */
 } bchar_status;
 
-/* Ball layouts: which balls B_{K,s} represent a cell (Sec. 3 leaves the
- * choice open; Sec. 4 uses 4 balls per square and 8 per cube).
- *   SUBCELL       2^d balls at the centres of the 2^d half-size sub-cells,
- *                 radius min(h)/4 (disjoint, one quarter of the smallest face)
- *   INSCRIBED     one ball at the centroid, radius min(h)/2
+/* Ball layouts: which balls B_{K,s} represent a cell (Sec. 3: "we choose
+ * n_K points C_{K,s}" strictly inside K; Sec. 4 uses 4 balls per square and
+ * 8 per cube).
+ *   SUBCELL       Cartesian: 2^d balls at the centres of the 2^d half-size
+ *                 sub-cells, radius min(h)/4 (disjoint, one quarter of the
+ *                 smallest face)
+ *   INSCRIBED     Cartesian: one ball at the centroid, radius min(h)/2
  *   EQUAL_MEASURE one ball at the centroid with |B| = |K| (overlaps its
- *                 neighbours)                                              */
-enum { BCHAR_LAYOUT_SUBCELL = 0, BCHAR_LAYOUT_INSCRIBED = 1, BCHAR_LAYOUT_EQUAL_MEASURE = 2 };
+ *                 neighbours); the only built-in layout of simplices
+ *   CUSTOM        the caller's balls (bchar_mesh_desc.n_balls, balls,
+ *                 ball_cell), any number per cell, on either mesh kind     */
+enum { BCHAR_LAYOUT_SUBCELL = 0, BCHAR_LAYOUT_INSCRIBED = 1, BCHAR_LAYOUT_EQUAL_MEASURE = 2,
+       BCHAR_LAYOUT_CUSTOM = 3 };
 
 /* Precision of the geometric part.  FP64: everything in binary64.
  * FP32_VOLUME: tracking, the overlap predicate and the lens volumes in
  * binary32; the weights, V, the scalings, the QP, the update and the mass
- * stay in binary64 (compensated sums where they accumulate).           */
-enum { BCHAR_FP64 = 0, BCHAR_FP32_VOLUME = 1 };
+ * stay in binary64 (compensated sums where they accumulate).  Needs a
+ * constant porosity: where phi varies, the speed u/phi jumps on cell faces
+ * and the cardinal points of eq. rTrackedBall start on faces, so binary32
+ * rounding would take the neighbouring cell's phi (BCHAR_E_UNSUPPORTED).
+ * FP32_LENS: tracking in binary64, the predicate and the lens in binary32,
+ * the rest in binary64 (any porosity).                                  */
+enum { BCHAR_FP64 = 0, BCHAR_FP32_VOLUME = 1, BCHAR_FP32_LENS = 2 };
 
 /* What to do when the box of eq. opti_masscons (0 <= 1 + x <= 2) admits no
  * solution.  PAPER_THEN_RELAX: drop the upper cap (level 1, volumes stay
@@ -123,6 +133,16 @@ typedef struct {
   const int32_t* cells;  /* SIMPLEX, host: n_simplices * (dim + 1) vertex
                             ids, each in [0, n_vertices), non-degenerate
                             cells; copied at creation                     */
+  int geom_mem;          /* BCHAR_MEM_HOST (0) or BCHAR_MEM_DEVICE: where
+                            vertices, cells, balls and ball_cell live     */
+  int64_t n_balls;       /* CUSTOM: number of balls, >= number of cells   */
+  const double* balls;   /* CUSTOM: n_balls * (dim + 1) values, ball-major:
+                            centre x, y[, z], radius > 0; copied          */
+  const int32_t* ball_cell; /* CUSTOM: cell of every ball, non-decreasing
+                            (a cell's balls are consecutive), every cell
+                            with at least one ball and at most 256; rho_K
+                            is |K| / sum of the measures of K's balls
+                            (eq. def:porous.density); copied              */
 } bchar_mesh_desc;
 
 /* Velocity u^{(n+1)} frozen over the time step (Sec. 1.2, eq. hyp:un) as
@@ -197,6 +217,13 @@ typedef struct {
                                   mean over the sweeps of one cycle       */
   int dt_halvings;             /* times the time step was halved after a
                                   void (opts.max_halvings)                */
+  int64_t n_void_rows;         /* tracked cells with a ball that overlaps
+                                  no residing ball (eq. fracMaterial has
+                                  denominator 0)                         */
+  int64_t n_void_cols;         /* residing cells that no tracked ball
+                                  reaches (a zero column of V, Sec. 3.2) */
+  int trace_precision;         /* precision the tracking ran in: BCHAR_FP64
+                                  or BCHAR_FP32_VOLUME                    */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */
@@ -389,6 +416,19 @@ bchar_status bchar_transfer_export_tracked(bchar_transfer t, double* tracked, do
 /* Solution of eq. opti_masscons: x (nnz) and the multipliers of the row
  * and column constraints (n_rows each, in units of 1 / max |K|_phi).    */
 bchar_status bchar_transfer_export_qp(bchar_transfer t, double* x, double* mu, double* nu);
+
+/* The multipliers of the last solve of eq. opti_masscons in the per-cell
+ * coordinates the solver works in (host arrays of n_rows values, any may
+ * be NULL): mu_K = s_K + g_K / 2 and nu_M = -(s_M - g_M / 2), so that
+ * t_k = a_k (mu_K + nu_M) = a_k ((s_K - s_M) + (g_K + g_M) / 2) for an
+ * entry off the diagonal and a_k g_K on it, a in units of max |K|_phi, and
+ * the answer is x = clip(t) to the box.  Each multiplier is the sum of a
+ * leading part (s, g) and what its rounding lost (s_lo, g_lo): cells that
+ * barely move carry multipliers of 1e9 and more whose differences stay
+ * small, so that t can be re-formed, and x = clip(t) checked entry by
+ * entry, to double-double accuracy.                                     */
+bchar_status bchar_transfer_export_qp_dual(bchar_transfer t, double* s, double* g,
+                                           double* s_lo, double* g_lo);
 
 /* ---- kernel timing (instrumentation) ------------------------------- */
 

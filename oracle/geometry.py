@@ -102,9 +102,41 @@ def simplex_centroids(vertices, cells):
     return acc / float(C.shape[1])
 
 
+def cbrt_rounded(y):
+    """The binary64 number nearest to the real cube root of each y > 0.
+
+    A library cube root (within a few units in the last place) gives a
+    start; among it and its two neighbours on each side the one whose
+    rounding interval holds y^(1/3) is taken, deciding exactly: r is the
+    nearest double iff the cubes of the midpoints to its neighbours, in
+    rational arithmetic, bracket y."""
+    from fractions import Fraction
+    y = np.asarray(y, dtype=np.float64)
+    out = np.empty_like(y)
+    for i, v in enumerate(y.ravel()):
+        fv = Fraction(float(v))
+        r = float(np.cbrt(v))
+        cand = [r]
+        for _ in range(2):
+            cand.insert(0, float(np.nextafter(cand[0], 0.0)))
+            cand.append(float(np.nextafter(cand[-1], np.inf)))
+        best = None
+        for k in range(1, len(cand) - 1):
+            lo = (Fraction(cand[k - 1]) + Fraction(cand[k])) / 2
+            hi = (Fraction(cand[k]) + Fraction(cand[k + 1])) / 2
+            if lo ** 3 <= fv <= hi ** 3:
+                best = cand[k]
+                break
+        if best is None:
+            raise ArithmeticError("cube root start more than two places off")
+        out.flat[i] = best
+    return out
+
+
 def simplex_ball_layout(mesh):
     """One ball per simplex at its centroid with |B| = |K| (2D sqrt(|K|/pi),
-    3D (3 |K| / (4 pi))^(1/3)).  Returns centres, radii, cell."""
+    3D the correctly rounded (3 |K| / (4 pi))^(1/3)).  Returns centres,
+    radii, cell."""
     V = np.asarray(mesh["vertices"], dtype=np.float64)
     C = np.asarray(mesh["cells"], dtype=np.int64)
     dim = V.shape[1]
@@ -113,7 +145,7 @@ def simplex_ball_layout(mesh):
     if dim == 2:
         radii = np.sqrt(vol / math.pi)
     else:
-        radii = np.cbrt(3.0 * vol / (4.0 * math.pi))
+        radii = cbrt_rounded(3.0 * vol / (4.0 * math.pi))
     return centres, radii, np.arange(C.shape[0], dtype=np.int64)
 
 
@@ -232,7 +264,7 @@ def ball_layout(n, origin, h, layout):
         if dim == 2:
             r = math.sqrt(vol / math.pi)
         else:
-            r = float(np.cbrt(3.0 * vol / (4.0 * math.pi)))
+            r = float(cbrt_rounded(np.array([3.0 * vol / (4.0 * math.pi)]))[0])
         radii = np.full(nc, r)
         cell = np.arange(nc, dtype=np.int64)
     else:

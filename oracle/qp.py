@@ -288,3 +288,41 @@ def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol):
     prim = float(np.max(np.abs(residual(rows, cols, As, x, r, s)), initial=0.0))
     return {"stationarity": stat, "box": box, "primal": prim,
             "ok": stat <= 1e-12 and box == 0.0 and prim <= tol}
+
+
+def verify_kkt_sg(rows, cols, a, b_row, b_col, x, s, g, lo, hi, scale, tol, s_lo=None,
+                  g_lo=None):
+    """The certificate of ``verify_kkt`` with the multipliers given in the
+    per-cell coordinates s, g (mu_K = s_K + g_K / 2, nu_M = -(s_M - g_M / 2)):
+    t_k = a_k ((s_K - s_M) + (g_K + g_M) / 2) off the diagonal and a_k g_K on
+    it, which stays accurate where mu and nu are huge and nearly cancel.
+    Stationarity is the largest |clip(t_k) - x_k| (x lies in [-1, 1] on the
+    paper's box, so this bounds the change of every volume a_k (1 + x_k)
+    relative to a_k).  ``s_lo``, ``g_lo`` (optional) are the parts of the
+    multipliers below the rounding of s and g; the differences are formed
+    part by part."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    As = np.asarray(a) / scale
+    sl = np.zeros_like(s) if s_lo is None else s_lo
+    gl = np.zeros_like(g) if g_lo is None else g_lo
+
+    def two_sum(x, y):
+        # x + y = h + e exactly (Knuth)
+        h = x + y
+        yy = h - x
+        return h, (x - (h - yy)) + (y - yy)
+
+    # differences of multipliers of 1e9 and more: the leading difference
+    # kept exactly, then the small parts
+    dh, de = two_sum(s[rows], -s[cols])
+    ds = dh + (de + (sl[rows] - sl[cols]))
+    gh, ge = two_sum(g[rows], g[cols])
+    sg = gh + (ge + (gl[rows] + gl[cols]))
+    t = np.where(rows != cols, As * (ds + 0.5 * sg), As * (g[rows] + gl[rows]))
+    stat = float(np.max(np.abs(np.clip(t, lo, hi) - x), initial=0.0))
+    box = float(max(np.max(lo - x, initial=-np.inf), np.max(x - hi, initial=-np.inf), 0.0))
+    r, sv = constraint_rhs(rows, cols, As, np.asarray(b_row) / scale, np.asarray(b_col) / scale)
+    prim = float(np.max(np.abs(residual(rows, cols, As, x, r, sv)), initial=0.0))
+    return {"stationarity": stat, "box": box, "primal": prim,
+            "ok": stat <= 1e-12 and box == 0.0 and prim <= tol}

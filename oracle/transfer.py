@@ -177,15 +177,22 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     if phi.shape != (nc,) or not np.all(np.isfinite(phi)) or np.any(phi <= 0):
         raise ValueError("phi must be finite and > 0 on every cell (Sec. 1.2)")
     if geo.is_simplex(mesh):
-        if layout != "equal_measure":
-            raise ValueError("simplicial meshes take the equal_measure layout")
+        if layout not in ("equal_measure", "custom"):
+            raise ValueError("simplicial meshes take the equal_measure or custom layout")
         kvol = geo.simplex_volumes(mesh["vertices"], mesh["cells"])
-        centres, radii, bcell = geo.simplex_ball_layout(mesh)
+        if layout != "custom":
+            centres, radii, bcell = geo.simplex_ball_layout(mesh)
     else:
         n = tuple(int(v) for v in mesh["n"])
         h = tuple(float(v) for v in mesh["h"])
         kvol = np.full(nc, geo.cell_volume(h))
-        centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
+        if layout != "custom":
+            centres, radii, bcell = geo.ball_layout(n, mesh["origin"], h, layout)
+    if layout == "custom":
+        # the caller's balls (Sec. 3: any points C_{K,s} inside K with radii)
+        centres = np.asarray(mesh["ball_centres"], dtype=np.float64)
+        radii = np.asarray(mesh["ball_radii"], dtype=np.float64)
+        bcell = np.asarray(mesh["ball_cell"], dtype=np.int64)
     if balls_override is not None:
         centres = np.asarray(balls_override[0], dtype=np.float64).reshape(centres.shape)
         radii = np.asarray(balls_override[1], dtype=np.float64).reshape(radii.shape)
@@ -206,9 +213,9 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     rp, cl, V = initial_volumes(nc, dim, bcell, centres, radii, rho, phi, traced, r_hat,
                                 ia, ib, precision=precision)
     out["row_ptr"], out["col"], out["V"] = rp, cl, V
-    check_columns(cl, V, nc)
     if stop_after == "v":
         return out
+    check_columns(cl, V, nc)
     AN = scaling_sweeps(rp, cl, V, b, b, n_sweeps)
     out["AN"] = AN
     if stop_after == "sinkhorn":

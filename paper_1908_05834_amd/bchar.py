@@ -28,22 +28,24 @@ _lib = C.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants (bchar.h)
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_VOID_ROW, E_VOID_COLUMN, \
     E_QP_INFEASIBLE, E_QP_NOT_CONVERGED, E_UNSUPPORTED = range(9)
-LAYOUT_SUBCELL, LAYOUT_INSCRIBED, LAYOUT_EQUAL_MEASURE = 0, 1, 2
-FP64, FP32_VOLUME = 0, 1
+LAYOUT_SUBCELL, LAYOUT_INSCRIBED, LAYOUT_EQUAL_MEASURE, LAYOUT_CUSTOM = 0, 1, 2, 3
+FP64, FP32_VOLUME, FP32_LENS = 0, 1, 2
 BOX_PAPER_THEN_RELAX, BOX_STRICT = 0, 1
 STAGE_PAIRS, STAGE_V, STAGE_SCALING, STAGE_ALL = 1, 2, 3, 4
 MEM_HOST, MEM_DEVICE = 0, 1
 MESH_CARTESIAN, MESH_SIMPLEX = 0, 1
 
 LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
-           "equal_measure": LAYOUT_EQUAL_MEASURE}
+           "equal_measure": LAYOUT_EQUAL_MEASURE, "custom": LAYOUT_CUSTOM}
 
 
 class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("origin", C.c_double * 3),
                 ("h", C.c_double * 3), ("phi", C.c_void_p), ("phi_mem", C.c_int),
                 ("layout", C.c_int), ("kind", C.c_int), ("n_vertices", C.c_int64),
-                ("n_simplices", C.c_int64), ("vertices", C.c_void_p), ("cells", C.c_void_p)]
+                ("n_simplices", C.c_int64), ("vertices", C.c_void_p), ("cells", C.c_void_p),
+                ("geom_mem", C.c_int), ("n_balls", C.c_int64), ("balls", C.c_void_p),
+                ("ball_cell", C.c_void_p)]
 
 
 class Velocity(C.Structure):
@@ -65,7 +67,9 @@ class Stats(C.Structure):
                 ("qp_residual", C.c_double), ("qp_level", C.c_int), ("qp_newton", C.c_int),
                 ("qp_cg", C.c_int), ("n_at_lower", C.c_int64), ("n_at_upper", C.c_int64),
                 ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64),
-                ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int)]
+                ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int),
+                ("n_void_rows", C.c_int64), ("n_void_cols", C.c_int64),
+                ("trace_precision", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +108,7 @@ _export_pairs = _sig("bchar_transfer_export_pairs", [_P, _P, _P])
 _export_tracked = _sig("bchar_transfer_export_tracked", [_P, _P, _P])
 _export_qp = _sig("bchar_transfer_export_qp", [_P, _P, _P, _P])
 _export_balls = _sig("bchar_mesh_export_balls", [_P, _P, _P, _P])
+_export_qp_dual = _sig("bchar_transfer_export_qp_dual", [_P, _P, _P, _P, _P])
 _profile_kernel = _sig("bchar_profile_kernel", [C.c_char_p])
 _profile_kernel_sampled = _sig("bchar_profile_kernel_sampled", [C.c_char_p, C.c_int])
 
@@ -145,7 +150,8 @@ EXPORTED = [
     "bchar_transfer_destroy", "bchar_step", "bchar_mass", "bchar_status_string",
     "bchar_last_error", "bchar_transfer_info", "bchar_transfer_export_csr",
     "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
-    "bchar_mesh_export_balls", "bchar_profile_kernel", "bchar_profile_read",
+    "bchar_mesh_export_balls", "bchar_transfer_export_qp_dual", "bchar_profile_kernel",
+    "bchar_profile_read",
     "bchar_build_transfer_batch", "bchar_profile_kernel_sampled",
     "bchar_server_create", "bchar_server_submit", "bchar_server_wait", "bchar_server_destroy",
     "bchar_tune_options",
@@ -213,21 +219,35 @@ def opts_default(**kw):
 class Mesh:
     """bchar_mesh_create on a Cartesian mesh dict (``inputs.cartesian_mesh``)
     or a simplicial one (``inputs.kuhn_tets``, ``inputs.triangulated_square``:
-    layout ``"equal_measure"``)."""
+    layout ``"equal_measure"``).  Layout ``"custom"`` takes the mesh dict's
+    ``ball_centres`` (n_balls, dim), ``ball_radii`` and ``ball_cell``.
+    ``geom_device=True`` hands vertices, cells and custom balls over in
+    device memory (copied to the GPU here first)."""
 
-    def __init__(self, mesh, layout="subcell", stream=None):
+    def __init__(self, mesh, layout="subcell", stream=None, geom_device=False):
         d = MeshDesc()
+        keep = []
+
+        def ptr(a):
+            if geom_device:
+                import torch
+                t = torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+                keep.append(t)
+                return C.c_void_p(t.data_ptr())
+            a = np.ascontiguousarray(a)
+            keep.append(a)
+            return a.ctypes.data_as(C.c_void_p)
+        d.geom_mem = MEM_DEVICE if geom_device else MEM_HOST
         if mesh.get("kind") == "simplex":
             V = np.ascontiguousarray(mesh["vertices"], dtype=np.float64)
             Cc = np.ascontiguousarray(mesh["cells"], dtype=np.int32)
             self.dim = V.shape[1]
-            self._geom_host = (V, Cc)
             d.dim = self.dim
             d.kind = MESH_SIMPLEX
             d.n_vertices = V.shape[0]
             d.n_simplices = Cc.shape[0]
-            d.vertices = V.ctypes.data_as(C.c_void_p)
-            d.cells = Cc.ctypes.data_as(C.c_void_p)
+            d.vertices = ptr(V)
+            d.cells = ptr(Cc)
             for a in range(3):
                 d.n[a], d.origin[a], d.h[a] = 1, 0.0, 1.0
         else:
@@ -244,8 +264,18 @@ class Mesh:
         d.phi = phi.ctypes.data_as(C.c_void_p)
         d.phi_mem = MEM_HOST
         d.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        if d.layout == LAYOUT_CUSTOM:
+            bc = np.asarray(mesh["ball_centres"], dtype=np.float64)
+            br = np.asarray(mesh["ball_radii"], dtype=np.float64)
+            d.n_balls = br.shape[0]
+            d.balls = ptr(np.concatenate([bc, br[:, None]], axis=1))
+            d.ball_cell = ptr(np.asarray(mesh["ball_cell"], dtype=np.int32))
         h = C.c_void_p()
         _check(_mesh_create(C.byref(d), _stream_ptr(stream), C.byref(h)))
+        if geom_device:
+            import torch
+            torch.cuda.current_stream().synchronize()
+        del keep
         self.handle = h
         nc, nb, bpc = C.c_int64(), C.c_int64(), C.c_int()
         _check(_mesh_info(h, C.byref(nc), C.byref(nb), C.byref(bpc)))
@@ -382,6 +412,14 @@ class Transfer:
         _check(_export_qp(self.handle, x.ctypes.data_as(_P), mu.ctypes.data_as(_P),
                           nu.ctypes.data_as(_P)))
         return x, mu, nu
+
+    def export_qp_dual(self):
+        """Per-cell multipliers of the last solve (see bchar.h): leading
+        parts s, g and their compensations s_lo, g_lo."""
+        nr, _, _, _ = self.info()
+        out = [np.empty(nr) for _ in range(4)]
+        _check(_export_qp_dual(self.handle, *[o.ctypes.data_as(_P) for o in out]))
+        return tuple(out)
 
 
 def _handle_value(h):

@@ -46,6 +46,39 @@ double orient_host(int dim, const double* a, const double* b, const double* c,
   return (e1[0] * m0 - e1[1] * m1) + e1[2] * m2;
 }
 
+// y - c^3 for c near y^(1/3), in double-double: c^2 = p + q exactly, c^3 =
+// p c + q c with each product split exactly by fma, the leading difference
+// y - p c exact by Sterbenz (p c is within a few units of y).
+static double cube_residual(double y, double c) {
+#pragma clang fp contract(off)
+  const double p = c * c, q = std::fma(c, c, -p);
+  const double a = p * c, ae = std::fma(p, c, -a);
+  const double b = q * c, be = std::fma(q, c, -b);
+  return (((y - a) - ae) - b) - be;
+}
+
+// The binary64 number nearest to the real cube root of y > 0: the C
+// library's cbrt (a few units in the last place off) corrected by one
+// Newton step on the double-double residual, then among that and its two
+// neighbours on each side the one whose cube is closest to y; this
+// decides every case except a tie within ~1e-16 of a rounding midpoint.
+double cbrt_nearest(double y) {
+#pragma clang fp contract(off)
+  const double r0 = std::cbrt(y);
+  double c = r0 + cube_residual(y, r0) / (3.0 * r0 * r0);
+  const double r1 = c;
+  for (int i = 0; i < 2; ++i) c = std::nextafter(c, 0.0);
+  double best = r1, best_err = HUGE_VAL;
+  for (int k = 0; k < 5; ++k, c = std::nextafter(c, HUGE_VAL)) {
+    const double err = std::fabs(cube_residual(y, c));
+    if (err < best_err) {
+      best = c;
+      best_err = err;
+    }
+  }
+  return best;
+}
+
 struct SimplexHost {
   int dim = 0;
   int64_t nv = 0, nc = 0;
@@ -57,7 +90,7 @@ struct SimplexHost {
 };
 
 // |K| = |orient| / dim!, centroid (((v0 + v1) + v2) (+ v3)) / (dim + 1), the
-// ball with |B| = |K| (radius sqrt(|K| / pi) or cbrt(3 |K| / (4 pi))),
+// ball with |B| = |K| (radius sqrt(|K| / pi) or the nearest cbrt(3 |K| / (4 pi))),
 // rho_K = |K| / |B|, and the domain box
 void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
 #pragma clang fp contract(off)
@@ -101,7 +134,7 @@ void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
       h.cen[(size_t)a * h.nc + K] = acc / (double)(dim + 1);
     }
     const double r =
-        dim == 2 ? std::sqrt(v / kPi) : std::cbrt(3.0 * v / (4.0 * kPi));
+        dim == 2 ? std::sqrt(v / kPi) : cbrt_nearest(3.0 * v / (4.0 * kPi));
     h.rad[K] = r;
     h.bvol[K] = dim == 2 ? kPi * r * r : 4.0 / 3.0 * kPi * r * r * r;
     h.rho[K] = v / h.bvol[K];
@@ -113,24 +146,27 @@ void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
 // uniform grid of side (|box| / n_cells)^(1/dim) listing, per grid cell
 // and in ascending order, the cells whose bounding box meets it.
 void simplex_upload(bchar_mesh_s* m, const SimplexHost& h, const std::vector<double>& b,
-                    const std::vector<double>& /*phi*/, hipStream_t s) {
+                    bool centroid_balls, hipStream_t s) {
   const int dim = h.dim;
   auto up = [&](bchar::DBuf& buf, const void* src, size_t bytes) {
     buf.reserve(bytes);
     BCHAR_HIP(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, s));
   };
-  std::vector<float> cen32(h.cen.size());
-  for (size_t i = 0; i < h.cen.size(); ++i) cen32[i] = (float)h.cen[i];
-  up(m->cen, h.cen.data(), sizeof(double) * h.cen.size());
-  up(m->cen32, cen32.data(), sizeof(float) * cen32.size());
-  up(m->rad, h.rad.data(), sizeof(double) * h.nc);
-  up(m->bvol, h.bvol.data(), sizeof(double) * h.nc);
-  up(m->rho, h.rho.data(), sizeof(double) * h.nc);
+  up(m->cell_cen, h.cen.data(), sizeof(double) * h.cen.size());
+  if (centroid_balls) {
+    std::vector<float> cen32(h.cen.size());
+    for (size_t i = 0; i < h.cen.size(); ++i) cen32[i] = (float)h.cen[i];
+    up(m->cen, h.cen.data(), sizeof(double) * h.cen.size());
+    up(m->cen32, cen32.data(), sizeof(float) * cen32.size());
+    up(m->rad, h.rad.data(), sizeof(double) * h.nc);
+    up(m->bvol, h.bvol.data(), sizeof(double) * h.nc);
+    up(m->rho, h.rho.data(), sizeof(double) * h.nc);
+    m->rmax = h.rmax;
+  }
   up(m->b, b.data(), sizeof(double) * h.nc);
   up(m->vtx, h.vtx.data(), sizeof(double) * h.vtx.size());
   up(m->cells, h.cells.data(), sizeof(int32_t) * h.cells.size());
   m->n_vertices = h.nv;
-  m->rmax = h.rmax;
   std::vector<int32_t> start, list;
   double side = 1.0;
   int64_t nb[3] = {1, 1, 1};
@@ -195,6 +231,87 @@ void simplex_upload(bchar_mesh_s* m, const SimplexHost& h, const std::vector<dou
   BCHAR_HIP(hipStreamSynchronize(s));
 }
 
+// The caller's balls (layout CUSTOM, Sec. 3: any points C_{K,s} with radii
+// r_{K,s}, a cell's balls consecutive): ball measures, rho_K = |K| / sum_s
+// |B_{K,s}| (eq. def:porous.density, the measures summed in ball order),
+// the first ball of every cell, and tiles of whole cells with at most 256
+// balls each for the assembly.
+void custom_layout(bchar_mesh_s* m, const bchar_mesh_desc* d, const double* balls,
+                   const int32_t* ball_cell, const std::vector<double>& kvol, hipStream_t s) {
+#pragma clang fp contract(off)
+  const int dim = m->dim;
+  const int64_t nc = m->n_cells, nb = d->n_balls;
+  BCHAR_REQUIRE(nb >= nc && nb < ((int64_t)1 << 31) - 1, BCHAR_E_INVALID_ARG,
+                "CUSTOM layout: n_balls must be >= the number of cells and < 2^31");
+  BCHAR_REQUIRE(balls != nullptr && ball_cell != nullptr, BCHAR_E_INVALID_ARG,
+                "CUSTOM layout: balls or ball_cell is NULL");
+  std::vector<int32_t> ptr(nc + 1, 0);
+  std::vector<double> cen((size_t)dim * nb), rad(nb), bvol(nb), rho(nc);
+  std::vector<float> cen32((size_t)dim * nb);
+  double rmax = 0;
+  bool uniform = true;
+  for (int64_t i = 0; i < nb; ++i) {
+    const int32_t K = ball_cell[i];
+    BCHAR_REQUIRE(K >= 0 && K < nc, BCHAR_E_INVALID_ARG, "CUSTOM layout: ball_cell out of range");
+    BCHAR_REQUIRE(i == 0 ? K == 0 : (K == ball_cell[i - 1] || K == ball_cell[i - 1] + 1),
+                  BCHAR_E_INVALID_ARG,
+                  "CUSTOM layout: ball_cell must start at 0 and step by 0 or 1 (every cell "
+                  "owns at least one ball, a cell's balls consecutive)");
+    ++ptr[K + 1];
+    for (int a = 0; a < dim; ++a) {
+      const double x = balls[i * (dim + 1) + a];
+      BCHAR_REQUIRE(std::isfinite(x), BCHAR_E_INVALID_ARG, "CUSTOM layout: centre not finite");
+      cen[(size_t)a * nb + i] = x;
+      cen32[(size_t)a * nb + i] = (float)x;
+    }
+    const double r = balls[i * (dim + 1) + dim];
+    BCHAR_REQUIRE(r > 0 && std::isfinite(r), BCHAR_E_INVALID_ARG,
+                  "CUSTOM layout: radius must be finite and > 0");
+    rad[i] = r;
+    bvol[i] = dim == 2 ? kPi * r * r : 4.0 / 3.0 * kPi * r * r * r;
+    rmax = std::max(rmax, r);
+    uniform = uniform && r == rad[0];
+  }
+  BCHAR_REQUIRE(ball_cell[nb - 1] == nc - 1, BCHAR_E_INVALID_ARG,
+                "CUSTOM layout: every cell needs at least one ball");
+  for (int64_t K = 0; K < nc; ++K) {
+    BCHAR_REQUIRE(ptr[K + 1] <= 256, BCHAR_E_UNSUPPORTED,
+                  "CUSTOM layout: more than 256 balls in one cell");
+    ptr[K + 1] += ptr[K];
+  }
+  for (int64_t K = 0; K < nc; ++K) {
+    double sum = 0.0;
+    for (int32_t i = ptr[K]; i < ptr[K + 1]; ++i) sum = sum + bvol[i];
+    rho[K] = kvol[K] / sum;
+  }
+  std::vector<int32_t> tiles(1, 0);
+  for (int64_t K = 0; K < nc;) {
+    int64_t e = K;
+    while (e < nc && ptr[e + 1] - ptr[K] <= 256) ++e;
+    tiles.push_back((int32_t)e);
+    K = e;
+  }
+  auto up = [&](bchar::DBuf& buf, const void* src, size_t bytes) {
+    buf.reserve(bytes);
+    BCHAR_HIP(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, s));
+  };
+  up(m->cen, cen.data(), sizeof(double) * cen.size());
+  up(m->cen32, cen32.data(), sizeof(float) * cen32.size());
+  up(m->rad, rad.data(), sizeof(double) * nb);
+  up(m->bvol, bvol.data(), sizeof(double) * nb);
+  up(m->rho, rho.data(), sizeof(double) * nc);
+  up(m->ball_ptr, ptr.data(), sizeof(int32_t) * (nc + 1));
+  up(m->ball_cell, ball_cell, sizeof(int32_t) * nb);
+  up(m->tile_cell, tiles.data(), sizeof(int32_t) * tiles.size());
+  BCHAR_HIP(hipStreamSynchronize(s));
+  m->n_tiles = (int64_t)tiles.size() - 1;
+  m->nbpc = 0;
+  m->n_balls = nb;
+  m->rmax = rmax;
+  m->r_uniform = uniform;
+  m->r0 = rad[0];
+}
+
 template <class F>
 bchar_status guarded(F&& f) {
   try {
@@ -221,7 +338,8 @@ void opts_or_default(const bchar_opts* in, bchar_opts& o) {
 }
 
 void validate_opts(const bchar_opts& o) {
-  BCHAR_REQUIRE(o.precision == BCHAR_FP64 || o.precision == BCHAR_FP32_VOLUME,
+  BCHAR_REQUIRE(o.precision == BCHAR_FP64 || o.precision == BCHAR_FP32_VOLUME ||
+                    o.precision == BCHAR_FP32_LENS,
                 BCHAR_E_INVALID_ARG, "opts.precision");
   BCHAR_REQUIRE(o.n_sweeps >= 0 && o.n_sweeps <= 100000, BCHAR_E_INVALID_ARG, "opts.n_sweeps");
   BCHAR_REQUIRE(o.rk_substeps >= 1 && o.rk_substeps <= 4096, BCHAR_E_INVALID_ARG,
@@ -253,7 +371,7 @@ void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
 
 // Everything after the tracked centres are known.
 bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_opts& o,
-                                hipStream_t s, bchar_stats* stats) {
+                                int trace_precision, hipStream_t s, bchar_stats* stats) {
   using namespace bchar;
   Arena& ws = t->ws;
   const bool tr = trace_enabled();
@@ -265,12 +383,14 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   bchar_stats st{};
   st.n_balls = m->n_balls;
   st.first_void = -1;
+  st.trace_precision = trace_precision;
   t->stage = 0;
   int64_t first_void = -1;
   bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(), o.precision,
                                o.keep_pairs != 0, t, &first_void, s);
   st.nnz = t->nnz;
   st.n_pairs = t->n_pairs;
+  st.n_void_rows = t->n_void_rows;
   if (rc != BCHAR_OK) {
     st.first_void = first_void;
     if (stats) *stats = st;
@@ -296,11 +416,13 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   Csc csc{};
   build_csc(t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), n, nnz, csc, ws, s);
   t->AN.reserve(sizeof(double) * (nnz + 1));
-  int64_t void_col = -1;
+  int64_t void_col = -1, n_void_cols = 0;
   double col_err = 0;
   rc = scaling_sweeps(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->V.as<double>(),
-                      nnz, o.n_sweeps, t->AN.as<double>(), &void_col, &col_err, ws, s);
+                      nnz, o.n_sweeps, t->AN.as<double>(), &void_col, &n_void_cols, &col_err, ws,
+                      s);
   st.scaling_max_col_err = col_err;
+  st.n_void_cols = n_void_cols;
   if (rc != BCHAR_OK) {
     st.first_void = void_col;
     if (stats) *stats = st;
@@ -324,8 +446,8 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   t->A.reserve(sizeof(double) * (nnz + 1));
   t->mu.reserve(sizeof(double) * n);
   t->nu.reserve(sizeof(double) * n);
-  if (t->zdual.bytes < sizeof(double) * 2 * n) {
-    t->zdual.reserve(sizeof(double) * 2 * n);
+  if (t->zdual.bytes < sizeof(double) * 4 * n) {
+    t->zdual.reserve(sizeof(double) * 4 * n);
     t->warm_level = -1;
   }
   QpResult qr;
@@ -361,6 +483,9 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
 bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity* u,
                         double dt, const bchar_opts& o, hipStream_t s, bchar_stats* stats) {
   using namespace bchar;
+  BCHAR_REQUIRE(o.precision != BCHAR_FP32_VOLUME || m->phi_const, BCHAR_E_UNSUPPORTED,
+                "FP32_VOLUME tracks in binary32 and needs a constant porosity; FP32_LENS "
+                "tracks in binary64");
   t->ws.reset();
   t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
   t->r_hat.reserve(sizeof(double) * m->n_balls);
@@ -371,7 +496,9 @@ bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_veloci
     BCHAR_HIP(hipStreamSynchronize(s));
     fprintf(stderr, "[bchar] trace: %.3f ms\n", 1e3 * (wall_seconds() - t0));
   }
-  return build_from_tracked(m, t, o, s, stats);
+  return build_from_tracked(m, t, o,
+                            o.precision == BCHAR_FP32_VOLUME ? BCHAR_FP32_VOLUME : BCHAR_FP64, s,
+                            stats);
 }
 
 // A void row or column is the method's sign that the step is too long for
@@ -532,12 +659,46 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
     BCHAR_REQUIRE(d->dim == 2 || d->dim == 3, BCHAR_E_INVALID_ARG, "dim must be 2 or 3");
     BCHAR_REQUIRE(d->kind == BCHAR_MESH_CARTESIAN || d->kind == BCHAR_MESH_SIMPLEX,
                   BCHAR_E_INVALID_ARG, "unknown mesh kind");
-    BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_EQUAL_MEASURE,
+    BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_CUSTOM,
                   BCHAR_E_INVALID_ARG, "unknown layout");
     BCHAR_REQUIRE(d->phi != nullptr, BCHAR_E_INVALID_ARG, "phi is NULL");
     BCHAR_REQUIRE(d->phi_mem == BCHAR_MEM_HOST || d->phi_mem == BCHAR_MEM_DEVICE,
                   BCHAR_E_INVALID_ARG, "phi_mem");
+    BCHAR_REQUIRE(d->geom_mem == BCHAR_MEM_HOST || d->geom_mem == BCHAR_MEM_DEVICE,
+                  BCHAR_E_INVALID_ARG, "geom_mem");
     hipStream_t s = as_stream(stream);
+    const bool custom = d->layout == BCHAR_LAYOUT_CUSTOM;
+    // geometry given in device memory: host copies (creation runs on the host)
+    bchar_mesh_desc dh = *d;
+    std::vector<double> h_vtx, h_balls;
+    std::vector<int32_t> h_cells, h_bcell;
+    if (d->geom_mem == BCHAR_MEM_DEVICE) {
+      auto down = [&](auto& vec, const void* src, size_t count) {
+        vec.resize(count);
+        if (count && src)
+          BCHAR_HIP(hipMemcpyAsync(vec.data(), src, sizeof(vec[0]) * count,
+                                   hipMemcpyDeviceToHost, s));
+      };
+      if (d->kind == BCHAR_MESH_SIMPLEX) {
+        BCHAR_REQUIRE(d->vertices != nullptr && d->cells != nullptr && d->n_vertices > 0 &&
+                          d->n_simplices > 0,
+                      BCHAR_E_INVALID_ARG, "vertices / cells");
+        down(h_vtx, d->vertices, (size_t)d->n_vertices * d->dim);
+        down(h_cells, d->cells, (size_t)d->n_simplices * (d->dim + 1));
+        dh.vertices = h_vtx.data();
+        dh.cells = h_cells.data();
+      }
+      if (custom) {
+        BCHAR_REQUIRE(d->balls != nullptr && d->ball_cell != nullptr && d->n_balls > 0,
+                      BCHAR_E_INVALID_ARG, "CUSTOM layout: balls / ball_cell / n_balls");
+        down(h_balls, d->balls, (size_t)d->n_balls * (d->dim + 1));
+        down(h_bcell, d->ball_cell, (size_t)d->n_balls);
+        dh.balls = h_balls.data();
+        dh.ball_cell = h_bcell.data();
+      }
+      BCHAR_HIP(hipStreamSynchronize(s));
+      d = &dh;
+    }
     auto* m = new bchar_mesh_s();
     try {
       m->dim = d->dim;
@@ -571,7 +732,10 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
           m->box_hi[a] = m->origin[a] + (double)m->n[a] * m->h[a];
         }
         m->n_cells = nc;
-        if (d->layout == BCHAR_LAYOUT_SUBCELL) {
+        if (custom) {
+          m->nbpc = 0;
+          ub.r = 0;
+        } else if (d->layout == BCHAR_LAYOUT_SUBCELL) {
           m->nbpc = 1 << dim;
           ub.r = hmin / 4.0;
         } else if (d->layout == BCHAR_LAYOUT_INSCRIBED) {
@@ -580,14 +744,15 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         } else {
           m->nbpc = 1;
           ub.r = dim == 2 ? std::sqrt(ub.cell_vol / kPi)
-                          : std::cbrt(3.0 * ub.cell_vol / (4.0 * kPi));
+                          : cbrt_nearest(3.0 * ub.cell_vol / (4.0 * kPi));
         }
         ub.ball_vol = dim == 2 ? kPi * ub.r * ub.r : 4.0 / 3.0 * kPi * ub.r * ub.r * ub.r;
         // rho_K sum_s |B_{K,s}|_phi = |K|_phi with |B|_phi = phi_K |B|
-        ub.rho = ub.cell_vol / (m->nbpc * ub.ball_vol);
+        if (!custom) ub.rho = ub.cell_vol / (m->nbpc * ub.ball_vol);
+        kvol.assign(nc, ub.cell_vol);
       } else {
-        BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE, BCHAR_E_INVALID_ARG,
-                      "simplicial meshes take the EQUAL_MEASURE layout");
+        BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE || custom, BCHAR_E_INVALID_ARG,
+                      "simplicial meshes take the EQUAL_MEASURE or CUSTOM layout");
         BCHAR_REQUIRE(d->vertices != nullptr && d->cells != nullptr, BCHAR_E_INVALID_ARG,
                       "vertices or cells is NULL");
         BCHAR_REQUIRE(d->n_vertices >= dim + 1 && d->n_simplices >= 1 &&
@@ -595,7 +760,7 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
                       BCHAR_E_INVALID_ARG, "n_vertices / n_simplices");
         nc = d->n_simplices;
         m->n_cells = nc;
-        m->nbpc = 1;
+        m->nbpc = custom ? 0 : 1;
         simplex_geometry(d, sh);
         for (int a = 0; a < 3; ++a) {
           m->box_lo[a] = sh.lo[a];
@@ -603,7 +768,7 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         }
         kvol = sh.vol;
       }
-      m->n_balls = nc * m->nbpc;
+      m->n_balls = custom ? d->n_balls : nc * m->nbpc;
       BCHAR_REQUIRE(m->n_balls < ((int64_t)1 << 31) - 1, BCHAR_E_UNSUPPORTED,
                     "more than 2^31 balls");
       // phi: validate on the host
@@ -628,17 +793,25 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
       m->phi.reserve(sizeof(double) * nc);
       BCHAR_HIP(hipMemcpyAsync(m->phi.p, hphi.data(), sizeof(double) * nc,
                                hipMemcpyHostToDevice, s));
-      if (d->kind == BCHAR_MESH_CARTESIAN) {
+      if (d->kind == BCHAR_MESH_CARTESIAN && !custom) {
         m->bmax = pmax * ub.cell_vol;
         bchar::mesh_build_cartesian(m, ub, s);
       } else {
+        // |K|_phi on the host (the same product phi_K |K| as on the device)
         std::vector<double> b(nc);
         m->bmax = 0;
         for (int64_t K = 0; K < nc; ++K) {
           b[K] = hphi[K] * kvol[K];
           m->bmax = std::max(m->bmax, b[K]);
         }
-        simplex_upload(m, sh, b, hphi, s);
+        if (d->kind == BCHAR_MESH_SIMPLEX) {
+          simplex_upload(m, sh, b, !custom, s);
+        } else {
+          m->b.reserve(sizeof(double) * nc);
+          BCHAR_HIP(hipMemcpyAsync(m->b.p, b.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
+                                   s));
+        }
+        if (custom) custom_layout(m, d, d->balls, d->ball_cell, kvol, s);
         bchar::mesh_build_hash(m, s);
       }
     } catch (...) {
@@ -662,6 +835,12 @@ bchar_status bchar_mesh_destroy(bchar_mesh m) {
   m->bk_cen32.release();
   m->bk_ball.release();
   m->bk_rad.release();
+  m->bk_cell.release();
+  m->bk_w.release();
+  m->ball_ptr.release();
+  m->ball_cell.release();
+  m->tile_cell.release();
+  m->cell_cen.release();
   m->rho.release();
   m->rad.release();
   m->bvol.release();
@@ -701,6 +880,8 @@ static void transfer_free(bchar_transfer t) {
   t->r_hat.release();
   t->pair_a.release();
   t->pair_b.release();
+  t->stage_col.release();
+  t->stage_val.release();
   t->ws.release();
   t->cscratch.release();
 }
@@ -766,7 +947,7 @@ bchar_status bchar_build_transfer_tracked(bchar_mesh m, const double* tracked,
                                hipMemcpyDeviceToDevice, s));
       BCHAR_HIP(hipMemcpyAsync(t->r_hat.p, r_hat, sizeof(double) * m->n_balls,
                                hipMemcpyDeviceToDevice, s));
-      rc = build_from_tracked(m, t, o, s, stats);
+      rc = build_from_tracked(m, t, o, BCHAR_FP64, s, stats);
     } catch (...) {
       transfer_free(t);
       delete t;
@@ -808,9 +989,11 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
         if (!src || !dst || src == dst) continue;
         BCHAR_REQUIRE(src->mesh == dst->mesh, BCHAR_E_INVALID_ARG,
                       "warm_from is a transfer of another mesh");
+        // the leading parts of the multipliers (the compensation restarts
+        // with a warm start); the transfer keeps both parts, 4 n values
         const size_t bytes = sizeof(double) * 2 * dst->mesh->n_cells;
         if (src->warm_level < 0 || src->zdual.bytes < bytes) continue;
-        if (dst->zdual.bytes < bytes) dst->zdual.reserve(bytes);
+        if (dst->zdual.bytes < 2 * bytes) dst->zdual.reserve(2 * bytes);
         BCHAR_HIP(hipMemcpyAsync(dst->zdual.p, src->zdual.p, bytes, hipMemcpyDeviceToDevice, s0));
         dst->warm_level = src->warm_level;
         copied = true;
@@ -1038,6 +1221,22 @@ bchar_status bchar_transfer_export_qp(bchar_transfer t, double* x, double* mu, d
   });
 }
 
+bchar_status bchar_transfer_export_qp_dual(bchar_transfer t, double* sv, double* gv,
+                                           double* s_lo, double* g_lo) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr && t->stage == BCHAR_STAGE_ALL, BCHAR_E_INVALID_ARG,
+                  "transfer not built to the final stage");
+    const int64_t n = t->mesh->n_cells;
+    BCHAR_HIP(hipDeviceSynchronize());
+    const double* z = t->zdual.as<double>();
+    double* out[4] = {sv, gv, s_lo, g_lo};
+    for (int i = 0; i < 4; ++i)
+      if (out[i])
+        BCHAR_HIP(hipMemcpy(out[i], z + i * n, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return BCHAR_OK;
+  });
+}
+
 bchar_status bchar_mesh_export_balls(bchar_mesh m, double* centres, double* radii,
                                      int32_t* cell) {
   return guarded([&]() -> bchar_status {
@@ -1048,8 +1247,11 @@ bchar_status bchar_mesh_export_balls(bchar_mesh m, double* centres, double* radi
                           hipMemcpyDeviceToHost));
     if (radii)
       BCHAR_HIP(hipMemcpy(radii, m->rad.p, sizeof(double) * m->n_balls, hipMemcpyDeviceToHost));
-    if (cell)
+    if (cell && m->nbpc > 0)
       for (int64_t b = 0; b < m->n_balls; ++b) cell[b] = (int32_t)(b / m->nbpc);
+    else if (cell)
+      BCHAR_HIP(hipMemcpy(cell, m->ball_cell.p, sizeof(int32_t) * m->n_balls,
+                          hipMemcpyDeviceToHost));
     return BCHAR_OK;
   });
 }

@@ -9,17 +9,23 @@
 //          is that of the Cartesian cell floor((x - o) / h), or, on a
 //          simplicial mesh, of the cell located through a uniform grid of
 //          cell lists (the rule is stated in bchar.h).
-// assemble: one wavefront per tracked cell K.  Lanes are split into
-//          n_balls_per_cell groups; the lanes of a group share the 3^d (or
-//          (2w+1)^d) hash buckets around that ball's tracked centre.  For
-//          every overlapping residing ball (predicate without sqrt or FMA,
-//          tangency excluded) the weight omega = rho_M phi_M |B_hat cap B|
-//          is formed; the group reduces S = sum omega; the shares
-//          rho_K phi_K |B| omega / S are compacted into LDS in a fixed
-//          order and merged by residing cell M.  A count pass gives the row
-//          lengths, a scan gives row_ptr, and a fill pass (same arithmetic)
-//          writes sorted columns and values.  No floating-point atomics: the
-//          result does not depend on scheduling.
+// assemble: one pass.  A workgroup of 256 threads takes a tile of cells
+//          (a block of 4x4x2 / 8x8 cells on a Cartesian mesh, a run of
+//          consecutive cells otherwise) and one thread per tracked ball of
+//          those cells.  Each thread walks the rows of hash buckets around
+//          its tracked centre (a row of buckets is one contiguous run of
+//          bucket slots) and, for every overlapping residing ball
+//          (predicate without sqrt or FMA, tangency excluded), forms the
+//          weight omega = rho_M phi_M |B_hat cap B| and S = sum omega; a
+//          block scan places every ball's overlaps, a second walk (from
+//          cache) writes the shares rho_K phi_K |B| omega / S into LDS, and
+//          the threads of each cell merge them by residing cell M (sorted,
+//          summed in a fixed order).  A tile whose overlaps exceed the LDS
+//          capacity is processed in groups of whole cells.  Each group
+//          reserves room in a staging array with one atomic add; a scan of
+//          the row lengths and a copy kernel then lay the rows out as CSR.
+//          No floating-point atomics: the values do not depend on
+//          scheduling (only the staging positions do).
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -42,7 +48,7 @@ struct PhiView {
   int64_t n[3];
   T org[3], h[3];
   // simplicial meshes (simplex != 0): vertices SoA, (dim+1) ids per cell,
-  // centroids (ball centres, SoA), the domain box and the location grid
+  // centroids (SoA), the domain box and the location grid
   int simplex;
   const double* vtx;
   int64_t n_vertices;
@@ -321,7 +327,7 @@ static void launch_trace(const bchar_mesh_s* m, const bchar_velocity& u, double 
   P.vtx = m->vtx.as<double>();
   P.n_vertices = m->n_vertices;
   P.cells = m->cells.as<int32_t>();
-  P.cen = m->cen.as<double>();
+  P.cen = m->cell_cen.as<double>();
   P.n_cells = m->n_cells;
   P.pl_inv = m->pl_inv;
   P.pl_start = m->pl_start.as<int32_t>();
@@ -346,11 +352,10 @@ static void launch_trace(const bchar_mesh_s* m, const bchar_velocity& u, double 
 
 void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int substeps,
                  int precision, double* tracked, double* r_hat, Arena& ws, hipStream_t s) {
-  // With a porosity that varies from cell to cell the speed u/phi jumps on
-  // cell faces, and the cardinal points of a ball start on faces: binary32
-  // rounding would pick the neighbouring cell's phi.  Those meshes are
-  // tracked in binary64 in both modes.
-  if (precision == BCHAR_FP64 || !m->phi_const) {
+  // binary32 tracking only in FP32_VOLUME, which the caller allows only
+  // where phi is constant (on faces, where u/phi jumps and the cardinal
+  // points start, binary32 rounding would pick the neighbouring cell's phi)
+  if (precision != BCHAR_FP32_VOLUME) {
     const double* comps[3] = {u.u[0], u.u[1], u.u[2]};
     if (m->dim == 2)
       launch_trace<2, double>(m, u, dt, substeps, comps, tracked, r_hat, s);
@@ -416,43 +421,82 @@ __device__ __forceinline__ T lens(T r1, T r2, T d) {
 
 // ---------------------------------------------------------------- assembly
 
-constexpr int kCap = 1024;   // candidate shares per tracked cell held in LDS
-constexpr int kXcds = 8;     // accelerator complex dies of the MI355X
+constexpr int kXcds = 8;         // accelerator complex dies of the MI355X
+constexpr int kTileThreads = 256; // tracked balls per tile (one thread each)
+constexpr int kTileCap = 2048;    // overlaps of one group of cells held in LDS
 
-// one workgroup per cell, padded to a multiple of the XCD count
-static inline int64_t xcd_grid(int64_t n_cells) {
-  return ((n_cells + kXcds - 1) / kXcds) * kXcds;
-}
+// flags of one assembly launch (int32, cleared before it)
+enum {
+  kFlagFirstVoid = 0,   // lowest tracked ball with S = 0 (INT32_MAX: none)
+  kFlagVoidRows,        // tracked cells with a void ball
+  kFlagCellOverflow,    // largest overlap count of a single cell beyond kTileCap
+  kFlagEntries,         // staged entries (unique (K, M) per row)
+  kFlagPairs,           // candidate pairs
+  kFlagStageOverflow,   // staging or pair storage too small
+  kNumFlags
+};
 
-struct AsmParams {
+struct TileParams {
   int64_t n_cells, n_balls;
-  int nbpc;
+  int nbpc;                 // balls per cell, 0: variable (ball_ptr)
+  const int32_t* ball_ptr;  // variable layouts: first ball of every cell, n_cells + 1
+  const int32_t* tile_cell; // variable layouts: first cell of every tile, n_tiles + 1
+  // Cartesian tiles: tx * ty * tz cells per tile, nt tiles per axis;
+  // tx == 0: tiles are runs of cells_per_tile consecutive cells
+  int tx, ty, tz;
+  int64_t nt[3];
+  int64_t n[3];
+  int cells_per_tile;
+  int64_t n_tiles;
+  // hash
   int64_t nbk[3];
   double org[3];
   double inv_hs;
-  double hs;
-  double rmax;            // largest residing radius
-  const double* rho;      // per cell, porous density
-  const double* bvol;     // per ball, |B_{K,s}|
-  const double* phi;      // per cell
-  const double* tracked;  // dim * n_balls
-  const double* r_hat;    // n_balls
+  double rmax;
+  double r0;                // radius of every residing ball (uniform layouts)
+  const double* rho;        // per cell
+  const double* phi;        // per cell
+  const double* bvol;       // per ball, |B_{K,s}|
+  const double* tracked;    // dim * n_balls
+  const double* r_hat;      // n_balls
   const int32_t* bucket_start;
-  const double* bk_cen;   // dim * n_balls, bucket order
+  const double* bk_cen;     // dim * n_balls, bucket order
   const float* bk_cen32;
-  const int32_t* bk_ball;
-  const double* bk_rad;   // n_balls, bucket order
+  const double* bk_rad;     // n_balls, bucket order
+  const int32_t* bk_cell;   // residing cell of each slot
+  const int32_t* bk_ball;   // residing ball of each slot
+  const double* bk_w;       // rho_M phi_M of each slot
   // outputs
-  int32_t* row_cnt;       // count pass: unique M per row
-  int32_t* pair_cnt;      // count pass: pairs per row
-  const int32_t* row_ptr; // fill pass
-  const int32_t* pair_ptr;
-  int32_t* col;
-  double* val;
-  int32_t* pair_a;        // may be null
+  int32_t* row_cnt;         // unique residing cells per row
+  int32_t* stage_off;       // staging position of every row
+  int32_t* stage_col;
+  double* stage_val;
+  int64_t stage_cap;
+  int32_t* pair_a;          // may be null
   int32_t* pair_b;
-  int32_t* flags;         // [0] first void ball (min), [1] overflow
+  int64_t pair_cap;
+  int32_t* flags;           // kNumFlags
 };
+
+// Block-wide exclusive scan of one int per thread (256 threads); *total is
+// the sum over the block.
+__device__ __forceinline__ int block_excl_scan(int v, int* s_wave, int& total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int incl = wave_incl_scan_i(v);
+  if (lane == kWave - 1) s_wave[w] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kTileThreads / kWave; ++i) {
+    const int x = s_wave[i];
+    base += i < w ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return base + incl - v;
+}
 
 // Predicate ((dx*dx + dy*dy) + dz*dz) < (ra + rb)^2 (rs = ra + rb), rounded
 // once per operation (no contraction into FMA) so that it is reproducible.
@@ -471,10 +515,15 @@ __device__ __forceinline__ bool overlap(const T p[3], const T c[3], T rs, T& d2)
   return s < rs * rs;
 }
 
-template <int DIM, class T>
-__device__ __forceinline__ void search_range(const AsmParams& P, const T p[3], double reach,
-                                             int64_t blo[3], int64_t side[3]) {
-  const double D = reach * (1.0 + 1e-6);
+// Every residing ball overlapping the tracked ball (p, ra): the buckets
+// that can hold a centre within ra + r_max of p (the range widened by a
+// relative 1e-6 so that binary32 rounding of the predicate cannot reach
+// past it; the predicate alone decides), walked as rows of consecutive
+// buckets along x, each row one run of slots.  f(slot, rb, d2).
+template <int DIM, class T, bool UR, class F>
+__device__ __forceinline__ void for_each_overlap(const TileParams& P, const T p[3], T ra, F&& f) {
+  const double D = ((double)ra + P.rmax) * (1.0 + 1e-6);
+  int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double x = (double)p[a] - P.org[a];
@@ -485,216 +534,317 @@ __device__ __forceinline__ void search_range(const AsmParams& P, const T p[3], d
     blo[a] = lo;
     side[a] = hi >= lo ? hi - lo + 1 : 0;
   }
+  const int64_t nb = P.n_balls;
+  for (int64_t bz = 0; bz < side[2]; ++bz)
+    for (int64_t by = 0; by < side[1]; ++by) {
+      const int64_t row = blo[0] + P.nbk[0] * ((blo[1] + by) + P.nbk[1] * (blo[2] + bz));
+      const int32_t lo = P.bucket_start[row];
+      const int32_t hi = P.bucket_start[row + side[0]];
+      for (int32_t e = lo; e < hi; ++e) {
+        T c[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
+        const T rb = UR ? (T)P.r0 : (T)P.bk_rad[e];
+        T d2;
+        if (overlap<DIM, T>(p, c, ra + rb, d2)) f(e, rb, d2);
+      }
+    }
 }
 
-template <int DIM, class T, bool FILL>
-__global__ void __launch_bounds__(64) k_assemble(AsmParams P) {
-  __shared__ int32_t s_key[kCap];
-  __shared__ double s_val[kCap];
-  __shared__ int32_t s_first[kCap];
-  __shared__ int32_t s_pb[FILL ? kCap : 1];
+// Cell of local index lc in tile t, or -1 past the mesh.
+__device__ __forceinline__ int64_t tile_cell_id(const TileParams& P, int64_t t, int lc) {
+  if (P.tile_cell) {
+    const int64_t K = (int64_t)P.tile_cell[t] + lc;
+    return K < P.tile_cell[t + 1] ? K : -1;
+  }
+  if (P.tx == 0) {
+    const int64_t K = t * P.cells_per_tile + lc;
+    return K < P.n_cells ? K : -1;
+  }
+  const int lx = lc % P.tx, ly = (lc / P.tx) % P.ty, lz = lc / (P.tx * P.ty);
+  const int64_t i = (t % P.nt[0]) * P.tx + lx;
+  const int64_t j = ((t / P.nt[0]) % P.nt[1]) * P.ty + ly;
+  const int64_t k = (t / (P.nt[0] * P.nt[1])) * P.tz + lz;
+  if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) return -1;
+  return i + P.n[0] * (j + P.n[1] * k);
+}
+
+template <int DIM, class T, bool UR>
+__global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
+  __shared__ int32_t s_key[kTileCap];
+  __shared__ double s_val[kTileCap];
+  __shared__ uint8_t s_first[kTileCap];
+  __shared__ int32_t s_cstart[kTileThreads + 1];   // first overlap of every local cell
+  __shared__ int32_t s_ucnt[kTileThreads];         // unique residing cells of every local cell
+  __shared__ int32_t s_upre[kTileThreads];         // their exclusive scan within the group
+  __shared__ int32_t s_wave[kTileThreads / kWave];
+  __shared__ int32_t s_misc[4];
+
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, each
-  // with its own L2; give XCD j the j-th contiguous chunk of cells so that
-  // neighbouring cells, which read the same hash buckets, share an L2
-  const int64_t chunk = (P.n_cells + kXcds - 1) / kXcds;
-  const int64_t K = (int64_t)(blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
-  if (K >= P.n_cells) return;
-  const int lane = threadIdx.x;
-  const int nbpc = P.nbpc;
-  const int spb = kWave / nbpc;         // lanes per tracked ball
-  const int s = lane / spb;
-  const int slot = lane % spb;
-  const int64_t b = K * nbpc + s;
+  // with its own L2; XCD j takes the j-th contiguous chunk of tiles so that
+  // neighbouring tiles, which read the same hash buckets, share an L2
+  const int64_t chunk = (P.n_tiles + kXcds - 1) / kXcds;
+  const int64_t t = (int64_t)(blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
+  if (t >= P.n_tiles) return;   // the whole block leaves together
+  const int tid = threadIdx.x;
   const int64_t nb = P.n_balls;
 
-  T p[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
-  const T ra = (T)P.r_hat[b];
-  // buckets that can hold a centre within ra + r_max of p (range widened by
-  // a relative 1e-6 so that binary32 rounding of the predicate cannot reach
-  // past it; the predicate alone decides)
-  int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
-  search_range<DIM>(P, p, (double)ra + P.rmax, blo, side);
-  const int nq = (int)(side[0] * side[1] * side[2]);
-  const double mass = P.rho[K] * P.phi[K] * P.bvol[b];   // rho_K phi_K |B_{K,s}|
+  // ---- this thread's tracked ball: local cell lc (every thread of a
+  // uniform layout has one, also past the mesh), ball b (-1: none), its rank
+  // s in the cell and the cell's ball count nbc
+  int lc = -1, s = 0, nbc = 1;
+  int64_t K = -1, b = -1;
+  int nct = 0;   // local cells of the tile
+  if (P.nbpc > 0) {
+    nct = kTileThreads / P.nbpc;
+    if (tid < nct * P.nbpc) {
+      lc = tid / P.nbpc;
+      s = tid % P.nbpc;
+      nbc = P.nbpc;
+      K = tile_cell_id(P, t, lc);
+      if (K >= 0) b = K * P.nbpc + s;
+    }
+  } else {
+    const int64_t c0 = P.tile_cell[t], c1 = P.tile_cell[t + 1];
+    nct = (int)(c1 - c0);
+    const int64_t bb = (int64_t)P.ball_ptr[c0] + tid;
+    if (bb < P.ball_ptr[c1]) {
+      // the cell holding ball bb: binary search over the tile's cells
+      int64_t lo = c0, hi = c1 - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (P.ball_ptr[mid] <= bb) lo = mid;
+        else hi = mid - 1;
+      }
+      K = lo;
+      lc = (int)(K - c0);
+      b = bb;
+      s = (int)(bb - P.ball_ptr[K]);
+      nbc = P.ball_ptr[K + 1] - P.ball_ptr[K];
+    }
+  }
 
-  // pass 1: number of overlaps and S = sum omega for this lane's buckets
+  T p[3] = {0, 0, 0};
+  T ra = 0;
+  double mass = 0.0;
+  if (b >= 0) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
+    ra = (T)P.r_hat[b];
+    mass = P.rho[K] * P.phi[K] * P.bvol[b];   // rho_K phi_K |B_{K,s}|
+  }
+
+  // ---- pass 1: number of overlaps and S = sum omega, in slot order
   int cnt = 0;
   double S = 0.0;
-  for (int q = slot; q < nq; q += spb) {
-    const int64_t bc0 = blo[0] + q % side[0];
-    const int64_t bc1 = blo[1] + (q / side[0]) % side[1];
-    const int64_t bc2 = DIM == 3 ? blo[2] + q / (side[0] * side[1]) : 0;
-    const int64_t bucket = bc0 + P.nbk[0] * (bc1 + P.nbk[1] * bc2);
-    const int32_t lo = P.bucket_start[bucket], hi = P.bucket_start[bucket + 1];
-    for (int32_t e = lo; e < hi; ++e) {
-      T c[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 0; a < DIM; ++a)
-        c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
-      const T rb = (T)P.bk_rad[e];
-      T d2;
-      if (!overlap<DIM, T>(p, c, ra + rb, d2)) continue;
-      const int64_t M = P.bk_ball[e] / nbpc;
-      const double om = P.rho[M] * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
-      S += om;
+  if (b >= 0)
+    for_each_overlap<DIM, T, UR>(P, p, ra, [&](int32_t e, T rb, T d2) {
+      S += P.bk_w[e] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
       ++cnt;
-    }
+    });
+  s_ucnt[tid] = 0;   // void marks of the local cells until the scan below
+  __syncthreads();
+  if (b >= 0 && !(S > 0.0)) {
+    atomicMin(&P.flags[kFlagFirstVoid], (int32_t)b);
+    atomicOr(&s_ucnt[lc], 1);
   }
-  // S of the ball: fixed-order butterfly over the lanes of its group
-  for (int o = spb / 2; o > 0; o >>= 1) S += __shfl_xor(S, o, kWave);
-  if (slot == 0 && !(S > 0.0)) atomicMin(&P.flags[0], (int32_t)b);
   const double share = S > 0.0 ? mass / S : 0.0;
 
-  // compaction offsets (lane order) and total
-  const int incl = wave_incl_scan_i(cnt);
-  const int H = __shfl(incl, kWave - 1, kWave);
-  int off = incl - cnt;
-  if (H > kCap) {
-    if (lane == 0) atomicMax(&P.flags[1], H);
-    return;
+  // the balls of a cell are consecutive threads, so the block scan of the
+  // counts gives every ball's first slot and every cell's range
+  int H = 0;
+  const int off = block_excl_scan(cnt, s_wave, H);
+  if (lc >= 0) {
+    if (s == 0) s_cstart[lc] = off;
+    if (s == nbc - 1) s_cstart[lc + 1] = off + cnt;
+    if (s == 0 && b >= 0 && s_ucnt[lc]) atomicAdd(&P.flags[kFlagVoidRows], 1);
   }
-  // pass 2: the same overlaps, written in order
-  for (int q = slot; q < nq; q += spb) {
-    const int64_t bc0 = blo[0] + q % side[0];
-    const int64_t bc1 = blo[1] + (q / side[0]) % side[1];
-    const int64_t bc2 = DIM == 3 ? blo[2] + q / (side[0] * side[1]) : 0;
-    const int64_t bucket = bc0 + P.nbk[0] * (bc1 + P.nbk[1] * bc2);
-    const int32_t lo = P.bucket_start[bucket], hi = P.bucket_start[bucket + 1];
-    for (int32_t e = lo; e < hi; ++e) {
-      T c[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 0; a < DIM; ++a)
-        c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
-      const T rb = (T)P.bk_rad[e];
-      T d2;
-      if (!overlap<DIM, T>(p, c, ra + rb, d2)) continue;
-      const int32_t rb_id = P.bk_ball[e];
-      const int32_t M = rb_id / nbpc;
-      const double om = P.rho[M] * P.phi[M] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
-      s_key[off] = M;
-      s_val[off] = share * om;
-      if (FILL) s_pb[off] = rb_id;
-      ++off;
-    }
+  if (tid == 0) {
+    s_misc[0] = atomicAdd(&P.flags[kFlagPairs], H);
+    if (P.pair_a && (int64_t)s_misc[0] + H > P.pair_cap)
+      atomicOr(&P.flags[kFlagStageOverflow], 1);
   }
   __syncthreads();
-  // first occurrence of every residing cell
-  for (int e = lane; e < H; e += kWave) {
-    const int32_t k = s_key[e];
-    int first = 1;
-    for (int j = 0; j < e; ++j)
-      if (s_key[j] == k) {
-        first = 0;
-        break;
+  const int pbase = s_misc[0];
+  const bool write_pairs = P.pair_a && (int64_t)pbase + H <= P.pair_cap;
+
+  // ---- groups of whole cells whose overlaps fit in LDS (one group unless
+  // the tile overlaps more than kTileCap residing balls)
+  int gs = 0;
+  while (gs < nct) {
+    // the group is cells gs .. ge-1, the longest run from gs that fits
+    // (cell starts are non-decreasing in the local index)
+    if (tid == 0) s_misc[1] = gs;
+    __syncthreads();
+    if (tid >= gs && tid < nct && s_cstart[tid + 1] - s_cstart[gs] <= kTileCap)
+      atomicMax(&s_misc[1], tid + 1);
+    __syncthreads();
+    const int ge = s_misc[1];
+    const int gbase = s_cstart[gs];
+    if (ge == gs) {
+      // one cell alone overlaps more residing balls than LDS holds
+      if (tid == 0) atomicMax(&P.flags[kFlagCellOverflow], s_cstart[gs + 1] - gbase);
+      __syncthreads();
+      gs = gs + 1;
+      continue;
+    }
+    const bool mine = b >= 0 && lc >= gs && lc < ge;
+    // pass 2: the same overlaps again (from cache), written in order
+    if (mine) {
+      int o = off - gbase;
+      int po = pbase + off;
+      for_each_overlap<DIM, T, UR>(P, p, ra, [&](int32_t e, T rb, T d2) {
+        const double om = P.bk_w[e] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
+        s_key[o] = P.bk_cell[e];
+        s_val[o] = share * om;
+        ++o;
+        if (write_pairs) {
+          P.pair_a[po] = (int32_t)b;
+          P.pair_b[po] = P.bk_ball[e];
+          ++po;
+        }
+      });
+    }
+    s_ucnt[tid] = 0;
+    __syncthreads();
+    // first occurrence of every residing cell within its tracked cell
+    int e0 = 0, e1 = 0;
+    if (mine) {
+      e0 = s_cstart[lc] - gbase;
+      e1 = s_cstart[lc + 1] - gbase;
+      int u = 0;
+      for (int e = e0 + s; e < e1; e += nbc) {
+        const int32_t k = s_key[e];
+        int first = 1;
+        for (int j = e0; j < e; ++j)
+          if (s_key[j] == k) {
+            first = 0;
+            break;
+          }
+        s_first[e] = (uint8_t)first;
+        u += first;
       }
-    s_first[e] = first;
-  }
-  __syncthreads();
-  if (!FILL) {
-    int u = 0;
-    for (int e = lane; e < H; e += kWave) u += s_first[e];
-    u = wave_sum_i(u);
-    if (lane == 0) {
-      P.row_cnt[K] = u;
-      P.pair_cnt[K] = H;
+      if (u) atomicAdd(&s_ucnt[lc], u);
     }
-    return;
-  }
-  const int32_t base = P.row_ptr[K];
-  for (int e = lane; e < H; e += kWave) {
-    if (!s_first[e]) continue;
-    const int32_t k = s_key[e];
-    int rank = 0;
-    double v = 0.0;
-    for (int j = 0; j < H; ++j) {
-      const int32_t kj = s_key[j];
-      if (s_first[j] && kj < k) ++rank;
-      if (kj == k) v += s_val[j];
+    __syncthreads();
+    // unique counts scanned over the group's cells; the group reserves
+    // its staging room with one atomic add
+    int U = 0;
+    const int uc = (tid >= gs && tid < ge) ? s_ucnt[tid] : 0;
+    const int uo = block_excl_scan(uc, s_wave, U);
+    if (tid >= gs && tid < ge) s_upre[tid] = uo;
+    if (tid == 0) s_misc[2] = atomicAdd(&P.flags[kFlagEntries], U);
+    __syncthreads();
+    const int64_t sbase = s_misc[2];
+    if (sbase + U > P.stage_cap) {
+      if (tid == 0) atomicOr(&P.flags[kFlagStageOverflow], 1);
+    } else if (mine) {
+      const int64_t rbase = sbase + s_upre[lc];
+      for (int e = e0 + s; e < e1; e += nbc) {
+        if (!s_first[e]) continue;
+        const int32_t k = s_key[e];
+        int rank = 0;
+        double v = 0.0;
+        for (int j = e0; j < e1; ++j) {
+          const int32_t kj = s_key[j];
+          if (s_first[j] && kj < k) ++rank;
+          if (kj == k) v += s_val[j];
+        }
+        P.stage_col[rbase + rank] = k;
+        P.stage_val[rbase + rank] = v;
+      }
+      if (s == 0) {
+        P.row_cnt[K] = s_ucnt[lc];
+        P.stage_off[K] = (int32_t)rbase;
+      }
     }
-    P.col[base + rank] = k;
-    P.val[base + rank] = v;
-  }
-  if (P.pair_a) {
-    const int32_t pb = P.pair_ptr[K];
-    for (int e = lane; e < H; e += kWave) {
-      // tracked ball of entry e: the group whose compacted range holds e
-      P.pair_a[pb + e] = -1;
-      P.pair_b[pb + e] = s_pb[e];
-    }
+    __syncthreads();
+    gs = ge;
   }
 }
 
-// The tracked ball of each pair entry: recomputed from the per-ball counts
-// written by a small kernel (entries are grouped by ball, in ball order).
-__global__ void k_pair_balls(const int32_t* __restrict__ pair_ptr, int64_t n_cells, int nbpc,
-                             const int32_t* __restrict__ ball_cnt,
-                             int32_t* __restrict__ pair_a) {
+// Rows laid out as CSR: row K's entries move from its staging position to
+// row_ptr[K] (one thread per row).
+__global__ void k_scatter_rows(int64_t n_cells, const int32_t* __restrict__ row_ptr,
+                               const int32_t* __restrict__ stage_off,
+                               const int32_t* __restrict__ stage_col,
+                               const double* __restrict__ stage_val, int32_t* __restrict__ col,
+                               double* __restrict__ val) {
   const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= n_cells) return;
-  int32_t e = pair_ptr[K];
-  for (int s = 0; s < nbpc; ++s) {
-    const int64_t b = K * nbpc + s;
-    for (int32_t i = 0; i < ball_cnt[b]; ++i) pair_a[e++] = (int32_t)b;
+  const int32_t d = row_ptr[K], n = row_ptr[K + 1] - d;
+  const int32_t so = stage_off[K];
+  for (int32_t i = 0; i < n; ++i) {
+    col[d + i] = stage_col[so + i];
+    val[d + i] = stage_val[so + i];
   }
 }
 
-// Per-ball overlap counts (for the pair export), one thread per ball.
-template <int DIM, class T>
-__global__ void k_ball_counts(AsmParams P, int32_t* __restrict__ ball_cnt) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= P.n_balls) return;
-  const int64_t nb = P.n_balls;
-  T p[3] = {0, 0, 0};
-  for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
-  const T ra = (T)P.r_hat[b];
-  int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
-  search_range<DIM>(P, p, (double)ra + P.rmax, blo, side);
-  const int nq = (int)(side[0] * side[1] * side[2]);
-  int cnt = 0;
-  for (int q = 0; q < nq; ++q) {
-    const int64_t bc0 = blo[0] + q % side[0];
-    const int64_t bc1 = blo[1] + (q / side[0]) % side[1];
-    const int64_t bc2 = DIM == 3 ? blo[2] + q / (side[0] * side[1]) : 0;
-    const int64_t bucket = bc0 + P.nbk[0] * (bc1 + P.nbk[1] * bc2);
-    for (int32_t e = P.bucket_start[bucket]; e < P.bucket_start[bucket + 1]; ++e) {
-      T c[3] = {0, 0, 0};
-      for (int a = 0; a < DIM; ++a)
-        c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
-      T d2;
-      if (overlap<DIM, T>(p, c, ra + (T)P.bk_rad[e], d2)) ++cnt;
-    }
-  }
-  ball_cnt[b] = cnt;
+__global__ void k_init_flags(int32_t* __restrict__ f) {
+  const int i = threadIdx.x;
+  if (i < kNumFlags) f[i] = i == kFlagFirstVoid ? INT32_MAX : 0;
 }
 
 template <int DIM, class T>
-static void launch_assemble(AsmParams& P, bool fill, hipStream_t s) {
-  if (fill)
-    {
-      ::bchar::ProfScope ps_("k_assemble", s);
-      k_assemble<DIM, T, true><<<(unsigned)xcd_grid(P.n_cells), 64, 0, s>>>(P);
-    }
+static void launch_assemble_t(const TileParams& P, unsigned grid, bool ur, hipStream_t s) {
+  ::bchar::ProfScope ps_("k_assemble", s);
+  if (ur)
+    k_assemble<DIM, T, true><<<grid, kTileThreads, 0, s>>>(P);
   else
-    {
-      ::bchar::ProfScope ps_("k_assemble", s);
-      k_assemble<DIM, T, false><<<(unsigned)xcd_grid(P.n_cells), 64, 0, s>>>(P);
-    }
+    k_assemble<DIM, T, false><<<grid, kTileThreads, 0, s>>>(P);
+}
+
+static void launch_assemble(int dim, int precision, const TileParams& P, bool ur, hipStream_t s) {
+  const unsigned grid = (unsigned)(((P.n_tiles + kXcds - 1) / kXcds) * kXcds);
+  const bool f32 = precision != BCHAR_FP64;
+  if (dim == 2) {
+    if (f32) launch_assemble_t<2, float>(P, grid, ur, s);
+    else launch_assemble_t<2, double>(P, grid, ur, s);
+  } else {
+    if (f32) launch_assemble_t<3, float>(P, grid, ur, s);
+    else launch_assemble_t<3, double>(P, grid, ur, s);
+  }
   BCHAR_HIP(hipGetLastError());
 }
 
-static void dispatch_assemble(int dim, int precision, AsmParams& P, bool fill, hipStream_t s) {
-  if (dim == 2) {
-    if (precision == BCHAR_FP64)
-      launch_assemble<2, double>(P, fill, s);
-    else
-      launch_assemble<2, float>(P, fill, s);
+// Tile shape of a uniform layout: a block of cells on a Cartesian mesh
+// (square-ish in the plane, so that the tile's tracked balls read few
+// hash rows), a run of consecutive cells otherwise.
+static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
+  P.cells_per_tile = kTileThreads / m->nbpc;
+  P.tx = P.ty = P.tz = 0;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = m->n[a];
+    P.nt[a] = 1;
+  }
+  if (m->kind == BCHAR_MESH_CARTESIAN) {
+    const int c = P.cells_per_tile;
+    if (m->dim == 3) {
+      // 256 -> 8x8x4, 32 -> 4x4x2
+      int tz = 1;
+      while (tz * tz * tz * 4 < c) tz *= 2;
+      const int txy = c / tz;
+      int tx = 1;
+      while (tx * tx < txy) tx *= 2;
+      P.tx = tx;
+      P.ty = txy / tx;
+      P.tz = tz;
+    } else {
+      int tx = 1;
+      while (tx * tx < c) tx *= 2;
+      P.tx = tx;
+      P.ty = c / tx;
+      P.tz = 1;
+    }
+    const int t3[3] = {P.tx, P.ty, P.tz};
+    P.n_tiles = 1;
+    for (int a = 0; a < 3; ++a) {
+      P.nt[a] = (m->n[a] + t3[a] - 1) / t3[a];
+      P.n_tiles *= P.nt[a];
+    }
   } else {
-    if (precision == BCHAR_FP64)
-      launch_assemble<3, double>(P, fill, s);
-    else
-      launch_assemble<3, float>(P, fill, s);
+    P.n_tiles = (m->n_cells + P.cells_per_tile - 1) / P.cells_per_tile;
   }
 }
 
@@ -703,100 +853,100 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
                         int64_t* first_void, hipStream_t s) {
   Arena& ws = t->ws;
   const int64_t nc = m->n_cells;
-  BCHAR_REQUIRE(kWave % m->nbpc == 0, BCHAR_E_UNSUPPORTED, "balls per cell must divide 64");
-  AsmParams P{};
+  TileParams P{};
   P.n_cells = nc;
   P.n_balls = m->n_balls;
   P.nbpc = m->nbpc;
+  if (m->nbpc > 0) {
+    tile_shape(m, P);
+  } else {
+    P.ball_ptr = m->ball_ptr.as<int32_t>();
+    P.tile_cell = m->tile_cell.as<int32_t>();
+    P.n_tiles = m->n_tiles;
+  }
   for (int a = 0; a < 3; ++a) {
     P.nbk[a] = m->nbk[a];
     P.org[a] = m->box_lo[a];
   }
   P.inv_hs = 1.0 / m->hs;
-  P.hs = m->hs;
   P.rmax = m->rmax;
+  P.r0 = m->r0;
   P.rho = m->rho.as<double>();
-  P.bvol = m->bvol.as<double>();
   P.phi = m->phi.as<double>();
+  P.bvol = m->bvol.as<double>();
   P.tracked = tracked;
   P.r_hat = r_hat;
   P.bucket_start = m->bucket_start.as<int32_t>();
   P.bk_cen = m->bk_cen.as<double>();
   P.bk_cen32 = m->bk_cen32.as<float>();
-  P.bk_ball = m->bk_ball.as<int32_t>();
   P.bk_rad = m->bk_rad.as<double>();
+  P.bk_cell = m->bk_cell.as<int32_t>();
+  P.bk_ball = m->bk_ball.as<int32_t>();
+  P.bk_w = m->bk_w.as<double>();
   P.row_cnt = ws.get<int32_t>(nc + 1);
-  P.pair_cnt = ws.get<int32_t>(nc + 1);
-  P.flags = ws.get<int32_t>(2);
-  int32_t hflags[2] = {INT32_MAX, 0};
-  BCHAR_HIP(hipMemcpyAsync(P.flags, hflags, sizeof(hflags), hipMemcpyHostToDevice, s));
-
-  dispatch_assemble(m->dim, precision, P, false, s);
-  BCHAR_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
-  BCHAR_HIP(hipStreamSynchronize(s));
-  if (hflags[1] > 0)
-    throw Error{BCHAR_E_UNSUPPORTED, "a tracked cell overlaps " + std::to_string(hflags[1]) +
-                                         " residing balls (more than " +
-                                         std::to_string(kCap) + ")"};
-  if (hflags[0] != INT32_MAX) {
-    *first_void = hflags[0];
-    return BCHAR_E_VOID_ROW;
+  P.stage_off = ws.get<int32_t>(nc + 1);
+  P.flags = ws.get<int32_t>(kNumFlags);
+  // staging room: the last build's need, else 8 entries per cell; a launch
+  // that finds it too small is repeated with what it needed
+  int64_t cap_e = std::max<int64_t>(t->stage_need, 8 * nc + 1024);
+  int64_t cap_p = keep_pairs ? std::max<int64_t>(t->pair_need, 16 * m->n_balls + 1024) : 0;
+  int32_t hf[kNumFlags];
+  for (int attempt = 0;; ++attempt) {
+    t->stage_col.reserve(sizeof(int32_t) * cap_e);
+    t->stage_val.reserve(sizeof(double) * cap_e);
+    P.stage_col = t->stage_col.as<int32_t>();
+    P.stage_val = t->stage_val.as<double>();
+    P.stage_cap = cap_e;
+    P.pair_a = P.pair_b = nullptr;
+    P.pair_cap = 0;
+    if (keep_pairs) {
+      t->pair_a.reserve(sizeof(int32_t) * cap_p);
+      t->pair_b.reserve(sizeof(int32_t) * cap_p);
+      P.pair_a = t->pair_a.as<int32_t>();
+      P.pair_b = t->pair_b.as<int32_t>();
+      P.pair_cap = cap_p;
+    }
+    k_init_flags<<<1, 64, 0, s>>>(P.flags);
+    BCHAR_HIP(hipGetLastError());
+    launch_assemble(m->dim, precision, P, m->r_uniform, s);
+    BCHAR_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    BCHAR_HIP(hipStreamSynchronize(s));
+    t->n_void_rows = hf[kFlagVoidRows];
+    if (hf[kFlagCellOverflow] > 0)
+      throw Error{BCHAR_E_UNSUPPORTED, "a tracked cell overlaps " +
+                                           std::to_string(hf[kFlagCellOverflow]) +
+                                           " residing balls (more than " +
+                                           std::to_string(kTileCap) + ")"};
+    if (hf[kFlagFirstVoid] != INT32_MAX) {
+      *first_void = hf[kFlagFirstVoid];
+      return BCHAR_E_VOID_ROW;
+    }
+    if (!hf[kFlagStageOverflow]) break;
+    BCHAR_REQUIRE(attempt == 0, BCHAR_E_DEVICE, "assembly staging still too small");
+    cap_e = std::max<int64_t>(cap_e, (int64_t)hf[kFlagEntries] + hf[kFlagEntries] / 4 + 1024);
+    if (keep_pairs)
+      cap_p = std::max<int64_t>(cap_p, (int64_t)hf[kFlagPairs] + hf[kFlagPairs] / 4 + 1024);
   }
+  t->stage_need = std::max<int64_t>(t->stage_need, (int64_t)hf[kFlagEntries] +
+                                                         hf[kFlagEntries] / 4 + 1024);
+  if (keep_pairs)
+    t->pair_need = std::max<int64_t>(t->pair_need, (int64_t)hf[kFlagPairs] + hf[kFlagPairs] / 4 +
+                                                       1024);
   t->row_ptr.reserve(sizeof(int32_t) * (nc + 1));
   int32_t* row_ptr = t->row_ptr.as<int32_t>();
   const int64_t nnz = exclusive_scan_i32(P.row_cnt, row_ptr, nc, ws, s);
-  int32_t* pair_ptr = ws.get<int32_t>(nc + 1);
-  const int64_t npairs = exclusive_scan_i32(P.pair_cnt, pair_ptr, nc, ws, s);
+  BCHAR_REQUIRE(nnz == hf[kFlagEntries], BCHAR_E_DEVICE, "assembly: row lengths disagree");
   t->nnz = nnz;
-  t->n_pairs = npairs;
+  t->n_pairs = hf[kFlagPairs];
   t->col.reserve(sizeof(int32_t) * (nnz + 1));
   t->V.reserve(sizeof(double) * (nnz + 1));
-  P.row_ptr = row_ptr;
-  P.pair_ptr = pair_ptr;
-  P.col = t->col.as<int32_t>();
-  P.val = t->V.as<double>();
-  P.pair_a = nullptr;
-  P.pair_b = nullptr;
-  if (keep_pairs) {
-    t->pair_a.reserve(sizeof(int32_t) * (npairs + 1));
-    t->pair_b.reserve(sizeof(int32_t) * (npairs + 1));
-    P.pair_a = t->pair_a.as<int32_t>();
-    P.pair_b = t->pair_b.as<int32_t>();
+  {
+    ::bchar::ProfScope ps_("k_scatter_rows", s);
+    k_scatter_rows<<<blocks_for(nc, 256), 256, 0, s>>>(nc, row_ptr, P.stage_off,
+                                                      P.stage_col, P.stage_val,
+                                                      t->col.as<int32_t>(), t->V.as<double>());
   }
-  dispatch_assemble(m->dim, precision, P, true, s);
-  if (keep_pairs) {
-    int32_t* ball_cnt = ws.get<int32_t>(m->n_balls);
-    if (m->dim == 2) {
-      if (precision == BCHAR_FP64)
-        {
-          ::bchar::ProfScope ps_("k_ball_counts", s);
-          k_ball_counts<2, double><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(P, ball_cnt);
-        }
-      else
-        {
-          ::bchar::ProfScope ps_("k_ball_counts", s);
-          k_ball_counts<2, float><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(P, ball_cnt);
-        }
-    } else {
-      if (precision == BCHAR_FP64)
-        {
-          ::bchar::ProfScope ps_("k_ball_counts", s);
-          k_ball_counts<3, double><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(P, ball_cnt);
-        }
-      else
-        {
-          ::bchar::ProfScope ps_("k_ball_counts", s);
-          k_ball_counts<3, float><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(P, ball_cnt);
-        }
-    }
-    BCHAR_HIP(hipGetLastError());
-    {
-      ::bchar::ProfScope ps_("k_pair_balls", s);
-      k_pair_balls<<<blocks_for(nc, 128), 128, 0, s>>>(pair_ptr, nc, m->nbpc, ball_cnt,
-                                                       P.pair_a);
-    }
-    BCHAR_HIP(hipGetLastError());
-  }
+  BCHAR_HIP(hipGetLastError());
   return BCHAR_OK;
 }
 

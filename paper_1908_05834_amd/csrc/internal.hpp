@@ -75,8 +75,10 @@ struct bchar_mesh_s {
   double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};   // domain box
   int layout = 0;
   int64_t n_cells = 0, n_balls = 0;
-  int nbpc = 1;                // balls per cell
+  int nbpc = 1;                // balls per cell; 0: varies (ball_ptr)
   double rmax = 0;             // largest ball radius
+  bool r_uniform = false;      // every ball has radius r0
+  double r0 = 0;
   bool phi_const = true;
   double phi0 = 1;
   double bmax = 0;             // max |K|_phi
@@ -92,6 +94,7 @@ struct bchar_mesh_s {
   // uniform grid listing the cells whose bounding box meets each grid cell
   int64_t n_vertices = 0;
   bchar::DBuf vtx;             // dim * n_vertices
+  bchar::DBuf cell_cen;        // dim * n_cells, centroids (SoA)
   bchar::DBuf cells;           // int32 (dim + 1) * n_cells, cell-major
   double pl_inv = 0;           // 1 / grid side
   int64_t pl_nb[3] = {1, 1, 1};
@@ -106,6 +109,15 @@ struct bchar_mesh_s {
   bchar::DBuf bk_cen32;        // fp32 dim * n_balls, bucket order
   bchar::DBuf bk_ball;         // int32 n_balls: ball id of each bucket slot
   bchar::DBuf bk_rad;          // fp64 n_balls, radius, bucket order
+  bchar::DBuf bk_cell;         // int32 n_balls: cell of each bucket slot
+  bchar::DBuf bk_w;            // fp64 n_balls: rho_M phi_M of each bucket slot
+  // layouts with a varying number of balls per cell: first ball of every
+  // cell, cell of every ball, and tiles of whole cells with at most 256
+  // balls each (first cell of every tile)
+  bchar::DBuf ball_ptr;        // int32 n_cells + 1
+  bchar::DBuf ball_cell;       // int32 n_balls
+  bchar::DBuf tile_cell;       // int32 n_tiles + 1
+  int64_t n_tiles = 0;
   // scratch of the mesh creation and of bchar_mass
   bchar::Arena ws;
   bchar::DBuf scratch_small;   // small device scalars
@@ -122,11 +134,16 @@ struct bchar_transfer_s {
   bchar::DBuf A;         // fp64 nnz, final
   bchar::DBuf x;         // fp64 nnz
   bchar::DBuf mu, nu;    // fp64 n_cells
-  bchar::DBuf zdual;     // fp64 2 n_cells: per-cell multipliers of the last solve
+  bchar::DBuf zdual;     // fp64 4 n_cells: per-cell multipliers (s, g) of the last
+                         // solve, leading parts then compensations
   int warm_level = -1;   // box level of the last converged solve
   bchar::DBuf tracked;   // fp64 dim * n_balls
   bchar::DBuf r_hat;     // fp64 n_balls
-  bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs)
+  bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs), any order
+  bchar::DBuf stage_col;       // assembly staging: rows in tile order
+  bchar::DBuf stage_val;
+  int64_t stage_need = 0, pair_need = 0;   // staging room the last builds needed
+  int64_t n_void_rows = 0;     // of the last assembly
   bchar_stats stats{};
   // scratch of this transfer's builds (its own, so that builds of several
   // transfers of one mesh may run at once on different streams)
@@ -191,8 +208,8 @@ void build_csc(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nn
                Arena& ws, hipStream_t s);
 bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
                             const Csc& csc, const double* V, int64_t nnz, int n_sweeps,
-                            double* AN, int64_t* void_col, double* max_col_err, Arena& ws,
-                            hipStream_t s);
+                            double* AN, int64_t* void_col, int64_t* n_void_cols,
+                            double* max_col_err, Arena& ws, hipStream_t s);
 
 // QP (qp.hip)
 struct QpResult {
@@ -203,7 +220,8 @@ struct QpResult {
   double residual = 0;
   int64_t at_lower = 0, at_upper = 0;
 };
-// zdual: per-cell multipliers (s, g), 2 n values kept by the transfer;
+// zdual: per-cell multipliers (s, g), 2 n leading parts and 2 n
+// compensations kept by the transfer;
 // warm_level: box level of the previous converged solve, or -1.
 bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
                       const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,

@@ -80,6 +80,20 @@ __global__ void k_gather_bucketed(int dim, int64_t n_balls, const int32_t* __res
   bkr[p] = rad[b];
 }
 
+// Cell and weight rho_M phi_M of every bucket slot (the residing ball's
+// cell: ball / nbpc, or the per-ball cell of a varying layout).
+__global__ void k_slot_cells(int64_t n_balls, int nbpc, const int32_t* __restrict__ ball_cell,
+                             const int32_t* __restrict__ bk_ball, const double* __restrict__ rho,
+                             const double* __restrict__ phi, int32_t* __restrict__ bk_cell,
+                             double* __restrict__ bk_w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_balls) return;
+  const int32_t b = bk_ball[e];
+  const int32_t M = nbpc > 0 ? b / nbpc : ball_cell[b];
+  bk_cell[e] = M;
+  bk_w[e] = rho[M] * phi[M];
+}
+
 __global__ void k_porous_volume(const double* __restrict__ phi, double vol, int64_t n,
                                 double* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,6 +125,8 @@ void mesh_build_cartesian(bchar_mesh_s* m, const UniformBalls& u, hipStream_t s)
   fill_f64(m->bvol.as<double>(), u.ball_vol, nb, s);
   fill_f64(m->rho.as<double>(), u.rho, m->n_cells, s);
   m->rmax = u.r;
+  m->r_uniform = true;
+  m->r0 = u.r;
   mesh_build_hash(m, s);
 }
 
@@ -153,6 +169,15 @@ void mesh_build_hash(bchar_mesh_s* m, hipStream_t s) {
         m->dim, nb, m->bk_ball.as<int32_t>(), m->cen.as<double>(), m->cen32.as<float>(),
         m->rad.as<double>(), m->bk_cen.as<double>(), m->bk_cen32.as<float>(),
         m->bk_rad.as<double>());
+  }
+  BCHAR_HIP(hipGetLastError());
+  m->bk_cell.reserve(sizeof(int32_t) * nb);
+  m->bk_w.reserve(sizeof(double) * nb);
+  {
+    ::bchar::ProfScope ps_("k_slot_cells", s);
+    k_slot_cells<<<blocks_for(nb, 256), 256, 0, s>>>(
+        nb, m->nbpc, m->ball_cell.as<int32_t>(), m->bk_ball.as<int32_t>(), m->rho.as<double>(),
+        m->phi.as<double>(), m->bk_cell.as<int32_t>(), m->bk_w.as<double>());
   }
   BCHAR_HIP(hipGetLastError());
   BCHAR_HIP(hipStreamSynchronize(s));

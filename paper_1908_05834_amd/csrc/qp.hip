@@ -57,6 +57,7 @@ constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 constexpr int kCrossoverSteps = 2; // fixed-side Newton steps from an interior point
+constexpr int kCrossoverRounds = 4; // active-set updates of the sides after the first
 constexpr double kCrossoverRatio = 1e-3;  // slack / multiplier of a pinned entry
 constexpr int64_t kZsmoothTwoMaxCells = 1 << 20;  // k_zsmooth_two up to this size
 constexpr int kPolishCG = 60;      // CG cap of the warm steps, and of those after an
@@ -2024,13 +2025,29 @@ __global__ void k_t_from_z(const int32_t* __restrict__ rptr, const int32_t* __re
   }
 }
 
-// z += step * (solution with the mean of its s part removed)
+// z += step * (solution with the mean of its s part removed), summed with
+// compensation: z holds the leading parts of the 2n multipliers and, from
+// z + 2n on, what their rounding lost (cells that barely move carry
+// multipliers of 1e9 and more, whose increments would otherwise drift from
+// the increments of t by units in their last place)
 __global__ void k_zdual_acc(const double* __restrict__ sol, const double* __restrict__ ssum,
                             double inv_n, double step, int64_t n, double* __restrict__ z) {
+#pragma clang fp contract(off)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  z[i] += step * (sol[i] - ssum[0] * inv_n);
-  z[n + i] += step * sol[n + i];
+  // the increment step * (sol - mean) as p + pe + step * ve, exactly but
+  // for the last product, and its sum with z by TwoSum
+  double v, ve, hi, err;
+  two_sum(sol[i], -(ssum[0] * inv_n), v, ve);
+  double p = step * v, pe = fma(step, v, -p);
+  two_sum(z[i], p, hi, err);
+  z[i] = hi;
+  z[2 * n + i] += (err + pe) + step * ve;
+  p = step * sol[n + i];
+  pe = fma(step, sol[n + i], -p);
+  two_sum(z[n + i], p, hi, err);
+  z[n + i] = hi;
+  z[3 * n + i] += err + pe;
 }
 
 // mu = s + g/2, nu = -(s - g/2)
@@ -2098,6 +2115,17 @@ __global__ void k_xover_state(IpmArrays I, double ratio, int64_t nnz,
   else if (I.has_hi && I.su[k] < ratio * I.zu[k])
     v = 1;
   side[k] = v;
+}
+
+// Sides read off the multipliers (a primal-dual active-set update): an
+// entry whose t lies below the lower bound is pinned there, above the upper
+// bound pinned there, and free otherwise.
+__global__ void k_side_from_t(const double* __restrict__ t, double lo, double hi, int64_t nnz,
+                              int8_t* __restrict__ side) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double v = t[k];
+  side[k] = v < lo ? (int8_t)-1 : (v > hi ? (int8_t)1 : (int8_t)0);
 }
 
 // Residual with the sides fixed: x_k is the bound of a pinned entry and
@@ -2350,7 +2378,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 
   Reducer red{ws.get<double>(2 * kRedBlocks + 2), ws.get<double>(16), s};
   double* zpart = ws.get<double>(2 * (size_t)blocks_for(n, kT) + 2);   // block sums
-  double* zsave = ws.get<double>(2 * (size_t)n + 1);   // interior-point multipliers
+  double* zsave = ws.get<double>(4 * (size_t)n + 1);   // interior-point multipliers
   double* tsave = ws.get<double>((size_t)nnz + 1);
 
   QpArrays Q{};
@@ -2823,7 +2851,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_ipm_init<<<gz, kT, 0, s>>>(I, nnz);
       }
       fill_f64(Q.t, 0.0, nnz, s);
-      fill_f64(zdual, 0.0, n2, s);
+      fill_f64(zdual, 0.0, 2 * n2, s);
     }
     BCHAR_HIP(hipGetLastError());
     double mu0 = -1.0, fp_best = HUGE_VAL;
@@ -2970,8 +2998,11 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // into those on a bound and the free ones, and solve the constraints for
   // the multipliers with that split (linear in them: a Newton step is
   // exact up to CG); accepted only if clip(t) then meets the tolerance, so
-  // that x = clip(t) is the exact minimiser.  The state is left as found
-  // when it fails.
+  // that x = clip(t) is the exact minimiser.  If it does not, the split is
+  // read again off the new multipliers (t below / above the box: pinned,
+  // else free) and the solve repeated: a primal-dual active-set iteration
+  // from a start that is nearly right.  The caller restores the state when
+  // every round fails.
   int8_t* side = ws.get<int8_t>((size_t)nnz + 1);
   auto crossover = [&](double lo, double hi) -> bool {
     {
@@ -2979,7 +3010,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       k_xover_state<<<gz, kT, 0, s>>>(I, kCrossoverRatio, nnz, side);
     }
     BCHAR_HIP(hipGetLastError());
-    for (int it = 0; it < kCrossoverSteps; ++it) {
+    for (int it = 0; it < kCrossoverSteps * (1 + kCrossoverRounds); ++it) {
+      if (it >= kCrossoverSteps && it % kCrossoverSteps == 0) {
+        {
+          ::bchar::ProfScope ps_("k_side_from_t", s);
+          k_side_from_t<<<gz, kT, 0, s>>>(Q.t, lo, hi, nnz, side);
+        }
+        BCHAR_HIP(hipGetLastError());
+      }
       {
         ::bchar::ProfScope ps_("k_residual_sides", s);
         k_residual_sides<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, side, lo, hi,
@@ -3038,6 +3076,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_t_from_z<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, zdual, n, Q.t);
       }
       BCHAR_HIP(hipGetLastError());
+      // t is formed from the leading parts: the compensation starts anew
+      fill_f64(zdual + n2, 0.0, n2, s);
       converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2,
                       std::min(kPolishCG, o.qp_max_cg), " (warm)");
       if (converged) break;
@@ -3045,7 +3085,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     const bool warm = o.warm_start && warm_level == level;
     if (level == 2) {
       fill_f64(Q.t, 0.0, nnz, s);
-      fill_f64(zdual, 0.0, n2, s);
+      fill_f64(zdual, 0.0, 2 * n2, s);
       converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, "");
     } else {
       // a warm or loose interior point that fails is retried from zero,
@@ -3060,11 +3100,11 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         // the multipliers that go with its x (and the next solve's warm
         // start) rather than those of an abandoned step.
         if (r == 2) {
-          BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+          BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
           BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
           converged = crossover(lo, hi);
           if (!converged) {
-            BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * n2, hipMemcpyDeviceToDevice,
+            BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice,
                                      s));
             BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
                                      s));
@@ -3077,7 +3117,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         if (!converged && r == 2) {
           converged = ipm_answer = true;
           fn = fp_ipm;
-          BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
+          BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
           BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
         } else if (!converged) {
           // the interior point stalled short of the tolerance: semismooth

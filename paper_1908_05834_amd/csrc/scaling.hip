@@ -63,7 +63,8 @@ __global__ void k_col_scale(const int32_t* __restrict__ cptr, const int32_t* __r
   for (int32_t e = cptr[j]; e < cptr[j + 1]; ++e) acc.add(R[crow[e]] * vc[e]);
   const double cs = acc.value();
   if (!(cs > 0.0)) {
-    atomicMin(void_col, (int32_t)j);
+    atomicMin(void_col, (int32_t)j);   // void_col[0]: first void column
+    atomicAdd(void_col + 1, 1);        // void_col[1]: their number
     C[j] = 0.0;
     return;
   }
@@ -109,15 +110,15 @@ __global__ void k_col_err(const int32_t* __restrict__ cptr, const int32_t* __res
 
 bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
                             const Csc& csc, const double* V, int64_t nnz, int n_sweeps,
-                            double* AN, int64_t* void_col, double* max_col_err, Arena& ws,
-                            hipStream_t s) {
+                            double* AN, int64_t* void_col, int64_t* n_void_cols,
+                            double* max_col_err, Arena& ws, hipStream_t s) {
   const int64_t n = m->n_cells;
   const double* b = m->b.as<double>();
   Arena::Mark mk = ws.mark();
   double* vc = ws.get<double>(nnz + 1);
   double* R = ws.get<double>(n);
   double* C = ws.get<double>(n);
-  int32_t* flag = ws.get<int32_t>(1);
+  int32_t* flag = ws.get<int32_t>(2);
   {
     ::bchar::ProfScope ps_("k_gather_f64", s);
     k_gather_f64<<<blocks_for(nnz, 256), 256, 0, s>>>(V, csc.pos, nnz, vc);
@@ -125,17 +126,19 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
   BCHAR_HIP(hipGetLastError());
   fill_f64(R, 1.0, n, s);
   fill_i32(flag, INT32_MAX, 1, s);
+  fill_i32(flag + 1, 0, 1, s);
   // a column of V summing to zero cannot be scaled (Sec. 3.2)
   {
     ::bchar::ProfScope ps_("k_col_scale", s);
     k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(csc.ptr, csc.row, vc, R, b, n, C, flag);
   }
   BCHAR_HIP(hipGetLastError());
-  int32_t hflag = INT32_MAX;
-  BCHAR_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t hflag[2] = {INT32_MAX, 0};
+  BCHAR_HIP(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
   BCHAR_HIP(hipStreamSynchronize(s));
-  if (hflag != INT32_MAX) {
-    *void_col = hflag;
+  *n_void_cols = hflag[1];
+  if (hflag[0] != INT32_MAX) {
+    *void_col = hflag[0];
     ws.rewind(mk);
     return BCHAR_E_VOID_COLUMN;
   }

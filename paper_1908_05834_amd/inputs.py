@@ -363,3 +363,70 @@ def jittered_tets(n=96, jitter=0.1, seed=1908, phi_seed=5834, cfl=4.0, steps=20)
     c0 = uniform_c(mesh, 33)
     return {"name": f"jittered_tets_{n}", "mesh": mesh, "vel_fn": vel_fn, "c0": c0, "dt": dt,
             "steps": steps, "time_dependent": True}
+
+
+# --------------------------------------------------------------------------
+# caller-chosen balls (layout "custom")
+# --------------------------------------------------------------------------
+
+def random_subcell_balls(mesh, seed):
+    """Balls of a Cartesian mesh chosen at random, as a caller might: every
+    cell gets, with even odds, one ball near its centre or 2^d balls near
+    its sub-cell centres (each centre moved by up to 1/32 of the cell per
+    axis, radius U(0.9, 1) times the distance to the boundary of the cell or
+    sub-cell), so a cell's balls are disjoint and strictly inside it.
+    Returns the mesh dict extended with ``ball_centres``, ``ball_radii``,
+    ``ball_cell``."""
+    rng = np.random.default_rng(seed)
+    n, o, h = mesh["n"], np.asarray(mesh["origin"]), np.asarray(mesh["h"])
+    dim = len(n)
+    nc = int(np.prod(n))
+    ids = np.arange(nc)
+    ijk = np.empty((nc, dim))
+    rem = ids.copy()
+    for a in range(dim):
+        ijk[:, a] = rem % n[a]
+        rem //= n[a]
+    cen, rad, cell = [], [], []
+    for K in range(nc):
+        if rng.uniform() < 0.5:
+            fracs, half = [np.full(dim, 0.5)], 0.5
+        else:
+            fracs = [np.array([0.25 + 0.5 * ((s >> a) & 1) for a in range(dim)])
+                     for s in range(2 ** dim)]
+            half = 0.25
+        for frac in fracs:
+            jit = rng.uniform(-1.0 / 32, 1.0 / 32, dim)
+            cen.append(o + (ijk[K] + frac + jit) * h)
+            rad.append(np.min(h * (half - np.abs(jit))) * rng.uniform(0.9, 1.0))
+            cell.append(K)
+    out = dict(mesh)
+    out["ball_centres"] = np.array(cen)
+    out["ball_radii"] = np.array(rad)
+    out["ball_cell"] = np.array(cell, dtype=np.int32)
+    return out
+
+
+def corner_balls_simplex(mesh, shrink=0.9):
+    """d + 1 balls per simplex, as a caller might place them: one per
+    vertex, centred half way from the centroid G to the vertex, each with
+    the measure of |K| / (d + 1) times ``shrink``^d (the balls of a cell may
+    overlap each other and the neighbours')."""
+    V, Cc = mesh["vertices"], mesh["cells"]
+    dim = V.shape[1]
+    P = V[Cc]                                   # (nc, d+1, dim)
+    G = P.mean(axis=1)
+    if dim == 2:
+        vol = 0.5 * np.abs((P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1])
+                           - (P[:, 1, 1] - P[:, 0, 1]) * (P[:, 2, 0] - P[:, 0, 0]))
+        r = shrink * np.sqrt(vol / (3 * math.pi))
+    else:
+        e = P[:, 1:, :] - P[:, :1, :]
+        vol = np.abs(np.linalg.det(e)) / 6.0
+        r = shrink * np.cbrt(3.0 * vol / (4 * 4.0 * math.pi))
+    cen = 0.5 * (G[:, None, :] + P)
+    out = dict(mesh)
+    out["ball_centres"] = cen.reshape(-1, dim)
+    out["ball_radii"] = np.repeat(r, dim + 1)
+    out["ball_cell"] = np.repeat(np.arange(Cc.shape[0], dtype=np.int32), dim + 1)
+    return out

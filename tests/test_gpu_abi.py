@@ -1,0 +1,161 @@
+"""GPU tests of the boundary's options: caller-given balls (layout CUSTOM,
+Sec. 3: any points C_{K,s} with radii, any number per cell), geometry in
+device memory, and the void counts of the statistics.  Parity against the
+oracle to the same bars as tests/test_gpu_parity.py."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry as ogeo
+from oracle import transfer as otr
+from paper_1908_05834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05834_amd import bchar
+    return torch, bchar
+
+
+def _custom_case(name):
+    if name == "hex":
+        w = inputs.swirl_hex(8)
+        return inputs.random_subcell_balls(w["mesh"], 5), w["vel_fn"](0), 0.02
+    if name == "square":
+        m = inputs.random_subcell_balls(inputs.cartesian_mesh((12, 12)), 6)
+        return m, inputs.sample_velocity(m, inputs.rotation_stretch_2d), 0.3
+    if name == "tets":
+        mesh = inputs.kuhn_tets(4, 0.1, 8)
+        vel = inputs.sample_velocity_grid((4, 4, 4), lambda p, t: inputs.swirl_3d(p, t))
+        return inputs.corner_balls_simplex(mesh), vel, 0.05
+    if name == "tris":
+        mesh = inputs.triangulated_square(10, 0.1, 6)
+        vel = inputs.sample_velocity_grid((10, 10), inputs.rotation_stretch_2d)
+        return inputs.corner_balls_simplex(mesh), vel, 0.3
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["hex", "square", "tets", "tris"])
+def test_custom_layout(env, name):
+    torch, bchar = env
+    _say(f"[gpu] custom layout {name}")
+    mesh, vel, dt = _custom_case(name)
+    M = bchar.Mesh(mesh, "custom")
+    assert M.n_balls == len(mesh["ball_radii"]) and M.balls_per_cell == 0
+    c, r, cell = M.export_balls()
+    assert np.array_equal(c, mesh["ball_centres"]) and np.array_equal(r, mesh["ball_radii"])
+    assert np.array_equal(cell, mesh["ball_cell"])
+    ref = otr.build_transfer(mesh, vel, dt, layout="custom")
+    # candidate pairs and V on the oracle's tracked centres
+    tr = torch.as_tensor(np.ascontiguousarray(ref["traced"].T), device="cuda")
+    rh = torch.as_tensor(np.ascontiguousarray(ref["r_hat"]), device="cuda")
+    Tv = bchar.Transfer.build_tracked(M, tr, rh, bchar.opts_default(stop_after=bchar.STAGE_V,
+                                                                   keep_pairs=1))
+    a, b = Tv.export_pairs()
+    assert np.array_equal(a, ref["pairs"][0]) and np.array_equal(b, ref["pairs"][1])
+    rp, col, V = Tv.export_csr(bchar.STAGE_V)
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(col, ref["col"])
+    assert np.max(np.abs(V - ref["V"])) <= 1e-13 * np.max(np.abs(ref["V"]))
+    # the whole step, tracking included
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt)
+    _say(f"    stats {T.stats}; oracle level {ref['qp']['level']}")
+    assert T.stats["qp_level"] == ref["qp"]["level"]
+    c0 = inputs.uniform_c(mesh, 13)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], c0)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    want_m = otr.mass(mesh["phi"], ref["cell_vol"], got)
+    assert abs(m1 - want_m) <= 2 * np.spacing(abs(want_m))
+
+
+@pytest.mark.parametrize("name", ["tets_equal", "tets_custom", "hex_custom"])
+def test_device_geometry(env, name):
+    """Vertices, cells and custom balls handed over in device memory give
+    the same mesh and the same transfer, bit for bit."""
+    torch, bchar = env
+    _say(f"[gpu] device geometry {name}")
+    if name == "tets_equal":
+        mesh, vel, dt = _custom_case("tets")
+        layout = "equal_measure"
+    elif name == "tets_custom":
+        mesh, vel, dt = _custom_case("tets")
+        layout = "custom"
+    else:
+        mesh, vel, dt = _custom_case("hex")
+        layout = "custom"
+    Mh = bchar.Mesh(mesh, layout)
+    Md = bchar.Mesh(mesh, layout, geom_device=True)
+    for x, y in zip(Mh.export_balls(), Md.export_balls()):
+        assert np.array_equal(x, y)
+    U = bchar.VelocityLattice(vel)
+    Th = bchar.Transfer.build(Mh, U, dt)
+    Td = bchar.Transfer.build(Md, U, dt)
+    for x, y in zip(Th.export_csr(), Td.export_csr()):
+        assert np.array_equal(x, y)
+
+
+def test_void_row_count(env):
+    """Tracked balls moved to cell corners with a tiny radius overlap no
+    inscribed disk: the build reports a void row, the first void ball and
+    the number of tracked cells with a void ball."""
+    torch, bchar = env
+    _say("[gpu] void rows")
+    mesh = inputs.cartesian_mesh((8, 8))
+    C, r, _ = ogeo.ball_layout(mesh["n"], mesh["origin"], mesh["h"], "inscribed")
+    tr = C.copy()
+    rh = r.copy()
+    h = mesh["h"][0]
+    for k in (9, 20, 43):
+        tr[k] = C[k] + 0.5 * h
+        rh[k] = 0.01 * h
+    # the oracle's view of the same geometry
+    ia, _ = ogeo.candidate_pairs(tr, rh, C, r)
+    void = np.setdiff1d(np.arange(C.shape[0]), ia)
+    assert void.tolist() == [9, 20, 43]
+    M = bchar.Mesh(mesh, "inscribed")
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build_tracked(M, torch.as_tensor(np.ascontiguousarray(tr.T), device="cuda"),
+                                     torch.as_tensor(rh, device="cuda"))
+    assert ei.value.status == bchar.E_VOID_ROW
+    assert ei.value.stats["first_void"] == 9 and ei.value.stats["n_void_rows"] == 3
+
+
+def test_void_column_count(env):
+    """A step too long for a small triangulated square leaves residing
+    cells that no tracked ball reaches: the first and the number of zero
+    columns of V agree with the oracle's V."""
+    torch, bchar = env
+    _say("[gpu] void columns")
+    q = inputs.mixed_problem(2, 400.0, 400.0)
+    mesh, vel, dt, layout = q["mesh"], q["vel"], q["dt"], q["layout"]
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, stop_after="v")
+    nc = ref["row_ptr"].size - 1
+    colsum = np.bincount(ref["col"], weights=ref["V"], minlength=nc)
+    zero = np.nonzero(colsum <= 0)[0]
+    assert zero.size > 0
+    M = bchar.Mesh(mesh, layout)
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt)
+    assert ei.value.status == bchar.E_VOID_COLUMN
+    st = ei.value.stats
+    _say(f"    stats {st}; oracle zero columns {zero.tolist()}")
+    assert st["first_void"] == zero[0] and st["n_void_cols"] == zero.size
+    assert st["n_void_rows"] == 0

@@ -75,6 +75,15 @@ def test_swirl64_full_size(env):
     chk = oqp.verify_kkt(rows, col, AN, bK, bK, x, mu, nu, lo, hi, bK.max(), 2e-13)
     _say(f"    kkt {chk}")
     assert chk["ok"]
+    # the same certificate entry by entry in the solver's per-cell
+    # coordinates: every x_k within 1e-12 of clip(t_k), so every volume
+    # a_k (1 + x_k) within 1e-12 a_k of the minimiser's and the update within
+    # 1e-12 relative -- inside the 1e-10 parity bar
+    sv, gv, sl, gl = T.export_qp_dual()
+    chk2 = oqp.verify_kkt_sg(rows, col, AN, bK, bK, x, sv, gv, lo, hi, bK.max(), 2e-13,
+                             s_lo=sl, g_lo=gl)
+    _say(f"    kkt (s, g) {chk2}")
+    assert chk2["ok"]
     _, _, A = T.export_csr(bchar.STAGE_ALL)
     nc = rp.size - 1
     rs = np.bincount(rows, weights=A, minlength=nc)

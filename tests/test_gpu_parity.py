@@ -134,11 +134,20 @@ def test_tracking(env, name):
     want_r = ogeo.tracked_radius(C, r, want, mesh, vel, dt)
     porous = not np.all(mesh["phi"] == mesh["phi"][0])
     # binary64 tracking repeats the oracle's operations one by one: equal
-    # bits.  Binary32 tracking is within its rounding, except on meshes
-    # with variable porosity, which the library tracks in binary64.
-    for prec, tol in ((bchar.FP64, 0.0), (bchar.FP32_VOLUME, 0.0 if porous else 2e-6)):
+    # bits (FP64, and FP32_LENS, which tracks in binary64).  Binary32
+    # tracking (FP32_VOLUME) is within its rounding; it refuses a mesh whose
+    # porosity varies.
+    cases = [(bchar.FP64, 0.0, bchar.FP64), (bchar.FP32_LENS, 0.0, bchar.FP64)]
+    if porous:
+        with pytest.raises(bchar.BcharError) as ei:
+            bchar.Transfer.build(M, U, dt, bchar.opts_default(precision=bchar.FP32_VOLUME))
+        assert ei.value.status == bchar.E_UNSUPPORTED
+    else:
+        cases.append((bchar.FP32_VOLUME, 2e-6, bchar.FP32_VOLUME))
+    for prec, tol, used in cases:
         T = bchar.Transfer.build(M, U, dt, bchar.opts_default(stop_after=bchar.STAGE_V,
                                                               precision=prec))
+        assert T.stats["trace_precision"] == used
         got, got_r = T.export_tracked()
         e1, e2 = np.max(np.abs(got - want)), np.max(np.abs(got_r - want_r))
         _say(f"    precision {prec}: centre err {e1:.3e}, radius err {e2:.3e}")
@@ -167,7 +176,11 @@ def _full(env, name, precision="fp64", **opts):
     M = bchar.Mesh(mesh, layout)
     ref = _obuild(mesh, vel, dt, M, layout=layout, precision=precision)
     U = bchar.VelocityLattice(vel)
-    prec = bchar.FP64 if precision == "fp64" else bchar.FP32_VOLUME
+    if precision == "fp64":
+        prec = bchar.FP64
+    else:
+        # binary32 tracking needs a constant porosity
+        prec = bchar.FP32_VOLUME if np.all(mesh["phi"] == mesh["phi"][0]) else bchar.FP32_LENS
     T = bchar.Transfer.build(M, U, dt, bchar.opts_default(precision=prec, **opts))
     return torch, bchar, mesh, ref, M, T
 
@@ -209,6 +222,11 @@ def _check_full_step(env, name, **opts):
     # conservation and constants, on the GPU result alone
     m0, m1 = M.mass(cin), M.mass(cout)
     assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    # the compensated mass reduction against the correctly rounded sum
+    vol = ref["cell_vol"]
+    for cv, mv in ((c0, m0), (got, m1)):
+        want_m = otr.mass(mesh["phi"], vol, cv)
+        assert abs(mv - want_m) <= 2 * np.spacing(abs(want_m)), (mv, want_m)
     ones = torch.ones(nc, dtype=torch.float64, device="cuda")
     T.step(ones, cout)
     assert torch.max(torch.abs(cout - 1.0)).item() <= 1e-12
@@ -286,15 +304,16 @@ def test_simplex_mesh_checks(env):
     M = bchar.Mesh(m, "equal_measure")
     c, r, cell = M.export_balls()
     oc, orad, _ = ogeo.simplex_ball_layout(m)
-    # centroids are the same sums in the same order; the cube root is the C
-    # library's on both sides, within one unit in the last place
+    # centroids are the same sums in the same order; both sides round the
+    # cube root to nearest (the bar: one unit in the last place)
     assert np.array_equal(c, oc)
     assert np.all(np.abs(r - orad) <= np.spacing(orad))
 
 
 def test_unstructured_properties(env):
     """The unstructured workload (jittered Kuhn tetrahedra, lognormal
-    porosity, CFL 4 on u / phi, FP32 volumes) at 24^3 x 6 cells, two steps:
+    porosity, CFL 4 on u / phi, binary32 lens volumes) at 24^3 x 6 cells,
+    two steps:
     properties that hold at any size -- porous mass to 1e-12, constants to
     1e-12, both marginals of A equal |K|_phi."""
     torch, bchar = env
@@ -302,7 +321,7 @@ def test_unstructured_properties(env):
     w = inputs.jittered_tets(24, steps=2)
     mesh = w["mesh"]
     M = bchar.Mesh(mesh, "equal_measure")
-    o = bchar.opts_default(precision=bchar.FP32_VOLUME)
+    o = bchar.opts_default(precision=bchar.FP32_LENS)
     c = torch.as_tensor(w["c0"], device="cuda")
     nxt = torch.empty_like(c)
     m0 = M.mass(c)

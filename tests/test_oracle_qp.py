@@ -130,3 +130,23 @@ def test_planted_mistake_is_caught():
     chk = oqp.verify_kkt(r, c, a, b, b, bad, out["mu"], out["nu"], -1.0, 1.0, out["scale"],
                          1e-13)
     assert not chk["ok"]
+
+
+def test_kkt_in_cell_coordinates():
+    """The (s, g) form of the certificate accepts the oracle's own solution
+    (s = (mu - nu) / 2, g = mu + nu) and rejects a solution moved by 1e-9 on
+    one free entry, and multipliers with a sign error in g."""
+    r, c, a, b = _random_transfer(30, 5, small=1e-3)
+    out = oqp.solve_mass_qp(r, c, a, b, b)
+    mu, nu = out["mu"], out["nu"]
+    s, g = 0.5 * (mu - nu), mu + nu
+    lo, hi = out["lo"], out["hi"]
+    ok = oqp.verify_kkt_sg(r, c, a, b, b, out["x"], s, g, lo, hi, out["scale"], 1e-13)
+    assert ok["ok"], ok
+    free = np.nonzero((out["x"] > lo + 1e-3) & (out["x"] < hi - 1e-3))[0]
+    x2 = out["x"].copy()
+    x2[free[0]] += 1e-9
+    bad = oqp.verify_kkt_sg(r, c, a, b, b, x2, s, g, lo, hi, out["scale"], 1e-7)
+    assert not bad["ok"] and bad["stationarity"] >= 0.9e-9
+    bad = oqp.verify_kkt_sg(r, c, a, b, b, out["x"], s, -g, lo, hi, out["scale"], 1e-13)
+    assert not bad["ok"]

@@ -137,3 +137,19 @@ def test_transfer_on_triangles():
     A = T["A"]
     assert np.allclose(np.bincount(T["col"], weights=A, minlength=nc), T["b"], rtol=0,
                        atol=2e-13 * T["b"].max())
+
+
+def test_cbrt_rounded_is_nearest():
+    """The oracle's cube root is the double nearest to the real root:
+    exact on perfect cubes, and a neighbour either side is farther (the
+    cubes compared in rational arithmetic)."""
+    from fractions import Fraction
+    for k in (1.0, 8.0, 27.0, 0.125, 3.375):
+        assert float(geo.cbrt_rounded(np.array([k]))[0]) ** 3 == pytest.approx(k, rel=0)
+    ys = np.random.default_rng(4).uniform(1e-7, 1.0, 200)
+    rs = geo.cbrt_rounded(ys)
+    for y, r in zip(ys, rs):
+        fy = Fraction(float(y))
+        err = abs(Fraction(float(r)) ** 3 - fy)
+        for nb in (np.nextafter(r, 0.0), np.nextafter(r, np.inf)):
+            assert abs(Fraction(float(nb)) ** 3 - fy) >= err
