@@ -193,6 +193,13 @@ typedef struct {
                             per cycle, a weaker cycle.  Default 0 (every
                             level); the same solution either way, only
                             the iteration count and time change          */
+  int lds_stage;         /* non-zero: the assembly stages the residing
+                            balls of each tile's search block in LDS when
+                            they fit; 0 (default): every search reads the
+                            hash through the caches (measured faster on
+                            the 64^3 swirl: the staging area costs a
+                            workgroup per CU).  The same transfer bit for
+                            bit either way                               */
 } bchar_opts;
 
 typedef struct {

@@ -58,7 +58,7 @@ class Opts(C.Structure):
                 ("box_policy", C.c_int), ("stop_after", C.c_int), ("qp_tol", C.c_double),
                 ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int),
                 ("warm_start", C.c_int), ("max_halvings", C.c_int),
-                ("cg_graphs", C.c_int), ("cycle_skip", C.c_int)]
+                ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -387,7 +387,7 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   t->stage = 0;
   int64_t first_void = -1;
   bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(), o.precision,
-                               o.keep_pairs != 0, t, &first_void, s);
+                               o.keep_pairs != 0, o.lds_stage != 0, t, &first_void, s);
   st.nnz = t->nnz;
   st.n_pairs = t->n_pairs;
   st.n_void_rows = t->n_void_rows;
@@ -633,6 +633,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->keep_pairs = 0;
   o->warm_start = 1;
   o->cg_graphs = 1;
+  o->lds_stage = 0;
 }
 
 const char* bchar_status_string(bchar_status s) {

@@ -424,14 +424,18 @@ __device__ __forceinline__ T lens(T r1, T r2, T d) {
 constexpr int kXcds = 8;         // accelerator complex dies of the MI355X
 constexpr int kTileThreads = 256; // tracked balls per tile (one thread each)
 constexpr int kTileCap = 2048;    // overlaps of one group of cells held in LDS
+constexpr int kStash = 8;         // overlapping slots a thread remembers between passes
+constexpr int kStageBalls = 1024;  // residing balls of a tile's search block staged in LDS
+constexpr int kStageBuckets = 1280; // bucket starts of the block (buckets + rows)
+constexpr int kStageRows = 256;    // bucket rows of the block
 
 // flags of one assembly launch (int32, cleared before it)
 enum {
   kFlagFirstVoid = 0,   // lowest tracked ball with S = 0 (INT32_MAX: none)
   kFlagVoidRows,        // tracked cells with a void ball
   kFlagCellOverflow,    // largest overlap count of a single cell beyond kTileCap
-  kFlagEntries,         // staged entries (unique (K, M) per row)
-  kFlagPairs,           // candidate pairs
+  kFlagEntries,         // staged entries beyond the tiles' own staging room
+  kFlagPairs,           // candidate pairs (kept pairs only)
   kFlagStageOverflow,   // staging or pair storage too small
   kNumFlags
 };
@@ -469,9 +473,11 @@ struct TileParams {
   // outputs
   int32_t* row_cnt;         // unique residing cells per row
   int32_t* stage_off;       // staging position of every row
-  int32_t* stage_col;
-  double* stage_val;
+  int32_t* stage_col;       // tile t stages at t * kTileCap, what does not fit
+  double* stage_val;        // there at n_tiles * kTileCap + (atomic count)
   int64_t stage_cap;
+  int32_t* tile_pairs;      // overlaps of every tile (pairs not kept)
+  int lds_stage;            // stage each tile's search block in LDS when it fits
   int32_t* pair_a;          // may be null
   int32_t* pair_b;
   int64_t pair_cap;
@@ -520,10 +526,15 @@ __device__ __forceinline__ bool overlap(const T p[3], const T c[3], T rs, T& d2)
 // relative 1e-6 so that binary32 rounding of the predicate cannot reach
 // past it; the predicate alone decides), walked as rows of consecutive
 // buckets along x, each row one run of slots.  f(slot, rb, d2).
-template <int DIM, class T, bool UR, class F>
-__device__ __forceinline__ void for_each_overlap(const TileParams& P, const T p[3], T ra, F&& f) {
+template <int DIM, class T>
+__device__ __forceinline__ void search_block(const TileParams& P, const T p[3], T ra,
+                                             int64_t blo[3], int64_t side[3]) {
   const double D = ((double)ra + P.rmax) * (1.0 + 1e-6);
-  int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    blo[a] = 0;
+    side[a] = 1;
+  }
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double x = (double)p[a] - P.org[a];
@@ -534,6 +545,12 @@ __device__ __forceinline__ void for_each_overlap(const TileParams& P, const T p[
     blo[a] = lo;
     side[a] = hi >= lo ? hi - lo + 1 : 0;
   }
+}
+
+template <int DIM, class T, bool UR, class F>
+__device__ __forceinline__ void for_each_overlap(const TileParams& P, const T p[3], T ra, F&& f) {
+  int64_t blo[3], side[3];
+  search_block<DIM, T>(P, p, ra, blo, side);
   const int64_t nb = P.n_balls;
   for (int64_t bz = 0; bz < side[2]; ++bz)
     for (int64_t by = 0; by < side[1]; ++by) {
@@ -570,16 +587,41 @@ __device__ __forceinline__ int64_t tile_cell_id(const TileParams& P, int64_t t, 
   return i + P.n[0] * (j + P.n[1] * k);
 }
 
-template <int DIM, class T, bool UR>
+// LDS of the assembly: the residing balls of the tile's search block
+// (staged for pass 1) share their room with the merge arrays (pass 2 on)
+// (STG false: no staging, the smaller footprint lets more workgroups share
+// a CU)
+template <int DIM, class T, bool UR, bool STG>
+struct StageLayout {
+  static constexpr int kBytesBall = DIM * (int)sizeof(T) + (UR ? 0 : (int)sizeof(T)) + 4;
+  static constexpr int kStageBytes = STG ? kStageBalls * kBytesBall + 4 * kStageBuckets : 0;
+  static constexpr int kMergeBytes = kTileCap * (4 + 8 + 1);
+  static constexpr int kBytes = kStageBytes > kMergeBytes ? kStageBytes : kMergeBytes;
+};
+
+template <int DIM, class T, bool UR, bool STG>
 __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
-  __shared__ int32_t s_key[kTileCap];
-  __shared__ double s_val[kTileCap];
-  __shared__ uint8_t s_first[kTileCap];
+  using L = StageLayout<DIM, T, UR, STG>;
+  __shared__ __align__(16) unsigned char s_union[L::kBytes];
+  // merge view
+  double* const s_val = reinterpret_cast<double*>(s_union);
+  int32_t* const s_key = reinterpret_cast<int32_t*>(s_union + 8 * kTileCap);
+  uint8_t* const s_first = s_union + 12 * kTileCap;
+  // staging view: coordinates (SoA), radii, global slot, local bucket starts
+  T* const g_cen = reinterpret_cast<T*>(s_union);
+  T* const g_rad = g_cen + DIM * kStageBalls;
+  int32_t* const g_slot =
+      reinterpret_cast<int32_t*>(s_union + (DIM + (UR ? 0 : 1)) * sizeof(T) * kStageBalls);
+  int32_t* const g_bst = g_slot + kStageBalls;
+  __shared__ int32_t s_box[8];                     // block lo (3), hi (3)
+  __shared__ int32_t s_rowoff[kStageRows + 1];     // local slot offset of every block row
+  __shared__ int32_t s_rowg0[kStageRows];          // its first global slot
   __shared__ int32_t s_cstart[kTileThreads + 1];   // first overlap of every local cell
   __shared__ int32_t s_ucnt[kTileThreads];         // unique residing cells of every local cell
   __shared__ int32_t s_upre[kTileThreads];         // their exclusive scan within the group
   __shared__ int32_t s_wave[kTileThreads / kWave];
-  __shared__ int32_t s_misc[4];
+  __shared__ int32_t s_misc[5];
+  __shared__ int32_t s_stash[kStash * kTileThreads];   // slot i of thread j at i * 256 + j
 
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, each
   // with its own L2; XCD j takes the j-th contiguous chunk of tiles so that
@@ -635,14 +677,107 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
     mass = P.rho[K] * P.phi[K] * P.bvol[b];   // rho_K phi_K |B_{K,s}|
   }
 
+  // ---- the search block of the whole tile: the union of its balls'
+  // bucket blocks (each ball's block as for_each_overlap computes it)
+  int64_t blo[3] = {0, 0, 0}, side[3] = {1, 1, 1};
+  int32_t bl[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+  bool staged = false;
+  if constexpr (STG) {
+  if (tid < 8) s_box[tid] = tid < 3 ? INT32_MAX : (tid < 6 ? -1 : 0);
+  __syncthreads();
+  if (b >= 0) {
+    search_block<DIM, T>(P, p, ra, blo, side);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      atomicMin(&s_box[a], (int32_t)blo[a]);
+      atomicMax(&s_box[3 + a], (int32_t)(blo[a] + side[a] - 1));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    bl[a] = s_box[a];
+    bn[a] = s_box[3 + a] - s_box[a] + 1;
+  }
+  // rows of buckets along x in the block, each a run of slots
+  const int nrows = bn[0] > 0 ? bn[1] * bn[2] : 0;
+  staged = nrows > 0 && nrows <= kStageRows &&
+                nrows * (bn[0] + 1) <= kStageBuckets;
+  if (staged) {
+    // one row per thread (nrows <= 256): its slots, scanned over the block
+    int n_r = 0;
+    if (tid < nrows) {
+      const int64_t row =
+          bl[0] + P.nbk[0] * ((bl[1] + tid % bn[1]) + P.nbk[1] * (bl[2] + tid / bn[1]));
+      const int32_t g0 = P.bucket_start[row];
+      s_rowg0[tid] = g0;
+      n_r = P.bucket_start[row + bn[0]] - g0;
+    }
+    int total_slots = 0;
+    const int ro = block_excl_scan(n_r, s_wave, total_slots);
+    if (tid < nrows) s_rowoff[tid] = ro;
+    if (tid == 0) s_rowoff[nrows] = total_slots;
+    __syncthreads();
+    staged = total_slots <= kStageBalls;   // the same on every thread
+  }
+  if (staged) {
+    // local bucket starts of every row, then the slots of all rows, both
+    // spread over the threads
+    const int nx1 = bn[0] + 1;
+    for (int q = tid; q < nrows * nx1; q += kTileThreads) {
+      const int r = q / nx1, i = q % nx1;
+      const int64_t row = bl[0] + P.nbk[0] * ((bl[1] + r % bn[1]) + P.nbk[1] * (bl[2] + r / bn[1]));
+      g_bst[q] = s_rowoff[r] + (P.bucket_start[row + i] - s_rowg0[r]);
+    }
+    const int total = s_rowoff[nrows];
+    for (int l = tid; l < total; l += kTileThreads) {
+      // the row holding local slot l: the last r with s_rowoff[r] <= l
+      int lo = 0, hi = nrows - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (s_rowoff[mid] <= l) lo = mid;
+        else hi = mid - 1;
+      }
+      const int32_t e = s_rowg0[lo] + (l - s_rowoff[lo]);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        g_cen[a * kStageBalls + l] =
+            sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
+      if (!UR) g_rad[l] = (T)P.bk_rad[e];
+      g_slot[l] = e;
+    }
+    __syncthreads();
+  }
+  }  // STG
+
   // ---- pass 1: number of overlaps and S = sum omega, in slot order
   int cnt = 0;
   double S = 0.0;
-  if (b >= 0)
-    for_each_overlap<DIM, T, UR>(P, p, ra, [&](int32_t e, T rb, T d2) {
-      S += P.bk_w[e] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
-      ++cnt;
-    });
+  auto count = [&](int32_t e, T rb, T d2) {
+    S += P.bk_w[e] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
+    if (cnt < kStash) s_stash[cnt * kTileThreads + tid] = e;
+    ++cnt;
+  };
+  if (b >= 0 && staged) {
+    // the same rows and slots as for_each_overlap, read from LDS
+    for (int64_t bz = 0; bz < side[2]; ++bz)
+      for (int64_t by = 0; by < side[1]; ++by) {
+        const int r = (int)((blo[1] + by - bl[1]) + bn[1] * (blo[2] + bz - bl[2]));
+        const int x0 = (int)(blo[0] - bl[0]);
+        const int lo = g_bst[r * (bn[0] + 1) + x0], hi = g_bst[r * (bn[0] + 1) + x0 + side[0]];
+        for (int l = lo; l < hi; ++l) {
+          T c[3] = {0, 0, 0};
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) c[a] = g_cen[a * kStageBalls + l];
+          const T rb = UR ? (T)P.r0 : g_rad[l];
+          T d2;
+          if (overlap<DIM, T>(p, c, ra + rb, d2)) count(g_slot[l], rb, d2);
+        }
+      }
+  } else if (b >= 0) {
+    for_each_overlap<DIM, T, UR>(P, p, ra, count);
+  }
+  __syncthreads();   // the staged block is dead from here on (merge arrays share its room)
   s_ucnt[tid] = 0;   // void marks of the local cells until the scan below
   __syncthreads();
   if (b >= 0 && !(S > 0.0)) {
@@ -661,9 +796,16 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
     if (s == 0 && b >= 0 && s_ucnt[lc]) atomicAdd(&P.flags[kFlagVoidRows], 1);
   }
   if (tid == 0) {
-    s_misc[0] = atomicAdd(&P.flags[kFlagPairs], H);
-    if (P.pair_a && (int64_t)s_misc[0] + H > P.pair_cap)
-      atomicOr(&P.flags[kFlagStageOverflow], 1);
+    // kept pairs reserve their room with an atomic add; otherwise only
+    // their number is written, per tile
+    if (P.pair_a) {
+      s_misc[0] = atomicAdd(&P.flags[kFlagPairs], H);
+      if ((int64_t)s_misc[0] + H > P.pair_cap) atomicOr(&P.flags[kFlagStageOverflow], 1);
+    } else {
+      s_misc[0] = 0;
+      P.tile_pairs[t] = H;
+    }
+    s_misc[3] = 0;   // staging entries used in the tile's own room
   }
   __syncthreads();
   const int pbase = s_misc[0];
@@ -690,11 +832,12 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
       continue;
     }
     const bool mine = b >= 0 && lc >= gs && lc < ge;
-    // pass 2: the same overlaps again (from cache), written in order
+    // pass 2: the same overlaps again, written in order: from the slots
+    // remembered in pass 1, or (more than kStash) by walking the buckets
     if (mine) {
       int o = off - gbase;
       int po = pbase + off;
-      for_each_overlap<DIM, T, UR>(P, p, ra, [&](int32_t e, T rb, T d2) {
+      auto put = [&](int32_t e, T rb, T d2) {
         const double om = P.bk_w[e] * (double)lens<DIM, T>(ra, rb, sqrt(d2));
         s_key[o] = P.bk_cell[e];
         s_val[o] = share * om;
@@ -704,7 +847,22 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
           P.pair_b[po] = P.bk_ball[e];
           ++po;
         }
-      });
+      };
+      if (cnt <= kStash) {
+        for (int i = 0; i < cnt; ++i) {
+          const int32_t e = s_stash[i * kTileThreads + tid];
+          T c[3] = {0, 0, 0};
+#pragma unroll
+          for (int a = 0; a < DIM; ++a)
+            c[a] = sizeof(T) == 8 ? (T)P.bk_cen[a * nb + e] : (T)P.bk_cen32[a * nb + e];
+          const T rb = UR ? (T)P.r0 : (T)P.bk_rad[e];
+          T d2;
+          overlap<DIM, T>(p, c, ra + rb, d2);
+          put(e, rb, d2);
+        }
+      } else {
+        for_each_overlap<DIM, T, UR>(P, p, ra, put);
+      }
     }
     s_ucnt[tid] = 0;
     __syncthreads();
@@ -728,15 +886,27 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
       if (u) atomicAdd(&s_ucnt[lc], u);
     }
     __syncthreads();
-    // unique counts scanned over the group's cells; the group reserves
-    // its staging room with one atomic add
+    // unique counts scanned over the group's cells; the group stages in
+    // the tile's own room while it lasts, else reserves room at the end
+    // of the staging array with one atomic add
     int U = 0;
     const int uc = (tid >= gs && tid < ge) ? s_ucnt[tid] : 0;
     const int uo = block_excl_scan(uc, s_wave, U);
     if (tid >= gs && tid < ge) s_upre[tid] = uo;
-    if (tid == 0) s_misc[2] = atomicAdd(&P.flags[kFlagEntries], U);
+    if (tid == 0) {
+      const int used = s_misc[3];
+      if (used + U <= kTileCap) {
+        s_misc[2] = used;
+        s_misc[3] = used + U;
+        s_misc[4] = 0;
+      } else {
+        s_misc[2] = atomicAdd(&P.flags[kFlagEntries], U);
+        s_misc[4] = 1;
+      }
+    }
     __syncthreads();
-    const int64_t sbase = s_misc[2];
+    const int64_t sbase = s_misc[4] ? P.n_tiles * kTileCap + s_misc[2]
+                                    : t * kTileCap + s_misc[2];
     if (sbase + U > P.stage_cap) {
       if (tid == 0) atomicOr(&P.flags[kFlagStageOverflow], 1);
     } else if (mine) {
@@ -789,10 +959,17 @@ __global__ void k_init_flags(int32_t* __restrict__ f) {
 template <int DIM, class T>
 static void launch_assemble_t(const TileParams& P, unsigned grid, bool ur, hipStream_t s) {
   ::bchar::ProfScope ps_("k_assemble", s);
-  if (ur)
-    k_assemble<DIM, T, true><<<grid, kTileThreads, 0, s>>>(P);
-  else
-    k_assemble<DIM, T, false><<<grid, kTileThreads, 0, s>>>(P);
+  if (P.lds_stage) {
+    if (ur)
+      k_assemble<DIM, T, true, true><<<grid, kTileThreads, 0, s>>>(P);
+    else
+      k_assemble<DIM, T, false, true><<<grid, kTileThreads, 0, s>>>(P);
+  } else {
+    if (ur)
+      k_assemble<DIM, T, true, false><<<grid, kTileThreads, 0, s>>>(P);
+    else
+      k_assemble<DIM, T, false, false><<<grid, kTileThreads, 0, s>>>(P);
+  }
 }
 
 static void launch_assemble(int dim, int precision, const TileParams& P, bool ur, hipStream_t s) {
@@ -849,7 +1026,7 @@ static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
 }
 
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
-                        int precision, bool keep_pairs, bchar_transfer_s* t,
+                        int precision, bool keep_pairs, bool lds_stage, bchar_transfer_s* t,
                         int64_t* first_void, hipStream_t s) {
   Arena& ws = t->ws;
   const int64_t nc = m->n_cells;
@@ -871,6 +1048,7 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.inv_hs = 1.0 / m->hs;
   P.rmax = m->rmax;
   P.r0 = m->r0;
+  P.lds_stage = lds_stage ? 1 : 0;
   P.rho = m->rho.as<double>();
   P.phi = m->phi.as<double>();
   P.bvol = m->bvol.as<double>();
@@ -886,11 +1064,16 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.row_cnt = ws.get<int32_t>(nc + 1);
   P.stage_off = ws.get<int32_t>(nc + 1);
   P.flags = ws.get<int32_t>(kNumFlags);
-  // staging room: the last build's need, else 8 entries per cell; a launch
-  // that finds it too small is repeated with what it needed
-  int64_t cap_e = std::max<int64_t>(t->stage_need, 8 * nc + 1024);
+  P.tile_pairs = ws.get<int32_t>(P.n_tiles + 1);
+  int32_t* pair_sum = ws.get<int32_t>(P.n_tiles + 1);
+  // staging: every tile's own room of kTileCap entries, then room for the
+  // groups that do not fit there (the last build's need, at least 1024); a
+  // launch that finds it too small is repeated with what it needed
+  const int64_t own = P.n_tiles * kTileCap;
+  int64_t cap_e = own + std::max<int64_t>(t->stage_need, 1024);
   int64_t cap_p = keep_pairs ? std::max<int64_t>(t->pair_need, 16 * m->n_balls + 1024) : 0;
   int32_t hf[kNumFlags];
+  int32_t npairs_tiles = 0;
   for (int attempt = 0;; ++attempt) {
     t->stage_col.reserve(sizeof(int32_t) * cap_e);
     t->stage_val.reserve(sizeof(double) * cap_e);
@@ -909,6 +1092,12 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
     k_init_flags<<<1, 64, 0, s>>>(P.flags);
     BCHAR_HIP(hipGetLastError());
     launch_assemble(m->dim, precision, P, m->r_uniform, s);
+    if (!keep_pairs) {
+      // the number of pairs: the tiles' counts summed (the scan's total)
+      exclusive_scan_i32_async(P.tile_pairs, pair_sum, P.n_tiles, ws, s);
+      BCHAR_HIP(hipMemcpyAsync(&npairs_tiles, pair_sum + P.n_tiles, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+    }
     BCHAR_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     BCHAR_HIP(hipStreamSynchronize(s));
     t->n_void_rows = hf[kFlagVoidRows];
@@ -923,21 +1112,21 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
     }
     if (!hf[kFlagStageOverflow]) break;
     BCHAR_REQUIRE(attempt == 0, BCHAR_E_DEVICE, "assembly staging still too small");
-    cap_e = std::max<int64_t>(cap_e, (int64_t)hf[kFlagEntries] + hf[kFlagEntries] / 4 + 1024);
+    cap_e = std::max<int64_t>(cap_e, own + (int64_t)hf[kFlagEntries] + hf[kFlagEntries] / 4 +
+                                         1024);
     if (keep_pairs)
       cap_p = std::max<int64_t>(cap_p, (int64_t)hf[kFlagPairs] + hf[kFlagPairs] / 4 + 1024);
   }
   t->stage_need = std::max<int64_t>(t->stage_need, (int64_t)hf[kFlagEntries] +
-                                                         hf[kFlagEntries] / 4 + 1024);
+                                                         hf[kFlagEntries] / 4);
   if (keep_pairs)
     t->pair_need = std::max<int64_t>(t->pair_need, (int64_t)hf[kFlagPairs] + hf[kFlagPairs] / 4 +
                                                        1024);
   t->row_ptr.reserve(sizeof(int32_t) * (nc + 1));
   int32_t* row_ptr = t->row_ptr.as<int32_t>();
   const int64_t nnz = exclusive_scan_i32(P.row_cnt, row_ptr, nc, ws, s);
-  BCHAR_REQUIRE(nnz == hf[kFlagEntries], BCHAR_E_DEVICE, "assembly: row lengths disagree");
   t->nnz = nnz;
-  t->n_pairs = hf[kFlagPairs];
+  t->n_pairs = keep_pairs ? hf[kFlagPairs] : npairs_tiles;
   t->col.reserve(sizeof(int32_t) * (nnz + 1));
   t->V.reserve(sizeof(double) * (nnz + 1));
   {

@@ -195,7 +195,7 @@ void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int 
                  int precision, double* tracked, double* r_hat, Arena& ws, hipStream_t s);
 // Returns BCHAR_OK or VOID_ROW (first_void set); allocates the CSR in t.
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
-                        int precision, bool keep_pairs, bchar_transfer_s* t,
+                        int precision, bool keep_pairs, bool lds_stage, bchar_transfer_s* t,
                         int64_t* first_void, hipStream_t s);
 
 // scaling (scaling.hip)

@@ -159,3 +159,37 @@ def test_void_column_count(env):
     _say(f"    stats {st}; oracle zero columns {zero.tolist()}")
     assert st["first_void"] == zero[0] and st["n_void_cols"] == zero.size
     assert st["n_void_rows"] == 0
+
+
+@pytest.mark.parametrize("name", ["swirl32", "porous3d", "tets", "hex_custom", "square"])
+def test_lds_staging_same_bits(env, name):
+    """The assembly staged in LDS and the one reading the hash in global
+    memory give the same pairs and the same V, bit for bit."""
+    torch, bchar = env
+    _say(f"[gpu] LDS staging on/off {name}")
+    if name == "swirl32":
+        w = inputs.swirl_hex(32)
+        mesh, vel, dt, layout = w["mesh"], w["vel_fn"](3), w["dt"], "subcell"
+    elif name == "porous3d":
+        w = inputs.porous_swirl_hex(8)
+        mesh, vel, dt, layout = w["mesh"], w["vel_fn"](0), 0.05, "subcell"
+    elif name == "tets":
+        mesh, vel, dt = _custom_case("tets")
+        layout = "equal_measure"
+    elif name == "hex_custom":
+        mesh, vel, dt = _custom_case("hex")
+        layout = "custom"
+    else:
+        mesh, vel, dt = _custom_case("square")
+        layout = "custom"
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    out = []
+    for stage in (1, 0):
+        T = bchar.Transfer.build(M, U, dt, bchar.opts_default(stop_after=bchar.STAGE_V,
+                                                              keep_pairs=1, lds_stage=stage))
+        out.append((T.export_pairs(), T.export_csr(bchar.STAGE_V), T.stats["n_pairs"]))
+    (p1, c1, n1), (p0, c0, n0) = out
+    assert n1 == n0
+    for x, y in zip(p1 + c1, p0 + c0):
+        assert np.array_equal(x, y)
