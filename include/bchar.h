@@ -399,6 +399,18 @@ bchar_status bchar_step(bchar_transfer t, const double* c_in, double* c_out, voi
  * the result is written to *host_out after synchronising `stream`.      */
 bchar_status bchar_mass(bchar_mesh mesh, const double* c, void* stream, double* host_out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops): the porous mass of bchar_mass, the same kernels and the
+ * same bits, written to device memory d_out (one binary64) in the order of
+ * `stream`, without synchronising and without allocating anything.  The
+ * block partials live in a device array of the library (8 KiB, one per
+ * GPU, held until the process ends) that every call on a GPU shares: calls
+ * that overlap on one GPU race, so order them on one stream (or
+ * synchronise between them).  Nothing carries over from one call to the
+ * next.  c: device, n_cells binary64.  Errors: INVALID_ARG (NULL, a mesh
+ * of more than 2^31 - 1 cells), DEVICE.                                   */
+bchar_status bchar_mass_into(bchar_mesh mesh, const double* c, double* d_out, void* stream);
+
 const char* bchar_status_string(bchar_status s);
 const char* bchar_last_error(void);
 

@@ -100,6 +100,7 @@ _build_tracked = _sig("bchar_build_transfer_tracked", [_P, _P, _P, C.POINTER(Opt
 _transfer_destroy = _sig("bchar_transfer_destroy", [_P])
 _step = _sig("bchar_step", [_P, _P, _P, _P])
 _mass = _sig("bchar_mass", [_P, _P, _P, C.POINTER(C.c_double)])
+_mass_into = _sig("bchar_mass_into", [_P, _P, _P, _P])
 _status_string = _sig("bchar_status_string", [C.c_int], C.c_char_p)
 _last_error = _sig("bchar_last_error", [], C.c_char_p)
 _transfer_info = _sig("bchar_transfer_info", [_P, _i64p, _i64p, _i64p, _ip])
@@ -147,7 +148,8 @@ _profile_read = _sig("bchar_profile_read", [_i64p, C.POINTER(C.c_double)])
 EXPORTED = [
     "bchar_opts_default", "bchar_mesh_create", "bchar_mesh_destroy", "bchar_mesh_info",
     "bchar_build_transfer", "bchar_rebuild_transfer", "bchar_build_transfer_tracked",
-    "bchar_transfer_destroy", "bchar_step", "bchar_mass", "bchar_status_string",
+    "bchar_transfer_destroy", "bchar_step", "bchar_mass", "bchar_mass_into",
+    "bchar_status_string",
     "bchar_last_error", "bchar_transfer_info", "bchar_transfer_export_csr",
     "bchar_transfer_export_pairs", "bchar_transfer_export_tracked", "bchar_transfer_export_qp",
     "bchar_mesh_export_balls", "bchar_transfer_export_qp_dual", "bchar_profile_kernel",
@@ -296,6 +298,11 @@ class Mesh:
         out = C.c_double()
         _check(_mass(self.handle, _dptr(c), _stream_ptr(stream), C.byref(out)))
         return out.value
+
+    def mass_into(self, c, out, stream=None):
+        """bchar_mass_into: the mass written to the one-element device
+        tensor ``out``, asynchronous, allocating nothing."""
+        _check(_mass_into(self.handle, _dptr(c), _dptr(out), _stream_ptr(stream)))
 
     def export_balls(self):
         cen = np.empty(self.dim * self.n_balls)

@@ -25,6 +25,7 @@ using bchar::Error;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int64_t kMassIntoMaxCells = ((int64_t)1 << 31) - 1;
 
 // ---- simplicial meshes (host side, at creation)
 
@@ -1127,6 +1128,17 @@ bchar_status bchar_mass(bchar_mesh m, const double* c, void* stream, double* hos
     BCHAR_REQUIRE(m != nullptr && c != nullptr && host_out != nullptr, BCHAR_E_INVALID_ARG,
                   "NULL argument");
     *host_out = bchar::porous_mass(m, c, m->ws, as_stream(stream));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_mass_into(bchar_mesh m, const double* c, double* d_out, void* stream) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(m != nullptr && c != nullptr && d_out != nullptr, BCHAR_E_INVALID_ARG,
+                  "NULL argument");
+    BCHAR_REQUIRE(m->n_cells <= kMassIntoMaxCells, BCHAR_E_INVALID_ARG,
+                  "bchar_mass_into takes at most 2^31 - 1 cells");
+    bchar::porous_mass_into(m, c, d_out, as_stream(stream));
     return BCHAR_OK;
   });
 }

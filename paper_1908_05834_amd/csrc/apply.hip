@@ -8,6 +8,8 @@
 //        gathered.
 // mass:  sum_K phi_K |K| c_K with TwoSum-compensated per-thread sums,
 //        a fixed-order block combine and a fixed-order final combine.
+#include <mutex>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -99,6 +101,47 @@ double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_
   BCHAR_HIP(hipStreamSynchronize(s));
   ws.rewind(mk);
   return out;
+}
+
+// ---- the mass without allocation (bchar_mass_into)
+//
+// The block partials live in a file-scope device array, one copy per GPU
+// for the life of the process.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there), taken once per device on its first use.
+constexpr int kMassScratch = 2 * kMassBlocks;   // hi and lo of every block partial
+static __device__ __align__(256) double scratch[kMassScratch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static double* mass_scratch() {
+  int dev = 0;
+  BCHAR_HIP(hipGetDevice(&dev));
+  BCHAR_REQUIRE(dev >= 0 && dev < kMaxDevices, BCHAR_E_UNSUPPORTED, "device index beyond 64");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    BCHAR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+void porous_mass_into(const bchar_mesh_s* m, const double* c, double* d_out, hipStream_t s) {
+  // the same kernels and order as porous_mass: the same bits
+  double* part = mass_scratch();
+  {
+    ::bchar::ProfScope ps_("k_mass_part", s);
+    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->n_cells, part);
+  }
+  BCHAR_HIP(hipGetLastError());
+  {
+    ::bchar::ProfScope ps_("k_mass_final", s);
+    k_mass_final<<<1, 64, 0, s>>>(part, kMassBlocks, d_out);
+  }
+  BCHAR_HIP(hipGetLastError());
 }
 
 }  // namespace bchar

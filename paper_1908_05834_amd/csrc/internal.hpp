@@ -231,6 +231,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 // apply / mass (apply.hip)
 void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s);
 double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_t s);
+// the same sum into device memory, asynchronous, allocating nothing (its
+// partials use a file-scope device array shared by every call on a GPU)
+void porous_mass_into(const bchar_mesh_s* m, const double* c, double* d_out, hipStream_t s);
 
 // ---------------------------------------------------------------- small helpers
 
