@@ -200,6 +200,12 @@ typedef struct {
                             the 64^3 swirl: the staging area costs a
                             workgroup per CU).  The same transfer bit for
                             bit either way                               */
+  int z_fuse_max_cells;  /* the fine level of the preconditioner runs its
+                            first two smoothing sweeps as one pass on meshes
+                            of at most this many cells (default 2^20: one
+                            launch fewer where launches cost, wider gathers
+                            than they save beyond); the same answer either
+                            way up to the solver's tolerance             */
 } bchar_opts;
 
 typedef struct {
@@ -231,6 +237,8 @@ typedef struct {
                                   reaches (a zero column of V, Sec. 3.2) */
   int trace_precision;         /* precision the tracking ran in: BCHAR_FP64
                                   or BCHAR_FP32_VOLUME                    */
+  int64_t device_bytes;        /* device memory the transfer holds after
+                                  the build (kept for the next rebuild)   */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */
@@ -365,12 +373,18 @@ typedef struct {
 } bchar_request_result;
 
 /* A server with n_workers worker threads, worker w on streams[w] with a
- * transfer of its own that every request it takes rebuilds (no device
- * allocation once the largest request has been seen).  Requests are taken
- * in submission order; the oldest waiting request starts only when the
- * sum of `bytes` of the requests in progress plus its own stays within
- * mem_budget bytes (0: no limit; a request larger than the budget runs
- * alone).  Errors: INVALID_ARG.                                         */
+ * transfer of its own that every request it takes rebuilds (its buffers
+ * are kept between requests: no device allocation once the largest
+ * request has been seen).  Requests are taken in submission order.
+ * Admission counts the device memory the workers hold: a worker's own
+ * (measured after each of its requests, stats.device_bytes) and, while it
+ * serves a request, at least that request's `bytes`.  The oldest waiting
+ * request starts only when the memory held with it stays within
+ * mem_budget bytes (0: no limit); while it waits, idle workers that hold
+ * memory release their buffers; a request larger than the budget starts
+ * alone, once nothing else runs or is held.  A `bytes` below what the
+ * build really takes lets the held memory exceed the budget by the
+ * difference.  Errors: INVALID_ARG.                                     */
 bchar_status bchar_server_create(int n_workers, void* const* streams, int64_t mem_budget,
                                  const bchar_opts* opts, bchar_server* out);
 

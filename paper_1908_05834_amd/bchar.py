@@ -58,7 +58,8 @@ class Opts(C.Structure):
                 ("box_policy", C.c_int), ("stop_after", C.c_int), ("qp_tol", C.c_double),
                 ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int),
                 ("warm_start", C.c_int), ("max_halvings", C.c_int),
-                ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int)]
+                ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int),
+                ("z_fuse_max_cells", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -69,7 +70,7 @@ class Stats(C.Structure):
                 ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64),
                 ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int),
                 ("n_void_rows", C.c_int64), ("n_void_cols", C.c_int64),
-                ("trace_precision", C.c_int)]
+                ("trace_precision", C.c_int), ("device_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -354,6 +354,7 @@ void validate_opts(const bchar_opts& o) {
                 "opts.qp_max_newton / qp_max_cg");
   BCHAR_REQUIRE(o.max_halvings >= 0 && o.max_halvings <= 20, BCHAR_E_INVALID_ARG,
                 "opts.max_halvings");
+  BCHAR_REQUIRE(o.z_fuse_max_cells >= 0, BCHAR_E_INVALID_ARG, "opts.z_fuse_max_cells");
 }
 
 void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
@@ -502,6 +503,18 @@ bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_veloci
                             stats);
 }
 
+// device memory a transfer holds (its buffers and scratch chunks)
+int64_t transfer_device_bytes(const bchar_transfer_s* t) {
+  const bchar::DBuf* bufs[] = {&t->row_ptr, &t->col,   &t->V,      &t->AN,        &t->A,
+                               &t->x,       &t->mu,    &t->nu,     &t->zdual,     &t->tracked,
+                               &t->r_hat,   &t->pair_a, &t->pair_b, &t->stage_col, &t->stage_val,
+                               &t->cscratch};
+  int64_t n = 0;
+  for (const auto* b : bufs) n += (int64_t)b->bytes;
+  for (const auto& c : t->ws.chunks) n += (int64_t)c.bytes;
+  return n;
+}
+
 // A void row or column is the method's sign that the step is too long for
 // the mesh: the build is repeated with half the step (the remedy the paper
 // gives), at most o.max_halvings times.
@@ -520,7 +533,11 @@ bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity
   }
   t->substeps = 1 << h;
   t->stats.dt_halvings = h;
-  if (stats) stats->dt_halvings = h;
+  t->stats.device_bytes = transfer_device_bytes(t);
+  if (stats) {
+    stats->dt_halvings = h;
+    stats->device_bytes = t->stats.device_bytes;
+  }
   return rc;
 }
 
@@ -539,6 +556,8 @@ void apply_substeps(bchar_transfer_s* t, const double* cin, double* cout, double
 
 // ---------------------------------------------------------------- serving
 
+static void transfer_free(bchar_transfer t);
+
 struct bchar_server_s {
   struct Item {
     bchar_request req;
@@ -548,7 +567,12 @@ struct bchar_server_s {
   };
   int dev = 0;
   bchar_opts opts{};
-  int64_t budget = 0, in_use = 0;
+  // Admission by memory: every worker keeps its transfer's buffers between
+  // requests, so what counts is the memory the workers hold.  retained[w]
+  // is worker w's, measured after each request and taken as at least the
+  // running request's declared bytes while it runs; held is their sum.
+  int64_t budget = 0, held = 0;
+  std::vector<int64_t> retained;
   int running = 0;                       // requests in progress
   std::vector<hipStream_t> streams;
   std::vector<bchar_transfer_s*> transfers;   // one per worker, rebuilt per request
@@ -560,6 +584,11 @@ struct bchar_server_s {
   bool stopping = false;
   std::vector<std::thread> workers;
 
+  // what the workers would hold if worker w took a request of `bytes`
+  int64_t projected(int w, int64_t bytes) const {
+    return held - retained[w] + std::max(retained[w], bytes);
+  }
+
   void work(int w) {
     (void)hipSetDevice(dev);
     bchar_transfer_s* t = transfers[w];
@@ -567,22 +596,48 @@ struct bchar_server_s {
     for (;;) {
       int64_t ticket = 0;
       Item* it = nullptr;
+      bool trim = false;
       {
         std::unique_lock<std::mutex> lk(mu);
-        // the oldest request starts once its bytes fit beside the running
-        // ones (alone if it does not fit at all)
+        // the oldest request starts once the memory the workers would then
+        // hold fits the budget, or alone (nothing running, no other worker
+        // holding memory) when it never fits; a worker that holds memory
+        // while the oldest request waits for memory gives it back
         cv.wait(lk, [&] {
           if (queue.empty()) return stopping;
           const Item& head = items[queue.front()];
-          return running == 0 || budget == 0 || in_use + head.bytes <= budget;
+          if (budget == 0 || projected(w, head.bytes) <= budget) return true;
+          if (running == 0 && held == retained[w]) return true;
+          if (retained[w] > 0) {
+            trim = true;
+            return true;
+          }
+          return false;
         });
         if (queue.empty()) return;
-        ticket = queue.front();
-        queue.pop_front();
-        it = &items[ticket];
-        in_use += it->bytes;
-        ++running;
-        it->res.t_start = bchar::wall_seconds();
+        if (!trim) {
+          ticket = queue.front();
+          queue.pop_front();
+          it = &items[ticket];
+          const int64_t r = std::max(retained[w], it->bytes);
+          held += r - retained[w];
+          retained[w] = r;
+          ++running;
+          it->res.t_start = bchar::wall_seconds();
+        }
+      }
+      if (trim) {
+        // release this worker's buffers (the next request allocates again)
+        (void)hipStreamSynchronize(s);
+        transfer_free(t);
+        t->stage_need = t->pair_need = 0;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          held -= retained[w];
+          retained[w] = 0;
+        }
+        cv.notify_all();
+        continue;
       }
       const bchar_request& r = it->req;
       bchar_status st = guarded([&]() -> bchar_status {
@@ -605,12 +660,14 @@ struct bchar_server_s {
         BCHAR_HIP(hipStreamSynchronize(s));
         return BCHAR_OK;
       });
+      const int64_t now = transfer_device_bytes(t);
       {
         std::lock_guard<std::mutex> lk(mu);
         it->res.status = st;
         it->res.t_done = bchar::wall_seconds();
         it->done = true;
-        in_use -= it->bytes;
+        held += now - retained[w];
+        retained[w] = now;
         --running;
       }
       cv.notify_all();
@@ -635,6 +692,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->warm_start = 1;
   o->cg_graphs = 1;
   o->lds_stage = 0;
+  o->z_fuse_max_cells = 1 << 20;
 }
 
 const char* bchar_status_string(bchar_status s) {
@@ -1280,6 +1338,7 @@ bchar_status bchar_server_create(int n_workers, void* const* streams, int64_t me
     validate_opts(srv->opts);
     BCHAR_HIP(hipGetDevice(&srv->dev));
     srv->budget = mem_budget;
+    srv->retained.assign(n_workers, 0);
     for (int w = 0; w < n_workers; ++w) {
       srv->streams.push_back(as_stream(streams[w]));
       srv->transfers.push_back(new bchar_transfer_s());

@@ -273,7 +273,7 @@ struct ProfModeGuard {
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s);
   ~ProfScope();
-  hipEvent_t end;   // recorded when the scope closes (null: not timed)
+  void* pair;       // this launch's start/end events in the timing state (null: not timed)
   hipStream_t s;
 };
 

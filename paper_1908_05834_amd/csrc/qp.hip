@@ -1731,6 +1731,7 @@ struct ZPrecond {
   Hierarchy* H;
   double omega = 0.7;
   int pre = 2, post = 2;
+  int64_t fuse_max = kZsmoothTwoMaxCells;   // the first two sweeps in one pass up to this size
   double *x, *x2, *res;   // 2n work vectors
 };
 
@@ -1748,7 +1749,7 @@ static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   // one pass for the first two sweeps saves a launch where launches cost
   // (up to ~10^6 cells); beyond, its wider gathers (b and B^-1 of every
   // neighbour instead of its iterate) cost more than the pass it saves
-  if (P.pre >= 2 && n <= kZsmoothTwoMaxCells) {
+  if (P.pre >= 2 && n <= P.fuse_max) {
     ::bchar::ProfScope ps_("k_zsmooth_two", s);
     k_zsmooth_two<<<gb, kT, 0, s>>>(P.Z, P.omega, r, x);
     k0 = 2;
@@ -2457,6 +2458,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 
   ZPrecond P;
   P.H = &H;
+  P.fuse_max = o.z_fuse_max_cells;
   P.Z.n = n;
   P.Z.rptr = row_ptr;
   P.Z.col = col;

@@ -1,4 +1,6 @@
 // Memory helpers, prefix scans, stable bucket sort and reductions.
+#include <list>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -282,7 +284,15 @@ struct ProfState {
   int64_t every = 1;      // time every `every`-th launch of it
   int64_t seen = 0;       // launches of it seen
   int64_t units = 0;      // replayable units seen
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  // timed launches: start and end events, and whether the end has been
+  // recorded (a scope records it when it closes); list nodes stay put, so a
+  // scope keeps a pointer to its own
+  struct Pair {
+    hipEvent_t a, b;
+    bool done;
+    bool counted;   // false: opened before the last reset, dropped when drained
+  };
+  std::list<Pair> pending;
   std::vector<hipEvent_t> free_events;
   int64_t launches = 0;
   double total_ms = 0;
@@ -301,17 +311,28 @@ hipEvent_t take_event(ProfState& p) {
   BCHAR_HIP(hipEventCreate(&e));
   return e;
 }
+// Sum the closed scopes (the caller holds the lock); each pair leaves the
+// list as it is counted, so a failure part way counts nothing twice, and
+// scopes still open are left for a later drain.
 void drain(ProfState& p) {
-  for (auto& pr : p.pending) {
-    BCHAR_HIP(hipEventSynchronize(pr.second));
+  for (auto it = p.pending.begin(); it != p.pending.end();) {
+    if (!it->done) {
+      ++it;
+      continue;
+    }
+    BCHAR_HIP(hipEventSynchronize(it->b));
     float ms = 0;
-    BCHAR_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-    p.total_ms += ms;
-    p.launches += 1;
-    p.free_events.push_back(pr.first);
-    p.free_events.push_back(pr.second);
+    BCHAR_HIP(hipEventElapsedTime(&ms, it->a, it->b));
+    const hipEvent_t a = it->a, b = it->b;
+    const bool counted = it->counted;
+    it = p.pending.erase(it);
+    if (counted) {
+      p.total_ms += ms;
+      p.launches += 1;
+    }
+    p.free_events.push_back(a);
+    p.free_events.push_back(b);
   }
-  p.pending.clear();
 }
 }  // namespace
 
@@ -329,7 +350,7 @@ bool prof_unit_due() {
 
 // The target is only read under the lock; a disabled scope costs one
 // relaxed atomic load.
-ProfScope::ProfScope(const char* name, hipStream_t st) : end(nullptr), s(st) {
+ProfScope::ProfScope(const char* name, hipStream_t st) : pair(nullptr), s(st) {
   ProfState& p = prof();
   if (t_mode == ProfMode::off || !p.on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(p.mu);
@@ -337,12 +358,20 @@ ProfScope::ProfScope(const char* name, hipStream_t st) : end(nullptr), s(st) {
   if (t_mode != ProfMode::all && (p.seen++ % p.every) != 0) return;
   hipEvent_t a = take_event(p), b = take_event(p);
   BCHAR_HIP(hipEventRecord(a, s));
-  p.pending.push_back({a, b});
-  end = b;
+  p.pending.push_back({a, b, false, true});
+  pair = &p.pending.back();
 }
 
+// The end event is recorded under the lock and the pair marked closed in
+// the same critical section, so that a concurrent drain never sees a pair
+// whose end is not yet recorded.
 ProfScope::~ProfScope() {
-  if (end) (void)hipEventRecord(end, s);
+  if (!pair) return;
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  auto* pr = static_cast<ProfState::Pair*>(pair);
+  (void)hipEventRecord(pr->b, s);
+  pr->done = true;
 }
 
 }  // namespace bchar
@@ -356,6 +385,7 @@ extern "C" bchar_status bchar_profile_kernel_sampled(const char* name, int every
     bchar::ProfState& p = bchar::prof();
     std::lock_guard<std::mutex> g(p.mu);
     bchar::drain(p);
+    for (auto& pr : p.pending) pr.counted = false;   // scopes still open
     p.target = name ? name : "";
     p.on.store(!p.target.empty(), std::memory_order_relaxed);
     p.every = every;

@@ -148,6 +148,42 @@ def test_server_requests_equal_runs_alone(env):
     srv.close()
 
 
+def test_server_admission_by_memory(env):
+    """A memory budget below two requests: with two workers the second
+    request starts only after the first has ended (its worker gives its
+    buffers back), a request larger than the budget runs alone, and every
+    result equals the same build and updates run alone, bit for bit."""
+    torch, bchar = env
+    probs = _problems(bchar)
+    m, v, dt = probs[0]
+    g = torch.Generator().manual_seed(11)
+    c0 = torch.rand(m.n_cells, dtype=torch.float64, generator=g).cuda()
+    T = bchar.Transfer.build(m, v, dt)
+    nxt = torch.empty_like(c0)
+    T.step(c0, nxt)
+    torch.cuda.synchronize()
+    want = nxt.cpu().numpy()
+    held = T.stats["device_bytes"]
+    T.close()
+    assert held > 0
+    _say(f"[gpu] server admission: a request holds {held} bytes")
+    # declared bytes B, budget 1.5 B: one request at a time
+    B = held
+    srv = bchar.Server(2, mem_budget=int(1.5 * B))
+    outs = [torch.empty_like(c0) for _ in range(3)]
+    tickets = [srv.submit(m, v, dt, 1, c0, outs[i], nbytes=B) for i in range(2)]
+    # larger than the budget: alone
+    tickets.append(srv.submit(m, v, dt, 1, c0, outs[2], nbytes=2 * B))
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for r in res:
+        assert r["status"] == bchar.OK
+    assert res[1]["t_start"] >= res[0]["t_done"], "the second request did not wait"
+    assert res[2]["t_start"] >= max(res[0]["t_done"], res[1]["t_done"])
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy().view(np.int64), want.view(np.int64))
+
+
 def test_cg_graph_replay_equals_eager_launches(env):
     """The CG iterations replayed from captured graphs (opts.cg_graphs)
     launch the same kernels on the same buffers as the eager loop: the

@@ -105,3 +105,30 @@ def test_swirl64_full_size(env):
     T.step(ones, cout)
     assert torch.max(torch.abs(cout - 1.0)).item() <= 1e-12
     T.close()
+
+
+def test_swirl24_against_stored_oracle(env):
+    """The largest size at which the oracle's least-change solve runs in
+    reasonable time (24^3 hexahedra, 110,592 balls, 48,120 entries: about
+    80 s on the host; 32^3 did not finish in 20 minutes): one step against
+    the oracle's, stored by tests/golden/make_swirl24.py, to the 1e-10 bar."""
+    import os
+    torch, bchar = env
+    _say("[gpu] 24^3 swirl against the stored oracle step")
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "swirl24_step.npz"))
+    w = inputs.swirl_hex(24)
+    M = bchar.Mesh(w["mesh"], "subcell")
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(w["vel_fn"](3)), w["dt"])
+    _say(f"    stats {T.stats}")
+    assert T.stats["qp_level"] == int(gold["qp_level"]) and T.stats["nnz"] == int(gold["nnz"])
+    c0 = inputs.uniform_c(w["mesh"], 11)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = gold["c1"]
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    m1 = M.mass(cout)
+    assert abs(m1 - float(gold["mass"])) <= 1e-12 * abs(float(gold["mass"]))

@@ -202,6 +202,13 @@ def test_full_step_cycle_skip(env, name):
     _check_full_step(env, name, cycle_skip=1)
 
 
+# the fine level's first two sweeps as two passes (the path of meshes above
+# 2^20 cells): the same minimiser to the same bar
+@pytest.mark.parametrize("name", ["swirl3d_subcell_16", "tets_porous", "solid_inscribed"])
+def test_full_step_unfused_sweeps(env, name):
+    _check_full_step(env, name, z_fuse_max_cells=0)
+
+
 def _check_full_step(env, name, **opts):
     _say(f"[gpu] full step {name} {opts}")
     torch, bchar, mesh, ref, M, T = _full(env, name, **opts)
