@@ -66,15 +66,17 @@ def algorithmic_bytes(kernel, n_cells, nnz, n_balls, stats):
     if kernel == "k_zop":
         return n_cells * (16 + 16 + 8 + 4 + 16) + 2 * nnz * 12
     if kernel == "k_assemble":
-        # two launches per build, a counting pass and a filling pass, both
-        # reading the tracked centre and radius (32 per ball), the residing
-        # balls through the hash (32 per ball) and phi (8 per cell); the
-        # filling pass writes the CSR entries (12 each): per launch, the
-        # inputs and half the output
-        return n_balls * (32 + 32) + n_cells * 8 + nnz * 12 // 2
+        # one launch per build: the build stage's 385 bytes per cell less
+        # the velocity (read by the trace) -- the residing balls through the
+        # hash (32 per ball), the bucket offsets (32 per cell), phi, |K| and
+        # rho (16 per cell), the CSR rows (12 per entry, 4 per cell) -- plus
+        # the tracked centres and radii the separate trace kernel wrote (32
+        # per ball)
+        return n_balls * 32 + n_cells * (32 + 16 + 4) + nnz * 12 + n_balls * 32
     if kernel == "k_trace":
-        # centre in, tracked centre and radius out, velocity lattice (24 B
-        # per node, about one node per cell)
+        # ball centre in (24 per ball), tracked centre and radius out (32
+        # per ball), the velocity lattice (24 per node, about one node per
+        # cell)
         return n_balls * (24 + 32) + n_cells * 24
     raise KeyError(kernel)
 
@@ -241,11 +243,64 @@ def cpu_baseline(sample_n=16, workload="swirl"):
         c1 = otr.apply(T["row_ptr"], T["col"], T["A"], T["b"], w["c0"])
         t1 = time.perf_counter()
     assert np.all(np.isfinite(c1))
+    model, ncpu = host_cpu()
     return {"value": n_cells / (t1 - t0), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cores": ncpu,
             "sample": f"one step (build + apply) of the {workload} workload on a "
                       f"{sample_n}^3 grid ({n_cells} cells, {what}, {prec.upper()}), "
                       f"{t1 - t0:.2f} s single-threaded"}
+
+
+def host_cpu():
+    """Model name of the host CPU and the number of cores the OS reports."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline_swirl64():
+    """The oracle on the host cores, one thread, on the headline workload
+    itself (64^3 hexahedra, 8 balls per cell, FP64): one step through the
+    tracking, candidate pairs, V and the N = 10 scaling sweeps.  Its
+    least-change solve does not finish in practical time at this size (a
+    full step takes about 80 s at 24^3 and more than 20 minutes at 32^3),
+    so the rate counts these stages only: an upper bound on the oracle's
+    full-step rate.  A full oracle step at 16^3 is given beside it."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import transfer as otr
+    from paper_1908_05834_amd import inputs
+
+    model, ncpu = host_cpu()
+    w = inputs.swirl_hex(64)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        T = otr.build_transfer(w["mesh"], w["vel_fn"](0), w["dt"], layout="subcell",
+                               stop_after="sinkhorn")
+        t1 = time.perf_counter()
+        w16 = inputs.swirl_hex(16)
+        t2 = time.perf_counter()
+        T16 = otr.build_transfer(w16["mesh"], w16["vel_fn"](0), w16["dt"], layout="subcell")
+        c16 = otr.apply(T16["row_ptr"], T16["col"], T16["A"], T16["b"], w16["c0"])
+        t3 = time.perf_counter()
+    assert np.all(np.isfinite(T["AN"])) and np.all(np.isfinite(c16))
+    nc = 64 ** 3
+    return {"value": nc / (t1 - t0), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of the 64^3 swirl (262,144 cells, 8 balls per cell, FP64) "
+                      f"through tracking, candidate pairs, V and the 10 scaling sweeps, "
+                      f"{t1 - t0:.1f} s single-threaded (the least-change solve left out: "
+                      f"an upper bound on the oracle's full-step rate)",
+            "full_step_16": {"value": 16 ** 3 / (t3 - t2), "seconds": t3 - t2,
+                             "cells": 16 ** 3},
+            "cpu_model": model, "host_cores": ncpu}
 
 
 def bench_mixed(args):
@@ -345,14 +400,17 @@ def bench_mixed(args):
     print(json.dumps(out))
 
 
-def bench_serve(args):
-    """Requests arriving as a Poisson process (seeded) at ``--rate`` per
-    second: each takes a problem from a pool of ``--problems`` resident
-    meshes (inputs.mixed_problem), builds its transfer and applies it a
-    number of times drawn from U{1..50}; the server (bchar_server_*) runs
-    them with ``--inflight`` workers, then with one (the serial path) on the
-    same arrivals.  Reports cell-updates/s and the latency from arrival to
-    result (p50, p99)."""
+def serve_run(requests, rate, seed, problems, workers, mem_budget_gib, per_request_mesh,
+              serial, n_hi=2.0e5):
+    """Requests arriving as a Poisson process (seeded) at ``rate`` per
+    second; each builds the transfer of one step and applies it U{1..50}
+    times.  With resident meshes the problem is drawn from a pool of
+    ``problems`` (inputs.mixed_problem); with ``per_request_mesh`` every
+    request draws its own problem (mixed_problem of seed 1000 + i, up to
+    ``n_hi`` cells) and creates its mesh on arrival, destroyed once its
+    result is in.  The server (bchar_server_*) runs them with ``workers``
+    workers (and again with one when ``serial``).  Latency is arrival to
+    result."""
     import threading
 
     import numpy as np
@@ -360,93 +418,128 @@ def bench_serve(args):
 
     from paper_1908_05834_amd import bchar, inputs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    D = max(1, args.inflight)
-    pool = []
-    for p in range(args.problems):
-        q = inputs.mixed_problem(p)
-        M = bchar.Mesh(q["mesh"], q["layout"])
-        c0 = torch.as_tensor(q["c0"], device="cuda")
-        pool.append({"M": M, "U": bchar.VelocityLattice(q["vel"]), "dt": q["dt"], "c0": c0,
-                     "m0": M.mass(c0), "name": q["name"]})
-    rng = np.random.default_rng(args.seed)
-    gaps = rng.exponential(1.0 / args.rate, size=args.requests)
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=requests)
     arrivals = np.cumsum(gaps) - gaps[0]
-    which = rng.integers(0, len(pool), size=args.requests)
-    nsteps = rng.integers(1, 51, size=args.requests)
+    nsteps = rng.integers(1, 51, size=requests)
+    pool = []
+    if per_request_mesh:
+        descs = [inputs.mixed_problem(1000 + i, n_hi=n_hi) for i in range(requests)]
+        which = np.arange(requests)
+    else:
+        for p in range(problems):
+            q = inputs.mixed_problem(p)
+            M = bchar.Mesh(q["mesh"], q["layout"])
+            c0 = torch.as_tensor(q["c0"], device="cuda")
+            pool.append({"M": M, "U": bchar.VelocityLattice(q["vel"]), "dt": q["dt"],
+                         "c0": c0, "m0": M.mass(c0)})
+        which = rng.integers(0, len(pool), size=requests)
 
-    def run(workers, label):
-        srv = bchar.Server(workers, mem_budget=int(args.mem_budget_gib * (1 << 30)))
-        # warm-up: every pool problem once (worker buffers reach their size)
-        for q in pool:
-            out, tmp = torch.empty_like(q["c0"]), torch.empty_like(q["c0"])
-            srv.wait(srv.submit(q["M"], q["U"], q["dt"], 1, q["c0"], out, tmp))
-        results = [None] * args.requests
-        tickets = [None] * args.requests
-        bufs = [None] * args.requests
+    def run(nw, label):
+        # a void makes the library repeat the build with half the step
+        srv = bchar.Server(nw, mem_budget=int(mem_budget_gib * (1 << 30)),
+                           opts=bchar.opts_default(max_halvings=4))
+        if pool:
+            # warm-up: every pool problem once (worker buffers reach their size)
+            for q in pool:
+                out, tmp = torch.empty_like(q["c0"]), torch.empty_like(q["c0"])
+                srv.wait(srv.submit(q["M"], q["U"], q["dt"], 1, q["c0"], out, tmp))
+        results = [None] * requests
+        tickets = [None] * requests
+        held = [None] * requests
+        pre = [0.0] * requests   # arrival to submission (mesh creation), seconds
         ready = threading.Semaphore(0)
 
         def collect():
-            for i in range(args.requests):
+            for i in range(requests):
                 ready.acquire()
                 results[i] = srv.wait(tickets[i])
-                q = pool[which[i]]
-                m = q["M"].mass(bufs[i][0])
+                q = held[i]["q"]
+                m = q["M"].mass(held[i]["out"])
                 results[i]["mass_err"] = abs(m - q["m0"]) / abs(q["m0"])
-                bufs[i] = None
+                results[i]["t_arrival"] = results[i]["t_submit"] - pre[i]
+                results[i]["cells"] = q["M"].n_cells
+                if per_request_mesh:
+                    q["M"].close()
+                held[i] = None
         th = threading.Thread(target=collect)
         th.start()
         t0 = time.perf_counter()
-        for i in range(args.requests):
+        for i in range(requests):
             dly = t0 + arrivals[i] - time.perf_counter()
             if dly > 0:
                 time.sleep(dly)
-            q = pool[which[i]]
+            ta = time.perf_counter()
+            if per_request_mesh:
+                d = descs[i]
+                M = bchar.Mesh(d["mesh"], d["layout"])
+                c0 = torch.as_tensor(d["c0"], device="cuda")
+                q = {"M": M, "U": bchar.VelocityLattice(d["vel"]), "dt": d["dt"], "c0": c0,
+                     "m0": M.mass(c0)}
+            else:
+                q = pool[which[i]]
             out, tmp = torch.empty_like(q["c0"]), torch.empty_like(q["c0"])
-            bufs[i] = (out, tmp)
+            held[i] = {"q": q, "out": out, "tmp": tmp}
+            pre[i] = time.perf_counter() - ta
             tickets[i] = srv.submit(q["M"], q["U"], q["dt"], int(nsteps[i]), q["c0"], out, tmp)
             ready.release()
-            if i % 25 == 24:
+            if i % 20 == 19:
                 log(f"  {label}: {i + 1} requests submitted at {time.perf_counter() - t0:.1f} s")
         th.join()
         srv.close()
         ok = all(r["status"] == bchar.OK for r in results)
-        lat = np.array([r["t_done"] - r["t_submit"] for r in results])
-        span = max(r["t_done"] for r in results) - min(r["t_submit"] for r in results)
-        cu = sum(pool[which[i]]["M"].n_cells * int(nsteps[i]) for i in range(args.requests))
+        lat = np.array([r["t_done"] - r["t_arrival"] for r in results])
+        span = max(r["t_done"] for r in results) - min(r["t_arrival"] for r in results)
+        cu = sum(r["cells"] * int(nsteps[i]) for i, r in enumerate(results))
         merr = max(r["mass_err"] for r in results)
         log(f"{label}: {span:.2f} s, p50 {np.percentile(lat, 50) * 1e3:.0f} ms, "
             f"p99 {np.percentile(lat, 99) * 1e3:.0f} ms")
-        return {"value": cu / span, "seconds": span, "ok": ok, "mass_err": merr,
+        return {"value": cu / span, "unit": "cell-updates/s", "seconds": span, "ok": ok,
+                "max_rel_mass_err": merr, "requests": requests, "rate_per_s": rate,
+                "workers": nw, "cells_mean": float(np.mean([r["cells"] for r in results])),
                 "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
-                "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
+                "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+                "mass_ok": bool(ok and merr <= 1e-12)}
 
-    par = run(D, f"{D} workers")
-    ser = run(1, "1 worker")
+    out = run(workers, f"{workers} workers")
+    if serial:
+        out["serial"] = run(1, "1 worker")
+    out["per_request_mesh"] = bool(per_request_mesh)
+    return out
+
+
+def bench_serve(args):
+    """The served workload alone: ``--requests`` Poisson arrivals at
+    ``--rate`` per second, served with ``--inflight`` workers and then by
+    one (the serial path) on the same arrivals."""
+    D = max(1, args.inflight)
+    r = serve_run(args.requests, args.rate, args.seed, args.problems, D, args.mem_budget_gib,
+                  bool(args.per_request_mesh), True, args.n_hi)
+    where = ("a mesh created per request (mixed problems up to "
+             f"{args.n_hi:.0f} cells)" if args.per_request_mesh else
+             f"problems drawn from {args.problems} resident meshes")
     out = {
         "metric": "B-char served cell-updates/s and p99 latency (arrival to result)",
-        "value": par["value"],
+        "value": r["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.requests,
-        "warmup": len(pool),
-        "ms_per_step": par["seconds"] / args.requests * 1e3,
+        "warmup": 0 if args.per_request_mesh else args.problems,
+        "ms_per_step": r["seconds"] / args.requests * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.requests} requests, Poisson arrivals at {args.rate}/s "
-                               f"(seed {args.seed}), problems drawn from {len(pool)} resident "
-                               "meshes of the batch of independent problems, U{1..50} "
-                               "updates each",
+                               f"(seed {args.seed}), {where}, U{{1..50}} updates each",
                    "workers": D, "mem_budget_gib": args.mem_budget_gib,
-                   "latency_ms_p50": par["latency_ms_p50"],
-                   "latency_ms_p99": par["latency_ms_p99"]},
-        "mass_ok": bool(par["ok"] and ser["ok"] and max(par["mass_err"], ser["mass_err"]) <= 1e-12),
-        "max_rel_mass_err": max(par["mass_err"], ser["mass_err"]),
-        "serial": ser,
+                   "latency_ms_p50": r["latency_ms_p50"],
+                   "latency_ms_p99": r["latency_ms_p99"]},
+        "mass_ok": bool(r["mass_ok"] and r["serial"]["mass_ok"]),
+        "max_rel_mass_err": max(r["max_rel_mass_err"], r["serial"]["max_rel_mass_err"]),
+        "serial": r["serial"],
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -464,10 +557,16 @@ def main():
                     help="swirl: fp64 by default; tets: fp32 (binary32 volumes)")
     ap.add_argument("--inflight", type=int, default=4,
                     help="transfers built at once on separate streams (1: one after another)")
-    ap.add_argument("--roofline-kernel", default="k_smooth")
     ap.add_argument("--build-kernel", default="k_assemble")
-    ap.add_argument("--smoother-kernel", default="k_zsmooth")
-    ap.add_argument("--coarse-kernel", default="k_fused_cycle")
+    ap.add_argument("--trace-kernel", default="k_trace")
+    ap.add_argument("--legs", type=int, choices=[0, 1], default=1,
+                    help="swirl: also run the FP32-volume leg and the served leg")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="served leg: requests")
+    ap.add_argument("--serve-rate", type=float, default=6.0,
+                    help="served leg: Poisson arrivals per second")
+    ap.add_argument("--serve-problems", type=int, default=16,
+                    help="served leg: resident problems the requests draw from")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     ap.add_argument("--cg-graphs", type=int, choices=[0, 1], default=1,
@@ -485,7 +584,12 @@ def main():
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--seed", type=int, default=0, help="serve: arrival seed")
     ap.add_argument("--mem-budget-gib", type=float, default=64.0,
-                    help="serve: device memory the requests in progress may take")
+                    help="serve: device memory the workers may hold")
+    ap.add_argument("--per-request-mesh", type=int, choices=[0, 1], default=0,
+                    help="serve: create each request's mesh on arrival (and destroy it "
+                         "after), instead of drawing from resident meshes")
+    ap.add_argument("--n-hi", type=float, default=2.0e5,
+                    help="serve with --per-request-mesh: largest mesh (cells)")
     ap.add_argument("--problems", type=int, default=32,
                     help="mixed workload: number of problems (seeds 0 .. problems-1)")
     ap.add_argument("--pmc-sum", nargs=3, metavar=("PROF_DIR", "COUNTER", "OUT"),
@@ -534,50 +638,107 @@ def main():
         bench_serve(args)
         return
 
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(torch.device("cuda:0"))
+    args.precision = args.precision or ("fp32" if args.workload == "tets" else "fp64")
+    args.n = args.n or (96 if args.workload == "tets" else 64)
+    res = run_transport(args, args.workload, args.precision, args.steps, args.warmup, D,
+                        bool(args.tune))
+    out = {
+        "metric": res["metric"],
+        "value": res["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": res["steps_timed"],
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": res["dtype"],
+        "data": "synthetic",
+        "config": res["config"],
+        "mass_ok": res["mass_ok"],
+        "max_rel_mass_err": res["max_rel_mass_err"],
+        "sequential": res["sequential"],
+        "roofline": res["roofline"],
+        "roofline_build_stage": res["roofline_build_stage"],
+        "roofline_step": res["roofline_step"],
+        "cpu_baseline": None,
+    }
+    if args.workload == "swirl" and args.legs:
+        # the FP32-volume mode on the same workload (binary32 tracking and
+        # lenses, binary64 adjustment), fewer steps
+        log("FP32-volume leg")
+        r32 = run_transport(args, "swirl", "fp32", max(4, args.steps // 2), args.warmup, D,
+                            False)
+        out["fp32_volume"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                              "steps": r32["steps_timed"], "mass_ok": r32["mass_ok"],
+                              "max_rel_mass_err": r32["max_rel_mass_err"],
+                              "sequential": r32["sequential"],
+                              "qp_cg_mean": r32["config"]["qp_cg_mean"],
+                              "trace_precision": r32["config"]["trace_precision"]}
+        # served requests: continuous batching with p50 / p99 latency
+        log("served leg")
+        sv = serve_run(requests=args.serve_requests, rate=args.serve_rate, seed=0,
+                       problems=args.serve_problems, workers=D, mem_budget_gib=64.0,
+                       per_request_mesh=False, serial=False)
+        out["served"] = sv
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = (cpu_baseline_swirl64() if args.workload == "swirl" and args.n == 64
+                               else cpu_baseline(args.cpu_sample if args.workload == "swirl"
+                                                 else 6, args.workload))
+    print(json.dumps(out))
+
+
+def step_bytes_per_cell(cg_iterations):
+    """Algorithmic bytes of one whole step per cell (the build 385, the
+    transposed pattern 35, the N = 10 scaling sweeps 1,500, 150 per CG
+    iteration of the least-change solve, the update 73 and the mass 24)."""
+    return 385 + 35 + 1500 + 150 * cg_iterations + 73 + 24
+
+
+def run_transport(args, workload, precision, steps, warmup, D, tune):
+    """The transfer of every step rebuilt and applied: first one build after
+    another (per-step latency; the build kernel timed with HIP events on
+    these steps), then D builds at once on their own streams (throughput).
+    Returns the measured figures."""
     import numpy as np
     import torch
 
     from paper_1908_05834_amd import bchar, inputs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    if args.workload == "tets":
-        args.n = args.n or 96
-        args.precision = args.precision or "fp32"
-        w = inputs.jittered_tets(args.n, steps=max(args.warmup + args.steps, 3))
+    if workload == "tets":
+        n = args.n or 96
+        w = inputs.jittered_tets(n, steps=max(warmup + steps, 3))
         layout = "equal_measure"
-        workload = (f"3D jittered Kuhn tetrahedra, {args.n}^3 cubes x 6 = {6 * args.n ** 3} "
-                    f"cells, lognormal phi, swirl at CFL 4, one centroid ball per cell, "
-                    f"dt = 1/128, transfer rebuilt every step")
-        metric = (f"B-char cell-updates/s (3D tets {6 * args.n ** 3}) at 1e-12 mass err; "
+        desc = (f"3D jittered Kuhn tetrahedra, {n}^3 cubes x 6 = {6 * n ** 3} "
+                f"cells, lognormal phi, swirl at CFL 4, one centroid ball per cell, "
+                f"dt = 1/128, transfer rebuilt every step")
+        metric = (f"B-char cell-updates/s (3D tets {6 * n ** 3}) at 1e-12 mass err; "
                   "served p99 latency")
     else:
-        args.n = args.n or 64
-        args.precision = args.precision or "fp64"
-        w = inputs.swirl_hex(args.n)
+        n = args.n or 64
+        w = inputs.swirl_hex(n)
         layout = "subcell"
-        workload = (f"3D swirl, unit cube, {args.n}^3 hexahedra, 8 balls per cell, "
-                    f"phi = 1, dt = 1/128, transfer rebuilt every step")
+        desc = (f"3D swirl, unit cube, {n}^3 hexahedra, 8 balls per cell, "
+                f"phi = 1, dt = 1/128, transfer rebuilt every step")
         metric = "B-char cell-updates/s (3D hex 64^3) at 1e-12 mass err; served p99 latency"
     # binary32 tracking (FP32_VOLUME) needs a constant porosity; the porous
     # unstructured workload tracks in binary64 with binary32 lenses
-    prec = bchar.FP64 if args.precision == "fp64" else (
-        bchar.FP32_LENS if args.workload == "tets" else bchar.FP32_VOLUME)
+    prec = bchar.FP64 if precision == "fp64" else (
+        bchar.FP32_LENS if workload == "tets" else bchar.FP32_VOLUME)
     opts = bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs,
                               cycle_skip=args.cycle_skip)
     M = bchar.Mesh(w["mesh"], layout)
-    # phase 1: one build after another (per-step latency); phase 2: D builds
-    # at once (throughput, the reported value).  Every interval's velocity
-    # lattice is resident on the device before timing.
-    # Both runs time the same intervals (warmup .. warmup + steps - 1) when
-    # the warm-up spans whole batches.
-    seq_total = args.warmup + args.steps
-    warm_batches = max(1, math.ceil(args.warmup / D))
-    timed_batches = max(1, math.ceil(args.steps / D))
-    steps_timed = timed_batches * D if D > 1 else args.steps
-    pipe_first = max(0, args.warmup - warm_batches * D)
+    seq_total = warmup + steps
+    warm_batches = max(1, math.ceil(warmup / D))
+    timed_batches = max(1, math.ceil(steps / D))
+    steps_timed = timed_batches * D if D > 1 else steps
+    pipe_first = max(0, warmup - warm_batches * D)
     pipe_total = pipe_first + (warm_batches + timed_batches) * D if D > 1 else 0
     vels = [bchar.VelocityLattice(w["vel_fn"](s % w["steps"]))
             for s in range(max(seq_total, pipe_total, 3))]
@@ -593,15 +754,9 @@ def main():
         mass_err = max(mass_err, e)
         return nxt, c, e
 
-    # ---- autotuning (untimed): which multigrid cycle builds D transfers in
-    # flight fastest on this workload, measured by the library on the first
-    # intervals (bchar_tune_options), unless --tune 0 fixes it
-    # one stream per build in flight, created once: the tuning and the
-    # in-flight phase share them (more streams than hardware queues would
-    # put two builds on one queue)
     streams = [torch.cuda.Stream() for _ in range(D)]
     tuned = None
-    if args.tune:
+    if tune:
         cands = [bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs, cycle_skip=v)
                  for v in (0, 1)]
         best, secs = bchar.tune_options([(M, vels[j % len(vels)], w["dt"]) for j in range(D)],
@@ -610,7 +765,8 @@ def main():
         tuned = {"option": "cycle_skip", "values": [0, 1], "seconds": secs, "chosen": best}
         log(f"tuned: cycle_skip {best} ({secs[0]:.3f} s against {secs[1]:.3f} s)")
 
-    # ---- phase 1: sequential
+    # ---- phase 1: one build after another; the build kernel (one launch a
+    # step) timed with HIP events over the timed steps
     c, nxt = c0.clone(), torch.empty_like(c0)
     T = None
     lat = []
@@ -618,6 +774,8 @@ def main():
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
     for s in range(seq_total):
+        if s == warmup:
+            bchar.profile_kernel(args.build_kernel)
         tw = time.perf_counter()
         if T is None:
             T = bchar.Transfer.build(M, vels[s], w["dt"], opts)
@@ -626,14 +784,20 @@ def main():
         c, nxt, e = apply(T, c, nxt)
         torch.cuda.synchronize()
         dt_s = time.perf_counter() - tw
-        if s == args.warmup - 1 or (args.warmup == 0 and s == 0):
+        if s == warmup - 1 or (warmup == 0 and s == 0):
             ts0 = time.perf_counter()
-        if s >= args.warmup:
+        if s >= warmup:
             lat.append(dt_s)
             seq_stats.append(T.stats)
         log(f"sequential step {s}: {dt_s:.3f} s, ipm {T.stats['qp_ipm']}, cg {T.stats['qp_cg']}, "
             f"mass err {e:.2e}")
     seq_elapsed = time.perf_counter() - ts0
+    b_launches, b_ms = bchar.profile_read()
+    bchar.profile_kernel(args.trace_kernel)
+    T.rebuild(vels[0], w["dt"], opts)
+    torch.cuda.synchronize()
+    t_launches, t_ms = bchar.profile_read()
+    bchar.profile_kernel(None)
 
     # ---- phase 2: D transfers built at once (D = 1: the sequential run)
     if D > 1:
@@ -657,10 +821,6 @@ def main():
         for _ in range(warm_batches):
             batch(False)
         torch.cuda.synchronize()
-        # every 17th launch: the events barely disturb the run, and as 17 is
-        # prime the sample runs through the levels of a cycle (unless a cycle
-        # launches the kernel a multiple of 17 times)
-        bchar.profile_kernel_sampled(args.roofline_kernel, 17)
         t0 = time.perf_counter()
         for b in range(timed_batches):
             batch(True)
@@ -668,98 +828,75 @@ def main():
                 f"{[s_['qp_cg'] for s_ in stats[-D:]]}, mass err {mass_err:.2e}")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        launches, kms = bchar.profile_read()
-        bchar.profile_kernel(None)
-        T_last = Ts[0]
     else:
-        # the sequential run is the timed one; time the roofline kernel over
-        # one more pass of the same steps
         stats = seq_stats
         elapsed = seq_elapsed
-        bchar.profile_kernel(args.roofline_kernel)
-        for s in range(args.warmup, seq_total):
-            T.rebuild(vels[s], w["dt"], opts)
-        torch.cuda.synchronize()
-        launches, kms = bchar.profile_read()
-        bchar.profile_kernel(None)
-        T_last = T
-    # the build kernel and the fine-level smoother, timed the same way over
-    # one more (untimed) build each
-    bchar.profile_kernel(args.build_kernel)
-    T_last.rebuild(vels[0], w["dt"], opts)
-    torch.cuda.synchronize()
-    b_launches, b_kms = bchar.profile_read()
-    bchar.profile_kernel(args.smoother_kernel)
-    T_last.rebuild(vels[1], w["dt"], opts)
-    torch.cuda.synchronize()
-    z_launches, z_kms = bchar.profile_read()
-    z_stats = T_last.stats
-    bchar.profile_kernel(args.coarse_kernel)
-    T_last.rebuild(vels[2], w["dt"], opts)
-    torch.cuda.synchronize()
-    c_launches, c_kms = bchar.profile_read()
-    bchar.profile_kernel(None)
 
     n_cells = M.n_cells
     value = n_cells * steps_timed / elapsed
     nnz = stats[-1]["nnz"]
+    cg_mean = float(np.mean([s_["qp_cg"] for s_ in stats]))
 
-    def roofline(kernel, n_launch, total_ms, st):
+    def roof(kernel, n_launch, total_ms, alg):
         if n_launch <= 0:
             return None
         avg_s = total_ms / 1e3 / n_launch
-        alg = algorithmic_bytes(kernel, n_cells, st["nnz"], M.n_balls, st)
         achieved = alg / avg_s / 1e9
-        traffic = measured_traffic(kernel, workload_key(args.workload, args.n, args.precision,
+        traffic = measured_traffic(kernel, workload_key(workload, n, precision,
                                                         opts.cycle_skip))
         return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches": n_launch, "avg_us": avg_s * 1e6,
-                "algorithmic_bytes_per_launch": alg}
+                "algorithmic_bytes_per_launch": alg,
+                "timing": "HIP events around each launch, sequential phase"}
 
-    roof = roofline(args.roofline_kernel, launches, kms, stats[-1])
-    roof_build = roofline(args.build_kernel, b_launches, b_kms, T_last.stats)
-    roof_smoother = roofline(args.smoother_kernel, z_launches, z_kms, z_stats)
-    roof_coarse = roofline(args.coarse_kernel, c_launches, c_kms, T_last.stats)
+    st = seq_stats[-1]
+    roof_build = roof(args.build_kernel, b_launches, b_ms,
+                      algorithmic_bytes(args.build_kernel, n_cells, st["nnz"], M.n_balls, st))
+    roof_trace = roof(args.trace_kernel, t_launches, t_ms,
+                      algorithmic_bytes(args.trace_kernel, n_cells, st["nnz"], M.n_balls, st))
+    # the build stage a1-a4 (tracking and assembly) against its 385 bytes
+    # per cell
+    stage = None
+    if roof_build and roof_trace:
+        t_stage = (roof_build["avg_us"] + roof_trace["avg_us"]) * 1e-6
+        ach = 385.0 * n_cells / t_stage / 1e9
+        stage = {"bound": "hbm", "kernels": [args.trace_kernel, args.build_kernel],
+                 "bytes_per_cell": 385, "seconds": t_stage, "achieved": ach,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    # the whole step (every stage, the least-change solve by its CG count)
+    bpc = step_bytes_per_cell(cg_mean)
+    ach_step = bpc * n_cells * steps_timed / elapsed / 1e9
+    step_roof = {"bound": "hbm", "bytes_per_cell": bpc, "qp_cg_mean": cg_mean,
+                 "bytes_per_step": bpc * n_cells, "achieved": ach_step, "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": ach_step / HBM_PEAK_GBS,
+                 "timing": "host clock over the timed steps of the reported run"}
     lat_ms = np.array(lat) * 1e3
-    out = {
+    return {
         "metric": metric,
         "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": steps_timed,
-        "warmup": args.warmup,
+        "steps_timed": steps_timed,
         "ms_per_step": elapsed / steps_timed * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 geometry + f64 adjustment",
-        "data": "synthetic",
-        "config": {"workload": workload,
-                   "n_cells": n_cells, "precision": args.precision, "nnz": nnz,
+        "dtype": "f64" if precision == "fp64" else "f32 geometry + f64 adjustment",
+        "config": {"workload": desc, "n_cells": n_cells, "precision": precision, "nnz": nnz,
                    "inflight_builds": D, "cg_graphs": args.cg_graphs,
                    "cycle_skip": int(opts.cycle_skip), "tuned": tuned,
+                   "trace_precision": int(st["trace_precision"]),
                    "qp_ipm_mean": float(np.mean([s_["qp_ipm"] for s_ in stats])),
-                   "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in stats])),
-                   "qp_levels": sorted({s_["qp_level"] for s_ in stats})},
+                   "qp_cg_mean": cg_mean,
+                   "qp_levels": sorted({s_["qp_level"] for s_ in stats}),
+                   "device_bytes_per_transfer": int(st["device_bytes"])},
         "mass_ok": bool(mass_err <= 1e-12),
         "max_rel_mass_err": mass_err,
-        "sequential": {"value": n_cells * args.steps / seq_elapsed,
+        "sequential": {"value": n_cells * steps / seq_elapsed,
                        "step_latency_ms_p50": float(np.percentile(lat_ms, 50)),
                        "step_latency_ms_p99": float(np.percentile(lat_ms, 99)),
                        "qp_cg_mean": float(np.mean([s_["qp_cg"] for s_ in seq_stats]))},
-        "roofline": roof,
-        "roofline_build": roof_build,
-        "roofline_smoother": roof_smoother,
-        "roofline_coarse": roof_coarse,
-        "cpu_baseline": None,
+        "roofline": roof_build,
+        "roofline_trace": roof_trace,
+        "roofline_build_stage": stage,
+        "roofline_step": step_roof,
     }
-    if not args.no_cpu_baseline:
-        # the oracle's cost grows faster than linearly on tetrahedra: a
-        # 6^3-cube sample (1,296 cells) keeps it to seconds
-        out["cpu_baseline"] = cpu_baseline(
-            args.cpu_sample if args.workload == "swirl" else 6, args.workload)
-    print(json.dumps(out))
 
 
 if __name__ == "__main__":

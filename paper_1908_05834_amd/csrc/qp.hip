@@ -3012,14 +3012,23 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       k_xover_state<<<gz, kT, 0, s>>>(I, kCrossoverRatio, nnz, side);
     }
     BCHAR_HIP(hipGetLastError());
-    for (int it = 0; it < kCrossoverSteps * (1 + kCrossoverRounds); ++it) {
-      if (it >= kCrossoverSteps && it % kCrossoverSteps == 0) {
+    // round 0: the interior point's sides, kCrossoverSteps steps; each
+    // later round: the sides read off t, one step, and no further round
+    // unless the residual fell tenfold (the split is not settling)
+    double f_prev = HUGE_VAL;
+    int round = 0, left = kCrossoverSteps;
+    for (int it = 0; round <= kCrossoverRounds; ++it) {
+      if (left == 0) {
+        ++round;
+        left = 1;
+        if (round > kCrossoverRounds) break;
         {
           ::bchar::ProfScope ps_("k_side_from_t", s);
           k_side_from_t<<<gz, kT, 0, s>>>(Q.t, lo, hi, nnz, side);
         }
         BCHAR_HIP(hipGetLastError());
       }
+      --left;
       {
         ::bchar::ProfScope ps_("k_residual_sides", s);
         k_residual_sides<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, side, lo, hi,
@@ -3051,6 +3060,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (f <= tol) {
         fn = f;
         return true;
+      }
+      if (left == 0) {
+        if (round > 0 && !(f < 0.1 * f_prev)) break;
+        f_prev = f;
       }
     }
     return false;
