@@ -200,6 +200,12 @@ typedef struct {
                             the 64^3 swirl: the staging area costs a
                             workgroup per CU).  The same transfer bit for
                             bit either way                               */
+  int halve_on_level2;   /* non-zero: with max_halvings, a build whose
+                            least-change problem would need level 2 (the
+                            equalities alone: volumes may turn negative and
+                            repeated updates grow without bound) is
+                            repeated with half the time step instead; the
+                            last allowed attempt may still take level 2 */
   int z_fuse_max_cells;  /* the fine level of the preconditioner runs its
                             first two smoothing sweeps as one pass on meshes
                             of at most this many cells (default 2^20: one

@@ -59,7 +59,7 @@ class Opts(C.Structure):
                 ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int),
                 ("warm_start", C.c_int), ("max_halvings", C.c_int),
                 ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int),
-                ("z_fuse_max_cells", C.c_int)]
+                ("halve_on_level2", C.c_int), ("z_fuse_max_cells", C.c_int)]
 
 
 class Stats(C.Structure):

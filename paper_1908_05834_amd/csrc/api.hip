@@ -526,10 +526,19 @@ bchar_status do_build(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_velocity
   bchar_status rc = BCHAR_OK;
   int h = 0;
   for (;; ++h) {
-    rc = build_once(m, t, u, std::ldexp(dt, -h), o, s, stats);
-    if ((rc != BCHAR_E_VOID_ROW && rc != BCHAR_E_VOID_COLUMN) || h >= o.max_halvings) break;
+    // with halve_on_level2 the least-change solve stops at level 1 (no
+    // negative volumes) and reports the box infeasible, except on the last
+    // allowed attempt, which may take level 2
+    bchar_opts oh = o;
+    if (h >= o.max_halvings) oh.halve_on_level2 = 0;
+    rc = build_once(m, t, u, std::ldexp(dt, -h), oh, s, stats);
+    const bool negative = rc == BCHAR_E_QP_INFEASIBLE && oh.halve_on_level2;
+    if ((rc != BCHAR_E_VOID_ROW && rc != BCHAR_E_VOID_COLUMN && !negative) ||
+        h >= o.max_halvings)
+      break;
     if (bchar::trace_enabled())
-      fprintf(stderr, "[bchar] void: step halved to dt / %d\n", 1 << (h + 1));
+      fprintf(stderr, "[bchar] %s: step halved to dt / %d\n", negative ? "level 2" : "void",
+              1 << (h + 1));
   }
   t->substeps = 1 << h;
   t->stats.dt_halvings = h;

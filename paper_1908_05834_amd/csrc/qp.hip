@@ -3080,7 +3080,9 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // point that fails declares the level infeasible.
   const double lo_levels[3] = {-1.0, -1.0, -HUGE_VAL};
   const double hi_levels[3] = {1.0, HUGE_VAL, HUGE_VAL};
-  const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : 2;
+  // the caller may stop at level 1 (it halves the step rather than accept
+  // negative volumes)
+  const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : (o.halve_on_level2 ? 1 : 2);
   bool converged = false, ipm_answer = false;
   int level = 0;
   for (level = 0; level <= max_level; ++level) {
@@ -3146,7 +3148,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   res.residual = fn;
   if (!converged) {
     res.level = level > max_level ? max_level : level;
-    return max_level == 0 ? BCHAR_E_QP_INFEASIBLE : BCHAR_E_QP_NOT_CONVERGED;
+    return max_level < 2 ? BCHAR_E_QP_INFEASIBLE : BCHAR_E_QP_NOT_CONVERGED;
   }
   res.level = level;
   {

@@ -35,18 +35,17 @@ def test_traffic_attached_only_to_its_workload_and_code(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    key = bench.workload_key("swirl", 64, "fp64", 1)
-    rec = {"kernel": "k_smooth", "workload_key": key,
-           "source_digest": bench.source_digest("k_smooth"), "bytes_per_launch": 123.0}
-    (prof / "traffic_k_smooth.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("k_smooth", key) == 123.0
-    # another cycle, size or workload: not this figure
-    assert bench.measured_traffic("k_smooth", bench.workload_key("swirl", 64, "fp64", 0)) is None
-    assert bench.measured_traffic("k_smooth", bench.workload_key("tets", 96, "fp32", 1)) is None
+    key = bench.workload_key("swirl", 64, "fp64")
+    rec = {"kernel": "k_assemble", "workload_key": key,
+           "source_digest": bench.source_digest("k_assemble"), "bytes_per_launch": 123.0}
+    (prof / "traffic_k_assemble.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("k_assemble", key) == 123.0
+    # another precision, size or workload: not this figure
+    assert bench.measured_traffic("k_assemble", bench.workload_key("swirl", 64, "fp32")) is None
+    assert bench.measured_traffic("k_assemble", bench.workload_key("tets", 96, "fp32")) is None
     # code changed since the counters were taken
     rec["source_digest"] = "0" * 16
-    (prof / "traffic_k_smooth.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("k_smooth", key) is None
+    (prof / "traffic_k_assemble.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("k_assemble", key) is None
     # no figure at all
-    assert bench.measured_traffic("k_zsmooth", key) is None
-
+    assert bench.measured_traffic("k_trace", key) is None
