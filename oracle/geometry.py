@@ -334,12 +334,54 @@ def cell_of_point(points, n, origin, h):
     return cid
 
 
-def speed(points, mesh, vel):
-    """v(x) = u^{(n+1)}(x) / phi(x), the right-hand side of eq. charac."""
-    u = q1_interpolate(points, vel["m"], vel["origin"], vel["spacing"], vel["u"])
+def q1_divergence(points, m, origin, spacing, u):
+    """div of the multilinear (Q1) interpolant of a nodal lattice field.
+
+    The point is clamped and its lattice cell chosen exactly as in
+    ``q1_interpolate``; on that cell the interpolant is the sum over the
+    corners of prod_b w_b times the nodal value, w_b = f_b or 1 - f_b, so
+    d/dx_a of it is (1/spacing_a) times the sum over the corners of
+    (+1 if the corner's bit a is set, else -1) prod_{b != a} w_b u_a(node).
+    Evaluated per axis a: the corners in binary order, the product over
+    the axes b != a in increasing order, then divided by spacing_a; the
+    divergence is the sum of the axes' terms in axis order.
+    """
+    pts = np.asarray(points, dtype=np.float64)
+    npnt, dim = pts.shape
+    m = [int(v) for v in m]
+    org = np.asarray(origin, dtype=np.float64)
+    sp = np.asarray(spacing, dtype=np.float64)
+    upper = org + (np.asarray(m) - 1) * sp
+    q = np.minimum(np.maximum(pts, org), upper)
+    t = (q - org) / sp
+    idx = np.minimum(np.floor(t).astype(np.int64), np.asarray(m) - 2)
+    idx = np.maximum(idx, 0)
+    f = t - idx
+    strides = [1]
+    for a in range(1, dim):
+        strides.append(strides[-1] * m[a - 1])
+    div = np.zeros(npnt)
+    for a in range(dim):
+        acc = np.zeros(npnt)
+        for corner in range(2 ** dim):
+            g = np.ones(npnt)
+            node = np.zeros(npnt, dtype=np.int64)
+            for b in range(dim):
+                bit = (corner >> b) & 1
+                if b != a:
+                    g = g * (f[:, b] if bit else (1.0 - f[:, b]))
+                node = node + (idx[:, b] + bit) * strides[b]
+            term = g * u[a][node]
+            acc = acc + (term if (corner >> a) & 1 else -term)
+        div = div + acc / sp[a]
+    return div
+
+
+def phi_at(points, mesh):
+    """phi of the cell holding each point (the rule of ``speed``)."""
     phi = np.asarray(mesh["phi"], dtype=np.float64)
     if phi_is_constant(phi):
-        return u / phi[0]
+        return np.full(np.asarray(points).shape[0], phi[0])
     if is_simplex(mesh):
         # the cell of the point clamped into the domain box (a cardinal
         # point of a boundary ball starts outside it)
@@ -347,7 +389,21 @@ def speed(points, mesh, vel):
         cid = locate_points(np.minimum(np.maximum(points, lo), hi), mesh)
     else:
         cid = cell_of_point(points, mesh["n"], mesh["origin"], mesh["h"])
-    return u / phi[cid][:, None]
+    return phi[cid]
+
+
+def speed(points, mesh, vel):
+    """v(x) = u^{(n+1)}(x) / phi(x), the right-hand side of eq. charac."""
+    u = q1_interpolate(points, vel["m"], vel["origin"], vel["spacing"], vel["u"])
+    return u / phi_at(points, mesh)[:, None]
+
+
+def dilation(points, mesh, vel):
+    """delta(x) = div u(x) / phi(x): the rate at which the flow of u/phi
+    dilates volume inside a cell of constant porosity (div of the Q1
+    interpolant, ``q1_divergence``)."""
+    d = q1_divergence(points, vel["m"], vel["origin"], vel["spacing"], vel["u"])
+    return d / phi_at(points, mesh)
 
 
 def phi_is_constant(phi):
@@ -384,17 +440,56 @@ def trace_points(points, mesh, vel, dt, substeps=1):
     return X
 
 
-def tracked_radius(centres, radii, traced_centres, mesh, vel, dt, substeps=1):
+def log_growth(points, mesh, vel, dt, substeps=1):
+    """Lambda = log(|B_hat|_phi / |B|_phi) of a ball tracked from each point.
+
+    The generalised Liouville formula (eq. genLiouville) says that the
+    porous volume W(t) of a region carried by the flow changes at the rate
+    of the integral of div u over it.  With that integral replaced by
+    delta(X(t)) W(t), delta = div u / phi at the tracked centre X(t) (exact
+    where div u / phi is constant over the ball), W(t^n) = W(t^{n+1})
+    exp(-int delta(X(t)) dt): the analogue of eq. expPhiB for a
+    non-solenoidal u.  The integral is taken by the same RK4 steps as the
+    centre (``trace_points``): the stage points are the centre's, and each
+    sub-interval adds -(tau/6) (d1 + 2 d2 + 2 d3 + d4), left to right.
+    Returns (traced centres, Lambda).
+    """
+    X = np.array(points, dtype=np.float64, copy=True)
+    lo, hi = domain_box(mesh)
+    tau = float(dt) / int(substeps)
+    lam = np.zeros(X.shape[0])
+    for _ in range(int(substeps)):
+        k1 = speed(X, mesh, vel)
+        d1 = dilation(X, mesh, vel)
+        Y = X - 0.5 * tau * k1
+        k2 = speed(Y, mesh, vel)
+        d2 = dilation(Y, mesh, vel)
+        Y = X - 0.5 * tau * k2
+        k3 = speed(Y, mesh, vel)
+        d3 = dilation(Y, mesh, vel)
+        Y = X - tau * k3
+        k4 = speed(Y, mesh, vel)
+        d4 = dilation(Y, mesh, vel)
+        X = X - (tau / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        X = np.minimum(np.maximum(X, lo), hi)
+        lam = lam - (tau / 6.0) * (d1 + 2.0 * d2 + 2.0 * d3 + d4)
+    return X, lam
+
+
+def tracked_radius(centres, radii, traced_centres, mesh, vel, dt, substeps=1,
+                   solenoidal=True):
     """Radius r_hat of every tracked ball.
 
-    phi constant in the domain: r_hat = r exactly (eq. ball_volChange).
-    Otherwise the 2d cardinal points C +- r e_a are tracked like the centre
-    and r_hat is the mean of their distances to the tracked centre
-    (eq. rTrackedBall; the paper writes the 2D case with 4 points, the 3D
-    analogue uses the 6 points on the coordinate axes).
+    phi constant in the domain and u solenoidal: r_hat = r exactly
+    (eq. ball_volChange).  Otherwise (non-constant phi, or a non-solenoidal
+    u, Sec. 3.2, Remark on non-solenoidal fields) the 2d cardinal points
+    C +- r e_a are tracked like the centre and r_hat is the mean of their
+    distances to the tracked centre (eq. rTrackedBall; the paper writes the
+    2D case with 4 points, the 3D analogue uses the 6 points on the
+    coordinate axes).
     """
     phi = np.asarray(mesh["phi"])
-    if phi_is_constant(phi):
+    if solenoidal and phi_is_constant(phi):
         return np.array(radii, dtype=np.float64, copy=True)
     C = np.asarray(centres, dtype=np.float64)
     dim = C.shape[1]

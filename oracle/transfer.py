@@ -63,17 +63,50 @@ def csr_rows(row_ptr):
 # Sec. 3.1: initial approximation V
 # --------------------------------------------------------------------------
 
+def tracked_ball_mass(ball_cell, radii, rho, phi, dim, lam=None):
+    """rho_K phi_hat_{K,s} |B_hat_{K,s}| of every tracked ball.
+
+    Solenoidal u: rho_K phi_K |B_{K,s}| (eq. expPhiB).  Otherwise that
+    times exp(Lambda_{K,s}), Lambda from ``geometry.log_growth`` (the
+    analogue of eq. expPhiB, Sec. 3.2, Remark on non-solenoidal fields),
+    the product taken in that order.
+    """
+    ball_cell = np.asarray(ball_cell, dtype=np.int64)
+    m = rho[ball_cell] * phi[ball_cell] * geo.ball_measure(radii, dim)
+    if lam is not None:
+        m = m * np.exp(np.asarray(lam, dtype=np.float64))
+    return m
+
+
+def row_targets(nc, ball_cell, ball_mass, b):
+    """Row targets of a non-solenoidal step: |F_{-dt}(K)|_phi.
+
+    eq. volTracked gives T_K = sum_s rho_K phi_hat_{K,s} |B_hat_{K,s}| (the
+    balls of K in order).  The trace-back regions of all cells cover the
+    domain once, so the exact targets sum to sum_M |M|_phi, the column
+    targets' sum; T is rescaled by that sum over sum_K T_K (both correctly
+    rounded) so that the constraints of eq. opti_masscons stay consistent:
+    b_loc[K] = T_K * (sum b / sum T).
+    """
+    T = np.zeros(nc)
+    for a in range(ball_mass.size):
+        T[ball_cell[a]] = T[ball_cell[a]] + ball_mass[a]
+    scale = math.fsum(np.asarray(b).tolist()) / math.fsum(T.tolist())
+    return T * scale, T, scale
+
+
 def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
-                    traced, r_hat, ia, ib, precision="fp64"):
+                    traced, r_hat, ia, ib, precision="fp64", lam=None):
     """V_{K_hat, M} of eq. ball_int, as CSR.
 
     For a candidate pair (tracked ball a of cell K, residing ball b of cell
     M) the weight is omega = rho_M phi_M |B_hat_a cap B_b| (Remark
     porousBallInt).  S_a = sum of omega over the pairs of a is the
     denominator of eq. fracMaterial.  The tracked ball carries the porous
-    mass rho_K phi_hat |B_hat| = rho_K phi_K |B_a| (eq. expPhiB), and that
-    mass is split over the residing balls in the ratios omega / S_a;
-    V_{K,M} sums those shares over the balls of K and of M.
+    mass rho_K phi_hat |B_hat| (``tracked_ball_mass``: rho_K phi_K |B_a|
+    for a solenoidal u, eq. expPhiB), and that mass is split over the
+    residing balls in the ratios omega / S_a; V_{K,M} sums those shares
+    over the balls of K and of M.
 
     ``precision="fp32"`` (FP32-volume mode) rounds centres and radii to
     binary32 before the distance and the lens, which are then evaluated in
@@ -100,7 +133,7 @@ def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
     void = np.nonzero(S <= 0.0)[0]
     if void.size:
         raise VoidRowError(int(void[0]), int(ball_cell[void[0]]))
-    mass = rho[ball_cell] * phi[ball_cell] * geo.ball_measure(radii, dim)
+    mass = tracked_ball_mass(ball_cell, radii, rho, phi, dim, lam)
     share = mass[ia] * omega / S[ia]
     return csr_from_coo(nc, ca, cb, share)
 
@@ -161,7 +194,8 @@ def mass(phi, cell_vol, c):
 
 def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
                    precision="fp64", box_policy="paper_then_relax", stop_after="all",
-                   traced_override=None, balls_override=None, qp_tol=1e-14):
+                   traced_override=None, balls_override=None, qp_tol=1e-14,
+                   solenoidal=True):
     """Transfer matrix of one time step: Algorithm 1 of Sec. 3.3.
 
     ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) or ``kind =
@@ -170,6 +204,13 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     ``traced_override`` replaces the tracked centres and ``balls_override``
     = (centres, radii) the residing balls of the layout (to compare the
     later stages on identical geometry); rho_K follows the given radii.
+
+    ``solenoidal=False`` (Sec. 3.2, Remark on non-solenoidal fields): r_hat
+    from the cardinal points whatever phi (eq. rTrackedBall), the tracked
+    ball masses from ``geometry.log_growth`` (``tracked_ball_mass``), and
+    the row targets from eq. volTracked (``row_targets``) instead of
+    |K|_phi; the column targets stay |M|_phi and the update still divides
+    by |K|_phi (eq. phys-inter-ELLAM).
     """
     dim = geo.mesh_dim(mesh)
     nc = geo.mesh_n_cells(mesh)
@@ -200,27 +241,38 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     b = phi * kvol                      # |K|_phi = b_loc = b_glob (eq. exactVol_traceback)
     out = {"centres": centres, "radii": radii, "ball_cell": bcell, "rho": rho, "b": b,
            "cell_vol": kvol}
-    if traced_override is None:
-        traced = geo.trace_points(centres, mesh, vel, dt, substeps)
+    lam = None
+    if solenoidal:
+        if traced_override is None:
+            traced = geo.trace_points(centres, mesh, vel, dt, substeps)
+        else:
+            traced = np.asarray(traced_override, dtype=np.float64)
+        b_loc = b
     else:
-        traced = np.asarray(traced_override, dtype=np.float64)
-    r_hat = geo.tracked_radius(centres, radii, traced, mesh, vel, dt, substeps)
+        if traced_override is not None:
+            raise ValueError("a non-solenoidal step tracks its own centres")
+        traced, lam = geo.log_growth(centres, mesh, vel, dt, substeps)
+        bm = tracked_ball_mass(bcell, radii, rho, phi, dim, lam)
+        b_loc, out["T"], out["target_scale"] = row_targets(nc, bcell, bm, b)
+    out["lam"], out["b_loc"] = lam, b_loc
+    r_hat = geo.tracked_radius(centres, radii, traced, mesh, vel, dt, substeps,
+                               solenoidal=solenoidal)
     out["traced"], out["r_hat"] = traced, r_hat
     ia, ib = geo.candidate_pairs(traced, r_hat, centres, radii, precision=precision)
     out["pairs"] = (ia, ib)
     if stop_after == "pairs":
         return out
     rp, cl, V = initial_volumes(nc, dim, bcell, centres, radii, rho, phi, traced, r_hat,
-                                ia, ib, precision=precision)
+                                ia, ib, precision=precision, lam=lam)
     out["row_ptr"], out["col"], out["V"] = rp, cl, V
     if stop_after == "v":
         return out
     check_columns(cl, V, nc)
-    AN = scaling_sweeps(rp, cl, V, b, b, n_sweeps)
+    AN = scaling_sweeps(rp, cl, V, b_loc, b, n_sweeps)
     out["AN"] = AN
     if stop_after == "sinkhorn":
         return out
-    res = solve_mass_qp(csr_rows(rp), cl, AN, b, b, box_policy=box_policy, tol=qp_tol)
+    res = solve_mass_qp(csr_rows(rp), cl, AN, b_loc, b, box_policy=box_policy, tol=qp_tol)
     out["qp"] = res
     out["A"] = AN * (1.0 + res["x"])
     return out

@@ -194,6 +194,23 @@ def deformation_2d(p, t=0.0, period=1.0, amplitude=1.0):
                          -np.sin(math.pi * y) ** 2 * np.sin(2 * math.pi * x)], axis=1)
 
 
+def sine_compression(amp):
+    """Non-solenoidal field u_a = amp_a sin(pi x_a), one axis at a time:
+    tangential on the unit box boundary, div u = pi sum_a amp_a cos(pi x_a)
+    (compression where it is negative, expansion where positive)."""
+    amp = tuple(float(v) for v in amp)
+
+    def f(p, t=0.0):
+        return np.stack([amp[a] * np.sin(math.pi * p[:, a]) for a in range(len(amp))], axis=1)
+    return f
+
+
+def compressible_swirl_3d(p, t=0.0, squeeze=0.3):
+    """The 3D swirl plus a sine compression of amplitude ``squeeze`` on
+    every axis (non-solenoidal, tangential on the unit cube boundary)."""
+    return swirl_3d(p, t) + sine_compression((squeeze,) * 3)(p, t)
+
+
 def constant_field(vec):
     vec = np.asarray(vec, dtype=np.float64)
 
