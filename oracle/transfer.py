@@ -13,6 +13,8 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
 
 from . import geometry as geo
 from .qp import solve_mass_qp
@@ -78,21 +80,35 @@ def tracked_ball_mass(ball_cell, radii, rho, phi, dim, lam=None):
     return m
 
 
-def row_targets(nc, ball_cell, ball_mass, b):
+def row_targets(nc, ball_cell, ball_mass, b, rows, cols):
     """Row targets of a non-solenoidal step: |F_{-dt}(K)|_phi.
 
     eq. volTracked gives T_K = sum_s rho_K phi_hat_{K,s} |B_hat_{K,s}| (the
     balls of K in order).  The trace-back regions of all cells cover the
-    domain once, so the exact targets sum to sum_M |M|_phi, the column
-    targets' sum; T is rescaled by that sum over sum_K T_K (both correctly
-    rounded) so that the constraints of eq. opti_masscons stay consistent:
-    b_loc[K] = T_K * (sum b / sum T).
+    domain once, so the exact targets of any set of tracked cells that
+    takes its material from a set of residing cells alone total the
+    porous volume of those residing cells.  The sets are the connected
+    components of the bipartite graph of V's pattern (row K -- column M
+    for every entry); within a component T is rescaled by
+    sum_{M in it} |M|_phi / sum_{K in it} T_K (both correctly rounded):
+    b_loc[K] = T_K * scale(component of K).  Without that the constraints
+    of eq. opti_masscons would be inconsistent on every component.
+    Returns (b_loc, T, scale of the whole domain, number of components).
     """
     T = np.zeros(nc)
     for a in range(ball_mass.size):
         T[ball_cell[a]] = T[ball_cell[a]] + ball_mass[a]
+    g = sp.coo_matrix((np.ones(len(rows)), (np.asarray(rows), nc + np.asarray(cols))),
+                      shape=(2 * nc, 2 * nc))
+    ncomp, lab = connected_components(g, directed=False)
+    b_loc = np.empty(nc)
+    for c in range(ncomp):
+        R = np.nonzero(lab[:nc] == c)[0]
+        Cc = np.nonzero(lab[nc:] == c)[0]
+        sc = math.fsum(np.asarray(b)[Cc].tolist()) / math.fsum(T[R].tolist())
+        b_loc[R] = T[R] * sc
     scale = math.fsum(np.asarray(b).tolist()) / math.fsum(T.tolist())
-    return T * scale, T, scale
+    return b_loc, T, scale, ncomp
 
 
 def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
@@ -247,14 +263,11 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
             traced = geo.trace_points(centres, mesh, vel, dt, substeps)
         else:
             traced = np.asarray(traced_override, dtype=np.float64)
-        b_loc = b
     else:
         if traced_override is not None:
             raise ValueError("a non-solenoidal step tracks its own centres")
         traced, lam = geo.log_growth(centres, mesh, vel, dt, substeps)
-        bm = tracked_ball_mass(bcell, radii, rho, phi, dim, lam)
-        b_loc, out["T"], out["target_scale"] = row_targets(nc, bcell, bm, b)
-    out["lam"], out["b_loc"] = lam, b_loc
+    out["lam"] = lam
     r_hat = geo.tracked_radius(centres, radii, traced, mesh, vel, dt, substeps,
                                solenoidal=solenoidal)
     out["traced"], out["r_hat"] = traced, r_hat
@@ -265,6 +278,13 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     rp, cl, V = initial_volumes(nc, dim, bcell, centres, radii, rho, phi, traced, r_hat,
                                 ia, ib, precision=precision, lam=lam)
     out["row_ptr"], out["col"], out["V"] = rp, cl, V
+    if solenoidal:
+        b_loc = b
+    else:
+        bm = tracked_ball_mass(bcell, radii, rho, phi, dim, lam)
+        b_loc, out["T"], out["target_scale"], out["n_groups"] = \
+            row_targets(nc, bcell, bm, b, csr_rows(rp), cl)
+    out["b_loc"] = b_loc
     if stop_after == "v":
         return out
     check_columns(cl, V, nc)

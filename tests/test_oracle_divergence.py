@@ -254,3 +254,35 @@ def test_liouville_growth_agrees_with_tracked_radius(dim):
     assert inner.sum() > 10
     assert np.max(np.abs(geom[inner] / liou[inner] - 1.0)) < 1e-7
     assert np.allclose(out["lam"], -delta * dt, rtol=1e-13, atol=0)
+
+
+def test_row_targets_rescale_each_component():
+    """Hand-worked: rows {0, 1} reach columns {0, 1} only and row 2 column 2
+    only; each component's targets total its columns' porous volumes."""
+    ball_cell = np.array([0, 0, 1, 2])
+    ball_mass = np.array([0.25, 0.75, 2.0, 3.0])       # T = (1, 2, 3)
+    b = np.array([1.0, 2.0, 2.5])
+    rows = np.array([0, 0, 1, 2])
+    cols = np.array([0, 1, 1, 2])
+    b_loc, T, scale, ncomp = otr.row_targets(3, ball_cell, ball_mass, b, rows, cols)
+    assert ncomp == 2
+    assert np.array_equal(T, [1.0, 2.0, 3.0])
+    assert np.array_equal(b_loc, [1.0, 2.0, 2.5])
+    assert scale == 5.5 / 6.0
+
+
+def test_disconnected_pattern_stays_consistent():
+    """Small random balls leave cells whose tracked balls reach only their
+    own residing balls (many components of V's pattern): each component's
+    targets total its columns' porous volumes, and the least-change problem
+    is solved (a single global factor would leave it inconsistent)."""
+    w = inputs.swirl_hex(8)
+    mesh = inputs.random_subcell_balls(w["mesh"], 5)
+    vel = inputs.sample_velocity(w["mesh"], inputs.compressible_swirl_3d)
+    out = otr.build_transfer(mesh, vel, 0.03, layout="custom", solenoidal=False)
+    assert out["n_groups"] > 10
+    rows = otr.csr_rows(out["row_ptr"])
+    rs = np.bincount(rows, weights=out["A"], minlength=out["b"].size)
+    cs = np.bincount(out["col"], weights=out["A"], minlength=out["b"].size)
+    assert np.max(np.abs(rs - out["b_loc"])) <= 1e-13 * out["b"].max()
+    assert np.max(np.abs(cs - out["b"])) <= 1e-13 * out["b"].max()
