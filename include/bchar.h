@@ -96,6 +96,30 @@ enum { BCHAR_STAGE_PAIRS = 1, BCHAR_STAGE_V = 2, BCHAR_STAGE_SCALING = 3, BCHAR_
 
 enum { BCHAR_MEM_HOST = 0, BCHAR_MEM_DEVICE = 1 };
 
+/* The velocity field (Sec. 3.2, Remark on non-solenoidal fields).  FREE:
+ * div u = 0 is assumed, so the porous volume of a tracked ball is that of
+ * the ball (eq. expPhiB) and the row targets are |K|_phi (eq.
+ * exactVol_traceback).  GENERAL: any u.  The generalised Liouville formula
+ * (eq. genLiouville), with div u over a carried ball taken as its value at
+ * the ball's centre times the ball's volume, makes the porous volume of
+ * the ball B_{K,s} tracked back over dt equal to phi_K |B_{K,s}| exp(lam),
+ * lam = -int (div u / phi)(X(t)) dt along the tracked centre X, div u that
+ * of the Q1 interpolant, integrated by the centre's own RK4 stages
+ * (exact where div u / phi is constant).  That mass, times rho_K, is the
+ * ball's mass in eq. ball_int; r_hat comes from the tracked cardinal
+ * points (eq. rTrackedBall) whatever phi; the row targets are eq.
+ * volTracked's T_K = sum_s rho_K phi_K |B_{K,s}| exp(lam_{K,s}), rescaled
+ * on every connected component of the bipartite graph of V's pattern
+ * (row K -- column M per entry) by sum_{M in it} |M|_phi /
+ * sum_{K in it} T_K: the trace-back regions cover the domain once, so the
+ * two sides of eq. opti_masscons must total the same on each set of cells
+ * that exchange material only among themselves (usually one component,
+ * the whole domain).  The column targets stay |M|_phi and the update
+ * still divides by |K|_phi (eq. phys-inter-ELLAM), so a compressing flow
+ * concentrates c.  Tracking runs in binary64 (FP32_VOLUME is
+ * UNSUPPORTED).                                                          */
+enum { BCHAR_DIV_FREE = 0, BCHAR_DIV_GENERAL = 1 };
+
 typedef struct bchar_mesh_s* bchar_mesh;
 typedef struct bchar_transfer_s* bchar_transfer;
 
@@ -212,6 +236,7 @@ typedef struct {
                             launch fewer where launches cost, wider gathers
                             than they save beyond); the same answer either
                             way up to the solver's tolerance             */
+  int divergence;        /* BCHAR_DIV_FREE (default) or BCHAR_DIV_GENERAL  */
 } bchar_opts;
 
 typedef struct {
@@ -245,6 +270,13 @@ typedef struct {
                                   or BCHAR_FP32_VOLUME                    */
   int64_t device_bytes;        /* device memory the transfer holds after
                                   the build (kept for the next rebuild)   */
+  double row_target_scale;     /* DIV_GENERAL: sum_M |M|_phi / sum_K T_K
+                                  over the whole domain (the factor on
+                                  eq. volTracked's T_K when V's pattern is
+                                  connected); 1 for DIV_FREE             */
+  int64_t n_target_groups;     /* DIV_GENERAL: connected components of V's
+                                  pattern, each rescaled on its own; 0 for
+                                  DIV_FREE                                */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */
@@ -451,6 +483,12 @@ bchar_status bchar_transfer_export_pairs(bchar_transfer t, int32_t* tracked, int
 
 /* Tracked centres (dim arrays of n_balls, x then y then z) and radii.   */
 bchar_status bchar_transfer_export_tracked(bchar_transfer t, double* tracked, double* r_hat);
+
+/* Per-ball log growth lam (n_balls) and row targets (n_rows) of the last
+ * build (host arrays, either may be NULL): DIV_GENERAL's values (see
+ * BCHAR_DIV_GENERAL), or 0 and |K|_phi for DIV_FREE.  Synchronises the
+ * device.                                                               */
+bchar_status bchar_transfer_export_targets(bchar_transfer t, double* lam, double* b_row);
 
 /* Solution of eq. opti_masscons: x (nnz) and the multipliers of the row
  * and column constraints (n_rows each, in units of 1 / max |K|_phi).    */

@@ -34,6 +34,7 @@ BOX_PAPER_THEN_RELAX, BOX_STRICT = 0, 1
 STAGE_PAIRS, STAGE_V, STAGE_SCALING, STAGE_ALL = 1, 2, 3, 4
 MEM_HOST, MEM_DEVICE = 0, 1
 MESH_CARTESIAN, MESH_SIMPLEX = 0, 1
+DIV_FREE, DIV_GENERAL = 0, 1
 
 LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
            "equal_measure": LAYOUT_EQUAL_MEASURE, "custom": LAYOUT_CUSTOM}
@@ -59,7 +60,8 @@ class Opts(C.Structure):
                 ("qp_max_newton", C.c_int), ("qp_max_cg", C.c_int), ("keep_pairs", C.c_int),
                 ("warm_start", C.c_int), ("max_halvings", C.c_int),
                 ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int),
-                ("halve_on_level2", C.c_int), ("z_fuse_max_cells", C.c_int)]
+                ("halve_on_level2", C.c_int), ("z_fuse_max_cells", C.c_int),
+                ("divergence", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -70,7 +72,8 @@ class Stats(C.Structure):
                 ("qp_ipm", C.c_int), ("qp_coarse_bytes", C.c_int64),
                 ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int),
                 ("n_void_rows", C.c_int64), ("n_void_cols", C.c_int64),
-                ("trace_precision", C.c_int), ("device_bytes", C.c_int64)]
+                ("trace_precision", C.c_int), ("device_bytes", C.c_int64),
+                ("row_target_scale", C.c_double), ("n_target_groups", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +111,7 @@ _transfer_info = _sig("bchar_transfer_info", [_P, _i64p, _i64p, _i64p, _ip])
 _export_csr = _sig("bchar_transfer_export_csr", [_P, C.c_int, _P, _P, _P])
 _export_pairs = _sig("bchar_transfer_export_pairs", [_P, _P, _P])
 _export_tracked = _sig("bchar_transfer_export_tracked", [_P, _P, _P])
+_export_targets = _sig("bchar_transfer_export_targets", [_P, _P, _P])
 _export_qp = _sig("bchar_transfer_export_qp", [_P, _P, _P, _P])
 _export_balls = _sig("bchar_mesh_export_balls", [_P, _P, _P, _P])
 _export_qp_dual = _sig("bchar_transfer_export_qp_dual", [_P, _P, _P, _P, _P])
@@ -157,7 +161,7 @@ EXPORTED = [
     "bchar_profile_read",
     "bchar_build_transfer_batch", "bchar_profile_kernel_sampled",
     "bchar_server_create", "bchar_server_submit", "bchar_server_wait", "bchar_server_destroy",
-    "bchar_tune_options",
+    "bchar_tune_options", "bchar_transfer_export_targets",
 ]
 
 
@@ -411,6 +415,13 @@ class Transfer:
         r = np.empty(nb)
         _check(_export_tracked(self.handle, t.ctypes.data_as(_P), r.ctypes.data_as(_P)))
         return t.reshape(dim, nb).T.copy(), r
+
+    def export_targets(self):
+        """Per-ball log growth and per-cell row targets of the last build."""
+        lam = np.empty(self.mesh.n_balls)
+        b = np.empty(self.mesh.n_cells)
+        _check(_export_targets(self.handle, lam.ctypes.data_as(_P), b.ctypes.data_as(_P)))
+        return lam, b
 
     def export_qp(self):
         nr, nnz, _, _ = self.info()

@@ -355,6 +355,8 @@ void validate_opts(const bchar_opts& o) {
   BCHAR_REQUIRE(o.max_halvings >= 0 && o.max_halvings <= 20, BCHAR_E_INVALID_ARG,
                 "opts.max_halvings");
   BCHAR_REQUIRE(o.z_fuse_max_cells >= 0, BCHAR_E_INVALID_ARG, "opts.z_fuse_max_cells");
+  BCHAR_REQUIRE(o.divergence == BCHAR_DIV_FREE || o.divergence == BCHAR_DIV_GENERAL,
+                BCHAR_E_INVALID_ARG, "opts.divergence");
 }
 
 void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
@@ -386,9 +388,11 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   st.n_balls = m->n_balls;
   st.first_void = -1;
   st.trace_precision = trace_precision;
+  st.row_target_scale = 1.0;
   t->stage = 0;
   int64_t first_void = -1;
-  bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(), o.precision,
+  bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(),
+                               t->general ? t->lam.as<double>() : nullptr, o.precision,
                                o.keep_pairs != 0, o.lds_stage != 0, t, &first_void, s);
   st.nnz = t->nnz;
   st.n_pairs = t->n_pairs;
@@ -415,14 +419,27 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
     return BCHAR_OK;
   }
   const int64_t n = m->n_cells, nnz = t->nnz;
+  t->groups = 0;
+  if (t->general) {
+    const TargetInfo ti = row_targets(m, t, t->lam.as<double>(), t->b_row.as<double>(), ws, s);
+    st.row_target_scale = ti.scale;
+    st.n_target_groups = ti.groups;
+    t->groups = ti.groups;
+    if (tr)
+      fprintf(stderr, "[bchar] row targets: scale %.17g, %lld groups, %d rounds\n", ti.scale,
+              (long long)ti.groups, ti.rounds);
+  }
   Csc csc{};
   build_csc(t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), n, nnz, csc, ws, s);
   t->AN.reserve(sizeof(double) * (nnz + 1));
   int64_t void_col = -1, n_void_cols = 0;
   double col_err = 0;
+  // row targets: |K|_phi (eq. exactVol_traceback), or eq. volTracked's for
+  // a non-solenoidal u
+  const double* b_row = t->general ? t->b_row.as<double>() : m->b.as<double>();
   rc = scaling_sweeps(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->V.as<double>(),
-                      nnz, o.n_sweeps, t->AN.as<double>(), &void_col, &n_void_cols, &col_err, ws,
-                      s);
+                      b_row, nnz, o.n_sweeps, t->AN.as<double>(), &void_col, &n_void_cols,
+                      &col_err, ws, s);
   st.scaling_max_col_err = col_err;
   st.n_void_cols = n_void_cols;
   if (rc != BCHAR_OK) {
@@ -453,9 +470,11 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
     t->warm_level = -1;
   }
   QpResult qr;
-  rc = solve_qp(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->AN.as<double>(), nnz,
-                o, t->x.as<double>(), t->mu.as<double>(), t->nu.as<double>(), t->A.as<double>(),
-                t->zdual.as<double>(), t->warm_level, qr, ws, s);
+  Groups grp{t->grp_lab.as<int32_t>(), t->grp_ptr.as<int32_t>(), t->grp_perm.as<int32_t>()};
+  rc = solve_qp(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->AN.as<double>(),
+                b_row, t->groups > 1 ? &grp : nullptr, nnz, o, t->x.as<double>(),
+                t->mu.as<double>(), t->nu.as<double>(), t->A.as<double>(), t->zdual.as<double>(),
+                t->warm_level, qr, ws, s);
   t->warm_level = rc == BCHAR_OK ? qr.level : -1;
   if (tr)
     fprintf(stderr, "[bchar] qp: %.3f ms (level %d, ipm %d, newton %d, cg %d, residual %.3e)\n",
@@ -488,12 +507,21 @@ bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_veloci
   BCHAR_REQUIRE(o.precision != BCHAR_FP32_VOLUME || m->phi_const, BCHAR_E_UNSUPPORTED,
                 "FP32_VOLUME tracks in binary32 and needs a constant porosity; FP32_LENS "
                 "tracks in binary64");
+  BCHAR_REQUIRE(o.precision != BCHAR_FP32_VOLUME || o.divergence == BCHAR_DIV_FREE,
+                BCHAR_E_UNSUPPORTED,
+                "FP32_VOLUME tracks in binary32 and needs a solenoidal u; FP32_LENS tracks in "
+                "binary64");
   t->ws.reset();
   t->tracked.reserve(sizeof(double) * m->dim * m->n_balls);
   t->r_hat.reserve(sizeof(double) * m->n_balls);
+  t->general = o.divergence == BCHAR_DIV_GENERAL;
+  if (t->general) {
+    t->lam.reserve(sizeof(double) * m->n_balls);
+    t->b_row.reserve(sizeof(double) * m->n_cells);
+  }
   const double t0 = trace_enabled() ? wall_seconds() : 0.0;
   trace_balls(m, *u, dt, o.rk_substeps, o.precision, t->tracked.as<double>(),
-              t->r_hat.as<double>(), t->ws, s);
+              t->r_hat.as<double>(), t->general ? t->lam.as<double>() : nullptr, t->ws, s);
   if (trace_enabled()) {
     BCHAR_HIP(hipStreamSynchronize(s));
     fprintf(stderr, "[bchar] trace: %.3f ms\n", 1e3 * (wall_seconds() - t0));
@@ -505,9 +533,11 @@ bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_veloci
 
 // device memory a transfer holds (its buffers and scratch chunks)
 int64_t transfer_device_bytes(const bchar_transfer_s* t) {
-  const bchar::DBuf* bufs[] = {&t->row_ptr, &t->col,   &t->V,      &t->AN,        &t->A,
-                               &t->x,       &t->mu,    &t->nu,     &t->zdual,     &t->tracked,
-                               &t->r_hat,   &t->pair_a, &t->pair_b, &t->stage_col, &t->stage_val,
+  const bchar::DBuf* bufs[] = {&t->row_ptr,   &t->col,       &t->V,        &t->AN,
+                               &t->A,         &t->x,         &t->mu,       &t->nu,
+                               &t->zdual,     &t->tracked,   &t->r_hat,    &t->lam,
+                               &t->b_row,     &t->grp_lab,   &t->grp_ptr,  &t->grp_perm,
+                               &t->pair_a,    &t->pair_b,    &t->stage_col, &t->stage_val,
                                &t->cscratch};
   int64_t n = 0;
   for (const auto* b : bufs) n += (int64_t)b->bytes;
@@ -702,6 +732,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->cg_graphs = 1;
   o->lds_stage = 0;
   o->z_fuse_max_cells = 1 << 20;
+  o->divergence = BCHAR_DIV_FREE;
 }
 
 const char* bchar_status_string(bchar_status s) {
@@ -1004,6 +1035,8 @@ bchar_status bchar_build_transfer_tracked(bchar_mesh m, const double* tracked,
     bchar_opts o;
     opts_or_default(opts, o);
     validate_opts(o);
+    BCHAR_REQUIRE(o.divergence == BCHAR_DIV_FREE, BCHAR_E_UNSUPPORTED,
+                  "a non-solenoidal build tracks its own balls (their growth is not given)");
     hipStream_t s = as_stream(stream);
     auto* t = new bchar_transfer_s();
     t->mesh = m;
@@ -1283,6 +1316,24 @@ bchar_status bchar_transfer_export_tracked(bchar_transfer t, double* tracked, do
                           hipMemcpyDeviceToHost));
     if (r_hat)
       BCHAR_HIP(hipMemcpy(r_hat, t->r_hat.p, sizeof(double) * m->n_balls,
+                          hipMemcpyDeviceToHost));
+    return BCHAR_OK;
+  });
+}
+
+bchar_status bchar_transfer_export_targets(bchar_transfer t, double* lam, double* b_row) {
+  return guarded([&]() -> bchar_status {
+    BCHAR_REQUIRE(t != nullptr, BCHAR_E_INVALID_ARG, "transfer is NULL");
+    const bchar_mesh_s* m = t->mesh;
+    BCHAR_HIP(hipDeviceSynchronize());
+    if (lam) {
+      if (t->general)
+        BCHAR_HIP(hipMemcpy(lam, t->lam.p, sizeof(double) * m->n_balls, hipMemcpyDeviceToHost));
+      else
+        for (int64_t i = 0; i < m->n_balls; ++i) lam[i] = 0.0;
+    }
+    if (b_row)
+      BCHAR_HIP(hipMemcpy(b_row, t->general ? t->b_row.p : m->b.p, sizeof(double) * m->n_cells,
                           hipMemcpyDeviceToHost));
     return BCHAR_OK;
   });

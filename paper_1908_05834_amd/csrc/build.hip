@@ -26,6 +26,9 @@
 //          the row lengths and a copy kernel then lay the rows out as CSR.
 //          No floating-point atomics: the values do not depend on
 //          scheduling (only the staging positions do).
+#include <cmath>
+#include <type_traits>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -151,18 +154,13 @@ __device__ int64_t locate(const PhiView<T>& P, const double x[3]) {
   return best < 0 ? 0 : best;
 }
 
-// Multilinear interpolation, written as the sum over the 2^d lattice
-// corners of (product of the per-axis weights f or 1 - f) times the nodal
-// value, corners in binary order, axes in order.  The query is clamped into
-// the lattice box, t = (q - origin) / spacing, the lattice cell is
-// floor(t) clamped to [0, m - 2].  Every operation is rounded on its own (no
-// contraction), so that binary64 tracking is reproducible operation by
-// operation.
+// Lattice cell and local coordinates of a query: the query is clamped
+// into the lattice box, t = (q - origin) / spacing, the lattice cell is
+// floor(t) clamped to [0, m - 2], f = t - cell.
 template <int DIM, class T>
-__device__ __forceinline__ void q1(const VelocityView<T>& V, const T x[3], T out[3]) {
+__device__ __forceinline__ void q1_cell(const VelocityView<T>& V, const T x[3], int64_t idx[3],
+                                        T f[3]) {
 #pragma clang fp contract(off)
-  int64_t idx[3] = {0, 0, 0};
-  T f[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     T q = x[a] < V.org[a] ? V.org[a] : (x[a] > V.upper[a] ? V.upper[a] : x[a]);
@@ -173,6 +171,19 @@ __device__ __forceinline__ void q1(const VelocityView<T>& V, const T x[3], T out
     idx[a] = i;
     f[a] = t - (T)i;
   }
+}
+
+// Multilinear interpolation, written as the sum over the 2^d lattice
+// corners of (product of the per-axis weights f or 1 - f) times the nodal
+// value, corners in binary order, axes in order.  Every operation is
+// rounded on its own (no contraction), so that binary64 tracking is
+// reproducible operation by operation.
+template <int DIM, class T>
+__device__ __forceinline__ void q1(const VelocityView<T>& V, const T x[3], T out[3]) {
+#pragma clang fp contract(off)
+  int64_t idx[3] = {0, 0, 0};
+  T f[3] = {0, 0, 0};
+  q1_cell<DIM, T>(V, x, idx, f);
   const int64_t stride[3] = {1, V.m[0], V.m[0] * V.m[1]};
 #pragma unroll
   for (int c = 0; c < DIM; ++c) out[c] = 0;
@@ -191,61 +202,105 @@ __device__ __forceinline__ void q1(const VelocityView<T>& V, const T x[3], T out
   }
 }
 
-// v = u / phi, phi of the cell containing x (floor((x - origin) / h),
-// clamped), or the common value when phi is constant.
+// div of the Q1 interpolant at x (same lattice cell as q1): per axis a,
+// the corners in binary order add (+ if the corner's bit a is set, else
+// -) the product of the other axes' weights times u_a at the corner, the
+// sum is divided by the spacing of a; the axes' terms are added in order.
 template <int DIM, class T>
-__device__ __forceinline__ void speed(const VelocityView<T>& V, const PhiView<T>& P,
-                                      const T x[3], T v[3]) {
+__device__ __forceinline__ T q1_div(const VelocityView<T>& V, const T x[3]) {
 #pragma clang fp contract(off)
-  q1<DIM, T>(V, x, v);
-  T ph;
-  if (P.constant) {
-    ph = P.phi0;
-  } else if (P.simplex) {
-    // the cell of x clamped into the domain box
+  int64_t idx[3] = {0, 0, 0};
+  T f[3] = {0, 0, 0};
+  q1_cell<DIM, T>(V, x, idx, f);
+  const int64_t stride[3] = {1, V.m[0], V.m[0] * V.m[1]};
+  T div = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    T acc = 0;
+#pragma unroll
+    for (int corner = 0; corner < (1 << DIM); ++corner) {
+      T g = 1;
+      int64_t node = 0;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        const int bit = (corner >> b) & 1;
+        if (b != a) g = g * (bit ? f[b] : (T)1 - f[b]);
+        node += (idx[b] + bit) * stride[b];
+      }
+      const T term = g * V.u[a][node];
+      acc = ((corner >> a) & 1) ? acc + term : acc - term;
+    }
+    div = div + acc / V.sp[a];
+  }
+  return div;
+}
+
+// phi of the cell containing x (floor((x - origin) / h), clamped; on a
+// simplicial mesh the located cell of x clamped into the domain box), or
+// the common value when phi is constant.
+template <int DIM, class T>
+__device__ __forceinline__ T phi_at(const PhiView<T>& P, const T x[3]) {
+#pragma clang fp contract(off)
+  if (P.constant) return P.phi0;
+  if (P.simplex) {
     double q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const double xa = (double)x[a];
       q[a] = xa < P.box_lo[a] ? P.box_lo[a] : (xa > P.box_hi[a] ? P.box_hi[a] : xa);
     }
-    ph = (T)P.phi[locate<DIM, T>(P, q)];
-  } else {
-    int64_t cid = 0, stride = 1;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      int64_t i = (int64_t)floor((x[a] - P.org[a]) / P.h[a]);
-      i = i < 0 ? 0 : (i >= P.n[a] ? P.n[a] - 1 : i);
-      cid += i * stride;
-      stride *= P.n[a];
-    }
-    ph = (T)P.phi[cid];
+    return (T)P.phi[locate<DIM, T>(P, q)];
   }
+  int64_t cid = 0, stride = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    int64_t i = (int64_t)floor((x[a] - P.org[a]) / P.h[a]);
+    i = i < 0 ? 0 : (i >= P.n[a] ? P.n[a] - 1 : i);
+    cid += i * stride;
+    stride *= P.n[a];
+  }
+  return (T)P.phi[cid];
+}
+
+// v = u / phi at x; with GROW also delta = div u / phi, the rate at which
+// the flow of u / phi dilates volume in a cell of constant porosity.
+template <int DIM, class T, bool GROW>
+__device__ __forceinline__ void speed(const VelocityView<T>& V, const PhiView<T>& P,
+                                      const T x[3], T v[3], T* delta) {
+#pragma clang fp contract(off)
+  q1<DIM, T>(V, x, v);
+  const T ph = phi_at<DIM, T>(P, x);
 #pragma unroll
   for (int a = 0; a < DIM; ++a) v[a] = v[a] / ph;
+  if (GROW) *delta = q1_div<DIM, T>(V, x) / ph;
 }
 
 // One classical RK4 step per sub-interval, backward: stage points
 // X - (tau/2) k1, X - (tau/2) k2, X - tau k3, update
 // X - (tau/6) (((k1 + 2 k2) + 2 k3) + k4), then clamp into the box.
-template <int DIM, class T>
+// With GROW the log growth lam of a carried region's porous volume takes
+// the same stages: lam - (tau/6) (((d1 + 2 d2) + 2 d3) + d4) with d the
+// dilation rate at the stage points (Liouville along the path).
+template <int DIM, class T, bool GROW>
 __device__ __forceinline__ void rk4_back(const VelocityView<T>& V, const PhiView<T>& P, T X[3],
-                                         T tau, int substeps, const T lo[3], const T hi[3]) {
+                                         T tau, int substeps, const T lo[3], const T hi[3],
+                                         T* lam) {
 #pragma clang fp contract(off)
   const T htau = (T)0.5 * tau;
   const T tau6 = tau / (T)6;
   for (int st = 0; st < substeps; ++st) {
     T k1[3], k2[3], k3[3], k4[3], y[3];
-    speed<DIM, T>(V, P, X, k1);
+    T d1 = 0, d2 = 0, d3 = 0, d4 = 0;
+    speed<DIM, T, GROW>(V, P, X, k1, &d1);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) y[a] = X[a] - htau * k1[a];
-    speed<DIM, T>(V, P, y, k2);
+    speed<DIM, T, GROW>(V, P, y, k2, &d2);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) y[a] = X[a] - htau * k2[a];
-    speed<DIM, T>(V, P, y, k3);
+    speed<DIM, T, GROW>(V, P, y, k3, &d3);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) y[a] = X[a] - tau * k3[a];
-    speed<DIM, T>(V, P, y, k4);
+    speed<DIM, T, GROW>(V, P, y, k4, &d4);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       T acc = k1[a] + (T)2 * k2[a];
@@ -255,14 +310,30 @@ __device__ __forceinline__ void rk4_back(const VelocityView<T>& V, const PhiView
       xa = xa > lo[a] ? xa : lo[a];
       X[a] = xa < hi[a] ? xa : hi[a];
     }
+    if (GROW) {
+      T acc = d1 + (T)2 * d2;
+      acc = acc + (T)2 * d3;
+      acc = acc + d4;
+      *lam = *lam - tau6 * acc;
+    }
   }
 }
 
-template <int DIM, class T>
-__global__ void k_trace(VelocityView<T> V, PhiView<T> P, const double* __restrict__ cen,
-                        const double* __restrict__ rad, int64_t n_balls, T tau, int substeps,
-                        T lo0, T lo1, T lo2, T hi0, T hi1, T hi2, double* __restrict__ tracked,
-                        double* __restrict__ r_hat) {
+// One thread per ball: the tracked centre (eq. charac), and r_hat: r when
+// phi is constant and u solenoidal (eq. ball_volChange), else the mean
+// distance of the 2d tracked cardinal points C +- r e_a to the tracked
+// centre (eq. rTrackedBall).  GROW (non-solenoidal u) also writes the log
+// growth lam of the ball's porous volume.  128 threads a block: the launch
+// bound lets the binary64 RK4 state stay in registers (the default bound
+// of 1024 threads caps a lane at 128 VGPRs and spills it to scratch).
+template <int DIM, class T, bool GROW>
+__global__ void __launch_bounds__(128) k_trace(VelocityView<T> V, PhiView<T> P,
+                                               const double* __restrict__ cen,
+                                               const double* __restrict__ rad, int64_t n_balls,
+                                               T tau, int substeps, T lo0, T lo1, T lo2, T hi0,
+                                               T hi1, T hi2, double* __restrict__ tracked,
+                                               double* __restrict__ r_hat,
+                                               double* __restrict__ lam_out) {
 #pragma clang fp contract(off)
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_balls) return;
@@ -272,11 +343,13 @@ __global__ void k_trace(VelocityView<T> V, PhiView<T> P, const double* __restric
 #pragma unroll
   for (int a = 0; a < DIM; ++a) C[a] = (T)cen[a * n_balls + b];
   T X[3] = {C[0], C[1], C[2]};
-  rk4_back<DIM, T>(V, P, X, tau, substeps, lo, hi);
+  T lam = 0;
+  rk4_back<DIM, T, GROW>(V, P, X, tau, substeps, lo, hi, &lam);
 #pragma unroll
   for (int a = 0; a < DIM; ++a) tracked[a * n_balls + b] = (double)X[a];
+  if (GROW) lam_out[b] = (double)lam;
   const T r = (T)rad[b];
-  if (P.constant) {
+  if (P.constant && !GROW) {
     r_hat[b] = (double)r;
     return;
   }
@@ -286,7 +359,7 @@ __global__ void k_trace(VelocityView<T> V, PhiView<T> P, const double* __restric
     for (int sg = 0; sg < 2; ++sg) {
       T Y[3] = {C[0], C[1], C[2]};
       Y[a] = sg == 0 ? Y[a] + r : Y[a] - r;
-      rk4_back<DIM, T>(V, P, Y, tau, substeps, lo, hi);
+      rk4_back<DIM, T, false>(V, P, Y, tau, substeps, lo, hi, nullptr);
       T d = Y[0] - X[0];
       T d2 = d * d;
       for (int c = 1; c < DIM; ++c) {
@@ -307,7 +380,7 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
 template <int DIM, class T>
 static void launch_trace(const bchar_mesh_s* m, const bchar_velocity& u, double dt,
                          int substeps, const T* const* comps, double* tracked, double* r_hat,
-                         hipStream_t s) {
+                         double* lam, hipStream_t s) {
   VelocityView<T> V;
   PhiView<T> P;
   for (int a = 0; a < 3; ++a) {
@@ -343,24 +416,36 @@ static void launch_trace(const bchar_mesh_s* m, const bchar_velocity& u, double 
   const T tau = (T)(dt / substeps);
   {
     ::bchar::ProfScope ps_("k_trace", s);
-    k_trace<DIM, T><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(
+    // the growth is tracked in binary64 only
+    if constexpr (std::is_same<T, double>::value) {
+      if (lam) {
+        k_trace<DIM, T, true><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(
+            V, P, m->cen.as<double>(), m->rad.as<double>(), m->n_balls, tau, substeps, lo[0],
+            lo[1], lo[2], hi[0], hi[1], hi[2], tracked, r_hat, lam);
+        BCHAR_HIP(hipGetLastError());
+        return;
+      }
+    }
+    k_trace<DIM, T, false><<<blocks_for(m->n_balls, 128), 128, 0, s>>>(
         V, P, m->cen.as<double>(), m->rad.as<double>(), m->n_balls, tau, substeps, lo[0], lo[1],
-        lo[2], hi[0], hi[1], hi[2], tracked, r_hat);
+        lo[2], hi[0], hi[1], hi[2], tracked, r_hat, nullptr);
   }
   BCHAR_HIP(hipGetLastError());
 }
 
 void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int substeps,
-                 int precision, double* tracked, double* r_hat, Arena& ws, hipStream_t s) {
+                 int precision, double* tracked, double* r_hat, double* lam, Arena& ws,
+                 hipStream_t s) {
   // binary32 tracking only in FP32_VOLUME, which the caller allows only
-  // where phi is constant (on faces, where u/phi jumps and the cardinal
-  // points start, binary32 rounding would pick the neighbouring cell's phi)
-  if (precision != BCHAR_FP32_VOLUME) {
+  // where phi is constant and u solenoidal (on faces, where u/phi jumps and
+  // the cardinal points start, binary32 rounding would pick the
+  // neighbouring cell's phi)
+  if (precision != BCHAR_FP32_VOLUME || lam) {
     const double* comps[3] = {u.u[0], u.u[1], u.u[2]};
     if (m->dim == 2)
-      launch_trace<2, double>(m, u, dt, substeps, comps, tracked, r_hat, s);
+      launch_trace<2, double>(m, u, dt, substeps, comps, tracked, r_hat, lam, s);
     else
-      launch_trace<3, double>(m, u, dt, substeps, comps, tracked, r_hat, s);
+      launch_trace<3, double>(m, u, dt, substeps, comps, tracked, r_hat, lam, s);
   } else {
     const int64_t nn = u.m[0] * u.m[1] * (m->dim == 3 ? u.m[2] : 1);
     const float* comps[3] = {nullptr, nullptr, nullptr};
@@ -374,10 +459,236 @@ void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int 
       comps[a] = c;
     }
     if (m->dim == 2)
-      launch_trace<2, float>(m, u, dt, substeps, comps, tracked, r_hat, s);
+      launch_trace<2, float>(m, u, dt, substeps, comps, tracked, r_hat, nullptr, s);
     else
-      launch_trace<3, float>(m, u, dt, substeps, comps, tracked, r_hat, s);
+      launch_trace<3, float>(m, u, dt, substeps, comps, tracked, r_hat, nullptr, s);
   }
+}
+
+// ---------------------------------------------------------------- row targets
+// Non-solenoidal u (Sec. 3.2, Remark on non-solenoidal fields): every
+// tracked ball carries rho_K phi_K |B_{K,s}| exp(lam) (the analogue of
+// eq. expPhiB) and their sum over the balls of K is T_K (eq. volTracked).
+// The trace-back regions cover the domain once, so the targets of the
+// tracked cells that take their material from a set of residing cells
+// alone must total those cells' porous volumes: the sets are the connected
+// components of the bipartite graph of V's pattern (row K -- column M per
+// entry), and within each, b_row = T_K sum_{M in it} |M|_phi /
+// sum_{K in it} T_K.  One component (the usual case) is the whole domain.
+
+constexpr int kTargetBlocks = 256;
+constexpr int kMaxCcRounds = 4096;
+
+__global__ void __launch_bounds__(256) k_tracked_mass(
+    int64_t n_cells, int nbpc, const int32_t* __restrict__ ball_ptr,
+    const double* __restrict__ rho, const double* __restrict__ phi,
+    const double* __restrict__ bvol, const double* __restrict__ lam,
+    const double* __restrict__ b, double* __restrict__ T, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double sh[32];
+  CSum st, sb;
+  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < n_cells;
+       K += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b0 = nbpc > 0 ? K * nbpc : ball_ptr[K];
+    const int64_t b1 = nbpc > 0 ? b0 + nbpc : ball_ptr[K + 1];
+    double t = 0.0;
+    for (int64_t q = b0; q < b1; ++q) t = t + (rho[K] * phi[K] * bvol[q]) * exp(lam[q]);
+    T[K] = t;
+    st.add(t);
+    sb.add(b[K]);
+  }
+  const CSum a = block_csum(st, sh);
+  const CSum c = block_csum(sb, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = a.hi;
+    part[4 * blockIdx.x + 1] = a.lo;
+    part[4 * blockIdx.x + 2] = c.hi;
+    part[4 * blockIdx.x + 3] = c.lo;
+  }
+}
+
+// out[0] = sum T, out[1] = sum b, out[2] = sum b / sum T (one block)
+__global__ void __launch_bounds__(256) k_target_scale(const double* __restrict__ part, int np,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[32];
+  CSum st, sb;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    CSum x;
+    x.hi = part[4 * i];
+    x.lo = part[4 * i + 1];
+    st.add(x);
+    x.hi = part[4 * i + 2];
+    x.lo = part[4 * i + 3];
+    sb.add(x);
+  }
+  const double t = block_csum(st, sh).value();
+  const double bb = block_csum(sb, sh).value();
+  if (threadIdx.x == 0) {
+    out[0] = t;
+    out[1] = bb;
+    out[2] = bb / t;
+  }
+}
+
+// Connected components by hooking and pointer jumping.  lab[v] <= v
+// always and points inside v's component; at the fixed point every node
+// holds the smallest node of its component.
+__global__ void k_cc_init(int64_t n2, int32_t* __restrict__ lab) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n2) lab[v] = (int32_t)v;
+}
+
+__global__ void k_cc_hook(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                          int64_t n, int32_t* lab, int32_t* __restrict__ changed) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= n) return;
+  for (int32_t e = row_ptr[K]; e < row_ptr[K + 1]; ++e) {
+    const int32_t a = __atomic_load_n(&lab[K], __ATOMIC_RELAXED);
+    const int32_t b = __atomic_load_n(&lab[n + col[e]], __ATOMIC_RELAXED);
+    if (a == b) continue;
+    const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    if (atomicMin(&lab[hi], lo) > lo) *changed = 1;
+  }
+}
+
+__global__ void k_cc_compress(int64_t n2, int32_t* lab) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n2) return;
+  int32_t l = __atomic_load_n(&lab[v], __ATOMIC_RELAXED);
+  for (;;) {
+    const int32_t p = __atomic_load_n(&lab[l], __ATOMIC_RELAXED);
+    if (p == l) break;
+    l = p;
+  }
+  __atomic_store_n(&lab[v], l, __ATOMIC_RELAXED);
+}
+
+__global__ void k_cc_roots(int64_t n2, const int32_t* __restrict__ lab,
+                           int32_t* __restrict__ count) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n2 && lab[v] == (int32_t)v) atomicAdd(count, 1);
+}
+
+// One wave per label: sum of T over the component's rows and of b over
+// its columns (members in ascending node order), and their ratio.
+__global__ void __launch_bounds__(64) k_cc_scale(int64_t n, const int32_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ T,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ scale) {
+  const int64_t c = blockIdx.x;
+  const int32_t p0 = ptr[c], p1 = ptr[c + 1];
+  if (p0 == p1) return;
+  CSum st, sb;
+  for (int32_t q = p0 + (int32_t)threadIdx.x; q < p1; q += 64) {
+    const int64_t v = perm[q];
+    if (v < n)
+      st.add(T[v]);
+    else
+      sb.add(b[v - n]);
+  }
+  wave_csum(st);
+  wave_csum(sb);
+  if (threadIdx.x == 0) scale[c] = sb.value() / st.value();
+}
+
+__global__ void k_scale_targets(int64_t n, const double* __restrict__ T,
+                                const int32_t* __restrict__ lab,
+                                const double* __restrict__ scale, double* __restrict__ b_row) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K < n) b_row[K] = T[K] * scale[lab ? lab[K] : 0];
+}
+
+TargetInfo row_targets(const bchar_mesh_s* m, bchar_transfer_s* t, const double* lam,
+                       double* b_row, Arena& ws, hipStream_t s) {
+  const int64_t n = m->n_cells, n2 = 2 * n;
+  const int32_t* row_ptr = t->row_ptr.as<int32_t>();
+  const int32_t* col = t->col.as<int32_t>();
+  Arena::Mark mk = ws.mark();
+  double* T = ws.get<double>(n);
+  double* part = ws.get<double>(4 * kTargetBlocks);
+  double* out = ws.get<double>(4);
+  t->grp_lab.reserve(sizeof(int32_t) * n2);
+  int32_t* lab = t->grp_lab.as<int32_t>();
+  int32_t* flag = ws.get<int32_t>(2);
+  {
+    ::bchar::ProfScope ps_("k_tracked_mass", s);
+    k_tracked_mass<<<kTargetBlocks, 256, 0, s>>>(
+        n, m->nbpc, m->ball_ptr.as<int32_t>(), m->rho.as<double>(), m->phi.as<double>(),
+        m->bvol.as<double>(), lam, m->b.as<double>(), T, part);
+  }
+  {
+    ::bchar::ProfScope ps_("k_target_scale", s);
+    k_target_scale<<<1, 256, 0, s>>>(part, kTargetBlocks, out);
+  }
+  {
+    ::bchar::ProfScope ps_("k_cc_init", s);
+    k_cc_init<<<blocks_for(n2, 256), 256, 0, s>>>(n2, lab);
+  }
+  BCHAR_HIP(hipGetLastError());
+  // hook and compress until no label moves (each round that reports a
+  // change lowered a label, so the rounds end)
+  int rounds = 0;
+  for (;; ++rounds) {
+    BCHAR_REQUIRE(rounds < kMaxCcRounds, BCHAR_E_DEVICE,
+                  "connected components of the transfer pattern did not settle");
+    fill_i32(flag, 0, 1, s);
+    {
+      ::bchar::ProfScope ps_("k_cc_hook", s);
+      k_cc_hook<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, n, lab, flag);
+    }
+    {
+      ::bchar::ProfScope ps_("k_cc_compress", s);
+      k_cc_compress<<<blocks_for(n2, 256), 256, 0, s>>>(n2, lab);
+    }
+    BCHAR_HIP(hipGetLastError());
+    int32_t h = 0;
+    BCHAR_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+    BCHAR_HIP(hipStreamSynchronize(s));
+    if (h == 0) break;
+  }
+  fill_i32(flag + 1, 0, 1, s);
+  {
+    ::bchar::ProfScope ps_("k_cc_roots", s);
+    k_cc_roots<<<blocks_for(n2, 256), 256, 0, s>>>(n2, lab, flag + 1);
+  }
+  BCHAR_HIP(hipGetLastError());
+  TargetInfo info;
+  double h[3];
+  int32_t groups = 0;
+  BCHAR_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+  BCHAR_HIP(hipMemcpyAsync(&groups, flag + 1, sizeof(groups), hipMemcpyDeviceToHost, s));
+  BCHAR_HIP(hipStreamSynchronize(s));
+  info.scale = h[2];
+  info.groups = groups;
+  BCHAR_REQUIRE(std::isfinite(h[2]) && h[2] > 0.0, BCHAR_E_INVALID_ARG,
+                "non-solenoidal step: the tracked porous volumes do not sum to a positive "
+                "finite value");
+  if (groups == 1) {
+    // one component: the whole domain's factor
+    ::bchar::ProfScope ps_("k_scale_targets", s);
+    k_scale_targets<<<blocks_for(n, 256), 256, 0, s>>>(n, T, nullptr, out + 2, b_row);
+  } else {
+    t->grp_ptr.reserve(sizeof(int32_t) * (n2 + 1));
+    t->grp_perm.reserve(sizeof(int32_t) * n2);
+    int32_t* ptr = t->grp_ptr.as<int32_t>();
+    int32_t* perm = t->grp_perm.as<int32_t>();
+    double* scale = ws.get<double>(n2);
+    bucket_sort(lab, n2, n2, ptr, perm, ws, s);
+    {
+      ::bchar::ProfScope ps_("k_cc_scale", s);
+      k_cc_scale<<<(unsigned)n2, 64, 0, s>>>(n, ptr, perm, T, m->b.as<double>(), scale);
+    }
+    {
+      ::bchar::ProfScope ps_("k_scale_targets", s);
+      k_scale_targets<<<blocks_for(n, 256), 256, 0, s>>>(n, T, lab, scale, b_row);
+    }
+  }
+  BCHAR_HIP(hipGetLastError());
+  BCHAR_HIP(hipStreamSynchronize(s));
+  ws.rewind(mk);
+  info.rounds = rounds + 1;
+  return info;
 }
 
 // ---------------------------------------------------------------- lens
@@ -461,6 +772,7 @@ struct TileParams {
   const double* rho;        // per cell
   const double* phi;        // per cell
   const double* bvol;       // per ball, |B_{K,s}|
+  const double* lam;        // per ball log growth (non-solenoidal u), or null
   const double* tracked;    // dim * n_balls
   const double* r_hat;      // n_balls
   const int32_t* bucket_start;
@@ -675,6 +987,8 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
     for (int a = 0; a < DIM; ++a) p[a] = (T)P.tracked[a * nb + b];
     ra = (T)P.r_hat[b];
     mass = P.rho[K] * P.phi[K] * P.bvol[b];   // rho_K phi_K |B_{K,s}|
+    // non-solenoidal u: times exp(lam), the Liouville growth of the ball
+    if (P.lam) mass = mass * exp(P.lam[b]);
   }
 
   // ---- the search block of the whole tile: the union of its balls'
@@ -1026,8 +1340,8 @@ static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
 }
 
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
-                        int precision, bool keep_pairs, bool lds_stage, bchar_transfer_s* t,
-                        int64_t* first_void, hipStream_t s) {
+                        const double* lam, int precision, bool keep_pairs, bool lds_stage,
+                        bchar_transfer_s* t, int64_t* first_void, hipStream_t s) {
   Arena& ws = t->ws;
   const int64_t nc = m->n_cells;
   TileParams P{};
@@ -1052,6 +1366,7 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.rho = m->rho.as<double>();
   P.phi = m->phi.as<double>();
   P.bvol = m->bvol.as<double>();
+  P.lam = lam;
   P.tracked = tracked;
   P.r_hat = r_hat;
   P.bucket_start = m->bucket_start.as<int32_t>();

@@ -139,6 +139,11 @@ struct bchar_transfer_s {
   int warm_level = -1;   // box level of the last converged solve
   bchar::DBuf tracked;   // fp64 dim * n_balls
   bchar::DBuf r_hat;     // fp64 n_balls
+  bchar::DBuf lam;       // fp64 n_balls, log growth (non-solenoidal builds)
+  bchar::DBuf b_row;     // fp64 n_cells, row targets (non-solenoidal builds)
+  bool general = false;  // the last build took a non-solenoidal u
+  int64_t groups = 0;    // components of the pattern (non-solenoidal builds)
+  bchar::DBuf grp_lab, grp_ptr, grp_perm;   // int32 2n, 2n + 1, 2n (groups > 1)
   bchar::DBuf pair_a, pair_b;  // int32 n_pairs (keep_pairs), any order
   bchar::DBuf stage_col;       // assembly staging: rows in tile order
   bchar::DBuf stage_val;
@@ -191,12 +196,27 @@ struct BuildOut {
   int32_t* pair_a;     // optional
   int32_t* pair_b;
 };
+// lam: non-null for a non-solenoidal u, receives the log growth of every
+// tracked ball (r_hat then always from the cardinal points)
 void trace_balls(const bchar_mesh_s* m, const bchar_velocity& u, double dt, int substeps,
-                 int precision, double* tracked, double* r_hat, Arena& ws, hipStream_t s);
+                 int precision, double* tracked, double* r_hat, double* lam, Arena& ws,
+                 hipStream_t s);
+// Row targets of a non-solenoidal step into b_row (after the assembly:
+// the components of V's pattern); syncs.
+struct TargetInfo {
+  double scale = 1.0;   // sum |M|_phi / sum T_K over the whole domain
+  int64_t groups = 0;   // connected components of the pattern
+  int rounds = 0;       // hook-and-compress rounds that found them
+};
+// With several components the labels and the grouping are left in
+// t->grp_lab, t->grp_ptr, t->grp_perm.
+TargetInfo row_targets(const bchar_mesh_s* m, bchar_transfer_s* t, const double* lam,
+                       double* b_row, Arena& ws, hipStream_t s);
 // Returns BCHAR_OK or VOID_ROW (first_void set); allocates the CSR in t.
+// lam: per-ball log growth (non-solenoidal u) or null.
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
-                        int precision, bool keep_pairs, bool lds_stage, bchar_transfer_s* t,
-                        int64_t* first_void, hipStream_t s);
+                        const double* lam, int precision, bool keep_pairs, bool lds_stage,
+                        bchar_transfer_s* t, int64_t* first_void, hipStream_t s);
 
 // scaling (scaling.hip)
 struct Csc {
@@ -206,9 +226,10 @@ struct Csc {
 };
 void build_csc(const int32_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, Csc& c,
                Arena& ws, hipStream_t s);
+// b_row: row targets (|K|_phi for a solenoidal u); columns take |M|_phi
 bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
-                            const Csc& csc, const double* V, int64_t nnz, int n_sweeps,
-                            double* AN, int64_t* void_col, int64_t* n_void_cols,
+                            const Csc& csc, const double* V, const double* b_row, int64_t nnz,
+                            int n_sweeps, double* AN, int64_t* void_col, int64_t* n_void_cols,
                             double* max_col_err, Arena& ws, hipStream_t s);
 
 // QP (qp.hip)
@@ -223,10 +244,21 @@ struct QpResult {
 // zdual: per-cell multipliers (s, g), 2 n leading parts and 2 n
 // compensations kept by the transfer;
 // warm_level: box level of the previous converged solve, or -1.
+// The connected components of the bipartite graph of the pattern (rows
+// 0..n-1, columns n..2n-1): every node's label (the smallest node of its
+// component) and the nodes grouped by label (ptr: 2n + 1, perm: 2n).
+struct Groups {
+  const int32_t* lab;
+  const int32_t* ptr;
+  const int32_t* perm;
+};
+// groups: the components when there are several (their null directions
+// are projected out of every Newton system), else null
 bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
-                      const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
-                      double* x, double* mu, double* nu, double* A, double* zdual,
-                      int warm_level, QpResult& res, Arena& ws, hipStream_t s);
+                      const Csc& csc, const double* AN, const double* b_row,
+                      const Groups* groups, int64_t nnz, const bchar_opts& o, double* x,
+                      double* mu, double* nu, double* A, double* zdual, int warm_level,
+                      QpResult& res, Arena& ws, hipStream_t s);
 
 // apply / mass (apply.hip)
 void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s);

@@ -56,6 +56,9 @@ constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relati
 constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
+constexpr int kFallbackNewton = 40; // semismooth steps on a level every interior point
+                                    // gave up on, and the short steps it may take
+constexpr int kFallbackPatience = 8;
 constexpr int kCrossoverSteps = 2; // fixed-side Newton steps from an interior point
 constexpr int kCrossoverRounds = 4; // active-set updates of the sides after the first
 constexpr double kCrossoverRatio = 1e-3;  // slack / multiplier of a pinned entry
@@ -1819,15 +1822,16 @@ __global__ void k_scale_a(const double* __restrict__ an, double inv, int64_t nnz
   if (k < nnz) a[k] = an[k] * inv;
 }
 
-// rr[i] = b_i/scale - sum_row a ; ss[j] = b_j/scale - sum_col a
+// rr[i] = b_row_i/scale - sum_row a ; ss[j] = b_j/scale - sum_col a
 __global__ void k_targets(const int32_t* __restrict__ rptr, const int32_t* __restrict__ cptr,
                           const double* __restrict__ a, const double* __restrict__ ac,
-                          const double* __restrict__ b, double inv, int64_t n,
-                          double* __restrict__ rr, double* __restrict__ ss) {
+                          const double* __restrict__ b_row, const double* __restrict__ b,
+                          double inv, int64_t n, double* __restrict__ rr,
+                          double* __restrict__ ss) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   CSum r, c;
-  r.add(b[i] * inv);
+  r.add(b_row[i] * inv);
   for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) r.add(-a[k]);
   c.add(b[i] * inv);
   for (int32_t e = cptr[i]; e < cptr[i + 1]; ++e) c.add(-ac[e]);
@@ -1904,6 +1908,37 @@ __global__ void k_zrhs(const double* __restrict__ F, int64_t n, double* __restri
     bz[i] = fr + fc;
     bz[n + i] = 0.5 * (fr - fc);
   }
+}
+
+// A pattern of several connected components leaves one null direction of
+// the Newton matrix per component (its multipliers moved by a constant):
+// the right-hand side is made orthogonal to each.  In y = (mu, -nu)
+// coordinates node v carries -F_row (rows) or F_col (columns); dm[c] =
+// their mean over component c (one wave per label, members in node order).
+__global__ void __launch_bounds__(64) k_group_mean(int64_t n, const int32_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ F,
+                                                   double* __restrict__ dm) {
+  const int64_t c = blockIdx.x;
+  const int32_t p0 = ptr[c], p1 = ptr[c + 1];
+  if (p0 == p1) return;
+  CSum acc;
+  for (int32_t q = p0 + (int32_t)threadIdx.x; q < p1; q += 64) {
+    const int64_t v = perm[q];
+    acc.add(v < n ? -F[v] : F[v]);
+  }
+  wave_csum(acc);
+  if (threadIdx.x == 0) dm[c] = acc.value() / (double)(p1 - p0);
+}
+
+// the (s, g) right-hand side of the mean-free y right-hand side
+__global__ void k_group_fix(int64_t n, const int32_t* __restrict__ lab,
+                            const double* __restrict__ dm, double* __restrict__ bz) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= n) return;
+  const double dr = dm[lab[K]], dc = dm[lab[n + K]];
+  bz[K] -= dr + dc;
+  bz[n + K] -= 0.5 * (dr - dc);
 }
 
 __global__ void k_sub_scalar(double* __restrict__ v, const double* __restrict__ sum,
@@ -2368,9 +2403,10 @@ __global__ void k_ipm_init(IpmArrays I, int64_t nnz) {
 // ====================================================================== solver
 
 bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
-                      const Csc& csc, const double* AN, int64_t nnz, const bchar_opts& o,
-                      double* x_out, double* mu_out, double* nu_out, double* A_out,
-                      double* zdual, int warm_level, QpResult& res, Arena& ws, hipStream_t s) {
+                      const Csc& csc, const double* AN, const double* b_row,
+                      const Groups* groups, int64_t nnz, const bchar_opts& o, double* x_out,
+                      double* mu_out, double* nu_out, double* A_out, double* zdual,
+                      int warm_level, QpResult& res, Arena& ws, hipStream_t s) {
   const int64_t n = m->n_cells;
   const int64_t n2 = 2 * n;
   const double scale = m->bmax;
@@ -2379,6 +2415,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
 
   Reducer red{ws.get<double>(2 * kRedBlocks + 2), ws.get<double>(16), s};
   double* zpart = ws.get<double>(2 * (size_t)blocks_for(n, kT) + 2);   // block sums
+  double* gmean = groups ? ws.get<double>(n2) : nullptr;   // per-component means
   double* zsave = ws.get<double>(4 * (size_t)n + 1);   // interior-point multipliers
   double* tsave = ws.get<double>((size_t)nnz + 1);
 
@@ -2409,8 +2446,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   }
   {
     ::bchar::ProfScope ps_("k_targets", s);
-    k_targets<<<gn, kT, 0, s>>>(row_ptr, csc.ptr, Q.a, Q.ac, m->b.as<double>(), inv, n, Q.rr,
-                                Q.ss);
+    k_targets<<<gn, kT, 0, s>>>(row_ptr, csc.ptr, Q.a, Q.ac, b_row, m->b.as<double>(), inv, n,
+                                Q.rr, Q.ss);
   }
   BCHAR_HIP(hipGetLastError());
 
@@ -2587,6 +2624,17 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     {
       ::bchar::ProfScope ps_("k_zrhs", s);
       k_zrhs<<<gn, kT, 0, s>>>(fv, n, cr);
+    }
+    if (groups) {
+      {
+        ::bchar::ProfScope ps_("k_group_mean", s);
+        k_group_mean<<<(unsigned)n2, 64, 0, s>>>(n, groups->ptr, groups->perm, fv, gmean);
+      }
+      {
+        ::bchar::ProfScope ps_("k_group_fix", s);
+        k_group_fix<<<gn, kT, 0, s>>>(n, groups->lab, gmean, cr);
+      }
+      BCHAR_HIP(hipGetLastError());
     }
     red.sum(cr, n, 12);
     {
@@ -2857,7 +2905,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     }
     BCHAR_HIP(hipGetLastError());
     double mu0 = -1.0, fp_best = HUGE_VAL;
-    std::vector<double> fp_hist;
+    std::vector<double> fp_hist, mu_hist;
     const bool loose = cg_rel > kIpmCgTight;
     int stall = 0;
     auto steps = [&](double* ap, double* ad) {
@@ -2904,10 +2952,15 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
                 wall_seconds());
       if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return 0;
       // no progress on an infeasible box: after kIpmInfeasIt iterations the
-      // complementarity has not even halved and |B x - r| fell by less
-      // than 10 % over the last five
+      // complementarity is not below half its start and has not halved
+      // over the last five either, and |B x - r| fell by less than 10 %
+      // over them (a feasible box whose answer lies far from the start can
+      // first drive the complementarity up by orders of magnitude, then
+      // bring it down)
       fp_hist.push_back(fp);
-      if (it >= kIpmInfeasIt && mu >= 0.5 * mu0 && fp >= 0.9 * fp_hist[it - 5]) {
+      mu_hist.push_back(mu);
+      if (it >= kIpmInfeasIt && mu >= 0.5 * mu0 && mu >= 0.5 * mu_hist[it - 5] &&
+          fp >= 0.9 * fp_hist[it - 5]) {
         if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no progress (infeasible?)\n");
         return 0;
       }
@@ -3141,6 +3194,15 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
           // Newton without the step-count cap
           converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, " (after interior point)");
         }
+      } else {
+        // every interior point gave up: an answer far from its start (some
+        // x of order 1 or more) can drive its complementarity up as if the
+        // box were empty.  Semismooth Newton from zero decides: on an empty
+        // box it stalls in short steps or unbounded multipliers.
+        fill_f64(Q.t, 0.0, nnz, s);
+        fill_f64(zdual, 0.0, 2 * n2, s);
+        converged = ssn(lo, hi, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
+                        o.qp_max_cg, " (interior point failed)");
       }
     }
     if (converged) break;

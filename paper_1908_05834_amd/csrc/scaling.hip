@@ -109,8 +109,8 @@ __global__ void k_col_err(const int32_t* __restrict__ cptr, const int32_t* __res
 }
 
 bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const int32_t* col,
-                            const Csc& csc, const double* V, int64_t nnz, int n_sweeps,
-                            double* AN, int64_t* void_col, int64_t* n_void_cols,
+                            const Csc& csc, const double* V, const double* b_row, int64_t nnz,
+                            int n_sweeps, double* AN, int64_t* void_col, int64_t* n_void_cols,
                             double* max_col_err, Arena& ws, hipStream_t s) {
   const int64_t n = m->n_cells;
   const double* b = m->b.as<double>();
@@ -152,7 +152,7 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
     }
     {
       ::bchar::ProfScope ps_("k_row_scale", s);
-      k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, V, C, b, n, R);
+      k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, V, C, b_row, n, R);
     }
     BCHAR_HIP(hipGetLastError());
   }

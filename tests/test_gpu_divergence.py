@@ -1,0 +1,162 @@
+"""GPU parity of the non-solenoidal step (Sec. 3.2, Remark on
+non-solenoidal fields; opts.divergence = DIV_GENERAL) against the oracle
+(``solenoidal=False``): tracked centres, radii and log growth bit for bit,
+row targets within 1e-14, pairs bit for bit, V within 1e-13, the updated
+concentrations within 1e-10 and the porous mass to rounding."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import geometry as ogeo
+from oracle import transfer as otr
+from paper_1908_05834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05834_amd import bchar
+    return torch, bchar
+
+
+def _case(name):
+    if name == "sine2d":
+        mesh = inputs.cartesian_mesh((24, 24))
+        return mesh, inputs.sample_velocity(mesh, inputs.sine_compression((0.5, -0.4))), 0.05, \
+            "subcell"
+    if name == "cswirl3d":
+        mesh = inputs.cartesian_mesh((10, 10, 10))
+        return mesh, inputs.sample_velocity(mesh, inputs.compressible_swirl_3d), 0.03, "subcell"
+    if name == "sine3d_inscribed":
+        mesh = inputs.cartesian_mesh((9, 9, 9))
+        f = inputs.sine_compression((0.5, -0.4, 0.3))
+        return mesh, inputs.sample_velocity(mesh, f), 0.05, "inscribed"
+    if name == "porous2d":
+        mesh = inputs.cartesian_mesh((12, 12), phi=inputs.lognormal_phi(144, 5834))
+        return mesh, inputs.sample_velocity(mesh, inputs.sine_compression((0.5, -0.4))), 0.04, \
+            "subcell"
+    if name == "tets":
+        mesh = inputs.kuhn_tets(4, 0.1, 8)
+        vel = inputs.sample_velocity_grid((4, 4, 4),
+                                          lambda p, t: inputs.compressible_swirl_3d(p, t))
+        return mesh, vel, 0.05, "equal_measure"
+    if name == "tris_porous":
+        mesh = inputs.triangulated_square(10, 0.1, 6, phi=inputs.lognormal_phi(200, 22))
+        vel = inputs.sample_velocity_grid((10, 10), inputs.sine_compression((0.6, 0.4)))
+        return mesh, vel, 0.08, "equal_measure"
+    if name == "custom_hex":
+        w = inputs.swirl_hex(8)
+        mesh = inputs.random_subcell_balls(w["mesh"], 5)
+        return mesh, inputs.sample_velocity(w["mesh"], inputs.compressible_swirl_3d), 0.03, \
+            "custom"
+    raise KeyError(name)
+
+
+CASES = ["sine2d", "cswirl3d", "sine3d_inscribed", "porous2d", "tets", "tris_porous",
+         "custom_hex"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_general_step_matches_oracle(env, name):
+    torch, bchar = env
+    _say(f"[gpu] non-solenoidal step {name}")
+    mesh, vel, dt, layout = _case(name)
+    M = bchar.Mesh(mesh, layout)
+    kw = {}
+    if ogeo.is_simplex(mesh):
+        # the same residing balls (the library's cube roots) on both sides
+        c, r, _ = M.export_balls()
+        kw["balls_override"] = (c, r)
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, solenoidal=False, **kw)
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt,
+                             bchar.opts_default(divergence=bchar.DIV_GENERAL, keep_pairs=1))
+    st = T.stats
+    _say(f"    stats {st}; oracle level {ref['qp']['level']} scale {ref['target_scale']}")
+    tr, rh = T.export_tracked()
+    assert np.array_equal(tr, ref["traced"]), "tracked centres differ"
+    assert np.array_equal(rh, ref["r_hat"]), "tracked radii differ"
+    lam, b_row = T.export_targets()
+    assert np.array_equal(lam, ref["lam"]), "log growth differs"
+    err_b = np.max(np.abs(b_row - ref["b_loc"]) / ref["b_loc"])
+    _say(f"    row targets rel err {err_b:.3e}")
+    assert err_b <= 1e-14
+    assert abs(st["row_target_scale"] - ref["target_scale"]) <= 4 * np.spacing(ref["target_scale"])
+    assert st["n_target_groups"] == ref["n_groups"]
+    a, b = T.export_pairs()
+    assert np.array_equal(a, ref["pairs"][0]) and np.array_equal(b, ref["pairs"][1])
+    rp, col, V = T.export_csr(bchar.STAGE_V)
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(col, ref["col"])
+    assert np.max(np.abs(V - ref["V"])) <= 1e-13 * np.max(np.abs(ref["V"]))
+    assert st["qp_level"] == ref["qp"]["level"]
+    c0 = inputs.uniform_c(mesh, 17)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], c0)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    # the porous mass is conserved although c is not (the flow compresses)
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    want_m = otr.mass(mesh["phi"], ref["cell_vol"], got)
+    assert abs(m1 - want_m) <= 2 * np.spacing(abs(want_m))
+    # a constant state is compressed by the row targets: c = b_row / |K|_phi
+    ones = torch.ones(M.n_cells, dtype=torch.float64, device="cuda")
+    T.step(ones, cout)
+    ratio = ref["b_loc"] / ref["b"]
+    assert np.max(np.abs(cout.cpu().numpy() - ratio)) <= 1e-10
+    assert np.max(np.abs(ratio - 1.0)) > 1e-3
+
+
+def test_general_rebuild_and_free_rebuild(env):
+    """A transfer rebuilt in the other mode gives each mode's own answer."""
+    torch, bchar = env
+    _say("[gpu] non-solenoidal rebuilds")
+    mesh, vel, dt, layout = _case("sine2d")
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    gen = bchar.opts_default(divergence=bchar.DIV_GENERAL)
+    T = bchar.Transfer.build(M, U, dt, gen)
+    lam1, b1 = T.export_targets()
+    T.rebuild(U, dt, bchar.opts_default())
+    lam0, b0 = T.export_targets()
+    assert np.all(lam0 == 0.0) and T.stats["row_target_scale"] == 1.0
+    assert T.stats["n_target_groups"] == 0
+    want = otr.build_transfer(mesh, vel, dt, layout=layout, stop_after="pairs")["b"]
+    assert np.array_equal(b0, want)
+    T.rebuild(U, dt, gen)
+    lam2, b2 = T.export_targets()
+    assert np.array_equal(lam1, lam2) and np.array_equal(b1, b2)
+
+
+def test_general_mode_rejections(env):
+    torch, bchar = env
+    _say("[gpu] non-solenoidal rejections")
+    mesh, vel, dt, layout = _case("sine2d")
+    M = bchar.Mesh(mesh, layout)
+    U = bchar.VelocityLattice(vel)
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build(M, U, dt, bchar.opts_default(divergence=bchar.DIV_GENERAL,
+                                                          precision=bchar.FP32_VOLUME))
+    assert ei.value.status == bchar.E_UNSUPPORTED
+    ref = otr.build_transfer(mesh, vel, dt, layout=layout, stop_after="pairs")
+    tr = torch.as_tensor(np.ascontiguousarray(ref["traced"].T), device="cuda")
+    rh = torch.as_tensor(np.ascontiguousarray(ref["r_hat"]), device="cuda")
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build_tracked(M, tr, rh, bchar.opts_default(divergence=bchar.DIV_GENERAL))
+    assert ei.value.status == bchar.E_UNSUPPORTED
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build(M, U, dt, bchar.opts_default(divergence=7))
+    assert ei.value.status == bchar.E_INVALID_ARG
