@@ -149,6 +149,85 @@ def simplex_ball_layout(mesh):
     return centres, radii, np.arange(C.shape[0], dtype=np.int64)
 
 
+PACK_SHRINK = 0.875
+
+
+def simplex_packed_layout(mesh, shrink=PACK_SHRINK):
+    """Several disjoint balls per simplex (``"packed"``; the paper leaves the
+    packing of generic cells open, Sec. 5).
+
+    Per cell, in this order: the inscribed ball (centre the incentre
+    I = sum_i w_i v_i / sum_i w_i, w_i the measure of the facet opposite
+    v_i, radius r = dim |K| / sum_i w_i), then for every vertex v_i the
+    ball tangent to the dim facets through v_i and to the inscribed ball:
+    centre v_i + t (I - v_i), radius t r, t = (L - r) / (L + r), L = |v_i -
+    I|.  Every radius is then multiplied by ``shrink`` (each ball keeps its
+    centre, so tangencies become gaps and the balls lie strictly inside).
+    A cell whose balls still overlap (possible for very flat simplices)
+    keeps its inscribed ball only.  Sums run in vertex and axis order;
+    every operation is rounded on its own.
+    Returns (centres (n_balls, dim), radii, ball_cell).
+    """
+    V = np.asarray(mesh["vertices"], dtype=np.float64)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    dim = V.shape[1]
+    nc = C.shape[0]
+    P = [V[C[:, i]] for i in range(dim + 1)]
+    vol = simplex_volumes(V, C)
+    w = []
+    for i in range(dim + 1):
+        o = [j for j in range(dim + 1) if j != i]
+        if dim == 2:
+            e = P[o[1]] - P[o[0]]
+            w.append(np.sqrt(e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]))
+        else:
+            u = P[o[1]] - P[o[0]]
+            v = P[o[2]] - P[o[0]]
+            c0 = u[:, 1] * v[:, 2] - u[:, 2] * v[:, 1]
+            c1 = u[:, 2] * v[:, 0] - u[:, 0] * v[:, 2]
+            c2 = u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0]
+            w.append(np.sqrt((c0 * c0 + c1 * c1) + c2 * c2) / 2.0)
+    W = w[0] + w[1]
+    for i in range(2, dim + 1):
+        W = W + w[i]
+    inc = np.zeros((nc, dim))
+    for a in range(dim):
+        acc = w[0] * P[0][:, a] + w[1] * P[1][:, a]
+        for i in range(2, dim + 1):
+            acc = acc + w[i] * P[i][:, a]
+        inc[:, a] = acc / W
+    r = (dim * vol) / W
+    cen = [inc]
+    rad = [shrink * r]
+    for i in range(dim + 1):
+        d = P[i] - inc
+        L2 = d[:, 0] * d[:, 0]
+        for a in range(1, dim):
+            L2 = L2 + d[:, a] * d[:, a]
+        L = np.sqrt(L2)
+        t = (L - r) / (L + r)
+        cen.append(P[i] + t[:, None] * (inc - P[i]))
+        rad.append(shrink * (t * r))
+    nb = dim + 2
+    # disjointness of every pair after the shrink
+    ok = np.ones(nc, dtype=bool)
+    for a in range(nb):
+        for b in range(a + 1, nb):
+            d = cen[a] - cen[b]
+            d2 = d[:, 0] * d[:, 0]
+            for k in range(1, dim):
+                d2 = d2 + d[:, k] * d[:, k]
+            ok &= np.sqrt(d2) >= rad[a] + rad[b]
+    centres, radii, cell = [], [], []
+    for K in range(nc):
+        take = range(nb) if ok[K] else range(1)
+        for q in take:
+            centres.append(cen[q][K])
+            radii.append(rad[q][K])
+            cell.append(K)
+    return np.array(centres), np.array(radii), np.array(cell, dtype=np.int64)
+
+
 def locate_points(points, mesh, chunk=2048):
     """Cell of a simplicial mesh holding each point.
 

@@ -234,11 +234,13 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     if phi.shape != (nc,) or not np.all(np.isfinite(phi)) or np.any(phi <= 0):
         raise ValueError("phi must be finite and > 0 on every cell (Sec. 1.2)")
     if geo.is_simplex(mesh):
-        if layout not in ("equal_measure", "custom"):
-            raise ValueError("simplicial meshes take the equal_measure or custom layout")
+        if layout not in ("equal_measure", "custom", "packed"):
+            raise ValueError("simplicial meshes take the equal_measure, packed or custom layout")
         kvol = geo.simplex_volumes(mesh["vertices"], mesh["cells"])
-        if layout != "custom":
+        if layout == "equal_measure":
             centres, radii, bcell = geo.simplex_ball_layout(mesh)
+        elif layout == "packed":
+            centres, radii, bcell = geo.simplex_packed_layout(mesh)
     else:
         n = tuple(int(v) for v in mesh["n"])
         h = tuple(float(v) for v in mesh["h"])
