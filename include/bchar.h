@@ -67,11 +67,22 @@ typedef enum {
  *                 smallest face)
  *   INSCRIBED     Cartesian: one ball at the centroid, radius min(h)/2
  *   EQUAL_MEASURE one ball at the centroid with |B| = |K| (overlaps its
- *                 neighbours); the only built-in layout of simplices
+ *                 neighbours)
  *   CUSTOM        the caller's balls (bchar_mesh_desc.n_balls, balls,
- *                 ball_cell), any number per cell, on either mesh kind     */
+ *                 ball_cell), any number per cell, on either mesh kind
+ *   PACKED        simplices: dim + 2 disjoint balls strictly inside each
+ *                 cell (the paper leaves the packing of generic cells open,
+ *                 Sec. 5).  In this order: the inscribed ball (centre the
+ *                 incentre sum_i w_i v_i / sum_i w_i, w_i the measure of
+ *                 the facet opposite vertex v_i; radius r = dim |K| /
+ *                 sum_i w_i), then per vertex the ball tangent to the dim
+ *                 facets through v_i and to the inscribed ball (centre
+ *                 v_i + t (I - v_i), radius t r, t = (L - r) / (L + r),
+ *                 L = |v_i - I|); every radius times 7/8, centres kept.  A
+ *                 cell whose balls would still overlap keeps the inscribed
+ *                 ball alone.  rho_K as for CUSTOM.                      */
 enum { BCHAR_LAYOUT_SUBCELL = 0, BCHAR_LAYOUT_INSCRIBED = 1, BCHAR_LAYOUT_EQUAL_MEASURE = 2,
-       BCHAR_LAYOUT_CUSTOM = 3 };
+       BCHAR_LAYOUT_CUSTOM = 3, BCHAR_LAYOUT_PACKED = 4 };
 
 /* Precision of the geometric part.  FP64: everything in binary64.
  * FP32_VOLUME: tracking, the overlap predicate and the lens volumes in

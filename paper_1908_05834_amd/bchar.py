@@ -28,7 +28,8 @@ _lib = C.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants (bchar.h)
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_VOID_ROW, E_VOID_COLUMN, \
     E_QP_INFEASIBLE, E_QP_NOT_CONVERGED, E_UNSUPPORTED = range(9)
-LAYOUT_SUBCELL, LAYOUT_INSCRIBED, LAYOUT_EQUAL_MEASURE, LAYOUT_CUSTOM = 0, 1, 2, 3
+LAYOUT_SUBCELL, LAYOUT_INSCRIBED, LAYOUT_EQUAL_MEASURE, LAYOUT_CUSTOM, LAYOUT_PACKED = \
+    0, 1, 2, 3, 4
 FP64, FP32_VOLUME, FP32_LENS = 0, 1, 2
 BOX_PAPER_THEN_RELAX, BOX_STRICT = 0, 1
 STAGE_PAIRS, STAGE_V, STAGE_SCALING, STAGE_ALL = 1, 2, 3, 4
@@ -37,7 +38,8 @@ MESH_CARTESIAN, MESH_SIMPLEX = 0, 1
 DIV_FREE, DIV_GENERAL = 0, 1
 
 LAYOUTS = {"subcell": LAYOUT_SUBCELL, "inscribed": LAYOUT_INSCRIBED,
-           "equal_measure": LAYOUT_EQUAL_MEASURE, "custom": LAYOUT_CUSTOM}
+           "equal_measure": LAYOUT_EQUAL_MEASURE, "custom": LAYOUT_CUSTOM,
+           "packed": LAYOUT_PACKED}
 
 
 class MeshDesc(C.Structure):

@@ -143,6 +143,92 @@ void simplex_geometry(const bchar_mesh_desc* d, SimplexHost& h) {
   }
 }
 
+// Several disjoint balls per simplex (layout PACKED): the inscribed ball
+// (incentre sum_i w_i v_i / sum_i w_i, w_i the measure of the facet
+// opposite v_i; radius dim |K| / sum_i w_i), then for every vertex the ball
+// tangent to the facets through it and to the inscribed ball (centre
+// v_i + t (I - v_i), radius t r, t = (L - r) / (L + r), L = |v_i - I|),
+// every radius times kPackShrink; a cell whose balls still overlap keeps
+// the inscribed ball alone.  Output in the CUSTOM format (ball-major
+// centre then radius; the cell of every ball).
+constexpr double kPackShrink = 0.875;
+
+void packed_simplex_balls(const SimplexHost& h, std::vector<double>& balls,
+                          std::vector<int32_t>& ball_cell) {
+#pragma clang fp contract(off)
+  const int dim = h.dim;
+  const int nb = dim + 2;
+  balls.clear();
+  ball_cell.clear();
+  balls.reserve((size_t)h.nc * nb * (dim + 1));
+  ball_cell.reserve((size_t)h.nc * nb);
+  for (int64_t K = 0; K < h.nc; ++K) {
+    double p[4][3] = {{0}};
+    for (int i = 0; i <= dim; ++i) {
+      const int32_t q = h.cells[(size_t)K * (dim + 1) + i];
+      for (int a = 0; a < dim; ++a) p[i][a] = h.vtx[(size_t)a * h.nv + q];
+    }
+    double w[4] = {0, 0, 0, 0};
+    for (int i = 0; i <= dim; ++i) {
+      int o[3], k = 0;
+      for (int j = 0; j <= dim; ++j)
+        if (j != i) o[k++] = j;
+      if (dim == 2) {
+        const double e0 = p[o[1]][0] - p[o[0]][0], e1 = p[o[1]][1] - p[o[0]][1];
+        w[i] = std::sqrt(e0 * e0 + e1 * e1);
+      } else {
+        double u[3], v[3];
+        for (int a = 0; a < 3; ++a) {
+          u[a] = p[o[1]][a] - p[o[0]][a];
+          v[a] = p[o[2]][a] - p[o[0]][a];
+        }
+        const double c0 = u[1] * v[2] - u[2] * v[1];
+        const double c1 = u[2] * v[0] - u[0] * v[2];
+        const double c2 = u[0] * v[1] - u[1] * v[0];
+        w[i] = std::sqrt((c0 * c0 + c1 * c1) + c2 * c2) / 2.0;
+      }
+    }
+    double W = w[0] + w[1];
+    for (int i = 2; i <= dim; ++i) W = W + w[i];
+    double inc[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      double acc = w[0] * p[0][a] + w[1] * p[1][a];
+      for (int i = 2; i <= dim; ++i) acc = acc + w[i] * p[i][a];
+      inc[a] = acc / W;
+    }
+    const double r = ((double)dim * h.vol[K]) / W;
+    double c[5][3] = {{0}}, rad[5] = {0, 0, 0, 0, 0};
+    for (int a = 0; a < dim; ++a) c[0][a] = inc[a];
+    rad[0] = kPackShrink * r;
+    for (int i = 0; i <= dim; ++i) {
+      double d[3];
+      for (int a = 0; a < dim; ++a) d[a] = p[i][a] - inc[a];
+      double L2 = d[0] * d[0];
+      for (int a = 1; a < dim; ++a) L2 = L2 + d[a] * d[a];
+      const double L = std::sqrt(L2);
+      const double t = (L - r) / (L + r);
+      for (int a = 0; a < dim; ++a) c[1 + i][a] = p[i][a] + t * (inc[a] - p[i][a]);
+      rad[1 + i] = kPackShrink * (t * r);
+    }
+    bool ok = true;
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b) {
+        double d2 = 0;
+        for (int k = 0; k < dim; ++k) {
+          const double dk = c[a][k] - c[b][k];
+          d2 = k == 0 ? dk * dk : d2 + dk * dk;
+        }
+        ok = ok && std::sqrt(d2) >= rad[a] + rad[b];
+      }
+    const int take = ok ? nb : 1;
+    for (int q = 0; q < take; ++q) {
+      for (int a = 0; a < dim; ++a) balls.push_back(c[q][a]);
+      balls.push_back(rad[q]);
+      ball_cell.push_back((int32_t)K);
+    }
+  }
+}
+
 // Device copies, and (when phi varies, so that tracking needs it) the
 // uniform grid of side (|box| / n_cells)^(1/dim) listing, per grid cell
 // and in ascending order, the cells whose bounding box meets it.
@@ -237,11 +323,11 @@ void simplex_upload(bchar_mesh_s* m, const SimplexHost& h, const std::vector<dou
 // |B_{K,s}| (eq. def:porous.density, the measures summed in ball order),
 // the first ball of every cell, and tiles of whole cells with at most 256
 // balls each for the assembly.
-void custom_layout(bchar_mesh_s* m, const bchar_mesh_desc* d, const double* balls,
-                   const int32_t* ball_cell, const std::vector<double>& kvol, hipStream_t s) {
+void custom_layout(bchar_mesh_s* m, int64_t nb, const double* balls, const int32_t* ball_cell,
+                   const std::vector<double>& kvol, hipStream_t s) {
 #pragma clang fp contract(off)
   const int dim = m->dim;
-  const int64_t nc = m->n_cells, nb = d->n_balls;
+  const int64_t nc = m->n_cells;
   BCHAR_REQUIRE(nb >= nc && nb < ((int64_t)1 << 31) - 1, BCHAR_E_INVALID_ARG,
                 "CUSTOM layout: n_balls must be >= the number of cells and < 2^31");
   BCHAR_REQUIRE(balls != nullptr && ball_cell != nullptr, BCHAR_E_INVALID_ARG,
@@ -759,7 +845,7 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
     BCHAR_REQUIRE(d->dim == 2 || d->dim == 3, BCHAR_E_INVALID_ARG, "dim must be 2 or 3");
     BCHAR_REQUIRE(d->kind == BCHAR_MESH_CARTESIAN || d->kind == BCHAR_MESH_SIMPLEX,
                   BCHAR_E_INVALID_ARG, "unknown mesh kind");
-    BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_CUSTOM,
+    BCHAR_REQUIRE(d->layout >= BCHAR_LAYOUT_SUBCELL && d->layout <= BCHAR_LAYOUT_PACKED,
                   BCHAR_E_INVALID_ARG, "unknown layout");
     BCHAR_REQUIRE(d->phi != nullptr, BCHAR_E_INVALID_ARG, "phi is NULL");
     BCHAR_REQUIRE(d->phi_mem == BCHAR_MEM_HOST || d->phi_mem == BCHAR_MEM_DEVICE,
@@ -768,6 +854,7 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
                   BCHAR_E_INVALID_ARG, "geom_mem");
     hipStream_t s = as_stream(stream);
     const bool custom = d->layout == BCHAR_LAYOUT_CUSTOM;
+    const bool packed = d->layout == BCHAR_LAYOUT_PACKED;
     // geometry given in device memory: host copies (creation runs on the host)
     bchar_mesh_desc dh = *d;
     std::vector<double> h_vtx, h_balls;
@@ -809,6 +896,8 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
       bchar::UniformBalls ub{};
       std::vector<double> kvol;   // simplex: |K| per cell
       SimplexHost sh;
+      std::vector<double> pballs;     // PACKED: the balls, CUSTOM format
+      std::vector<int32_t> pcell;
       if (d->kind == BCHAR_MESH_CARTESIAN) {
         double hmin = 1e300;
         ub.cell_vol = 1.0;
@@ -832,6 +921,8 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
           m->box_hi[a] = m->origin[a] + (double)m->n[a] * m->h[a];
         }
         m->n_cells = nc;
+        BCHAR_REQUIRE(!packed, BCHAR_E_INVALID_ARG,
+                      "PACKED is a simplex layout (SUBCELL packs Cartesian cells)");
         if (custom) {
           m->nbpc = 0;
           ub.r = 0;
@@ -851,8 +942,9 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         if (!custom) ub.rho = ub.cell_vol / (m->nbpc * ub.ball_vol);
         kvol.assign(nc, ub.cell_vol);
       } else {
-        BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE || custom, BCHAR_E_INVALID_ARG,
-                      "simplicial meshes take the EQUAL_MEASURE or CUSTOM layout");
+        BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE || custom || packed,
+                      BCHAR_E_INVALID_ARG,
+                      "simplicial meshes take the EQUAL_MEASURE, PACKED or CUSTOM layout");
         BCHAR_REQUIRE(d->vertices != nullptr && d->cells != nullptr, BCHAR_E_INVALID_ARG,
                       "vertices or cells is NULL");
         BCHAR_REQUIRE(d->n_vertices >= dim + 1 && d->n_simplices >= 1 &&
@@ -860,15 +952,16 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
                       BCHAR_E_INVALID_ARG, "n_vertices / n_simplices");
         nc = d->n_simplices;
         m->n_cells = nc;
-        m->nbpc = custom ? 0 : 1;
+        m->nbpc = custom || packed ? 0 : 1;
         simplex_geometry(d, sh);
         for (int a = 0; a < 3; ++a) {
           m->box_lo[a] = sh.lo[a];
           m->box_hi[a] = sh.hi[a];
         }
         kvol = sh.vol;
+        if (packed) packed_simplex_balls(sh, pballs, pcell);
       }
-      m->n_balls = custom ? d->n_balls : nc * m->nbpc;
+      m->n_balls = custom ? d->n_balls : (packed ? (int64_t)pcell.size() : nc * m->nbpc);
       BCHAR_REQUIRE(m->n_balls < ((int64_t)1 << 31) - 1, BCHAR_E_UNSUPPORTED,
                     "more than 2^31 balls");
       // phi: validate on the host
@@ -905,13 +998,15 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
           m->bmax = std::max(m->bmax, b[K]);
         }
         if (d->kind == BCHAR_MESH_SIMPLEX) {
-          simplex_upload(m, sh, b, !custom, s);
+          simplex_upload(m, sh, b, !custom && !packed, s);
         } else {
           m->b.reserve(sizeof(double) * nc);
           BCHAR_HIP(hipMemcpyAsync(m->b.p, b.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
                                    s));
         }
-        if (custom) custom_layout(m, d, d->balls, d->ball_cell, kvol, s);
+        if (custom) custom_layout(m, d->n_balls, d->balls, d->ball_cell, kvol, s);
+        if (packed)
+          custom_layout(m, (int64_t)pcell.size(), pballs.data(), pcell.data(), kvol, s);
         bchar::mesh_build_hash(m, s);
       }
     } catch (...) {

@@ -193,3 +193,69 @@ def test_lds_staging_same_bits(env, name):
     assert n1 == n0
     for x, y in zip(p1 + c1, p0 + c0):
         assert np.array_equal(x, y)
+
+
+def _packed_case(name):
+    if name == "tris":
+        mesh = inputs.triangulated_square(10, 0.1, 6)
+        vel = inputs.sample_velocity_grid((10, 10), inputs.rotation_stretch_2d)
+        return mesh, vel, 0.022, True
+    if name == "tets_porous":
+        mesh = inputs.kuhn_tets(4, 0.1, 8, phi=inputs.lognormal_phi(6 * 4 ** 3, 21))
+        vel = inputs.sample_velocity_grid((4, 4, 4), lambda p, t: inputs.swirl_3d(p, t))
+        return mesh, vel, 0.004, True
+    if name == "tets_compressible":
+        mesh = inputs.kuhn_tets(4, 0.1, 8)
+        vel = inputs.sample_velocity_grid((4, 4, 4),
+                                          lambda p, t: inputs.compressible_swirl_3d(p, t))
+        return mesh, vel, 0.0125, False
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["tris", "tets_porous", "tets_compressible"])
+def test_packed_simplex_layout(env, name):
+    """Several balls per simplex (layout PACKED): the library's balls equal
+    the oracle's rule bit for bit, and the step on them matches the
+    oracle's to the parity bars.  (Disjoint balls leave gaps: steps much
+    longer than these send the small corner balls into them, a void row.)"""
+    torch, bchar = env
+    _say(f"[gpu] packed layout {name}")
+    mesh, vel, dt, solenoidal = _packed_case(name)
+    M = bchar.Mesh(mesh, "packed")
+    c, r, cell = M.export_balls()
+    oc, orr, ocell = ogeo.simplex_packed_layout(mesh)
+    assert np.array_equal(cell, ocell)
+    assert np.array_equal(c, oc) and np.array_equal(r, orr)
+    dim = mesh["vertices"].shape[1]
+    assert np.mean(np.bincount(cell) == dim + 2) > 0.9
+    ref = otr.build_transfer(mesh, vel, dt, layout="packed", solenoidal=solenoidal)
+    opts = bchar.opts_default(keep_pairs=1,
+                              divergence=bchar.DIV_FREE if solenoidal else bchar.DIV_GENERAL)
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt, opts)
+    _say(f"    stats {T.stats}; oracle level {ref['qp']['level']}")
+    tr, rh = T.export_tracked()
+    assert np.array_equal(tr, ref["traced"]) and np.array_equal(rh, ref["r_hat"])
+    a, b = T.export_pairs()
+    assert np.array_equal(a, ref["pairs"][0]) and np.array_equal(b, ref["pairs"][1])
+    rp, col, V = T.export_csr(bchar.STAGE_V)
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(col, ref["col"])
+    assert np.max(np.abs(V - ref["V"])) <= 1e-13 * np.max(np.abs(ref["V"]))
+    assert T.stats["qp_level"] == ref["qp"]["level"]
+    c0 = inputs.uniform_c(mesh, 23)
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], c0)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= 1e-10
+    m0, m1 = M.mass(cin), M.mass(cout)
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+
+
+def test_packed_rejected_on_cartesian(env):
+    torch, bchar = env
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Mesh(inputs.cartesian_mesh((4, 4)), "packed")
+    assert ei.value.status == bchar.E_INVALID_ARG
