@@ -765,12 +765,25 @@ def run_transport(args, workload, precision, steps, warmup, D, tune):
     streams = [torch.cuda.Stream() for _ in range(D)]
     tuned = None
     if tune:
-        cands = [bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs, cycle_skip=v)
-                 for v in (0, 1)]
-        best, secs = bchar.tune_options([(M, vels[j % len(vels)], w["dt"]) for j in range(D)],
-                                        cands, streams, rounds=2)
+        jobs = [(M, vels[j % len(vels)], w["dt"]) for j in range(D)]
+        # the assembly's tile shape and LDS staging, timed on builds that
+        # stop after V (the same transfer bit for bit whichever is chosen)
+        shapes = [(a, l) for a in (0, 1, -1) for l in (0, 1)]
+        kc = [bchar.opts_default(precision=prec, stop_after=bchar.STAGE_V, tile_aspect=a,
+                                 lds_stage=l) for a, l in shapes]
+        kb, ksecs = bchar.tune_options(jobs, kc, streams, rounds=3)
+        aspect, lds = shapes[kb]
+        log(f"tuned: tile_aspect {aspect}, lds_stage {lds} "
+            f"({', '.join(f'{x:.4f}' for x in ksecs)} s)")
+        # the multigrid cycle, timed on whole builds
+        cands = [bchar.opts_default(precision=prec, cg_graphs=args.cg_graphs, cycle_skip=v,
+                                    tile_aspect=aspect, lds_stage=lds) for v in (0, 1)]
+        best, secs = bchar.tune_options(jobs, cands, streams, rounds=2)
         opts = cands[best]
-        tuned = {"option": "cycle_skip", "values": [0, 1], "seconds": secs, "chosen": best}
+        tuned = {"option": "cycle_skip", "values": [0, 1], "seconds": secs, "chosen": best,
+                 "assembly": {"options": ["tile_aspect", "lds_stage"],
+                              "values": [list(x) for x in shapes], "seconds": ksecs,
+                              "chosen": [aspect, lds]}}
         log(f"tuned: cycle_skip {best} ({secs[0]:.3f} s against {secs[1]:.3f} s)")
 
     # ---- phase 1: one build after another; the build kernel (one launch a

@@ -248,6 +248,15 @@ typedef struct {
                             than they save beyond); the same answer either
                             way up to the solver's tolerance             */
   int divergence;        /* BCHAR_DIV_FREE (default) or BCHAR_DIV_GENERAL  */
+  int tile_aspect;       /* Cartesian meshes: shape of the assembly's tiles
+                            of 256 / balls-per-cell cells.  0 (default): the
+                            most cubic power-of-two box (32 cells: 4x4x2,
+                            64 in 2D: 8x8); a in [-4, 4]: the last axis's
+                            extent divided (a > 0) or multiplied (a < 0)
+                            by 2^|a| and the others refitted (32 cells:
+                            a = 1 gives 8x4x1, a = -1 4x2x4).  The same
+                            transfer bit for bit; only the assembly's
+                            speed changes (a tuning knob)               */
 } bchar_opts;
 
 typedef struct {

@@ -63,7 +63,7 @@ class Opts(C.Structure):
                 ("warm_start", C.c_int), ("max_halvings", C.c_int),
                 ("cg_graphs", C.c_int), ("cycle_skip", C.c_int), ("lds_stage", C.c_int),
                 ("halve_on_level2", C.c_int), ("z_fuse_max_cells", C.c_int),
-                ("divergence", C.c_int)]
+                ("divergence", C.c_int), ("tile_aspect", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -443,6 +443,8 @@ void validate_opts(const bchar_opts& o) {
   BCHAR_REQUIRE(o.z_fuse_max_cells >= 0, BCHAR_E_INVALID_ARG, "opts.z_fuse_max_cells");
   BCHAR_REQUIRE(o.divergence == BCHAR_DIV_FREE || o.divergence == BCHAR_DIV_GENERAL,
                 BCHAR_E_INVALID_ARG, "opts.divergence");
+  BCHAR_REQUIRE(o.tile_aspect >= -4 && o.tile_aspect <= 4, BCHAR_E_INVALID_ARG,
+                "opts.tile_aspect");
 }
 
 void validate_velocity(const bchar_mesh_s* m, const bchar_velocity* u) {
@@ -479,7 +481,8 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   int64_t first_void = -1;
   bchar_status rc = assemble_v(m, t->tracked.as<double>(), t->r_hat.as<double>(),
                                t->general ? t->lam.as<double>() : nullptr, o.precision,
-                               o.keep_pairs != 0, o.lds_stage != 0, t, &first_void, s);
+                               o.keep_pairs != 0, o.lds_stage != 0, o.tile_aspect, t,
+                               &first_void, s);
   st.nnz = t->nnz;
   st.n_pairs = t->n_pairs;
   st.n_void_rows = t->n_void_rows;
@@ -819,6 +822,7 @@ void bchar_opts_default(bchar_opts* o) {
   o->lds_stage = 0;
   o->z_fuse_max_cells = 1 << 20;
   o->divergence = BCHAR_DIV_FREE;
+  o->tile_aspect = 0;
 }
 
 const char* bchar_status_string(bchar_status s) {

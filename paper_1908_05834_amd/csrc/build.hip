@@ -1302,7 +1302,12 @@ static void launch_assemble(int dim, int precision, const TileParams& P, bool ur
 // Tile shape of a uniform layout: a block of cells on a Cartesian mesh
 // (square-ish in the plane, so that the tile's tracked balls read few
 // hash rows), a run of consecutive cells otherwise.
-static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
+// Cartesian tiles of kTileThreads / nbpc cells: the most cubic power-of-
+// two box (256 cells -> 8x8x4, 32 -> 4x4x2; 2D 64 -> 8x8), or with
+// aspect a != 0 the last axis's extent divided (a > 0) or multiplied
+// (a < 0) by 2^|a|, the others refitted (32 cells: a = 1 -> 8x4x1,
+// a = -1 -> 4x2x4).  Rows come out in cell order whatever the shape.
+static void tile_shape(const bchar_mesh_s* m, int aspect, TileParams& P) {
   P.cells_per_tile = kTileThreads / m->nbpc;
   P.tx = P.ty = P.tz = 0;
   for (int a = 0; a < 3; ++a) {
@@ -1311,10 +1316,15 @@ static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
   }
   if (m->kind == BCHAR_MESH_CARTESIAN) {
     const int c = P.cells_per_tile;
+    auto shifted = [&](int e) {
+      for (int k = 0; k < aspect && e > 1; ++k) e /= 2;
+      for (int k = 0; k < -aspect && e < c; ++k) e *= 2;
+      return e;
+    };
     if (m->dim == 3) {
-      // 256 -> 8x8x4, 32 -> 4x4x2
       int tz = 1;
       while (tz * tz * tz * 4 < c) tz *= 2;
+      tz = shifted(tz);
       const int txy = c / tz;
       int tx = 1;
       while (tx * tx < txy) tx *= 2;
@@ -1322,10 +1332,11 @@ static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
       P.ty = txy / tx;
       P.tz = tz;
     } else {
-      int tx = 1;
-      while (tx * tx < c) tx *= 2;
-      P.tx = tx;
-      P.ty = c / tx;
+      int ty = 1;
+      while (ty * ty < c) ty *= 2;
+      ty = shifted(c / ty);
+      P.ty = ty;
+      P.tx = c / ty;
       P.tz = 1;
     }
     const int t3[3] = {P.tx, P.ty, P.tz};
@@ -1341,7 +1352,8 @@ static void tile_shape(const bchar_mesh_s* m, TileParams& P) {
 
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
                         const double* lam, int precision, bool keep_pairs, bool lds_stage,
-                        bchar_transfer_s* t, int64_t* first_void, hipStream_t s) {
+                        int tile_aspect, bchar_transfer_s* t, int64_t* first_void,
+                        hipStream_t s) {
   Arena& ws = t->ws;
   const int64_t nc = m->n_cells;
   TileParams P{};
@@ -1349,7 +1361,7 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.n_balls = m->n_balls;
   P.nbpc = m->nbpc;
   if (m->nbpc > 0) {
-    tile_shape(m, P);
+    tile_shape(m, tile_aspect, P);
   } else {
     P.ball_ptr = m->ball_ptr.as<int32_t>();
     P.tile_cell = m->tile_cell.as<int32_t>();

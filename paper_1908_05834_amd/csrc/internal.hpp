@@ -216,7 +216,8 @@ TargetInfo row_targets(const bchar_mesh_s* m, bchar_transfer_s* t, const double*
 // lam: per-ball log growth (non-solenoidal u) or null.
 bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_hat,
                         const double* lam, int precision, bool keep_pairs, bool lds_stage,
-                        bchar_transfer_s* t, int64_t* first_void, hipStream_t s);
+                        int tile_aspect, bchar_transfer_s* t, int64_t* first_void,
+                        hipStream_t s);
 
 // scaling (scaling.hip)
 struct Csc {

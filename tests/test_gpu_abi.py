@@ -259,3 +259,30 @@ def test_packed_rejected_on_cartesian(env):
     with pytest.raises(bchar.BcharError) as ei:
         bchar.Mesh(inputs.cartesian_mesh((4, 4)), "packed")
     assert ei.value.status == bchar.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("name", ["swirl32", "porous3d", "square2d"])
+def test_tile_aspect_same_bits(env, name):
+    """Every tile shape of the assembly gives the same pairs and the same
+    V, bit for bit (the tuner may pick any of them)."""
+    torch, bchar = env
+    _say(f"[gpu] tile aspects {name}")
+    if name == "swirl32":
+        w = inputs.swirl_hex(32)
+        mesh, vel, dt = w["mesh"], w["vel_fn"](3), w["dt"]
+    elif name == "porous3d":
+        w = inputs.porous_swirl_hex(8)
+        mesh, vel, dt = w["mesh"], w["vel_fn"](0), 0.05
+    else:
+        mesh = inputs.cartesian_mesh((40, 24))
+        vel, dt = inputs.sample_velocity(mesh, inputs.rotation_stretch_2d), 0.6
+    M = bchar.Mesh(mesh, "subcell")
+    U = bchar.VelocityLattice(vel)
+    out = {}
+    for a in (0, 1, 2, -1, -2):
+        T = bchar.Transfer.build(M, U, dt, bchar.opts_default(stop_after=bchar.STAGE_V,
+                                                              keep_pairs=1, tile_aspect=a))
+        out[a] = (T.export_pairs(), T.export_csr(bchar.STAGE_V))
+    for a in (1, 2, -1, -2):
+        for x, y in zip(out[a][0] + out[a][1], out[0][0] + out[0][1]):
+            assert np.array_equal(x, y), a
