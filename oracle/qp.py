@@ -102,9 +102,11 @@ def _dpsi(t, d, lo, hi):
     return out
 
 
-def feasible_lp(rows, cols, a, b_row, b_col, lo, hi):
+def feasible_lp(rows, cols, a, b_row, b_col, lo, hi, active=None):
     """Is {lo <= x <= hi, row/col sums of a(1+x) = b} non-empty?  Decided
-    with an LP on y = a(1+x) >= 0 plus slacks: minimise the total slack."""
+    with an LP on y = a(1+x) >= 0 plus slacks: minimise the total slack.
+    ``active`` (per cell, optional): only those rows and columns are
+    constrained."""
     nz = a.size
     nr, nc = len(b_row), len(b_col)
     ylo = a * (1.0 + lo) if np.isfinite(lo) else np.full(nz, -np.inf)
@@ -113,8 +115,13 @@ def feasible_lp(rows, cols, a, b_row, b_col, lo, hi):
     E = sp.vstack([
         sp.csr_matrix((np.ones(nz), (rows, np.arange(nz))), shape=(nr, nz)),
         sp.csr_matrix((np.ones(nz), (cols, np.arange(nz))), shape=(nc, nz)),
-    ])
-    m = nr + nc
+    ]).tocsr()
+    beq_all = np.concatenate([b_row, b_col])
+    if active is not None:
+        keep = np.concatenate([np.asarray(active), np.asarray(active)])
+        E = E[keep]
+        b_row, b_col = beq_all[keep], np.zeros(0)
+    m = E.shape[0]
     I = sp.identity(m, format="csr")
     Aeq = sp.hstack([E, I, -I]).tocsr()
     beq = np.concatenate([b_row, b_col])
@@ -160,7 +167,7 @@ def _cell_coordinates_matrix(rows, cols, w, nr):
                          shape=(2 * nr, 2 * nr))
 
 
-def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
+def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter, active=None):
     """Damped semismooth Newton on the dual; inputs already scaled so that
     max |b| = 1.  Returns (x, t, mu, nu, residual_inf, iterations, ok).
 
@@ -179,31 +186,43 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
     """
     nr, nc = r.size, s.size
     assert nr == nc, "rows and columns are both indexed by cells"
+    # cells whose row and column are unconstrained (ghost cells) keep
+    # multipliers 0: their residuals are dropped and their (s, g) unknowns
+    # removed from every Newton system
+    act = np.ones(nr, dtype=bool) if active is None else np.asarray(active, dtype=bool)
+    act2 = np.concatenate([act, act])
+    keep = np.nonzero(act2)[0]
+
+    def resid(x):
+        return np.where(act2, residual(rows, cols, a, x, r, s), 0.0)
+
     mu = np.zeros(nr)
     nu = np.zeros(nc)
     t = np.zeros(a.size)
-    rs = np.concatenate([r, s])
+    rs = np.where(act2, np.concatenate([r, s]), 0.0)
     off = rows != cols
     a2 = a * a
     x = np.clip(t, lo, hi)
-    F = residual(rows, cols, a, x, r, s)
+    F = resid(x)
     for it in range(1, max_iter + 1):
         fn = float(np.max(np.abs(F)))
         if fn <= tol:
             return x, t, mu, nu, fn, it - 1, True
         free = (t > lo) & (t < hi)
-        Jz = _cell_coordinates_matrix(rows, cols, a2 * free, nr)
+        Jz = _cell_coordinates_matrix(rows, cols, a2 * free, nr)[keep][:, keep]
         dg = Jz.diagonal()
         dg = np.where(dg > 0, dg, max(float(dg.max(initial=0.0)), 1e-300))
         Jz = Jz + sp.diags(1e-14 * dg)
         # right-hand side: y-space (-F_row, F_col) mapped to (s, g)
         fr, fc = -F[:nr], F[nr:]
-        bz = np.concatenate([fr + fc, 0.5 * (fr - fc)])
+        bz = np.concatenate([fr + fc, 0.5 * (fr - fc)])[keep]
         Dh = 1.0 / np.sqrt(Jz.diagonal())
         lu = spla.splu((sp.diags(Dh) @ Jz @ sp.diags(Dh)).tocsc())
-        z = Dh * lu.solve(Dh * bz)
+        zk = Dh * lu.solve(Dh * bz)
         for _ in range(2):
-            z = z + Dh * lu.solve(Dh * (bz - Jz @ z))
+            zk = zk + Dh * lu.solve(Dh * (bz - Jz @ zk))
+        z = np.zeros(2 * nr)
+        z[keep] = zk
         zs, zg = z[:nr], z[nr:]
         dt = a * np.where(off, (zs[rows] - zs[cols]) + 0.5 * (zg[rows] + zg[cols]), zg[rows])
         dmu = zs + 0.5 * zg
@@ -221,7 +240,7 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
             # accept a full step that shrinks the residual
             if step == 1.0:
                 xt = np.clip(t + dt, lo, hi)
-                Ft = residual(rows, cols, a, xt, r, s)
+                Ft = resid(xt)
                 if float(np.max(np.abs(Ft))) < 0.5 * fn:
                     break
             step *= 0.5
@@ -230,7 +249,7 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
         t = t + step * dt
         mu, nu = mu + step * dmu, nu + step * dnu
         x = np.clip(t, lo, hi)
-        F = residual(rows, cols, a, x, r, s)
+        F = resid(x)
         if not np.all(np.isfinite(F)) or float(np.max(np.abs(t))) > 1e12:
             return x, t, mu, nu, float(np.max(np.abs(F))), it, False
     fn = float(np.max(np.abs(F)))
@@ -238,10 +257,12 @@ def _newton(rows, cols, a, r, s, lo, hi, tol, max_iter):
 
 
 def solve_mass_qp(rows, cols, a, b_row, b_col, box_policy="paper_then_relax",
-                  tol=1e-14, max_iter=200, levels=None):
+                  tol=1e-14, max_iter=200, levels=None, active=None):
     """Unique minimiser of eq. opti_masscons; see the module docstring.
 
-    ``tol`` bounds max |A_hat(1+x) - b| relative to max |b|.
+    ``tol`` bounds max |A_hat(1+x) - b| relative to max |b|.  ``active``
+    (per cell, optional): the cells whose row and column are constrained
+    (ghost cells, Sec. 3.2, Remark on inflow and outflow, are not).
     Returns a dict: ``x`` (n_z), ``mu``, ``nu`` (dual, in the units of the
     scaled problem a / max|b|), ``level``, ``residual`` (relative),
     ``iterations``, ``lo``, ``hi``.
@@ -258,12 +279,13 @@ def solve_mass_qp(rows, cols, a, b_row, b_col, box_policy="paper_then_relax",
         levels = (0,) if box_policy == "strict" else (0, 1, 2)
     for level in levels:
         lo, hi = BOX_LEVELS[level]
-        x, t, mu, nu, res, it, ok = _newton(rows, cols, As, r, s, lo, hi, tol, max_iter)
+        x, t, mu, nu, res, it, ok = _newton(rows, cols, As, r, s, lo, hi, tol, max_iter,
+                                            active)
         if ok:
             return {"x": x, "t": t, "mu": mu, "nu": nu, "level": level, "residual": res,
                     "iterations": it, "lo": lo, "hi": hi, "scale": scale}
         if level < 2:
-            feas, _ = feasible_lp(rows, cols, As, bR, bC, lo, hi)
+            feas, _ = feasible_lp(rows, cols, As, bR, bC, lo, hi, active)
             if feas:
                 raise QPNotConverged(f"Newton stalled at level {level} (residual {res:.3e})"
                                      " although the LP finds the box feasible")
@@ -272,7 +294,7 @@ def solve_mass_qp(rows, cols, a, b_row, b_col, box_policy="paper_then_relax",
     raise QPInfeasible("box infeasible at every allowed level")
 
 
-def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol):
+def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol, active=None):
     """Certificate of optimality for a returned (x, lambda): x lies in the
     box, meets every constraint to ``tol`` (relative to ``scale``), and
     equals clip(a (mu_i + nu_j)) entrywise up to the rounding of the sum
@@ -285,7 +307,10 @@ def verify_kkt(rows, cols, a, b_row, b_col, x, mu, nu, lo, hi, scale, tol):
     stat = float(np.max((np.abs(np.clip(t, lo, hi) - x)) / (1.0 + mag), initial=0.0))
     box = float(max(np.max(lo - x, initial=-np.inf), np.max(x - hi, initial=-np.inf), 0.0))
     r, s = constraint_rhs(rows, cols, As, np.asarray(b_row) / scale, np.asarray(b_col) / scale)
-    prim = float(np.max(np.abs(residual(rows, cols, As, x, r, s)), initial=0.0))
+    F = residual(rows, cols, As, x, r, s)
+    if active is not None:
+        F = np.where(np.concatenate([active, active]), F, 0.0)
+    prim = float(np.max(np.abs(F), initial=0.0))
     return {"stationarity": stat, "box": box, "primal": prim,
             "ok": stat <= 1e-12 and box == 0.0 and prim <= tol}
 

@@ -112,7 +112,7 @@ def row_targets(nc, ball_cell, ball_mass, b, rows, cols):
 
 
 def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
-                    traced, r_hat, ia, ib, precision="fp64", lam=None):
+                    traced, r_hat, ia, ib, precision="fp64", lam=None, ghost=None):
     """V_{K_hat, M} of eq. ball_int, as CSR.
 
     For a candidate pair (tracked ball a of cell K, residing ball b of cell
@@ -146,7 +146,12 @@ def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
     omega = rho[cb] * phi[cb] * lens
     nballs = ball_cell.size
     S = np.bincount(ia, weights=omega, minlength=nballs)
-    void = np.nonzero(S <= 0.0)[0]
+    bad = S <= 0.0
+    if ghost is not None:
+        # a ghost cell's ball tracked into nothing carries its mass out of
+        # the problem (Sec. 3.2, Remark on inflow and outflow)
+        bad &= ~np.asarray(ghost)[ball_cell]
+    void = np.nonzero(bad)[0]
     if void.size:
         raise VoidRowError(int(void[0]), int(ball_cell[void[0]]))
     mass = tracked_ball_mass(ball_cell, radii, rho, phi, dim, lam)
@@ -158,30 +163,43 @@ def initial_volumes(nc, dim, ball_cell, centres, radii, rho, phi,
 # Sec. 3.2: mass adjustment sweeps, eq. volAdj
 # --------------------------------------------------------------------------
 
-def scaling_sweeps(row_ptr, col, val, b_loc, b_glob, n_sweeps):
+def scaling_sweeps(row_ptr, col, val, b_loc, b_glob, n_sweeps, active=None):
     """A^(N) from A^(0) = V by N sweeps of eq. volAdj.
 
     Each sweep first scales every column j to sum |M_j|_phi, then every row
     i to sum |F_{-dt}(K_i)|_phi (= |K_i|_phi for solenoidal u, eq.
     exactVol_traceback).  Rows therefore hold exactly after every sweep.
+    ``active`` (per cell, optional): only those rows and columns are scaled
+    (ghost cells have no target).
     """
     a = np.array(val, dtype=np.float64, copy=True)
     rows = csr_rows(row_ptr)
     nc = row_ptr.size - 1
+    act = None if active is None else np.asarray(active, dtype=bool)
     for _ in range(int(n_sweeps)):
         cs = np.bincount(col, weights=a, minlength=nc)
-        if np.any(cs <= 0.0):
-            raise VoidColumnError(int(np.nonzero(cs <= 0.0)[0][0]))
-        a = a * (np.asarray(b_glob)[col] / cs[col])
+        bad = cs <= 0.0 if act is None else (cs <= 0.0) & act
+        if np.any(bad):
+            raise VoidColumnError(int(np.nonzero(bad)[0][0]))
+        if act is None:
+            a = a * (np.asarray(b_glob)[col] / cs[col])
+        else:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                a = a * np.where(act[col], np.asarray(b_glob)[col] / cs[col], 1.0)
         rs = np.bincount(rows, weights=a, minlength=nc)
-        a = a * (np.asarray(b_loc)[rows] / rs[rows])
+        if act is None:
+            a = a * (np.asarray(b_loc)[rows] / rs[rows])
+        else:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                a = a * np.where(act[rows], np.asarray(b_loc)[rows] / rs[rows], 1.0)
     return a
 
 
-def check_columns(col, val, nc):
+def check_columns(col, val, nc, active=None):
     cs = np.bincount(col, weights=val, minlength=nc)
-    if np.any(cs <= 0.0):
-        raise VoidColumnError(int(np.nonzero(cs <= 0.0)[0][0]))
+    bad = cs <= 0.0 if active is None else (cs <= 0.0) & np.asarray(active)
+    if np.any(bad):
+        raise VoidColumnError(int(np.nonzero(bad)[0][0]))
 
 
 # --------------------------------------------------------------------------
@@ -197,11 +215,26 @@ def apply(row_ptr, col, val, b_loc, c):
     return num / np.asarray(b_loc, dtype=np.float64)
 
 
-def mass(phi, cell_vol, c):
-    """sum_K phi_K |K| c_K (Sec. 2.1), correctly rounded (math.fsum)."""
+def mass(phi, cell_vol, c, active=None):
+    """sum_K phi_K |K| c_K (Sec. 2.1), correctly rounded (math.fsum); over
+    the ``active`` cells only when given (the domain without its ghost
+    cells)."""
     terms = np.asarray(phi, dtype=np.float64) * np.asarray(cell_vol, dtype=np.float64) \
         * np.asarray(c, dtype=np.float64)
+    if active is not None:
+        terms = terms[np.asarray(active, dtype=bool)]
     return math.fsum(terms.tolist())
+
+
+def ghost_cells(n, n_ghost):
+    """Ghost flag of every cell of a Cartesian grid of n cells per axis
+    (ids x-fastest): the cells within n_ghost of the grid's boundary."""
+    dim = len(n)
+    ids = np.indices(tuple(int(v) for v in n[::-1])).reshape(dim, -1)[::-1]
+    g = np.zeros(ids.shape[1], dtype=bool)
+    for a in range(dim):
+        g |= (ids[a] < n_ghost) | (ids[a] >= int(n[a]) - n_ghost)
+    return g
 
 
 # --------------------------------------------------------------------------
@@ -211,7 +244,7 @@ def mass(phi, cell_vol, c):
 def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
                    precision="fp64", box_policy="paper_then_relax", stop_after="all",
                    traced_override=None, balls_override=None, qp_tol=1e-14,
-                   solenoidal=True):
+                   solenoidal=True, n_ghost=0):
     """Transfer matrix of one time step: Algorithm 1 of Sec. 3.3.
 
     ``mesh``: dict with ``n``, ``origin``, ``h`` (Cartesian) or ``kind =
@@ -227,6 +260,16 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     the row targets from eq. volTracked (``row_targets``) instead of
     |K|_phi; the column targets stay |M|_phi and the update still divides
     by |K|_phi (eq. phys-inter-ELLAM).
+
+    ``n_ghost > 0`` (Cartesian meshes; Sec. 3.2, Remark on inflow and
+    outflow, option b): the grid's outer ``n_ghost`` layers are ghost cells.
+    They carry balls and are tracked like the others, but their rows and
+    columns have no target: they are not scaled, the least-change problem
+    constrains the interior cells' rows and columns only (the ghost cells'
+    multipliers stay 0), and a ghost ball tracked into nothing or a ghost
+    column that nothing reaches is no void.  Material then enters the
+    interior from ghost cells (whose concentrations are the inflow data)
+    and leaves it into ghost cells.
     """
     dim = geo.mesh_dim(mesh)
     nc = geo.mesh_n_cells(mesh)
@@ -259,6 +302,13 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     b = phi * kvol                      # |K|_phi = b_loc = b_glob (eq. exactVol_traceback)
     out = {"centres": centres, "radii": radii, "ball_cell": bcell, "rho": rho, "b": b,
            "cell_vol": kvol}
+    ghost = active = None
+    if n_ghost:
+        if geo.is_simplex(mesh) or not solenoidal:
+            raise ValueError("ghost cells: Cartesian meshes and solenoidal steps")
+        ghost = ghost_cells(mesh["n"], int(n_ghost))
+        active = ~ghost
+    out["ghost"] = ghost
     lam = None
     if solenoidal:
         if traced_override is None:
@@ -278,7 +328,7 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     if stop_after == "pairs":
         return out
     rp, cl, V = initial_volumes(nc, dim, bcell, centres, radii, rho, phi, traced, r_hat,
-                                ia, ib, precision=precision, lam=lam)
+                                ia, ib, precision=precision, lam=lam, ghost=ghost)
     out["row_ptr"], out["col"], out["V"] = rp, cl, V
     if solenoidal:
         b_loc = b
@@ -289,12 +339,13 @@ def build_transfer(mesh, vel, dt, layout="subcell", n_sweeps=10, substeps=1,
     out["b_loc"] = b_loc
     if stop_after == "v":
         return out
-    check_columns(cl, V, nc)
-    AN = scaling_sweeps(rp, cl, V, b_loc, b, n_sweeps)
+    check_columns(cl, V, nc, active)
+    AN = scaling_sweeps(rp, cl, V, b_loc, b, n_sweeps, active)
     out["AN"] = AN
     if stop_after == "sinkhorn":
         return out
-    res = solve_mass_qp(csr_rows(rp), cl, AN, b_loc, b, box_policy=box_policy, tol=qp_tol)
+    res = solve_mass_qp(csr_rows(rp), cl, AN, b_loc, b, box_policy=box_policy, tol=qp_tol,
+                        active=active)
     out["qp"] = res
     out["A"] = AN * (1.0 + res["x"])
     return out
