@@ -178,6 +178,24 @@ typedef struct {
                             with at least one ball and at most 256; rho_K
                             is |K| / sum of the measures of K's balls
                             (eq. def:porous.density); copied              */
+  int64_t n_ghost;       /* CARTESIAN: layers of ghost cells on every side
+                            (Sec. 3.2, Remark on inflow and outflow, option
+                            b), 0 (default) for none; n[a] > 2 n_ghost.  The
+                            grid described by n, origin, h includes them.
+                            Ghost cells carry balls and are tracked like
+                            the others, but their rows and columns have no
+                            target: the scaling leaves them alone, the
+                            least-change problem constrains the interior
+                            cells' rows and columns only (the ghost cells'
+                            multipliers stay 0), and a ghost ball tracked
+                            into nothing or a ghost column nothing reaches
+                            is no void.  Material enters the interior from
+                            ghost cells, whose concentrations the caller
+                            sets to the inflow data before every update,
+                            and leaves it into ghost cells.  bchar_mass
+                            sums the interior cells; the ghost entries of
+                            an update's output mean nothing.  Solenoidal
+                            steps only (DIV_GENERAL: UNSUPPORTED)         */
 } bchar_mesh_desc;
 
 /* Velocity u^{(n+1)} frozen over the time step (Sec. 1.2, eq. hyp:un) as

@@ -596,6 +596,8 @@ bchar_status build_once(bchar_mesh_s* m, bchar_transfer_s* t, const bchar_veloci
   BCHAR_REQUIRE(o.precision != BCHAR_FP32_VOLUME || m->phi_const, BCHAR_E_UNSUPPORTED,
                 "FP32_VOLUME tracks in binary32 and needs a constant porosity; FP32_LENS "
                 "tracks in binary64");
+  BCHAR_REQUIRE(m->n_ghost == 0 || o.divergence == BCHAR_DIV_FREE, BCHAR_E_UNSUPPORTED,
+                "ghost cells take solenoidal steps only");
   BCHAR_REQUIRE(o.precision != BCHAR_FP32_VOLUME || o.divergence == BCHAR_DIV_FREE,
                 BCHAR_E_UNSUPPORTED,
                 "FP32_VOLUME tracks in binary32 and needs a solenoidal u; FP32_LENS tracks in "
@@ -927,6 +929,11 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         m->n_cells = nc;
         BCHAR_REQUIRE(!packed, BCHAR_E_INVALID_ARG,
                       "PACKED is a simplex layout (SUBCELL packs Cartesian cells)");
+        BCHAR_REQUIRE(d->n_ghost >= 0, BCHAR_E_INVALID_ARG, "n_ghost must be >= 0");
+        for (int a = 0; a < dim; ++a)
+          BCHAR_REQUIRE(d->n[a] > 2 * d->n_ghost, BCHAR_E_INVALID_ARG,
+                        "n_ghost layers leave no interior cell");
+        m->n_ghost = d->n_ghost;
         if (custom) {
           m->nbpc = 0;
           ub.r = 0;
@@ -949,6 +956,8 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
         BCHAR_REQUIRE(d->layout == BCHAR_LAYOUT_EQUAL_MEASURE || custom || packed,
                       BCHAR_E_INVALID_ARG,
                       "simplicial meshes take the EQUAL_MEASURE, PACKED or CUSTOM layout");
+        BCHAR_REQUIRE(d->n_ghost == 0, BCHAR_E_INVALID_ARG,
+                      "ghost cells are built for Cartesian meshes");
         BCHAR_REQUIRE(d->vertices != nullptr && d->cells != nullptr, BCHAR_E_INVALID_ARG,
                       "vertices or cells is NULL");
         BCHAR_REQUIRE(d->n_vertices >= dim + 1 && d->n_simplices >= 1 &&
@@ -990,6 +999,22 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
       m->phi.reserve(sizeof(double) * nc);
       BCHAR_HIP(hipMemcpyAsync(m->phi.p, hphi.data(), sizeof(double) * nc,
                                hipMemcpyHostToDevice, s));
+      std::vector<uint8_t> hghost;
+      if (m->n_ghost > 0) {
+        // cells within n_ghost of the grid's boundary (ids x-fastest)
+        hghost.assign(nc, 0);
+        const int64_t g = m->n_ghost;
+        for (int64_t K = 0; K < nc; ++K) {
+          const int64_t idx[3] = {K % m->n[0], (K / m->n[0]) % m->n[1],
+                                  K / (m->n[0] * m->n[1])};
+          bool gh = false;
+          for (int a = 0; a < dim; ++a) gh = gh || idx[a] < g || idx[a] >= m->n[a] - g;
+          hghost[K] = gh ? 1 : 0;
+        }
+        m->ghost.reserve(nc);
+        BCHAR_HIP(hipMemcpyAsync(m->ghost.p, hghost.data(), nc, hipMemcpyHostToDevice, s));
+        BCHAR_HIP(hipStreamSynchronize(s));
+      }
       if (d->kind == BCHAR_MESH_CARTESIAN && !custom) {
         m->bmax = pmax * ub.cell_vol;
         bchar::mesh_build_cartesian(m, ub, s);
@@ -1026,6 +1051,7 @@ bchar_status bchar_mesh_destroy(bchar_mesh m) {
   if (!m) return BCHAR_OK;
   (void)hipDeviceSynchronize();
   m->phi.release();
+  m->ghost.release();
   m->b.release();
   m->cen.release();
   m->cen32.release();

@@ -50,15 +50,17 @@ void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, 
 
 constexpr int kMassBlocks = 512;
 
+// ghost (optional): cells left out (ghost cells hold boundary data)
 __global__ void __launch_bounds__(256) k_mass_part(const double* __restrict__ b,
-                                                   const double* __restrict__ c, int64_t n,
+                                                   const double* __restrict__ c,
+                                                   const uint8_t* __restrict__ ghost, int64_t n,
                                                    double* __restrict__ part) {
   __shared__ double sh[32];
   CSum acc;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     // phi_K |K| c_K as the product of two roundings; the sum is compensated
-    acc.add(b[i] * c[i]);
+    if (!ghost || !ghost[i]) acc.add(b[i] * c[i]);
   }
   CSum tot = block_csum(acc, sh);
   if (threadIdx.x == 0) {
@@ -87,7 +89,8 @@ double porous_mass(const bchar_mesh_s* m, const double* c, Arena& ws, hipStream_
   double* part = ws.get<double>(2 * kMassBlocks + 1);
   {
     ::bchar::ProfScope ps_("k_mass_part", s);
-    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->n_cells, part);
+    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->ghost.as<uint8_t>(),
+                                            m->n_cells, part);
   }
   BCHAR_HIP(hipGetLastError());
   {
@@ -134,7 +137,8 @@ void porous_mass_into(const bchar_mesh_s* m, const double* c, double* d_out, hip
   double* part = mass_scratch();
   {
     ::bchar::ProfScope ps_("k_mass_part", s);
-    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->n_cells, part);
+    k_mass_part<<<kMassBlocks, 256, 0, s>>>(m->b.as<double>(), c, m->ghost.as<uint8_t>(),
+                                            m->n_cells, part);
   }
   BCHAR_HIP(hipGetLastError());
   {

@@ -773,6 +773,7 @@ struct TileParams {
   const double* phi;        // per cell
   const double* bvol;       // per ball, |B_{K,s}|
   const double* lam;        // per ball log growth (non-solenoidal u), or null
+  const uint8_t* ghost;     // per cell ghost flag, or null (no ghost cells)
   const double* tracked;    // dim * n_balls
   const double* r_hat;      // n_balls
   const int32_t* bucket_start;
@@ -1094,7 +1095,9 @@ __global__ void __launch_bounds__(kTileThreads) k_assemble(TileParams P) {
   __syncthreads();   // the staged block is dead from here on (merge arrays share its room)
   s_ucnt[tid] = 0;   // void marks of the local cells until the scan below
   __syncthreads();
-  if (b >= 0 && !(S > 0.0)) {
+  // a ghost cell's ball that meets nothing carries its mass out of the
+  // problem: no void
+  if (b >= 0 && !(S > 0.0) && !(P.ghost && P.ghost[K])) {
     atomicMin(&P.flags[kFlagFirstVoid], (int32_t)b);
     atomicOr(&s_ucnt[lc], 1);
   }
@@ -1379,6 +1382,7 @@ bchar_status assemble_v(bchar_mesh_s* m, const double* tracked, const double* r_
   P.phi = m->phi.as<double>();
   P.bvol = m->bvol.as<double>();
   P.lam = lam;
+  P.ghost = m->ghost.as<uint8_t>();
   P.tracked = tracked;
   P.r_hat = r_hat;
   P.bucket_start = m->bucket_start.as<int32_t>();

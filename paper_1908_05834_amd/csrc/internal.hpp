@@ -114,6 +114,10 @@ struct bchar_mesh_s {
   // layouts with a varying number of balls per cell: first ball of every
   // cell, cell of every ball, and tiles of whole cells with at most 256
   // balls each (first cell of every tile)
+  // ghost cells (Cartesian, n_ghost layers on every side): flag per cell
+  // (uint8), empty when there are none
+  int64_t n_ghost = 0;
+  bchar::DBuf ghost;           // uint8 n_cells
   bchar::DBuf ball_ptr;        // int32 n_cells + 1
   bchar::DBuf ball_cell;       // int32 n_balls
   bchar::DBuf tile_cell;       // int32 n_tiles + 1

@@ -1477,6 +1477,7 @@ struct ZCells {
   double* tau_s;         // relative shifts
   double* tau_g;
   double* bi;            // 3 per cell: inverse of the 2x2 cell block (ss, sg, gg)
+  const uint8_t* ghost;  // per cell: unconstrained row and column (ghost cell), or null
 };
 
 __global__ void k_diag_pos(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
@@ -1510,9 +1511,11 @@ __global__ void k_zcells(ZCells Z, double rel, double mu) {
   const double A = A0 + ts, C = C0 + tg, B = 0.5 * (R - Cs);
   // A C - B^2 written as a sum of non-negative terms
   const double det = (R + Cs) * wkk + R * Cs + ts * C0 + tg * A0 + ts * tg;
-  Z.bi[3 * K + 0] = C / det;
-  Z.bi[3 * K + 1] = -B / det;
-  Z.bi[3 * K + 2] = A / det;
+  // a ghost cell's (s, g) stay 0: a zero block keeps every sweep off them
+  const bool gh = Z.ghost && Z.ghost[K];
+  Z.bi[3 * K + 0] = gh ? 0.0 : C / det;
+  Z.bi[3 * K + 1] = gh ? 0.0 : -B / det;
+  Z.bi[3 * K + 2] = gh ? 0.0 : A / det;
 }
 
 // out = J_z z for cell K
@@ -1615,6 +1618,7 @@ __global__ void __launch_bounds__(kT) k_zop(ZCells Z, const double* __restrict__
   if (K < Z.n) {
     double os, og;
     zapply_cell(Z, z, z + Z.n, K, os, og);
+    if (Z.ghost && Z.ghost[K]) os = og = 0.0;   // ghost unknowns held at 0
     out[K] = os;
     out[Z.n + K] = og;
     acc.add(z[K] * os);
@@ -1695,8 +1699,9 @@ __global__ void __launch_bounds__(kT) k_zresid(ZCells Z, const double* __restric
   if (K >= Z.n) return;
   double os, og;
   zapply_cell(Z, x, x + Z.n, K, os, og);
-  r[K] = b[K] - os;
-  r[Z.n + K] = b[Z.n + K] - og;
+  const bool gh = Z.ghost && Z.ghost[K];
+  r[K] = gh ? 0.0 : b[K] - os;
+  r[Z.n + K] = gh ? 0.0 : b[Z.n + K] - og;
 }
 
 // coarse (cell) residual: y-space residual of the rows attached to M and
@@ -1721,9 +1726,10 @@ __global__ void k_zrestrict(const int32_t* __restrict__ mptr, const int32_t* __r
 
 // x += P e: row K takes e[best K], column K takes e[K]
 __global__ void k_zprolong(const int32_t* __restrict__ best, const double* __restrict__ e,
-                           int64_t n, double* __restrict__ x) {
+                           const uint8_t* __restrict__ ghost, int64_t n,
+                           double* __restrict__ x) {
   const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= n) return;
+  if (K >= n || (ghost && ghost[K])) return;
   const double er = e[best[K]], ec = e[K];
   x[K] += 0.5 * (er + ec);
   x[n + K] += er - ec;
@@ -1781,7 +1787,7 @@ static bool zprecondition(ZPrecond& P, const double* r, double* z, hipStream_t s
   vcycle(*P.H, 1, s);
   {
     ::bchar::ProfScope ps_("k_zprolong", s);
-    k_zprolong<<<gb, kT, 0, s>>>(P.Z.best, L1.x, n, x);
+    k_zprolong<<<gb, kT, 0, s>>>(P.Z.best, L1.x, P.Z.ghost, n, x);
   }
   for (int k = 0; k < P.post; ++k) {
     double* out = (k + 1 == P.post) ? z : x2;
@@ -1939,6 +1945,16 @@ __global__ void k_group_fix(int64_t n, const int32_t* __restrict__ lab,
   const double dr = dm[lab[K]], dc = dm[lab[n + K]];
   bz[K] -= dr + dc;
   bz[n + K] -= 0.5 * (dr - dc);
+}
+
+// residuals of ghost cells' rows and columns (no target) set to 0
+__global__ void k_zero_ghost(const uint8_t* __restrict__ ghost, int64_t n,
+                             double* __restrict__ F) {
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K < n && ghost[K]) {
+    F[K] = 0.0;
+    F[n + K] = 0.0;
+  }
 }
 
 __global__ void k_sub_scalar(double* __restrict__ v, const double* __restrict__ sum,
@@ -2514,6 +2530,16 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   P.Z.tau_s = ws.get<double>(n);
   P.Z.tau_g = ws.get<double>(n);
   P.Z.bi = ws.get<double>(3 * n);
+  P.Z.ghost = m->ghost.as<uint8_t>();
+  // the constant-s direction is removed from every system unless ghost
+  // cells (multipliers held at 0) anchor the multipliers
+  const double inv_mean = P.Z.ghost ? 0.0 : 1.0 / (double)n;
+  auto zero_ghost = [&](double* v) {
+    if (!P.Z.ghost) return;
+    ::bchar::ProfScope ps_("k_zero_ghost", s);
+    k_zero_ghost<<<gn, kT, 0, s>>>(P.Z.ghost, n, v);
+    BCHAR_HIP(hipGetLastError());
+  };
   P.x = ws.get<double>(n2);
   P.x2 = ws.get<double>(n2);
   P.res = ws.get<double>(n2);
@@ -2639,7 +2665,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     red.sum(cr, n, 12);
     {
       ::bchar::ProfScope ps_("k_sub_scalar", s);
-      k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, 1.0 / (double)n, n);
+      k_sub_scalar<<<gn, kT, 0, s>>>(cr, red.out + 12, inv_mean, n);
     }
     if (from_cx) {
       // start from the solution already in cx: r = rhs - J cx
@@ -2709,7 +2735,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     red.sum(cx, n, 13);
     {
       ::bchar::ProfScope ps_("k_zdual_dir", s);
-      k_zdual_dir<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, cx, red.out + 13, 1.0 / (double)n, n,
+      k_zdual_dir<<<gn, kT, 0, s>>>(Q.rptr, Q.col, Q.a, cx, red.out + 13, inv_mean, n,
                                     dmu, dnu, Q.dt);
     }
     BCHAR_HIP(hipGetLastError());
@@ -2732,6 +2758,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
                                      Q.rr, Q.ss, n, Q.F);
       }
+      zero_ghost(Q.F);
       red.maxabs(Q.F, n2, 0);
       fn = red.fetch(0);
       if (!(fn == fn)) return false;
@@ -2797,6 +2824,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
           k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, Q.dt, 1.0, lo, hi,
                                        Q.rr, Q.ss, n, cq);
         }
+        zero_ghost(cq);
         red.maxabs(cq, n2, 14);
         full = red.fetch(14) < 0.5 * fn;
       }
@@ -2852,7 +2880,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_zdual_acc", s);
-        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, step, n, zdual);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, inv_mean, step, n, zdual);
       }
       BCHAR_HIP(hipGetLastError());
       red.maxabs(Q.t, nnz, 15);
@@ -2938,6 +2966,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         ::bchar::ProfScope ps_("k_ipm_rhs", s);
         k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
       }
+      zero_ghost(rp);
+      zero_ghost(Q.F);
       BCHAR_HIP(hipGetLastError());
       red.maxabs(rp, n2, 1);
       red.maxabs(Q.F, n2, 5);
@@ -3022,6 +3052,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         ::bchar::ProfScope ps_("k_ipm_rhs", s);
         k_ipm_rhs<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, I, Q.rr, Q.ss, n, rp, Q.F);
       }
+      zero_ghost(rp);
+      zero_ghost(Q.F);
       // the corrector's system differs from the predictor's in the
       // right-hand side only: start CG from the predictor's solution
       if (pcg(Q.F, cg_tol, true, o.qp_max_cg) >= o.qp_max_cg) {
@@ -3041,7 +3073,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_zdual_acc", s);
-        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, ad, n, zdual);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, inv_mean, ad, n, zdual);
       }
       BCHAR_HIP(hipGetLastError());
     }
@@ -3087,6 +3119,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         k_residual_sides<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, side, lo, hi,
                                            Q.rr, Q.ss, n, Q.F);
       }
+      zero_ghost(Q.F);
       {
         ::bchar::ProfScope ps_("k_side_weights", s);
         k_side_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, side, nnz, L0.w);
@@ -3099,13 +3132,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       }
       {
         ::bchar::ProfScope ps_("k_zdual_acc", s);
-        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, 1.0 / (double)n, 1.0, n, zdual);
+        k_zdual_acc<<<gn, kT, 0, s>>>(cx, red.out + 13, inv_mean, 1.0, n, zdual);
       }
       {
         ::bchar::ProfScope ps_("k_residual", s);
         k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0, lo, hi,
                                      Q.rr, Q.ss, n, Q.F);
       }
+      zero_ghost(Q.F);
       red.maxabs(Q.F, n2, 0);
       const double f = red.fetch(0);
       if (trace_enabled())

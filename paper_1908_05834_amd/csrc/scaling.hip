@@ -53,12 +53,17 @@ __global__ void k_gather_f64(const double* __restrict__ src, const int32_t* __re
   if (e < n) dst[e] = src[idx[e]];
 }
 
+// ghost (optional): cells without targets (ghost cells), left unscaled
 __global__ void k_col_scale(const int32_t* __restrict__ cptr, const int32_t* __restrict__ crow,
                             const double* __restrict__ vc, const double* __restrict__ R,
-                            const double* __restrict__ b, int64_t n, double* __restrict__ C,
-                            int32_t* __restrict__ void_col) {
+                            const double* __restrict__ b, const uint8_t* __restrict__ ghost,
+                            int64_t n, double* __restrict__ C, int32_t* __restrict__ void_col) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  if (ghost && ghost[j]) {
+    C[j] = 1.0;
+    return;
+  }
   CSum acc;
   for (int32_t e = cptr[j]; e < cptr[j + 1]; ++e) acc.add(R[crow[e]] * vc[e]);
   const double cs = acc.value();
@@ -73,9 +78,14 @@ __global__ void k_col_scale(const int32_t* __restrict__ cptr, const int32_t* __r
 
 __global__ void k_row_scale(const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
                             const double* __restrict__ v, const double* __restrict__ C,
-                            const double* __restrict__ b, int64_t n, double* __restrict__ R) {
+                            const double* __restrict__ b, const uint8_t* __restrict__ ghost,
+                            int64_t n, double* __restrict__ R) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (ghost && ghost[i]) {
+    R[i] = 1.0;
+    return;
+  }
   CSum acc;
   for (int32_t k = rptr[i]; k < rptr[i + 1]; ++k) acc.add(v[k] * C[col[k]]);
   const double rs = acc.value();
@@ -94,12 +104,14 @@ __global__ void k_apply_scaling(const int32_t* __restrict__ rptr, const int32_t*
 
 // max_j |sum_i a_ij / b_j - 1| over the final matrix (CSC order)
 __global__ void k_col_err(const int32_t* __restrict__ cptr, const int32_t* __restrict__ pos,
-                          const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                          const double* __restrict__ a, const double* __restrict__ b,
+                          const uint8_t* __restrict__ ghost, int64_t n,
                           double* __restrict__ part) {
   __shared__ double sh[16];
   double m = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
+    if (ghost && ghost[j]) continue;
     CSum acc;
     for (int32_t e = cptr[j]; e < cptr[j + 1]; ++e) acc.add(a[pos[e]]);
     m = fmax(m, fabs(acc.value() / b[j] - 1.0));
@@ -114,6 +126,7 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
                             double* max_col_err, Arena& ws, hipStream_t s) {
   const int64_t n = m->n_cells;
   const double* b = m->b.as<double>();
+  const uint8_t* ghost = m->ghost.as<uint8_t>();
   Arena::Mark mk = ws.mark();
   double* vc = ws.get<double>(nnz + 1);
   double* R = ws.get<double>(n);
@@ -130,7 +143,8 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
   // a column of V summing to zero cannot be scaled (Sec. 3.2)
   {
     ::bchar::ProfScope ps_("k_col_scale", s);
-    k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(csc.ptr, csc.row, vc, R, b, n, C, flag);
+    k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(csc.ptr, csc.row, vc, R, b, ghost, n, C,
+                                                    flag);
   }
   BCHAR_HIP(hipGetLastError());
   int32_t hflag[2] = {INT32_MAX, 0};
@@ -146,13 +160,14 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
     if (it > 0) {
       {
         ::bchar::ProfScope ps_("k_col_scale", s);
-        k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(csc.ptr, csc.row, vc, R, b, n, C, flag);
+        k_col_scale<<<blocks_for(n, 256), 256, 0, s>>>(csc.ptr, csc.row, vc, R, b, ghost, n, C,
+                                                        flag);
       }
       BCHAR_HIP(hipGetLastError());
     }
     {
       ::bchar::ProfScope ps_("k_row_scale", s);
-      k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, V, C, b_row, n, R);
+      k_row_scale<<<blocks_for(n, 256), 256, 0, s>>>(row_ptr, col, V, C, b_row, ghost, n, R);
     }
     BCHAR_HIP(hipGetLastError());
   }
@@ -169,7 +184,7 @@ bchar_status scaling_sweeps(const bchar_mesh_s* m, const int32_t* row_ptr, const
   double* part = ws.get<double>(nb);
   {
     ::bchar::ProfScope ps_("k_col_err", s);
-    k_col_err<<<nb, 256, 0, s>>>(csc.ptr, csc.pos, AN, b, n, part);
+    k_col_err<<<nb, 256, 0, s>>>(csc.ptr, csc.pos, AN, b, ghost, n, part);
   }
   BCHAR_HIP(hipGetLastError());
   double h[nb];

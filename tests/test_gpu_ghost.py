@@ -1,0 +1,138 @@
+"""GPU parity of ghost cells (Sec. 3.2, Remark on inflow and outflow,
+option b; mesh descriptor n_ghost) against the oracle (``n_ghost``): the
+paper's translation test (Sec. 4.1, test case 1) step by step, its printed
+B-char errors from the GPU's own result, an outflow's interior mass
+balance, a 3D translation, and the rejections."""
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import transfer as otr
+from paper_1908_05834_amd import inputs
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05834_amd import bchar
+    return torch, bchar
+
+
+def _grid(n, g, dim=2):
+    h = 1.0 / n
+    return inputs.cartesian_mesh((n + 2 * g,) * dim, length=h * (n + 2 * g),
+                                 origin=(-g * h,) * dim)
+
+
+def _box(mesh, lo, hi):
+    cen = inputs.cell_centroids(mesh)
+    inside = np.all((cen > np.asarray(lo)) & (cen < np.asarray(hi)), axis=1)
+    return inside.astype(np.float64)
+
+
+def _run(env, mesh, vel, dt, g, c0, steps, check_v=True):
+    """The oracle's and the library's transfer on the same ghost grid, and
+    both concentrations after every update (ghost cells reset to 0)."""
+    torch, bchar = env
+    ref = otr.build_transfer(mesh, vel, dt, layout="subcell", n_ghost=g)
+    M = bchar.Mesh(mesh, "subcell", n_ghost=g)
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt, bchar.opts_default(keep_pairs=1))
+    _say(f"    stats {T.stats}; oracle level {ref['qp']['level']}")
+    assert T.stats["qp_level"] == ref["qp"]["level"]
+    if check_v:
+        a, b = T.export_pairs()
+        assert np.array_equal(a, ref["pairs"][0]) and np.array_equal(b, ref["pairs"][1])
+        rp, col, V = T.export_csr(bchar.STAGE_V)
+        assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(col, ref["col"])
+        assert np.max(np.abs(V - ref["V"])) <= 1e-13 * np.max(np.abs(ref["V"]))
+    ghost = ref["ghost"]
+    gd = torch.as_tensor(ghost, device="cuda")
+    c = torch.as_tensor(c0, device="cuda")
+    nxt = torch.empty_like(c)
+    want = np.array(c0)
+    act = ~ghost
+    for k in range(steps):
+        T.step(c, nxt)
+        c, nxt = nxt, c
+        c[gd] = 0.0
+        want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], want)
+        want[ghost] = 0.0
+        got = c.cpu().numpy()
+        err = np.max(np.abs(got - want)[act]) / max(np.max(np.abs(want)), 1e-300)
+        assert err <= 1e-10, (k, err)
+        m = M.mass(c)
+        want_m = otr.mass(mesh["phi"], ref["cell_vol"], got, act)
+        assert abs(m - want_m) <= 2 * np.spacing(abs(want_m)), (m, want_m)
+    return ref, M, T, c.cpu().numpy()
+
+
+@pytest.mark.parametrize("row", json.load(open(os.path.join(HERE, "golden",
+                                                             "tc1_translation_errors.json")))
+                         ["rows"][:2])
+def test_translation_test_case(env, row):
+    n, dt = row["n"], row["dt"]
+    _say(f"[gpu] ghost translation {n}^2 dt {dt}")
+    mesh = _grid(n, 1)
+    vel = inputs.sample_velocity(mesh, inputs.constant_field((1.0 / 16.0, 0.0)))
+    c0 = _box(mesh, (1 / 16, 1 / 16), (5 / 16, 5 / 16))
+    ref, M, T, c = _run(env, mesh, vel, dt, 1, c0, int(round(8.0 / dt)))
+    exact = _box(mesh, (9 / 16, 1 / 16), (13 / 16, 5 / 16))
+    act = ~ref["ghost"]
+    vol = ref["cell_vol"]
+    e1 = np.sum(vol[act] * np.abs(c - exact)[act]) / np.sum(vol[act] * exact[act])
+    e2 = math.sqrt(np.sum(vol[act] * ((c - exact) ** 2)[act])
+                   / np.sum(vol[act] * exact[act] ** 2))
+    _say(f"    E1 {e1:.6f} (paper {row['E1']}), E2 {e2:.6f} (paper {row['E2']})")
+    assert abs(e1 - row["E1"]) <= 1.5e-5 and abs(e2 - row["E2"]) <= 1.5e-5
+
+
+def test_outflow_mass_balance(env):
+    _say("[gpu] ghost outflow")
+    n, g = 16, 1
+    mesh = _grid(n, g)
+    vel = inputs.sample_velocity(mesh, inputs.constant_field((1.0 / 16.0, 0.0)))
+    c0 = _box(mesh, (12 / 16, 6 / 16), (15.5 / 16, 10 / 16))
+    ref, M, T, c = _run(env, mesh, vel, 0.8, g, c0, 4, check_v=False)
+    # material has left: the interior mass fell
+    act = ~ref["ghost"]
+    assert otr.mass(mesh["phi"], ref["cell_vol"], c, act) < \
+        0.9 * otr.mass(mesh["phi"], ref["cell_vol"], c0, act)
+
+
+def test_translation_3d(env):
+    _say("[gpu] ghost translation 3D")
+    n, g = 8, 1
+    mesh = _grid(n, g, dim=3)
+    vel = inputs.sample_velocity(mesh, inputs.constant_field((0.05, 0.02, -0.03)))
+    c0 = _box(mesh, (0.2, 0.3, 0.4), (0.6, 0.7, 0.8))
+    _run(env, mesh, vel, 1.0, g, c0, 3)
+
+
+def test_ghost_rejections(env):
+    torch, bchar = env
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Mesh(inputs.cartesian_mesh((4, 4)), "subcell", n_ghost=2)
+    assert ei.value.status == bchar.E_INVALID_ARG
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Mesh(inputs.triangulated_square(4, 0.1, 3), "equal_measure", n_ghost=1)
+    assert ei.value.status == bchar.E_INVALID_ARG
+    mesh = _grid(8, 1)
+    M = bchar.Mesh(mesh, "subcell", n_ghost=1)
+    vel = bchar.VelocityLattice(inputs.sample_velocity(mesh, inputs.sine_compression((0.3, 0.2))))
+    with pytest.raises(bchar.BcharError) as ei:
+        bchar.Transfer.build(M, vel, 0.05, bchar.opts_default(divergence=bchar.DIV_GENERAL))
+    assert ei.value.status == bchar.E_UNSUPPORTED
