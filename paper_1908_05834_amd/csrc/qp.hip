@@ -3228,11 +3228,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
           // Newton without the step-count cap
           converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, " (after interior point)");
         }
-      } else {
-        // every interior point gave up: an answer far from its start (some
-        // x of order 1 or more) can drive its complementarity up as if the
-        // box were empty.  Semismooth Newton from zero decides: on an empty
-        // box it stalls in short steps or unbounded multipliers.
+      } else if (level == 1) {
+        // every interior point gave up on the box x >= -1: an answer far
+        // from its start (some x of order 1 or more) can drive the
+        // complementarity up as if the box were empty.  Semismooth Newton
+        // from zero decides before the equalities alone (which allow
+        // negative volumes) are taken: on an empty box it stalls in short
+        // steps or unbounded multipliers.  (The paper's box, level 0, is
+        // empty often enough that the interior point's verdict stands.)
         fill_f64(Q.t, 0.0, nnz, s);
         fill_f64(zdual, 0.0, 2 * n2, s);
         converged = ssn(lo, hi, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,

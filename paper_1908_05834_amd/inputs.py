@@ -312,6 +312,21 @@ def swirl_hex(n=64, steps=None):
             "steps": 128 if steps is None else steps, "time_dependent": True}
 
 
+def compressible_swirl_hex(n=64, steps=None, squeeze=0.3):
+    """``swirl_hex`` with the sine compression of amplitude ``squeeze`` added
+    on every axis (a non-solenoidal field, tangential on the walls; the
+    swirl part reverses with cos(pi t), the compression does not)."""
+    mesh = cartesian_mesh((n, n, n))
+    dt = 1.0 / 128.0
+
+    def vel_fn(step):
+        return sample_velocity(mesh, lambda p, t: compressible_swirl_3d(p, t, squeeze),
+                               (step + 0.5) * dt)
+    c0 = disk_indicator(mesh, (0.35, 0.35, 0.35), 0.15)
+    return {"name": f"compressible_swirl_hex_{n}^3", "mesh": mesh, "vel_fn": vel_fn, "c0": c0,
+            "dt": dt, "steps": 128 if steps is None else steps, "time_dependent": True}
+
+
 def porous_swirl_hex(n=32, seed=5834, steps=20):
     """3D swirl with a lognormal porosity phi = clip(exp(0.5 Z), 0.05, 1)
     per cell, c^0 ~ U[0,1]; exercises the tracked-radius rule for
