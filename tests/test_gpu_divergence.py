@@ -54,6 +54,9 @@ def _case(name):
         mesh = inputs.triangulated_square(10, 0.1, 6, phi=inputs.lognormal_phi(200, 22))
         vel = inputs.sample_velocity_grid((10, 10), inputs.sine_compression((0.6, 0.4)))
         return mesh, vel, 0.08, "equal_measure"
+    if name == "cswirl12":
+        w = inputs.compressible_swirl_hex(12, squeeze=0.1)
+        return w["mesh"], w["vel_fn"](0), w["dt"], "subcell"
     if name == "custom_hex":
         w = inputs.swirl_hex(8)
         mesh = inputs.random_subcell_balls(w["mesh"], 5)
@@ -63,7 +66,7 @@ def _case(name):
 
 
 CASES = ["sine2d", "cswirl3d", "sine3d_inscribed", "porous2d", "tets", "tris_porous",
-         "custom_hex"]
+         "custom_hex", "cswirl12"]
 
 
 @pytest.mark.parametrize("name", CASES)
