@@ -136,3 +136,44 @@ def test_ghost_rejections(env):
     with pytest.raises(bchar.BcharError) as ei:
         bchar.Transfer.build(M, vel, 0.05, bchar.opts_default(divergence=bchar.DIV_GENERAL))
     assert ei.value.status == bchar.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["porous", "fp32_lens", "halving"])
+def test_ghost_variants(env, name):
+    """Ghost cells with a porous medium (r_hat from the cardinal points),
+    with binary32 lenses, and with step halving after a void column: the
+    oracle's step (for halving, its transfer of the halved step applied as
+    often, ghost values carried between the sub-steps as the library does)."""
+    torch, bchar = env
+    _say(f"[gpu] ghost variant {name}")
+    n, g = 12, 1
+    mesh = _grid(n, g)
+    if name == "porous":
+        mesh = dict(mesh, phi=inputs.lognormal_phi(int(np.prod(mesh["n"])), 77))
+    vel = inputs.sample_velocity(mesh, lambda p, t=0.0: np.stack(
+        [0.08 + 0.05 * p[:, 1], 0.03 * np.sin(3.0 * p[:, 0])], axis=1))
+    dt = 2.4 if name == "halving" else 0.6
+    M = bchar.Mesh(mesh, "subcell", n_ghost=g)
+    opts = bchar.opts_default(precision=bchar.FP32_LENS if name == "fp32_lens" else bchar.FP64,
+                              max_halvings=4 if name == "halving" else 0)
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(vel), dt, opts)
+    h = T.stats["dt_halvings"]
+    assert h == (1 if name == "halving" else 0)
+    ref = otr.build_transfer(mesh, vel, dt / 2 ** h, layout="subcell", n_ghost=g,
+                             precision="fp32" if name == "fp32_lens" else "fp64")
+    _say(f"    stats {T.stats}; oracle level {ref['qp']['level']}")
+    assert T.stats["qp_level"] == ref["qp"]["level"]
+    ghost = ref["ghost"]
+    c0 = inputs.uniform_c(mesh, 5)
+    c0[ghost] = 0.0
+    cin = torch.as_tensor(c0, device="cuda")
+    cout = torch.empty_like(cin)
+    T.step(cin, cout)
+    got = cout.cpu().numpy()
+    want = np.array(c0)
+    for _ in range(2 ** h):
+        want = otr.apply(ref["row_ptr"], ref["col"], ref["A"], ref["b"], want)
+    act = ~ghost
+    err = np.max(np.abs(got - want)[act]) / np.max(np.abs(want))
+    _say(f"    c rel err {err:.3e}")
+    assert err <= (1e-5 if name == "fp32_lens" else 1e-10)
