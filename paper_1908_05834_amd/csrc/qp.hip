@@ -2978,8 +2978,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (mu0 < 0.0) mu0 = mu;
       fn = fp;
       if (trace_enabled())
-        fprintf(stderr, "[bchar]   ipm %d: |B x - r| %.3e, mu %.3e, t %.3f s\n", it, fp, mu,
-                wall_seconds());
+        fprintf(stderr, "[bchar]   ipm %d: |B x - r| %.3e, mu %.3e, cg %d, t %.3f s\n", it, fp,
+                mu, res.cg, wall_seconds());
       if (!(mu == mu) || !(fp == fp) || mu > 1e8 * mu0) return 0;
       // no progress on an infeasible box: after kIpmInfeasIt iterations the
       // complementarity is not below half its start and has not halved
@@ -3143,7 +3143,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       red.maxabs(Q.F, n2, 0);
       const double f = red.fetch(0);
       if (trace_enabled())
-        fprintf(stderr, "[bchar]   crossover %d: |F| of clip(t) %.3e\n", it, f);
+        fprintf(stderr, "[bchar]   crossover %d: |F| of clip(t) %.3e, cg %d, t %.3f s\n", it, f,
+                res.cg, wall_seconds());
       if (f <= tol) {
         fn = f;
         return true;
