@@ -360,6 +360,7 @@ def bench_mixed(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cg = []
+        levels = [0, 0, 0]
         halvings = 0
         per_call = 64 if depth > 1 else 1
         for b0 in range(0, len(probs), per_call):
@@ -367,18 +368,19 @@ def bench_mixed(args):
             Ts = bchar.build_batch([(None, q["M"], q["U"], q["dt"]) for q in chunk], opts, streams)
             for q, T in zip(chunk, Ts):
                 cg.append(T.stats["qp_cg"])
+                levels[T.stats["qp_level"]] += 1
                 halvings += T.stats["dt_halvings"]
                 finish(q, T)
             if depth > 1 or b0 % 16 == 15:
                 log(f"  depth {depth}: problems up to {min(b0 + per_call, len(probs)) - 1} done "
                     f"at {time.perf_counter() - t0:.2f} s")
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, cg, halvings
+        return time.perf_counter() - t0, cg, halvings, levels
 
     run(D)   # warm-up pass (code objects, allocator)
-    t_seq, cg_seq, _ = run(1)
+    t_seq, cg_seq, _, _ = run(1)
     log(f"mixed, one at a time: {t_seq:.3f} s")
-    t_par, cg_par, halvings = run(D)
+    t_par, cg_par, halvings, levels = run(D)
     log(f"mixed, {D} in flight: {t_par:.3f} s, {halvings} time steps halved")
     assert cg_seq == cg_par
     out = {
@@ -399,7 +401,9 @@ def bench_mixed(args):
                                "logU[4e3, 2e5] cells, four Fourier modes, CFL ~ U[0.5, 4]",
                    "problems": len(probs), "cells_total": cells, "inflight_builds": D,
                    "dt_halvings": halvings,
-                   "qp_cg_mean": float(np.mean(cg_par))},
+                   "qp_cg_mean": float(np.mean(cg_par)),
+                   "qp_levels": {"paper_box": levels[0], "nonnegative": levels[1],
+                                 "equalities_only": levels[2]}},
         "mass_ok": bool(mass_err <= 1e-12),
         "max_rel_mass_err": mass_err,
         "sequential": {"value": cells * steps / t_seq, "seconds": t_seq},

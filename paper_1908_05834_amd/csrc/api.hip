@@ -558,12 +558,13 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
     t->zdual.reserve(sizeof(double) * 4 * n);
     t->warm_level = -1;
   }
+  if (t->warm_level < 0) t->warm_newton_skip = 0;
   QpResult qr;
   Groups grp{t->grp_lab.as<int32_t>(), t->grp_ptr.as<int32_t>(), t->grp_perm.as<int32_t>()};
   rc = solve_qp(m, t->row_ptr.as<int32_t>(), t->col.as<int32_t>(), csc, t->AN.as<double>(),
                 b_row, t->groups > 1 ? &grp : nullptr, nnz, o, t->x.as<double>(),
                 t->mu.as<double>(), t->nu.as<double>(), t->A.as<double>(), t->zdual.as<double>(),
-                t->warm_level, qr, ws, s);
+                t->warm_level, t->warm_newton_skip, qr, ws, s);
   t->warm_level = rc == BCHAR_OK ? qr.level : -1;
   if (tr)
     fprintf(stderr, "[bchar] qp: %.3f ms (level %d, ipm %d, newton %d, cg %d, residual %.3e)\n",
@@ -1223,6 +1224,7 @@ bchar_status bchar_build_transfer_batch(bchar_build_job* jobs, int n_jobs,
         if (dst->zdual.bytes < 2 * bytes) dst->zdual.reserve(2 * bytes);
         BCHAR_HIP(hipMemcpyAsync(dst->zdual.p, src->zdual.p, bytes, hipMemcpyDeviceToDevice, s0));
         dst->warm_level = src->warm_level;
+        dst->warm_newton_skip = src->warm_newton_skip;
         copied = true;
       }
       if (copied) BCHAR_HIP(hipStreamSynchronize(s0));

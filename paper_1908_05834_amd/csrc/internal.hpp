@@ -141,6 +141,8 @@ struct bchar_transfer_s {
   bchar::DBuf zdual;     // fp64 4 n_cells: per-cell multipliers (s, g) of the last
                          // solve, leading parts then compensations
   int warm_level = -1;   // box level of the last converged solve
+  int warm_newton_skip = 0;  // rebuilds left that start with the warm interior point
+                             // (the semismooth warm attempt failed recently)
   bchar::DBuf tracked;   // fp64 dim * n_balls
   bchar::DBuf r_hat;     // fp64 n_balls
   bchar::DBuf lam;       // fp64 n_balls, log growth (non-solenoidal builds)
@@ -248,7 +250,9 @@ struct QpResult {
 };
 // zdual: per-cell multipliers (s, g), 2 n leading parts and 2 n
 // compensations kept by the transfer;
-// warm_level: box level of the previous converged solve, or -1.
+// warm_level: box level of the previous converged solve, or -1;
+// warm_newton_skip: solves left that skip the semismooth warm attempt (set
+// to kWarmNewtonPause when it fails, counted down by each warm solve).
 // The connected components of the bipartite graph of the pattern (rows
 // 0..n-1, columns n..2n-1): every node's label (the smallest node of its
 // component) and the nodes grouped by label (ptr: 2n + 1, perm: 2n).
@@ -263,7 +267,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
                       const Csc& csc, const double* AN, const double* b_row,
                       const Groups* groups, int64_t nnz, const bchar_opts& o, double* x,
                       double* mu, double* nu, double* A, double* zdual, int warm_level,
-                      QpResult& res, Arena& ws, hipStream_t s);
+                      int& warm_newton_skip, QpResult& res, Arena& ws, hipStream_t s);
 
 // apply / mass (apply.hip)
 void apply_transfer(const bchar_transfer_s* t, const double* cin, double* cout, hipStream_t s);

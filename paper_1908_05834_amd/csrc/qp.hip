@@ -54,7 +54,13 @@ constexpr double kIpmWarmShift = 1e-3; // distance from the box of a warm interi
 constexpr int kIpmInfeasIt = 10;       // iterations before the no-progress test
 constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relative to
 constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
+constexpr double kIpmMuFloor = 1e-14;  // complementarity at rounding level
+constexpr int kCorrectionSteps = 40;  // Newton steps of the equality correction at most
+constexpr double kIpmNearFeasible = 1e-8;  // |B x - r| of an interior point that stalls
+                                           // there, handed to the polish and then
+                                           // to the equality correction
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
+constexpr int kWarmNewtonPause = 3;  // warm solves that skip them after they failed
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 constexpr int kFallbackNewton = 40; // semismooth steps on a level every interior point
                                     // gave up on, and the short steps it may take
@@ -2121,12 +2127,14 @@ __global__ void k_axpy2(double* __restrict__ y, const double* __restrict__ x, do
 // counts the entries within `thr` of each bound
 __global__ void k_final(const double* __restrict__ an, const double* __restrict__ t,
                         const double* __restrict__ xi, double lo, double hi, double thr,
-                        int64_t nnz, double* __restrict__ x, double* __restrict__ A,
+                        int clip, int64_t nnz, double* __restrict__ x, double* __restrict__ A,
                         int32_t* __restrict__ counts) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnz) return;
-  // the interior point's iterate stays in the box up to its rounding
-  const double xk = clipv(xi ? xi[k] : t[k], lo, hi);
+  // the interior point's iterate stays in the box up to its rounding; a
+  // corrected one is taken as it is (clip = 0)
+  const double v = xi ? xi[k] : t[k];
+  const double xk = clip ? clipv(v, lo, hi) : v;
   x[k] = xk;
   A[k] = an[k] * (1.0 + xk);
   if (xk - lo <= thr) atomicAdd(&counts[0], 1);
@@ -2422,7 +2430,8 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
                       const Csc& csc, const double* AN, const double* b_row,
                       const Groups* groups, int64_t nnz, const bchar_opts& o, double* x_out,
                       double* mu_out, double* nu_out, double* A_out, double* zdual,
-                      int warm_level, QpResult& res, Arena& ws, hipStream_t s) {
+                      int warm_level, int& warm_newton_skip, QpResult& res, Arena& ws,
+                      hipStream_t s) {
   const int64_t n = m->n_cells;
   const int64_t n2 = 2 * n;
   const double scale = m->bmax;
@@ -2935,7 +2944,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     double mu0 = -1.0, fp_best = HUGE_VAL;
     std::vector<double> fp_hist, mu_hist;
     const bool loose = cg_rel > kIpmCgTight;
-    int stall = 0;
+    int stall = 0, stall_near = 0;
     auto steps = [&](double* ap, double* ad) {
       {
         ::bchar::ProfScope ps_("k_reduce_final_max", s);
@@ -3005,6 +3014,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (fp_best <= 1e-10 && mu <= 1e-10 && fp > 0.5 * fp_best) {
         // stalled: |B x - r| no longer halves
         if (++stall >= 2) return 1;
+      } else if (fp_best <= kIpmNearFeasible && mu <= kIpmMuFloor && fp > 0.5 * fp_best) {
+        // the complementarity is at rounding level and |B x - r| creeps:
+        // the directions are as exact as CG makes them on these systems
+        if (++stall_near >= 4) return 1;
       }
       if (fp < fp_best) fp_best = fp;
       {
@@ -3157,6 +3170,57 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
     return false;
   };
 
+  // ---------------------------------------------------------------- equality correction
+  // An interior point that stalls near the tolerance on a box level (the
+  // directions no longer improve |B x - r|, and semismooth Newton from its
+  // t does not converge either) has an x in the box that meets the
+  // constraints to about 1e-10.  The least-norm correction d with
+  // B d = r - B x (Newton steps of the equality-only problem, all weights
+  // a_k^2, repeated while they reduce the residual: the relative shift of
+  // the Newton matrix lets each remove only part of it) puts it on the
+  // constraints, so that mass is conserved to rounding.  Weighting the
+  // correction by the interior point's own scaling (moving only the entries
+  // away from the box) gives systems that CG does not solve here.  So an
+  // entry on the box may leave it by its share of d: a sliver a_k can take
+  // a share far above |d| relative to a_k, while its volume a_k (1 + x_k)
+  // moves by a_k d_k, of the order of the residual removed.  The
+  // multipliers are the interior point's (zsave).
+  auto equality_correction = [&]() -> bool {
+    BCHAR_HIP(hipMemcpyAsync(Q.t, I.x, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
+    {
+      ::bchar::ProfScope ps_("k_fine_weights", s);
+      k_fine_weights<<<gz, kT, 0, s>>>(Q.a, csc.pos, Q.t, -HUGE_VAL, HUGE_VAL, 0.0, nnz, L0.w);
+    }
+    BCHAR_HIP(hipGetLastError());
+    refresh();
+    double f_prev = HUGE_VAL;
+    for (int it = 0; it < kCorrectionSteps; ++it) {
+      {
+        ::bchar::ProfScope ps_("k_residual", s);
+        k_residual<<<gn, kT, 0, s>>>(Q.rptr, Q.cptr, Q.cpos, Q.a, Q.ac, Q.t, nullptr, 0.0,
+                                     -HUGE_VAL, HUGE_VAL, Q.rr, Q.ss, n, Q.F);
+      }
+      zero_ghost(Q.F);
+      red.maxabs(Q.F, n2, 0);
+      fn = red.fetch(0);
+      if (trace_enabled())
+        fprintf(stderr, "[bchar]   equality correction %d: |B x - r| %.3e, cg %d\n", it, fn,
+                res.cg);
+      if (!(fn == fn)) return false;
+      if (fn <= tol) return true;
+      if (!(fn < 0.9 * f_prev)) return false;
+      f_prev = fn;
+      pcg(Q.F, 0.1 * tol, false, o.qp_max_cg);
+      {
+        ::bchar::ProfScope ps_("k_axpy2", s);
+        k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, 1.0, nnz);
+      }
+      BCHAR_HIP(hipGetLastError());
+    }
+    return false;
+  };
+
   // ---------------------------------------------------------------- box levels
   // Level 0 is the paper's box, level 1 keeps x >= -1 only, level 2 keeps
   // the equalities alone.  A level with a bound is solved by the interior
@@ -3171,7 +3235,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // the caller may stop at level 1 (it halves the step rather than accept
   // negative volumes)
   const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : (o.halve_on_level2 ? 1 : 2);
-  bool converged = false, ipm_answer = false;
+  bool converged = false, ipm_answer = false, corrected = false;
   int level = 0;
   for (level = 0; level <= max_level; ++level) {
     const double lo = lo_levels[level], hi = hi_levels[level];
@@ -3183,8 +3247,16 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       BCHAR_HIP(hipGetLastError());
       // t is formed from the leading parts: the compensation starts anew
       fill_f64(zdual + n2, 0.0, n2, s);
-      converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2,
-                      std::min(kPolishCG, o.qp_max_cg), " (warm)");
+      // a warm attempt that failed is not repeated on the next few solves
+      // (the flow keeps changing as much from step to step): they go to
+      // the warm interior point at once
+      if (warm_newton_skip > 0) {
+        --warm_newton_skip;
+      } else {
+        converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2,
+                        std::min(kPolishCG, o.qp_max_cg), " (warm)");
+        if (!converged) warm_newton_skip = kWarmNewtonPause;
+      }
       if (converged) break;
     }
     const bool warm = o.warm_start && warm_level == level;
@@ -3204,9 +3276,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         // multipliers are kept, so that an interior-point answer leaves
         // the multipliers that go with its x (and the next solve's warm
         // start) rather than those of an abandoned step.
+        // the interior point's multipliers and t, kept for its own answer
+        BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
+        BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
         if (r == 2) {
-          BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
-          BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
           converged = crossover(lo, hi);
           if (!converged) {
             BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice,
@@ -3226,8 +3299,12 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
           BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
         } else if (!converged) {
           // the interior point stalled short of the tolerance: semismooth
-          // Newton without the step-count cap
-          converged = ssn(lo, hi, o.qp_max_newton, 0, o.qp_max_cg, " (after interior point)");
+          // Newton without the step-count cap, as long as its steps are not
+          // all short, then the equality correction of the interior
+          // point's x
+          converged = ssn(lo, hi, o.qp_max_newton, kFallbackPatience, o.qp_max_cg,
+                          " (after interior point)");
+          if (!converged) converged = corrected = equality_correction();
         }
       } else if (level == 1) {
         // every interior point gave up on the box x >= -1: an answer far
@@ -3260,8 +3337,14 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   fill_i32(counts, 0, 2, s);
   {
     ::bchar::ProfScope ps_("k_final", s);
-    k_final<<<gz, kT, 0, s>>>(AN, Q.t, ipm_answer ? I.x : nullptr, lo, hi,
-                              ipm_answer ? 1e-12 : 0.0, nnz, x_out, A_out, counts);
+    // a corrected x is taken as it is (it may leave the box by its share of
+    // the correction); entries within 1e-12 of a bound, or beyond it, count
+    // as on it
+    if (corrected)
+      k_final<<<gz, kT, 0, s>>>(AN, Q.t, nullptr, lo, hi, 1e-12, 0, nnz, x_out, A_out, counts);
+    else
+      k_final<<<gz, kT, 0, s>>>(AN, Q.t, ipm_answer ? I.x : nullptr, lo, hi,
+                                ipm_answer ? 1e-12 : 0.0, 1, nnz, x_out, A_out, counts);
   }
   BCHAR_HIP(hipGetLastError());
   int32_t hc[2];
