@@ -3236,6 +3236,45 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // negative volumes)
   const int max_level = o.box_policy == BCHAR_BOX_STRICT ? 0 : (o.halve_on_level2 ? 1 : 2);
   bool converged = false, ipm_answer = false, corrected = false;
+  // The answer of a level from an interior point that ended at (r = 2) or
+  // near (r = 1) the tolerance: crossover, semismooth polish, its own x,
+  // or the equality correction (sets converged, ipm_answer, corrected).
+  auto finish_interior_point = [&](int r, double lo, double hi) {
+    // an interior point at the tolerance is an answer already: one
+    // short semismooth step is enough to give up on the exact one.  Its
+    // multipliers and t are kept, so that an interior-point answer leaves
+    // the multipliers that go with its x (and the next solve's warm
+    // start) rather than those of an abandoned step.
+    BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
+    BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    if (r == 2) {
+      converged = crossover(lo, hi);
+      if (!converged) {
+        BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice,
+                                 s));
+        BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                                 s));
+      }
+    }
+    if (!converged)
+      converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
+                      r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
+                      " (after interior point)");
+    if (!converged && r == 2) {
+      converged = ipm_answer = true;
+      fn = fp_ipm;
+      BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
+      BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    } else if (!converged) {
+      // the interior point stalled short of the tolerance: semismooth
+      // Newton without the step-count cap, as long as its steps are not
+      // all short, then the equality correction of the interior
+      // point's x
+      converged = ssn(lo, hi, o.qp_max_newton, kFallbackPatience, o.qp_max_cg,
+                      " (after interior point)");
+      if (!converged) converged = corrected = equality_correction();
+    }
+  };
   int level = 0;
   for (level = 0; level <= max_level; ++level) {
     const double lo = lo_levels[level], hi = hi_levels[level];
@@ -3271,53 +3310,31 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (r == 0) r = ipm(lo, hi, false, kIpmCgLoose);
       if (r == 0) r = ipm(lo, hi, false, kIpmCgTight);
       if (r > 0) {
-        // an interior point at the tolerance is an answer already: one
-        // short semismooth step is enough to give up on the exact one.  Its
-        // multipliers are kept, so that an interior-point answer leaves
-        // the multipliers that go with its x (and the next solve's warm
-        // start) rather than those of an abandoned step.
-        // the interior point's multipliers and t, kept for its own answer
-        BCHAR_HIP(hipMemcpyAsync(zsave, zdual, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
-        BCHAR_HIP(hipMemcpyAsync(tsave, Q.t, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
-        if (r == 2) {
-          converged = crossover(lo, hi);
-          if (!converged) {
-            BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice,
-                                     s));
-            BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
-                                     s));
-          }
-        }
-        if (!converged)
-          converged = ssn(lo, hi, std::min(kPolishNewton, o.qp_max_newton), r == 2 ? 1 : 2,
-                          r == 2 ? std::min(kPolishCG, o.qp_max_cg) : o.qp_max_cg,
-                          " (after interior point)");
-        if (!converged && r == 2) {
-          converged = ipm_answer = true;
-          fn = fp_ipm;
-          BCHAR_HIP(hipMemcpyAsync(zdual, zsave, sizeof(double) * 2 * n2, hipMemcpyDeviceToDevice, s));
-          BCHAR_HIP(hipMemcpyAsync(Q.t, tsave, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
-        } else if (!converged) {
-          // the interior point stalled short of the tolerance: semismooth
-          // Newton without the step-count cap, as long as its steps are not
-          // all short, then the equality correction of the interior
-          // point's x
-          converged = ssn(lo, hi, o.qp_max_newton, kFallbackPatience, o.qp_max_cg,
-                          " (after interior point)");
-          if (!converged) converged = corrected = equality_correction();
-        }
+        finish_interior_point(r, lo, hi);
       } else if (level == 1) {
-        // every interior point gave up on the box x >= -1: an answer far
-        // from its start (some x of order 1 or more) can drive the
-        // complementarity up as if the box were empty.  Semismooth Newton
-        // from zero decides before the equalities alone (which allow
-        // negative volumes) are taken: on an empty box it stalls in short
-        // steps or unbounded multipliers.  (The paper's box, level 0, is
-        // empty often enough that the interior point's verdict stands.)
+        // every interior point from x = 0 gave up on the box x >= -1: an
+        // answer far from that start (some x of order 1 or more) can stall
+        // it as if the box were empty.  One more interior point starts
+        // from the minimiser of the equalities alone (a linear problem:
+        // semismooth Newton without a box, a few steps), whose entries
+        // below -1 it moves into the box; then semismooth Newton from zero
+        // decides before the equalities alone (which allow negative
+        // volumes) are taken: on an empty box both stall.  (The paper's
+        // box, level 0, is empty often enough that the interior point's
+        // verdict stands.)
         fill_f64(Q.t, 0.0, nnz, s);
         fill_f64(zdual, 0.0, 2 * n2, s);
-        converged = ssn(lo, hi, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
-                        o.qp_max_cg, " (interior point failed)");
+        if (ssn(-HUGE_VAL, HUGE_VAL, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
+                o.qp_max_cg, " (equalities alone, start of an interior point)")) {
+          const int r2 = ipm(lo, hi, true, kIpmCgTight);
+          if (r2 > 0) finish_interior_point(r2, lo, hi);
+        }
+        if (!converged) {
+          fill_f64(Q.t, 0.0, nnz, s);
+          fill_f64(zdual, 0.0, 2 * n2, s);
+          converged = ssn(lo, hi, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
+                          o.qp_max_cg, " (interior point failed)");
+        }
       }
     }
     if (converged) break;

@@ -92,3 +92,31 @@ def test_hard_batch_problem(env, p):
     ones = torch.ones_like(c0)
     T.step(ones, c1)
     assert torch.max(torch.abs(c1 - 1.0)).item() <= 1e-9
+
+
+def test_level1_batch_problem_matches_oracle(env):
+    """Problem 47 of the batch: the paper's box is empty, x >= -1 is not;
+    the interior point from x = 0 gives up and the one started from the
+    minimiser of the equalities alone finds the answer.  The oracle's step
+    (tests/golden/batch47_step.npz, written by make_batch47.py from the
+    oracle alone) at 4,096 sampled cells within the 1e-10 bar, the same
+    box level and the same porous mass."""
+    torch, bchar = env
+    ref = np.load(os.path.join(os.path.dirname(GOLDEN), "batch47_step.npz"))
+    q = inputs.mixed_problem(47)
+    _say(f"[gpu] batch problem 47 ({q['name']}) against the oracle")
+    M = bchar.Mesh(q["mesh"], q["layout"])
+    T = bchar.Transfer.build(M, bchar.VelocityLattice(q["vel"]), q["dt"],
+                             bchar.opts_default(max_halvings=4))
+    st = T.stats
+    _say(f"    stats {st}")
+    assert st["nnz"] == int(ref["nnz"]) and st["qp_level"] == int(ref["qp_level"]) == 1
+    c0 = torch.as_tensor(q["c0"], device="cuda")
+    c1 = torch.empty_like(c0)
+    T.step(c0, c1)
+    got = c1.cpu().numpy()[ref["idx"]]
+    err = np.max(np.abs(got - ref["c1"])) / float(ref["c1_max"])
+    _say(f"    c rel err at the sampled cells {err:.3e}")
+    assert err <= 1e-10
+    m1 = M.mass(c1)
+    assert abs(m1 - float(ref["mass"])) <= 1e-12 * abs(float(ref["mass"]))
