@@ -56,6 +56,7 @@ constexpr double kIpmCgLoose = 1.0;    // CG tolerance of the directions, relati
 constexpr double kIpmCgTight = 1e-2;   // min(|rhs|, mu): first try, and retry
 constexpr double kIpmMuFloor = 1e-14;  // complementarity at rounding level
 constexpr int kCorrectionSteps = 40;  // Newton steps of the equality correction at most
+constexpr double kIpmDiverged = 1e3;   // complementarity growth of an empty-looking box
 constexpr double kIpmNearFeasible = 1e-8;  // |B x - r| of an interior point that stalls
                                            // there, handed to the polish and then
                                            // to the equality correction
@@ -2923,9 +2924,12 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   I.dzu = ws.get<double>(nnz + 1);
   double* rp = ws.get<double>(n2);
   double fp_ipm = HUGE_VAL;
+  bool ipm_diverged = false;   // the last interior point stopped with its complementarity
+                               // grown by kIpmDiverged (the box looks empty)
   auto ipm = [&](double lo, double hi, bool warm, double cg_rel) -> int {
     I.lo = lo;
     I.hi = hi;
+    ipm_diverged = false;
     I.has_hi = std::isinf(hi) ? 0 : 1;
     const double m_pairs = (double)nnz * (I.has_hi ? 2.0 : 1.0);
     if (warm) {
@@ -3001,6 +3005,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       if (it >= kIpmInfeasIt && mu >= 0.5 * mu0 && mu >= 0.5 * mu_hist[it - 5] &&
           fp >= 0.9 * fp_hist[it - 5]) {
         if (trace_enabled()) fprintf(stderr, "[bchar]   stop: no progress (infeasible?)\n");
+        ipm_diverged = mu >= kIpmDiverged * mu0;
         return 0;
       }
       // loose directions that no longer reduce |B x - r| (by 10 % over
@@ -3324,7 +3329,10 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         // verdict stands.)
         fill_f64(Q.t, 0.0, nnz, s);
         fill_f64(zdual, 0.0, 2 * n2, s);
-        if (ssn(-HUGE_VAL, HUGE_VAL, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
+        // (not when the last one's complementarity blew up: the box then
+        // looks empty, and the restart would only confirm it)
+        if (!ipm_diverged &&
+            ssn(-HUGE_VAL, HUGE_VAL, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
                 o.qp_max_cg, " (equalities alone, start of an interior point)")) {
           const int r2 = ipm(lo, hi, true, kIpmCgTight);
           if (r2 > 0) finish_interior_point(r2, lo, hi);
