@@ -16,7 +16,11 @@
 // interior point (Mehrotra predictor-corrector), whose Newton systems keep
 // every entry with a positive weight, and semismooth Newton finishes from
 // its t; a rebuild first tries semismooth Newton from the previous
-// multipliers.  Every Newton system is a weighted bipartite graph
+// multipliers.  An interior point that stalls just short of the tolerance
+// (systems at the edge of what CG solves) is finished by a least-norm
+// correction onto the equalities; on the box x >= -1 an interior point
+// that gives up from x = 0 is restarted from the minimiser of the
+// equalities alone.  Every Newton system is a weighted bipartite graph
 // Laplacian L (d_mu; -d_nu) = (-F_row; F_col), solved by preconditioned
 // conjugate gradients in per-cell coordinates.  t_k = a_k (mu_i + nu_j) is
 // carried per entry and updated by increments, since the multipliers span
