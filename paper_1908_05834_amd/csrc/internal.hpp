@@ -142,7 +142,8 @@ struct bchar_transfer_s {
                          // solve, leading parts then compensations
   int warm_level = -1;   // box level of the last converged solve
   int warm_newton_skip = 0;  // rebuilds left that start with the warm interior point
-                             // (the semismooth warm attempt failed recently)
+                             // (the semismooth warm attempt recently failed before
+                             // taking a step)
   bchar::DBuf tracked;   // fp64 dim * n_balls
   bchar::DBuf r_hat;     // fp64 n_balls
   bchar::DBuf lam;       // fp64 n_balls, log growth (non-solenoidal builds)
@@ -252,7 +253,8 @@ struct QpResult {
 // compensations kept by the transfer;
 // warm_level: box level of the previous converged solve, or -1;
 // warm_newton_skip: solves left that skip the semismooth warm attempt (set
-// to kWarmNewtonPause when it fails, counted down by each warm solve).
+// to kWarmNewtonPause when it fails before its first step, counted down by
+// each warm solve).
 // The connected components of the bipartite graph of the pattern (rows
 // 0..n-1, columns n..2n-1): every node's label (the smallest node of its
 // component) and the nodes grouped by label (ptr: 2n + 1, perm: 2n).

@@ -66,6 +66,7 @@ constexpr double kIpmNearFeasible = 1e-8;  // |B x - r| of an interior point tha
                                            // to the equality correction
 constexpr int kWarmNewton = 3;     // semismooth steps tried from a warm start
 constexpr int kWarmNewtonPause = 3;  // warm solves that skip them after they failed
+                                     // without a step
 constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 constexpr int kFallbackNewton = 40; // semismooth steps on a level every interior point
                                     // gave up on, and the short steps it may take
@@ -2763,6 +2764,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   // derivative.  Returns true once max |F| <= tol; fn holds the last
   // residual.
   double fn = 0.0;
+  int ssn_steps = 0;   // steps taken by semismooth Newton so far
   auto ssn = [&](double lo, double hi, int max_it, int patience, int max_cg,
                  const char* tag) -> bool {
     int short_steps = 0;
@@ -2891,6 +2893,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       {
         ::bchar::ProfScope ps_("k_axpy2", s);
         k_axpy2<<<gz, kT, 0, s>>>(Q.t, Q.dt, step, nnz);
+        ++ssn_steps;
       }
       {
         ::bchar::ProfScope ps_("k_zdual_acc", s);
@@ -3295,15 +3298,18 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
       BCHAR_HIP(hipGetLastError());
       // t is formed from the leading parts: the compensation starts anew
       fill_f64(zdual + n2, 0.0, n2, s);
-      // a warm attempt that failed is not repeated on the next few solves
-      // (the flow keeps changing as much from step to step): they go to
-      // the warm interior point at once
+      // a warm attempt that failed before its first step (its first
+      // system beyond kPolishCG iterations) is not repeated on the next
+      // few solves (the flow keeps changing as much from step to step):
+      // they go to the warm interior point at once.  An attempt that took
+      // steps leaves the interior point a better start and is kept.
       if (warm_newton_skip > 0) {
         --warm_newton_skip;
       } else {
+        const int steps_before = ssn_steps;
         converged = ssn(lo, hi, std::min(kWarmNewton, o.qp_max_newton), 2,
                         std::min(kPolishCG, o.qp_max_cg), " (warm)");
-        if (!converged) warm_newton_skip = kWarmNewtonPause;
+        if (!converged && ssn_steps == steps_before) warm_newton_skip = kWarmNewtonPause;
       }
       if (converged) break;
     }
