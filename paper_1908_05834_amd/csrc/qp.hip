@@ -3336,7 +3336,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         // decides before the equalities alone (which allow negative
         // volumes) are taken: on an empty box both stall.  (The paper's
         // box, level 0, is empty often enough that the interior point's
-        // verdict stands.)
+        // conclusion stands.)
         fill_f64(Q.t, 0.0, nnz, s);
         fill_f64(zdual, 0.0, 2 * n2, s);
         // (not when the last one's complementarity blew up: the box then
