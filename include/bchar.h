@@ -196,6 +196,14 @@ typedef struct {
                             sums the interior cells; the ghost entries of
                             an update's output mean nothing.  Solenoidal
                             steps only (DIV_GENERAL: UNSUPPORTED)         */
+  double hash_scale;     /* side of the spatial hash's buckets as a multiple
+                            of 2 r_max (r_max: the largest residing ball):
+                            0 (default) means 1, else within [0.25, 4].
+                            Every side finds the same overlapping pairs
+                            (the searched block of buckets widens or
+                            narrows with it); it trades buckets visited
+                            against balls tested per bucket, a tuning
+                            knob for the candidate search (Sec. 3.1)      */
 } bchar_mesh_desc;
 
 /* Velocity u^{(n+1)} frozen over the time step (Sec. 1.2, eq. hyp:un) as

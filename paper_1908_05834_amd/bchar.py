@@ -48,7 +48,7 @@ class MeshDesc(C.Structure):
                 ("layout", C.c_int), ("kind", C.c_int), ("n_vertices", C.c_int64),
                 ("n_simplices", C.c_int64), ("vertices", C.c_void_p), ("cells", C.c_void_p),
                 ("geom_mem", C.c_int), ("n_balls", C.c_int64), ("balls", C.c_void_p),
-                ("ball_cell", C.c_void_p), ("n_ghost", C.c_int64)]
+                ("ball_cell", C.c_void_p), ("n_ghost", C.c_int64), ("hash_scale", C.c_double)]
 
 
 class Velocity(C.Structure):
@@ -232,11 +232,14 @@ class Mesh:
     ``ball_centres`` (n_balls, dim), ``ball_radii`` and ``ball_cell``.
     ``geom_device=True`` hands vertices, cells and custom balls over in
     device memory (copied to the GPU here first).  ``n_ghost``: layers of
-    ghost cells on every side of a Cartesian grid (included in ``n``)."""
+    ghost cells on every side of a Cartesian grid (included in ``n``).
+    ``hash_scale``: bucket side of the spatial hash over 2 r_max (0: 1)."""
 
-    def __init__(self, mesh, layout="subcell", stream=None, geom_device=False, n_ghost=0):
+    def __init__(self, mesh, layout="subcell", stream=None, geom_device=False, n_ghost=0,
+                 hash_scale=0.0):
         d = MeshDesc()
         d.n_ghost = int(n_ghost)
+        d.hash_scale = float(hash_scale)
         keep = []
 
         def ptr(a):

@@ -893,8 +893,11 @@ bchar_status bchar_mesh_create(const bchar_mesh_desc* d, void* stream, bchar_mes
       BCHAR_HIP(hipStreamSynchronize(s));
       d = &dh;
     }
+    BCHAR_REQUIRE(d->hash_scale == 0.0 || (d->hash_scale >= 0.25 && d->hash_scale <= 4.0),
+                  BCHAR_E_INVALID_ARG, "hash_scale must be 0 or within [0.25, 4]");
     auto* m = new bchar_mesh_s();
     try {
+      m->hash_scale = d->hash_scale == 0.0 ? 1.0 : d->hash_scale;
       m->dim = d->dim;
       m->layout = d->layout;
       m->kind = d->kind;

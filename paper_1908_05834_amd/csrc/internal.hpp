@@ -77,6 +77,7 @@ struct bchar_mesh_s {
   int64_t n_cells = 0, n_balls = 0;
   int nbpc = 1;                // balls per cell; 0: varies (ball_ptr)
   double rmax = 0;             // largest ball radius
+  double hash_scale = 1.0;     // bucket side of the hash / (2 rmax)
   bool r_uniform = false;      // every ball has radius r0
   double r0 = 0;
   bool phi_const = true;

@@ -3,10 +3,10 @@
 // The balls of a Cartesian cell follow the layout chosen at creation
 // (see bchar.h); those of a simplicial mesh come from the host (one
 // centroid ball per cell).  Residing balls are bucketed on a uniform grid
-// of side hs = 2 r_max over the domain box, so that every ball overlapping
-// a tracked ball of radius r_hat <= r_max lies in the 3^d buckets around
-// the tracked centre; larger tracked radii widen the searched block
-// (build.hip).  Bucket contents (centres, binary64 and binary32, and
+// of side hs = 2 r_max over the domain box (times the mesh's hash_scale),
+// so that every ball overlapping a tracked ball of radius r_hat <= r_max
+// lies in the 3^d buckets around the tracked centre; larger tracked radii
+// or smaller buckets widen the searched block (build.hip).  Bucket contents (centres, binary64 and binary32, and
 // radii) are stored contiguously in bucket order (SoA) so that a query
 // streams them.
 #include "device_util.hpp"
@@ -132,8 +132,8 @@ void mesh_build_cartesian(bchar_mesh_s* m, const UniformBalls& u, hipStream_t s)
 
 void mesh_build_hash(bchar_mesh_s* m, hipStream_t s) {
   const int64_t nb = m->n_balls;
-  // uniform bucket grid of side 2 r_max over the domain box
-  m->hs = 2.0 * m->rmax;
+  // uniform bucket grid of side 2 r_max (times hash_scale) over the domain box
+  m->hs = 2.0 * m->rmax * m->hash_scale;
   m->n_buckets = 1;
   for (int a = 0; a < 3; ++a) {
     if (a < m->dim) {

@@ -286,3 +286,52 @@ def test_tile_aspect_same_bits(env, name):
     for a in (1, 2, -1, -2):
         for x, y in zip(out[a][0] + out[a][1], out[0][0] + out[0][1]):
             assert np.array_equal(x, y), a
+
+
+@pytest.mark.parametrize("name", ["swirl32", "porous3d", "tets"])
+def test_hash_scale_same_pairs(env, name):
+    """Every bucket side of the spatial hash (mesh hash_scale) finds the same
+    overlapping pairs; V agrees to rounding (the residing balls of a cell
+    may be met in another order) and the step within the parity bar."""
+    torch, bchar = env
+    _say(f"[gpu] hash scales {name}")
+    if name == "swirl32":
+        w = inputs.swirl_hex(32)
+        mesh, vel, dt, layout = w["mesh"], w["vel_fn"](3), w["dt"], "subcell"
+    elif name == "porous3d":
+        w = inputs.porous_swirl_hex(8)
+        mesh, vel, dt, layout = w["mesh"], w["vel_fn"](0), 0.05, "subcell"
+    else:
+        mesh = inputs.kuhn_tets(4, 0.1, 8)
+        vel = inputs.sample_velocity_grid((4, 4, 4), lambda p, t: inputs.swirl_3d(p, t))
+        dt, layout = 0.05, "equal_measure"
+    out = {}
+    c0 = inputs.uniform_c(mesh, 29)
+    for hsc in (0.0, 0.25, 0.5, 2.0, 4.0):
+        M = bchar.Mesh(mesh, layout, hash_scale=hsc)
+        U = bchar.VelocityLattice(vel)
+        T = bchar.Transfer.build(M, U, dt, bchar.opts_default(keep_pairs=1))
+        a, b = T.export_pairs()
+        o = np.lexsort((b, a))
+        cin = torch.as_tensor(c0, device="cuda")
+        cout = torch.empty_like(cin)
+        T.step(cin, cout)
+        out[hsc] = (a[o], b[o], T.export_csr(bchar.STAGE_V), cout.cpu().numpy())
+    a0, b0, (rp0, col0, V0), c_ref = out[0.0]
+    for hsc in (0.25, 0.5, 2.0, 4.0):
+        a, b, (rp, col, V), c = out[hsc]
+        assert np.array_equal(a, a0) and np.array_equal(b, b0), hsc
+        assert np.array_equal(rp, rp0) and np.array_equal(col, col0), hsc
+        dv = np.max(np.abs(V - V0)) / np.max(np.abs(V0))
+        dc = np.max(np.abs(c - c_ref)) / np.max(np.abs(c_ref))
+        _say(f"    scale {hsc}: V rel diff {dv:.3e}, c rel diff {dc:.3e}")
+        assert dv <= 1e-15 and dc <= 1e-10
+
+
+def test_hash_scale_rejected(env):
+    torch, bchar = env
+    mesh = inputs.cartesian_mesh((8, 8))
+    for hsc in (0.1, 5.0, -1.0):
+        with pytest.raises(bchar.BcharError) as ei:
+            bchar.Mesh(mesh, "subcell", hash_scale=hsc)
+        assert ei.value.status == bchar.E_INVALID_ARG
