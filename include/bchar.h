@@ -323,6 +323,14 @@ typedef struct {
   int64_t n_target_groups;     /* DIV_GENERAL: connected components of V's
                                   pattern, each rescaled on its own; 0 for
                                   DIV_FREE                                */
+  int qp_corrected;            /* 1 when the least-change answer is an
+                                  interior point that stalled just short of
+                                  the tolerance, put onto the row and column
+                                  sums by a least-norm correction: the sums
+                                  hold to qp_tol, but entries on the box
+                                  may leave it by their share of the
+                                  correction (n_at_lower / n_at_upper count
+                                  those on or beyond a bound); else 0      */
 } bchar_stats;
 
 /* Fill *opts with the defaults listed above.                            */

@@ -75,7 +75,8 @@ class Stats(C.Structure):
                 ("qp_smooth_bytes", C.c_int64), ("dt_halvings", C.c_int),
                 ("n_void_rows", C.c_int64), ("n_void_cols", C.c_int64),
                 ("trace_precision", C.c_int), ("device_bytes", C.c_int64),
-                ("row_target_scale", C.c_double), ("n_target_groups", C.c_int64)]
+                ("row_target_scale", C.c_double), ("n_target_groups", C.c_int64),
+                ("qp_corrected", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

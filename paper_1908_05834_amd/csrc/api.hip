@@ -578,6 +578,7 @@ bchar_status build_from_tracked(bchar_mesh_s* m, bchar_transfer_s* t, const bcha
   st.qp_residual = qr.residual;
   st.n_at_lower = qr.at_lower;
   st.n_at_upper = qr.at_upper;
+  st.qp_corrected = qr.corrected ? 1 : 0;
   if (stats) *stats = st;
   t->stats = st;
   if (rc != BCHAR_OK) {

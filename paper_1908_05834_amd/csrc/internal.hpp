@@ -249,6 +249,7 @@ struct QpResult {
                               // over the sweeps of one cycle
   double residual = 0;
   int64_t at_lower = 0, at_upper = 0;
+  bool corrected = false;     // the answer came from the equality correction
 };
 // zdual: per-cell multipliers (s, g), 2 n leading parts and 2 n
 // compensations kept by the transfer;

@@ -3385,6 +3385,7 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
   int32_t hc[2];
   BCHAR_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, s));
   BCHAR_HIP(hipStreamSynchronize(s));
+  res.corrected = corrected;
   res.at_lower = hc[0];
   res.at_upper = hc[1];
   return BCHAR_OK;

@@ -60,6 +60,8 @@ def test_hard_batch_problem(env, p):
     _say(f"    stats {st}")
     assert st["dt_halvings"] == 0 and st["nnz"] == rec["nnz"]
     assert st["qp_level"] == want_level
+    # the answer is the corrected interior point, and the stats say so
+    assert st["qp_corrected"] == 1
     rp, col, AN = T.export_csr(bchar.STAGE_SCALING)
     _, _, A = T.export_csr(bchar.STAGE_ALL)
     x, mu, nu = T.export_qp()
@@ -111,6 +113,7 @@ def test_level1_batch_problem_matches_oracle(env):
     st = T.stats
     _say(f"    stats {st}")
     assert st["nnz"] == int(ref["nnz"]) and st["qp_level"] == int(ref["qp_level"]) == 1
+    assert st["qp_corrected"] == 0
     c0 = torch.as_tensor(q["c0"], device="cuda")
     c1 = torch.empty_like(c0)
     T.step(c0, c1)
