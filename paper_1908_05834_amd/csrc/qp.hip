@@ -71,6 +71,8 @@ constexpr int kPolishNewton = 6;   // semismooth steps after the interior point
 constexpr int kFallbackNewton = 40; // semismooth steps on a level every interior point
                                     // gave up on, and the short steps it may take
 constexpr int kFallbackPatience = 8;
+constexpr int kFallbackNewtonLong = 100;  // the same from zero on x >= -1 once every
+constexpr int kFallbackPatienceLong = 40; // interior point there gave up
 constexpr int kCrossoverSteps = 2; // fixed-side Newton steps from an interior point
 constexpr int kCrossoverRounds = 4; // active-set updates of the sides after the first
 constexpr double kCrossoverRatio = 1e-3;  // slack / multiplier of a pinned entry
@@ -3350,8 +3352,11 @@ bchar_status solve_qp(const bchar_mesh_s* m, const int32_t* row_ptr, const int32
         if (!converged) {
           fill_f64(Q.t, 0.0, nnz, s);
           fill_f64(zdual, 0.0, 2 * n2, s);
-          converged = ssn(lo, hi, std::min(kFallbackNewton, o.qp_max_newton), kFallbackPatience,
-                          o.qp_max_cg, " (interior point failed)");
+          // patient: from zero the answer may take dozens of short steps
+          // (the non-solenoidal swirl at 32^3 needs about 40); a Newton
+          // system that CG cannot solve still ends it at once
+          converged = ssn(lo, hi, std::min(kFallbackNewtonLong, o.qp_max_newton),
+                          kFallbackPatienceLong, o.qp_max_cg, " (interior point failed)");
         }
       }
     }
